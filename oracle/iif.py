@@ -1,0 +1,166 @@
+"""IIF2 time stepping with the implicit reaction stage.
+
+Paper: Sec. 3, integrating-factor form (3.2), the r-th order family (3.3)
+with Lagrange coefficients (3.4), and IIF2 (3.5):
+
+    U^{n+1} = exp(A dt) (U^n + dt/2 F(U^n)) + dt/2 F(U^{n+1}).
+
+The implicit stage solves  G(U) = U - dt/2 F(U) - W = 0,  W = exp(A dt)(...),
+a system of the size of the unknowns (Sec. 5: the sparse basis is global, so
+the "local implicit property" is lost and Newton iterations are needed).
+
+Readings:
+* The spec form of the stage is a pointwise quasi-Newton iteration with
+  the same root as Newton on G:
+      U <- U - P[(I_s - dt/2 J_f(u_q))^{-1} (R G)_q],
+  with a species-by-species Jacobian inverse at every quadrature point q.
+  `implicit_stage_newton_dense` is the exact-Jacobian Newton on tiny grids
+  that pins the root.
+* Initial guess U^0 = W + dt/2 F(U^n); stop when ||G||_2 <= tol * max(1, ||W||_2)
+  (tol = 1e-13 unless given), at most 50 corrections.
+* F(U^{n+1}) of the accepted iterate is reused as F(U^n) of the next step
+  (same input, same value).
+* One Krylov exponential per species (the diffusion operator of a system is
+  block diagonal, species s scaled by D_s).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import krylov, reaction
+from .operator import assemble_A, inf_norm
+
+TOL_DEFAULT = 1e-13
+MAX_ITER_DEFAULT = 50
+
+
+def iif_alpha(r: int):
+    """Lagrange coefficients of (3.4): alpha_i for i = -1 .. r-2 (returns a dict).
+
+    alpha_{-i} = (1/dt) int_0^dt prod_{k=-1..r-2, k != i} (tau + k dt)/((k - i) dt) dtau,
+    evaluated with dt = 1 by exact polynomial integration.
+    """
+    from numpy.polynomial import polynomial as P
+
+    out = {}
+    for i in range(-1, r - 1):
+        poly = np.array([1.0])
+        for kk in range(-1, r - 1):
+            if kk == i:
+                continue
+            poly = P.polymul(poly, np.array([kk, 1.0]) / (kk - i))
+        integ = P.polyint(poly)
+        out[i] = float(P.polyval(1.0, integ) - P.polyval(0.0, integ))
+    return out
+
+
+class Problem:
+    """One instance: operator, quadrature, reaction and step parameters."""
+
+    def __init__(self, d, N, k, D, rx, dt, M, sigma=20.0, kappas=None, nq=None):
+        self.d, self.N, self.k = d, N, k
+        self.D = list(D)
+        self.S = len(self.D)
+        self.rx = np.asarray(rx, dtype=np.float64)
+        self.dt, self.M = float(dt), int(M)
+        A1 = assemble_A(d, N, k, sigma, kappas, 1.0)
+        self.A = [Ds * A1 for Ds in self.D]
+        self.anorm = [inf_norm(a) for a in self.A]
+        self.quad = reaction.Quadrature(d, N, k, nq)
+        self.ndof = A1.shape[0]
+
+    def F(self, U):
+        return reaction.F(self.quad, self.rx, U)
+
+
+def implicit_stage(prob: Problem, W, Fn, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT):
+    """Pointwise quasi-Newton solve of U - dt/2 F(U) = W.
+
+    Returns (U, F(U), info) with info = {iters, residual, converged}.
+    """
+    dt2 = 0.5 * prob.dt
+    S = prob.S
+    U = W + dt2 * Fn
+    wnorm = float(np.linalg.norm(W))
+    it = 0
+    while True:
+        uq = [prob.quad.R(U[s]) for s in range(S)]
+        fq = reaction.f_eval(prob.rx, uq)
+        FU = np.array([prob.quad.P(fq[s]) for s in range(S)])
+        G = U - dt2 * FU - W
+        res = float(np.linalg.norm(G))
+        if res <= tol * max(1.0, wnorm):
+            return U, FU, {"iters": it, "residual": res, "converged": True}
+        if it == max_iter:
+            return U, FU, {"iters": it, "residual": res, "converged": False}
+        Gq = [prob.quad.R(G[s]) for s in range(S)]
+        J = reaction.f_jac(prob.rx, uq)
+        if S == 1:
+            dq = [Gq[0] / (1.0 - dt2 * J[0][0])]
+        else:
+            a, b = 1.0 - dt2 * J[0][0], -dt2 * J[0][1]
+            c, d = -dt2 * J[1][0], 1.0 - dt2 * J[1][1]
+            det = a * d - b * c
+            dq = [(d * Gq[0] - b * Gq[1]) / det, (a * Gq[1] - c * Gq[0]) / det]
+        U = U - np.array([prob.quad.P(dq[s]) for s in range(S)])
+        it += 1
+
+
+def implicit_stage_newton_dense(prob: Problem, W, Fn, tol=1e-14, max_iter=30):
+    """Exact-Jacobian Newton on G(U) = U - dt/2 P f(R U) - W (tiny grids only).
+
+    J_G = I - dt/2 P diag(J_f) R, with R and P formed as explicit matrices.
+    """
+    S, n = prob.S, prob.ndof
+    dt2 = 0.5 * prob.dt
+    Rm = np.stack([prob.quad.R(e).ravel() for e in np.eye(n)], axis=1)  # npts x n
+    Wq = prob.quad.weights().ravel()
+    Pm = (Rm * Wq[:, None]).T  # n x npts
+    U = W + dt2 * Fn
+    for _ in range(max_iter):
+        uq = [Rm @ U[s] for s in range(S)]
+        fq = reaction.f_eval(prob.rx, uq)
+        G = U - dt2 * np.array([Pm @ fq[s] for s in range(S)]) - W
+        if np.linalg.norm(G) <= tol * max(1.0, np.linalg.norm(W)):
+            break
+        J = reaction.f_jac(prob.rx, uq)
+        JG = np.eye(S * n)
+        for s in range(S):
+            for t in range(S):
+                JG[s * n : (s + 1) * n, t * n : (t + 1) * n] -= dt2 * (Pm * J[s][t][None, :]) @ Rm
+        U = U - np.linalg.solve(JG, G.ravel()).reshape(S, n)
+    return U
+
+
+def expv_species(prob: Problem, v, dense: bool = False):
+    """exp(A_s dt) v_s for every species (Krylov with M, or dense)."""
+    out, infos = [], []
+    for s in range(prob.S):
+        if dense:
+            out.append(krylov.dense_expv(prob.A[s], prob.dt, v[s]))
+            infos.append({"m": -1})
+        else:
+            w, info = krylov.expv(prob.A[s], prob.dt, v[s], prob.M, prob.anorm[s])
+            out.append(w)
+            infos.append(info)
+    return np.array(out), infos
+
+
+def iif2_step(prob: Problem, U, Fn, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT):
+    """One IIF2 step (3.5).  Returns (U^{n+1}, F(U^{n+1}), info)."""
+    v = U + 0.5 * prob.dt * Fn
+    W, kinfo = expv_species(prob, v, dense)
+    U1, F1, ninfo = implicit_stage(prob, W, Fn, tol, max_iter)
+    ninfo["krylov"] = kinfo
+    return U1, F1, ninfo
+
+
+def iif2_run(prob: Problem, U0, steps: int, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT):
+    """`steps` IIF2 steps from U0 (species, ndof).  Returns (U, F(U), infos)."""
+    U = np.array(U0, dtype=np.float64).reshape(prob.S, prob.ndof)
+    Fn = prob.F(U)
+    infos = []
+    for _ in range(steps):
+        U, Fn, info = iif2_step(prob, U, Fn, dense, tol, max_iter)
+        infos.append(info)
+    return U, Fn, infos

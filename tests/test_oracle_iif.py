@@ -1,0 +1,103 @@
+"""Pins for IIF2 and its implicit reaction stage (Sec. 3, eqs. 3.3-3.6; Sec. 5)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import iif, krylov, project, sparsegrid
+from paper_1810_11111_amd import inputs as I
+
+
+def test_lagrange_coefficients_give_iif2_iif3(golden_dir):
+    with open(os.path.join(golden_dir, "paper_values.json")) as fh:
+        g = json.load(fh)["iif_alpha"]
+    a2 = iif.iif_alpha(2)
+    assert np.allclose([a2[-1], a2[0]], g["r2"], atol=1e-15)
+    a3 = iif.iif_alpha(3)
+    assert np.allclose([a3[-1], a3[0], a3[1]], g["r3"], atol=1e-15)
+
+
+def test_pointwise_stage_has_newton_root():
+    d, N, k = 2, 3, 1
+    prob = iif.Problem(d, N, k, [0.01, 1.0], I.rx_schnakenberg(0.1, 0.9), 0.2, 10)
+    n = prob.ndof
+    rng = np.random.default_rng(0)
+    W = np.zeros((2, n))
+    W[0, 0], W[1, 0] = 1.0, 0.9
+    W += rng.uniform(-0.05, 0.05, W.shape)
+    Fn = prob.F(W)
+    U1, _, info = iif.implicit_stage(prob, W, Fn, tol=1e-15)
+    U2 = iif.implicit_stage_newton_dense(prob, W, Fn)
+    assert info["converged"]
+    assert np.abs(U1 - U2).max() <= 1e-13 * np.abs(U2).max()
+    G = U1 - 0.1 * prob.F(U1) - W
+    assert np.linalg.norm(G) < 1e-13
+
+
+def test_linear_stage_closed_form():
+    d, N, k = 2, 3, 1
+    prob = iif.Problem(d, N, k, [1.0], I.rx_linear(-1.0), 0.01, 10)
+    W = np.random.default_rng(1).uniform(-1, 1, (1, prob.ndof))
+    U, _, info = iif.implicit_stage(prob, W, prob.F(W), tol=1e-15)
+    assert np.abs(U - W / 1.005).max() < 1e-15 and info["iters"] <= 2
+
+
+def test_constant_state_with_linear_decay():
+    d, N, k = 2, 4, 1
+    dt = 0.05
+    prob = iif.Problem(d, N, k, [1.0], I.rx_linear(-1.0), dt, 10)
+    U0 = np.zeros((1, prob.ndof))
+    U0[0, 0] = 0.7
+    U, _, infos = iif.iif2_run(prob, U0, 6)
+    assert infos[0]["krylov"][0]["m"] == 1
+    ref = 0.7 * ((1 - dt / 2) / (1 + dt / 2)) ** 6
+    assert abs(U[0, 0] - ref) < 1e-15 and np.abs(U[0, 1:]).max() < 1e-15
+
+
+def test_zero_reaction_is_repeated_exponential():
+    d, N, k = 2, 4, 1
+    prob = iif.Problem(d, N, k, [0.1], I.rx_zeros(1), 0.01, 12)
+    U0 = np.random.default_rng(2).uniform(-1, 1, (1, prob.ndof))
+    U, _, _ = iif.iif2_run(prob, U0, 3)
+    v = U0[0]
+    for _ in range(3):
+        v, _ = krylov.expv(prob.A[0], prob.dt, v, 12, prob.anorm[0])
+    assert np.abs(U[0] - v).max() < 1e-14
+
+
+def test_mean_trapezoid_identity_with_dense_exponential():
+    """Periodic: exp(A dt) keeps the mean coefficient, so U_0^{n+1} = U_0^n + dt/2 (F_0^n + F_0^{n+1})."""
+    d, N, k = 2, 3, 1
+    prob = iif.Problem(d, N, k, [1.0], I.rx_quadratic(-1.0), 0.01, 10)
+    U0 = project.project_terms(d, N, k, [(0.5, [I.SIN, I.SIN]), (0.3, [I.ONE, I.ONE])])[None]
+    F0 = prob.F(U0)
+    U1, F1, _ = iif.iif2_step(prob, U0, F0, dense=True, tol=1e-15)
+    assert abs(U1[0, 0] - (U0[0, 0] + 0.005 * (F0[0, 0] + F1[0, 0]))) < 1e-14
+
+
+@pytest.mark.slow
+def test_example4_matches_table7(golden_dir):
+    """Example 4 (stiff linear 2-species system): the IIF2 error is dominated by the
+    time discretisation, so its magnitude is pinned, not only its order.
+    Initial v is read as (b - c) prod cos(2 pi x_i), the value of the exact solution at t=0."""
+    with open(os.path.join(golden_dir, "paper_values.json")) as fh:
+        g = json.load(fh)["example4_table7"]
+    d, k, T, M = g["d"], g["k"], g["T"], g["M"]
+    a, b, c = g["a"], g["b"], g["c"]
+    kk = 1.0 / (4 * d * np.pi ** 2)
+    uerr, verr = [], []
+    for N in (5, 6, 7):
+        dt = 2.0 ** -N
+        prob = iif.Problem(d, N, k, [kk * a, kk * a], I.rx_stiff_linear_system(b, c), dt, M)
+        P = project.project_terms(d, N, k, [(1.0, [I.COS] * d)])
+        U, _, _ = iif.iif2_run(prob, np.array([2 * P, (b - c) * P]), int(round(T / dt)))
+        fu = np.exp(-(b + a) * T) + np.exp(-(c + a) * T)
+        fv = (b - c) * np.exp(-(c + a) * T)
+        uerr.append(project.l2_error(U[0], fu * P, fu ** 2 * 0.25))
+        verr.append(project.l2_error(U[1], fv * P, fv ** 2 * 0.25))
+    for i in range(3):
+        assert abs(uerr[i] / g["u_error"][i] - 1) < 0.15, (uerr, g["u_error"])
+        assert abs(verr[i] / g["v_error"][i] - 1) < 0.15, (verr, g["v_error"])
+        assert abs(verr[i] / uerr[i] / (b - c) - 1) < 0.02
+    assert all(1.7 < np.log2(uerr[i] / uerr[i + 1]) < 2.3 for i in range(2))
