@@ -102,6 +102,14 @@ def test_smooth_eigenvalue_converges_to_minus_4pi2():
     assert errs[0] > 3 * errs[1] > 9 * errs[2]
 
 
+def test_single_periodic_cell_by_hand():
+    """N = 0, k = 1: one cell whose two ends meet at the periodic face.  For
+    phi_1 = sqrt(3)(2x-1): int phi_1'^2 = 12, jump 2 sqrt(3), mean derivative
+    2 sqrt(3), so B = 12 - 2*12 + 20*12 = 228; phi_0 = 1 has no jump and no slope."""
+    B = operator.full_grid_sipg(0, 1)
+    assert np.allclose(B, [[0.0, 0.0], [0.0, 228.0]], atol=1e-12)
+
+
 def test_inf_norm():
     A = operator.assemble_A(2, 3, 1)
     assert operator.inf_norm(A) == pytest.approx(np.abs(A.toarray()).sum(axis=1).max(), rel=1e-15)
