@@ -1,0 +1,207 @@
+/*
+ * sgdg.h -- C ABI of the sparse-grid Krylov IIF discontinuous Galerkin library
+ * for AMD MI355X (gfx950).
+ *
+ * Method: Liu, Cheng, Chen, Zhang, "Krylov implicit integration factor
+ * discontinuous Galerkin methods on sparse grids for high dimensional
+ * reaction-diffusion equations" (arXiv:1810.11111).
+ *
+ * Problem (Sec. 1, eq. 1.1 on the periodic unit cube, diagonal diffusion):
+ *     u_t = div(K(x) grad u) + f(u),   K = diag(D_s k_ii(x_i)),  x in [0,1]^d,
+ * discretised in space by the symmetric interior-penalty DG method on the
+ * sparse multiwavelet space V_N^k (Sec. 2.1, eqs. 2.6-2.11) -- giving
+ * dU/dt = A U + F(U) (Sec. 3, eq. 3.1) -- and in time by the Krylov IIF2 scheme
+ * (Sec. 3, eqs. 3.5, 3.7, 3.8).
+ *
+ * Conventions for every call
+ *   - Every function returns an sgdg_status.  No C++ exception crosses the ABI.
+ *   - Argument errors are detected on the host before any device work is
+ *     queued; nothing is written in that case.  sgdg_last_error() returns a
+ *     message for the calling thread's last failure.
+ *   - "device pointer" arguments are HIP device allocations owned by the
+ *     caller; "host pointer" arguments are ordinary memory owned by the caller.
+ *     The library never frees caller memory.
+ *   - Device work is queued asynchronously on `stream` (a hipStream_t passed as
+ *     void*; NULL means the default stream).  Results are valid after the
+ *     caller synchronises that stream.
+ *   - A plan is immutable after sg_dg_build and may be used from several
+ *     threads; calls that share a workspace must not overlap in time.
+ *
+ * Vector layout ("plan vector")
+ *   A plan holds `ninst` independent instances.  Instance i contributes
+ *   nspecies_i * ndof_i consecutive entries starting at offset_i (see
+ *   sg_dg_info); inside an instance the species are consecutive blocks of
+ *   ndof_i entries.  Inside a species the DOFs are in the canonical order:
+ *     - level blocks l in N_0^d with |l|_1 <= N (eq. 2.9), sorted by |l|_1 and
+ *       then lexicographically in (l_1, ..., l_d);
+ *     - inside a block a row-major d-dimensional array, axis m of extent
+ *       c(l_m)(k+1) with c(0) = 1, c(l) = 2^(l-1), index j_m (k+1) + p_m for
+ *       cell j_m and 0-based wavelet/Legendre index p_m (eqs. 2.6, 2.8).
+ *   Calls that take `nrhs` operate on nrhs plan vectors stored one after the
+ *   other (right-hand side r starts at r * total, total from sg_dg_total).
+ *
+ * Basis (eq. 2.6): level 0 is sqrt(2p+1) P_p(2x-1); level n >= 1, cell j is
+ * 2^((n-1)/2) psi_p(2^(n-1) x - j) with psi_p the Alpert multiwavelets on [0,1],
+ * fixed by vanishing moments of order k+p and a sign rule (the highest nonzero
+ * Legendre coefficient on the right half is positive).
+ */
+#ifndef SGDG_H
+#define SGDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SGDG_OK = 0,
+  SGDG_ERR_ARG = 1,         /* invalid argument (nothing was done)                  */
+  SGDG_ERR_ALLOC = 2,       /* device or host allocation failed                     */
+  SGDG_ERR_HIP = 3,         /* a HIP runtime call failed                            */
+  SGDG_ERR_UNSUPPORTED = 4, /* valid request outside what this build implements     */
+  SGDG_ERR_NOCONV = 5,      /* implicit stage did not reach its tolerance (stats)   */
+  SGDG_ERR_NONFINITE = 6    /* a NaN/Inf was produced or consumed (stats)           */
+} sgdg_status;
+
+/* Precision of the operator sweeps (the matrix-free products A x).  Inner
+ * products, norms, the Hessenberg exponential, the Krylov combination and the
+ * implicit-stage residual are always FP64 (FP64 accumulation).            */
+typedef enum {
+  SGDG_FP64 = 0,       /* sweeps, Krylov basis and state in FP64                 */
+  SGDG_FP32_SWEEP = 1, /* sweep input/output and Krylov basis in FP32, FP32 sums  */
+  SGDG_BF16_SWEEP = 2  /* sweep input BF16, output and Krylov basis FP32, FP32 sums */
+} sgdg_precision;
+
+/* Diagonal diffusion factor of one axis: k_ii(x) = a0 + a1 sin(2 pi freq x + phase).
+ * Must be positive on [0,1] (eq. 1.2 bounds).                               */
+typedef struct {
+  double a0, a1, freq, phase;
+} sgdg_kdiag;
+
+/* One instance (Sec. 2.1 scheme on [0,1]^d, periodic boundary). */
+typedef struct {
+  int32_t d;          /* space dimension, 1..6                                  */
+  int32_t n;          /* sparse-grid level N >= 0 (|l|_1 <= N), 2^N finest cells */
+  int32_t k;          /* polynomial degree, 1..3 (the scheme needs k >= 1)       */
+  int32_t nspecies;   /* 1 or 2                                                 */
+  double sigma;       /* interior penalty sigma (<= 0 selects 20); penalty sigma/h_N */
+  double D[2];        /* per-species diffusion multiplier D_s > 0                */
+  const sgdg_kdiag* kdiag; /* NULL: k_ii = 1; else d entries, read during build only */
+  /* Reaction f_s(u0, u1) = sum_{a,b=0..3} rx[s][a][b] u0^a u1^b (degree <= 3 used). */
+  double rx[2][4][4];
+} sgdg_desc;
+
+/* A separable 1D factor of initial data, for sg_dg_project. */
+typedef struct {
+  int32_t kind;   /* 0: cos(2 pi a x + b);  1: indicator of [a, b)              */
+  int32_t pad;
+  double a, b;
+} sgdg_factor1d;
+
+/* Per-problem statistics written on the device (one entry per right-hand
+ * side, instance and species slot: index (r * ninst + i) * 2 + s).          */
+typedef struct {
+  int32_t krylov_m;     /* Krylov dimension reached (< M after a breakdown)     */
+  int32_t newton_iters; /* corrections applied by the implicit stage            */
+  double h_next;        /* h_{m+1,m}: a-posteriori Krylov size estimate         */
+  double residual;      /* final ||G||_2 of the implicit stage (per instance)    */
+  int32_t status;       /* SGDG_OK, SGDG_ERR_NOCONV or SGDG_ERR_NONFINITE         */
+  int32_t pad;
+} sgdg_stats;
+
+typedef struct sgdg_plan sgdg_plan;
+
+/* Message for the calling thread's last non-OK status (static storage). */
+const char* sgdg_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Plan construction (host; uploads tables once -- the paper notes the 1D
+ * integrals are assembled once before the time evolution, Sec. 4 intro).
+ * descs: host array of ninst descriptors; every instance must have the same
+ * d.  prec: sweep precision of the plan.  *out receives the plan.
+ * Builds the 1D hierarchical SIPG operators (eq. 2.10 bilinear form, faces of
+ * Omega_N, penalty sigma/h_N), the level-block tables and the Gauss tables
+ * (k+1 points per axis in every finest cell) used by the reaction transforms,
+ * on the current HIP device.  Errors: SGDG_ERR_ARG, _ALLOC, _HIP.           */
+sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_t prec, sgdg_plan** out);
+
+/* Frees the plan and its device tables (synchronises the device first). */
+sgdg_status sg_dg_destroy(sgdg_plan* plan);
+
+/* Sizes of instance `inst`: DOFs per species (eq. 2.9 index set), offset of
+ * the instance in a plan vector, Gauss points per species ((k+1) 2^N)^d.     */
+sgdg_status sg_dg_info(const sgdg_plan* plan, int32_t inst, int64_t* ndof, int64_t* offset,
+                       int64_t* npoints);
+
+/* Entries of one plan vector (sum over instances of nspecies * ndof). */
+sgdg_status sg_dg_total(const sgdg_plan* plan, int64_t* total);
+
+/* Device workspace (bytes) needed by krylov_expv and by iif2_step for Krylov
+ * dimension M (1..48) and nrhs right-hand sides.                            */
+sgdg_status sg_dg_workspace_size(const sgdg_plan* plan, int32_t M, int32_t nrhs, size_t* krylov_bytes,
+                                 size_t* iif2_bytes);
+
+/* Host export of the canonical DOF order of instance `inst`: level, cell and
+ * 0-based index p for every DOF and axis (host arrays of ndof*d int32,
+ * row-major [dof][axis]).                                                   */
+sgdg_status sg_dg_layout(const sgdg_plan* plan, int32_t inst, int32_t* lev, int32_t* cell, int32_t* p);
+
+/* L2 projection (Sec. 2.2, u_h(0) = P u) of amp * prod_m g_m(x_m) onto the
+ * sparse space of instance `inst`; factors: host array of d descriptors;
+ * out: host array of ndof doubles (overwritten).  Computed on the host with a
+ * 16-point Gauss rule per finest cell.                                      */
+sgdg_status sg_dg_project(const sgdg_plan* plan, int32_t inst, double amp, const sgdg_factor1d* factors,
+                          double* out);
+
+/* ||A_s||_inf (max absolute row sum) of species s of instance inst (host). */
+sgdg_status sg_dg_norm_inf(const sgdg_plan* plan, int32_t inst, int32_t species, double* out);
+
+/* ------------------------------------------------------------------------ */
+/* y = A x for nrhs plan vectors (Sec. 2.1, eq. 2.10 with the orthonormal
+ * mass matrix; Sec. 4 "unidirectional principle"):
+ *   A = - sum_i D_s (I x .. x B_i x .. x I) restricted to |l|_1 <= N,
+ * applied matrix-free from the 1D hierarchical operators B_i.
+ * x, y: device pointers of nrhs*total elements, not aliased.  Element type
+ * by plan precision: FP64 -> double/double, FP32 -> float/float, BF16 ->
+ * bfloat16 (uint16 bits)/float.  Errors: SGDG_ERR_ARG, SGDG_ERR_HIP.        */
+sgdg_status sg_dg_apply(const sgdg_plan* plan, int32_t nrhs, const void* x, void* y, void* stream);
+
+/* w ~ exp(h A) v (Sec. 3, eq. 3.8): Arnoldi (eq. 3.7) with M products per
+ * species, instance and right-hand side, classical Gram-Schmidt with one
+ * re-orthogonalisation pass, happy breakdown when h_{j+1,j} <= 1e-12 ||A_s||_inf,
+ * then gamma V_m exp(h H_m) e_1 with exp by Pade approximation with scaling
+ * and squaring (Higham 2005, degrees 3..13).  M is clamped to the DOF count
+ * of each species.  v, w: device FP64 plan vectors (nrhs*total), may alias.
+ * workspace: device buffer of at least krylov_bytes (sg_dg_workspace_size).
+ * stats: device array of nrhs*ninst*2 sgdg_stats or NULL.                   */
+sgdg_status krylov_expv(const sgdg_plan* plan, int32_t nrhs, double h, int32_t M, const double* v, double* w,
+                        void* workspace, size_t workspace_bytes, sgdg_stats* stats, void* stream);
+
+/* F(U) = P f(R U) (Sec. 5: reconstruction at the Gauss points of the finest
+ * mesh, pointwise f, Gauss quadrature back to the sparse space).  U, F:
+ * device FP64 plan vectors (nrhs*total), not aliased; workspace as for
+ * iif2_step.                                                                */
+sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const double* U, double* F, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* One IIF2 step (Sec. 3, eq. 3.5):
+ *   W = exp(A dt) (U + dt/2 F(U));  solve U' - dt/2 F(U') = W;  U <- U'.
+ * The implicit stage iterates U <- U - P[(I - dt/2 J_f(u_q))^{-1} (R G)_q],
+ * G = U - dt/2 F(U) - W, from U = W + dt/2 F(U^n), until
+ * ||G||_2 <= newton_tol * max(1, ||W||_2) per instance and right-hand side or
+ * newton_max corrections (status SGDG_ERR_NOCONV in stats; U holds the last
+ * iterate).  U: device FP64 plan vectors, updated in place.  Fcache: device
+ * FP64 plan vectors holding F(U) on entry (computed by sgdg_reaction for the
+ * first step) and F(U') on return; NULL recomputes it every step.
+ * workspace: at least iif2_bytes.  stats: device array or NULL.             */
+sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcache,
+                      double newton_tol, int32_t newton_max, void* workspace, size_t workspace_bytes,
+                      sgdg_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGDG_H */

@@ -1,0 +1,148 @@
+// Internal declarations shared by the host plan builder and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sgdg.h"
+
+#define SGDG_MAX_D 6
+#define SGDG_MAX_M 48
+#define SGDG_MAX_K 3
+
+namespace sgdg {
+
+// One level block of one species of one instance.
+struct GBlock {
+  int64_t start;  // first element in a plan vector
+  int32_t size;
+  int32_t inst;
+  int32_t species;
+  int32_t lsum;  // |l|_1
+  int32_t lev[SGDG_MAX_D];
+  int32_t ext[SGDG_MAX_D];  // c(l_m)(k+1)
+};
+
+// A contiguous piece (<= CHUNK elements) of one species segment; every
+// element of a chunk belongs to blocks b0..b1 of that segment.
+struct Chunk {
+  int64_t start;
+  int32_t count;
+  int32_t b0, b1;
+  int32_t inst;
+  int32_t species;
+  int32_t problem;  // inst * 2 + species
+};
+
+// Per-instance constants seen by the kernels.
+struct InstDev {
+  int32_t N, k, S, nb;
+  int64_t offset, ndof;
+  double D[2];
+  int32_t blkid_off;              // into blkid: (N+1)^d entries, -1 where |l|_1 > N
+  int32_t gblk_off;               // global index of this instance's species-0 block 0
+  int32_t bcsr_off[SGDG_MAX_D];   // into BCsr table per direction
+  int32_t pow[SGDG_MAX_D];        // (N+1)^(d-1-i)
+  int32_t n1;                     // (k+1) 2^N
+  int32_t rx_off;                 // unused placeholder for alignment
+  double rx[2][4][4];
+  double anorm[2];                // ||A_s||_inf
+};
+
+// Cell-block CSR of a 1D hierarchical operator: for target cell t (cell
+// index c = 0 for level 0, 2^(l-1)+j for level l >= 1) the source cells
+// src[cptr[t] .. cptr[t+1]) in ascending order, each with a (k+1)x(k+1)
+// block val[e][pt][ps] of B(v_source, v_target).
+struct BCsr {
+  int64_t cptr_off;  // into cptr (ncell + 1 entries)
+  int64_t src_off;   // into src (block index)
+  int64_t val_off;   // into val / valf (scalar index of block 0)
+  int32_t ncell;
+  int32_t k;
+};
+
+struct DevTables {
+  GBlock* gblk = nullptr;
+  Chunk* chunks = nullptr;
+  InstDev* inst = nullptr;
+  int32_t* blkid = nullptr;
+  int64_t* lstart = nullptr;  // per (instance, local block): start inside a species segment
+  BCsr* bcsr = nullptr;
+  int32_t* cptr = nullptr;
+  int32_t* src = nullptr;
+  double* val = nullptr;
+  float* valf = nullptr;
+  int32_t* pchunk0 = nullptr;  // [inst*2+s]: first chunk of the species segment
+  int32_t* pnchunk = nullptr;  // [inst*2+s]: its number of chunks
+};
+
+struct HostInstance {
+  sgdg_desc desc;
+  std::vector<sgdg_kdiag> kdiag;  // d entries (a0=1,a1=0 when none)
+  int64_t ndof = 0, offset = 0, npoints = 0;
+  std::vector<std::vector<int>> blocks;  // level tuples, canonical order
+  std::vector<int64_t> bstart;           // start inside a species segment
+  std::vector<int32_t> bsize;
+  // 1D operator per direction (cell-block CSR, host copy)
+  std::vector<int> dir_tab;  // index into plan's op tables per direction
+  double anorm[2] = {0, 0};
+};
+
+struct Op1D {  // host cell-block CSR
+  int N, k;
+  std::vector<int32_t> cptr, src;
+  std::vector<double> val;  // nnzb * (k+1)^2
+  std::vector<double> kd;   // kdiag descriptor used (a0,a1,freq,phase), for sharing
+  double sigma;
+};
+
+}  // namespace sgdg
+
+struct sgdg_plan {
+  int32_t ninst = 0, d = 0, prec = 0;
+  int32_t device = 0;
+  int64_t total = 0;
+  int32_t nchunks = 0, nblocks = 0;
+  std::vector<sgdg::HostInstance> inst;
+  std::vector<sgdg::Op1D> ops;
+  std::vector<sgdg::GBlock> gblk;
+  std::vector<sgdg::Chunk> chunks;
+  std::vector<std::vector<int32_t>> chunks_by_k;  // chunk ids grouped by k (index k)
+  std::vector<int32_t*> dev_chunk_lists;          // device copies of chunks_by_k
+  std::vector<sgdg::InstDev> instdev;
+  std::vector<int32_t> pchunk0, pnchunk;  // host copies of the per-species chunk ranges
+  sgdg::DevTables dev;
+  std::vector<void*> allocations;
+  // reaction tables (filled by the reaction module)
+  void* rdata = nullptr;
+};
+
+namespace sgdg {
+
+constexpr int CHUNK = 256;
+
+// error reporting
+sgdg_status fail(sgdg_status st, const std::string& msg);
+sgdg_status hip_fail(hipError_t e, const char* what);
+
+// host basis construction (host_basis.cpp)
+void gauss01(int n, std::vector<double>& x, std::vector<double>& w);
+void legendre01_all(int n, double x, double* val, double* der);  // orthonormal on [0,1], degrees 0..n
+struct Basis1D {
+  int k;
+  std::vector<double> cL, cR;  // psi_p halves: (k+1)x(k+1), [p][q]
+  std::vector<double> ML, MR;  // child coefficients from parent: [q_child][i_parent]
+};
+const Basis1D& basis1d(int k);
+double hier_value(const Basis1D& b, int level, int j, int p, double x, bool deriv);
+
+// 1D operator (host_operator.cpp)
+Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd);
+
+// enumeration helpers
+inline int level_count(int l) { return l == 0 ? 1 : (1 << (l - 1)); }
+
+}  // namespace sgdg

@@ -1,0 +1,135 @@
+// Device-side building blocks shared by the sweep, Krylov and reaction kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace sgdg {
+
+// bfloat16 stored as its 16 high float bits; round to nearest even on store.
+__device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t f_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));  // inf/nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Precision policies of a sweep: input element, output element, matrix value, accumulator.
+struct PrecF64 {
+  using X = double;
+  using Y = double;
+  using V = double;
+  using A = double;
+  __device__ static A load(const X* p) { return *p; }
+  __device__ static const V* vals(const DevTables& T) { return T.val; }
+};
+struct PrecF32 {
+  using X = float;
+  using Y = float;
+  using V = float;
+  using A = float;
+  __device__ static A load(const X* p) { return *p; }
+  __device__ static const V* vals(const DevTables& T) { return T.valf; }
+};
+struct PrecBF16 {
+  using X = uint16_t;
+  using Y = float;
+  using V = float;
+  using A = float;
+  __device__ static A load(const X* p) { return bf16_to_f(*p); }
+  __device__ static const V* vals(const DevTables& T) { return T.valf; }
+};
+
+// Locate the level block of global element g inside chunk ch (binary search
+// over the chunk's block range).
+__device__ __forceinline__ int find_block(const DevTables& T, const Chunk& ch, int64_t g) {
+  int lo = ch.b0, hi = ch.b1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (T.gblk[mid].start <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// y_g = (A x)_g for one output element g of a plan vector (x points at the
+// start of the plan vector).  Returns the accumulated value (already scaled by
+// -D_s).
+template <int D, int K, class P>
+__device__ __forceinline__ typename P::A apply_one(const DevTables& T, const Chunk& ch, int64_t g,
+                                                   const typename P::X* __restrict__ x) {
+  using A = typename P::A;
+  using V = typename P::V;
+  constexpr int K1 = K + 1;
+  const int bi = find_block(T, ch, g);
+  const GBlock& B = T.gblk[bi];
+  const InstDev& I = T.inst[B.inst];
+  int ext[D], sh[D], t[D], lev[D];
+  int L = (int)(g - B.start);
+  {
+    int rem = L;
+    for (int m = D - 1; m >= 0; --m) {
+      lev[m] = B.lev[m];
+      sh[m] = lev[m] > 0 ? lev[m] - 1 : 0;
+      ext[m] = K1 << sh[m];
+      int q = (rem / K1) >> sh[m];
+      t[m] = rem - q * ext[m];
+      rem = q;
+    }
+  }
+  // strides, prefix (axes before i) and suffix (axes after i) offsets
+  int str[D];
+  str[D - 1] = 1;
+  for (int m = D - 2; m >= 0; --m) str[m] = str[m + 1] * ext[m + 1];
+  int pre[D + 1], suf[D + 1];
+  pre[0] = 0;
+  for (int m = 0; m < D; ++m) pre[m + 1] = pre[m] * ext[m] + t[m];
+  suf[D] = 0;
+  for (int m = D - 1; m >= 0; --m) suf[m] = suf[m + 1] + t[m] * str[m];
+  int linall = 0;
+  for (int m = 0; m < D; ++m) linall += lev[m] * I.pow[m];
+
+  const int64_t seg = I.offset + (int64_t)B.species * I.ndof;
+  const V* __restrict__ vals = P::vals(T);
+  A acc = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int li = lev[i];
+    const int budget = I.N - B.lsum + li;
+    const int lim = 1 << budget;
+    const int pt = t[i] % K1;
+    const int jt = t[i] / K1;
+    const int tcell = li == 0 ? 0 : (1 << (li - 1)) + jt;
+    const int S = str[i];
+    const int Ahi = pre[i];
+    const int Blo = suf[i + 1];
+    const int lin = linall - li * I.pow[i];
+    const BCsr bc = T.bcsr[I.bcsr_off[i]];
+    const int e0 = T.cptr[bc.cptr_off + tcell];
+    const int e1 = T.cptr[bc.cptr_off + tcell + 1];
+    const int32_t* __restrict__ src = T.src + bc.src_off;
+    const V* __restrict__ vrow = vals + bc.val_off + pt * K1;
+    for (int e = e0; e < e1; ++e) {
+      const int sc = src[e];
+      if (sc >= lim) break;
+      const int lc = sc == 0 ? 0 : 32 - __clz(sc);
+      const int jc = sc == 0 ? 0 : sc - (1 << (lc - 1));
+      const int extc = lc == 0 ? K1 : (K1 << (lc - 1));
+      const int sb = T.blkid[I.blkid_off + lin + lc * I.pow[i]];
+      const int64_t base = seg + T.lstart[sb] + (int64_t)(Ahi * extc + jc * K1) * S + Blo;
+      const V* __restrict__ v = vrow + (int64_t)e * K1 * K1;
+#pragma unroll
+      for (int pc = 0; pc < K1; ++pc) acc += (A)v[pc] * P::load(x + base + (int64_t)pc * S);
+    }
+  }
+  return acc * (A)(-I.D[B.species]);
+}
+
+template <class P>
+void launch_apply(const sgdg_plan* plan, int nrhs, const void* x, void* y, int64_t xs, int64_t ys, hipStream_t s);
+
+}  // namespace sgdg

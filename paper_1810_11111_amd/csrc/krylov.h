@@ -1,0 +1,30 @@
+// Krylov workspace layout and launchers shared by krylov.hip and iif2.hip.
+#pragma once
+
+#include "internal.h"
+
+namespace sgdg {
+
+// Device-side view of a Krylov workspace (one carve-up of a caller buffer).
+struct KrylovWs {
+  void* V;           // (M+1) basis vectors: [i][rhs][total], FP64 or FP32
+  uint16_t* Vb;      // BF16 sweep copy of the current basis vector (BF16 plans)
+  void* wy;          // sweep output [rhs][total]: FP64 or FP32
+  double* w1;        // FP64 vector after the first Gram-Schmidt pass
+  double* part1;     // per-chunk partial sums [rhs][chunk][M+2]
+  double* part2;
+  double* H;         // [problem][(M+1) x M], problem = (rhs*ninst + inst)*2 + species
+  double* y;         // [problem][M]: first column of exp(h H_m)
+  double* beta;      // [problem]
+  int32_t* m;        // [problem]: Krylov dimension reached
+  int32_t* done;     // [problem]: no further Arnoldi steps
+};
+
+size_t krylov_ws_bytes(const sgdg_plan* plan, int M, int nrhs);
+KrylovWs krylov_carve(const sgdg_plan* plan, int M, int nrhs, void* base);
+
+// w = exp(h A) v for nrhs plan vectors (v, w FP64, may alias).
+sgdg_status krylov_run(const sgdg_plan* plan, int nrhs, double h, int M, const double* v, double* w,
+                       const KrylovWs& ws, sgdg_stats* stats, hipStream_t s);
+
+}  // namespace sgdg

@@ -1,0 +1,159 @@
+"""GPU parity of sg_dg_apply (y = A x, Sec. 2.1 eq. 2.10) against the oracle's explicit A.
+
+Bound (FP64): the sweep and the oracle's CSR product sum the same terms in a
+different order, so elementwise |y - y_ref| <= c u (|A| |x|) with u = 2^-53;
+the test uses  max|y - y_ref| <= 1e-13 * max(|A| |x|)  (about 450 u, far above
+the ~30-term rounding bound, far below any indexing mistake).  FP32 sweeps:
+2e-5 of the same scale; BF16 inputs (relative rounding 2^-9): 1e-2.
+"""
+import numpy as np
+import pytest
+
+from oracle import operator, sparsegrid
+from paper_1810_11111_amd import inputs as I
+
+from _gpu_common import bf16_bits, lib, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (d, N, k, D, kdiag) -- spans several 256-element chunks with ragged tails
+    (1, 6, 3, [1.0], None),
+    (2, 0, 1, [1.0], None),
+    (2, 5, 1, [1.0], None),
+    (2, 4, 2, [0.01, 1.0], None),
+    (3, 4, 2, [1.0], (1.0, 0.5, 1.0)),
+    (4, 3, 1, [2.0], None),
+    (5, 2, 1, [1.0], None),
+]
+
+
+def _oracle_A(d, N, k, kdiag):
+    kap = None
+    if kdiag is not None:
+        a0, a1, f = kdiag
+        fn = lambda x: a0 + a1 * np.sin(2 * np.pi * f * x)  # noqa: E731
+        kap = [fn] * d
+    return operator.assemble_A(d, N, k, 20.0, kap, 1.0)
+
+
+def _check(y, yref, A, x, tol, what):
+    scale = np.abs(A) @ np.abs(x)
+    err = np.abs(y - yref).max()
+    assert err <= tol * max(scale.max(), 1e-300), f"{what}: err {err:.3e} scale {scale.max():.3e}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"d{c[0]}N{c[1]}k{c[2]}s{len(c[3])}")
+def test_apply_fp64_matches_explicit_operator(case):
+    sg = lib()
+    import torch
+
+    d, N, k, D, kdiag = case
+    inst = I.Instance(d, N, k, D, I.rx_zeros(len(D)), kdiag=kdiag)
+    say("apply fp64", case)
+    plan = sg.Plan([inst], "fp64")
+    nd, off, _ = plan.info(0)
+    assert nd == sparsegrid.dof_count(d, N, k)
+    # canonical order: bit-exact against the oracle's enumeration
+    lev, cell, p = plan.layout(0)
+    olev, ocell, odeg, _ = sparsegrid.enumerate_dofs(d, N, k)
+    assert np.array_equal(lev, olev) and np.array_equal(cell, ocell) and np.array_equal(p, odeg)
+    A1 = _oracle_A(d, N, k, kdiag)
+    nrhs = 3
+    X = I.smooth_random(plan.total, 7 + d * 10 + N, nrhs)
+    xd = to_dev(X)
+    yd = torch.zeros_like(xd)
+    plan.apply(xd, yd, nrhs=nrhs)
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy()
+    for r in range(nrhs):
+        for s, Ds in enumerate(D):
+            seg = slice(off + s * nd, off + (s + 1) * nd)
+            _check(Y[r, seg], Ds * (A1 @ X[r, seg]), Ds * A1, X[r, seg], 1e-13, f"rhs {r} species {s}")
+    # ||A_s||_inf agrees with the explicit matrix
+    for s, Ds in enumerate(D):
+        assert plan.norm_inf(0, s) == pytest.approx(Ds * operator.inf_norm(A1), rel=1e-12)
+    plan.close()
+
+
+def test_apply_smooth_input_cancellation():
+    """Smooth x: A x is small against |A||x| (cancellation); the bound still holds."""
+    sg = lib()
+    import torch
+
+    d, N, k = 2, 6, 1
+    say("apply smooth", d, N, k)
+    plan = sg.Plan([I.Instance(d, N, k, [1.0], I.rx_zeros(1))], "fp64")
+    x = plan.project(0, 1.0, [I.SIN, I.COS])
+    y = torch.zeros(plan.total, dtype=torch.float64, device="cuda")
+    plan.apply(to_dev(x), y)
+    torch.cuda.synchronize()
+    A = _oracle_A(d, N, k, None)
+    _check(y.cpu().numpy(), A @ x, A, x, 1e-13, "smooth")
+    # the Rayleigh quotient approaches the continuous eigenvalue -8 pi^2 of sin*cos
+    rq = x @ y.cpu().numpy() / (x @ x)
+    assert abs(rq / (-8 * np.pi ** 2) - 1) < 0.02
+
+
+def test_apply_multi_instance_uneven_levels():
+    """Batched plan with uneven (N, k) and two species, as the Gray-Scott batch."""
+    sg = lib()
+    import torch
+
+    insts = [I.Instance(2, 3 + (i % 4), 1 + ((i // 4) % 2), [0.5 + i, 0.25], I.rx_zeros(2)) for i in range(8)]
+    say("apply multi-instance", len(insts))
+    plan = sg.Plan(insts, "fp64")
+    X = I.smooth_random(plan.total, 99, 1)[0]
+    yd = torch.zeros(plan.total, dtype=torch.float64, device="cuda")
+    plan.apply(to_dev(X), yd)
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy()
+    for i, inst in enumerate(insts):
+        nd, off, _ = plan.info(i)
+        A1 = _oracle_A(2, inst.N, inst.k, None)
+        for s, Ds in enumerate(inst.D):
+            seg = slice(off + s * nd, off + (s + 1) * nd)
+            _check(Y[seg], Ds * (A1 @ X[seg]), Ds * A1, X[seg], 1e-13, f"inst {i} species {s}")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 1e-2)])
+def test_apply_reduced_precision(prec, tol):
+    sg = lib()
+    import torch
+
+    d, N, k = 3, 4, 1
+    say("apply", prec, d, N, k)
+    plan = sg.Plan([I.Instance(d, N, k, [1.0], I.rx_zeros(1))], prec)
+    X = I.smooth_random(plan.total, 5, 1)[0]
+    A = _oracle_A(d, N, k, None)
+    if prec == "fp32":
+        xd = to_dev(X.astype(np.float32))
+        xin = X.astype(np.float32).astype(np.float64)
+    else:
+        bits, xin = bf16_bits(X)
+        xd = to_dev(bits.view(np.int16))
+    yd = torch.zeros(plan.total, dtype=torch.float32, device="cuda")
+    plan.apply(xd, yd)
+    torch.cuda.synchronize()
+    _check(yd.cpu().numpy().astype(np.float64), A @ xin, A, xin, tol, prec)
+
+
+@pytest.mark.parametrize("name", ["heat_linear_d2", "schnakenberg_d2", "allen_cahn_d3", "quadratic_d4"])
+def test_apply_full_size_workloads(name):
+    """Workload-size operators (the configurations the benchmark runs)."""
+    sg = lib()
+    import torch
+
+    wl = getattr(I, name)()
+    inst = wl.instances[0]
+    say("apply full size", name)
+    plan = sg.Plan([inst], "fp64")
+    X = I.smooth_random(plan.total, 11, 1)[0]
+    yd = torch.zeros(plan.total, dtype=torch.float64, device="cuda")
+    plan.apply(to_dev(X), yd)
+    torch.cuda.synchronize()
+    A1 = _oracle_A(inst.d, inst.N, inst.k, inst.kdiag)
+    nd = plan.info(0)[0]
+    for s, Ds in enumerate(inst.D):
+        seg = slice(s * nd, (s + 1) * nd)
+        _check(yd.cpu().numpy()[seg], Ds * (A1 @ X[seg]), Ds * A1, X[seg], 1e-13, f"{name} species {s}")
