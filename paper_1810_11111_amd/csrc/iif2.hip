@@ -1,0 +1,209 @@
+// IIF2 time step (Sec. 3, eq. 3.5) with the implicit reaction stage.
+//
+//   v = U^n + dt/2 F(U^n);  W = exp(A dt) v  (one Krylov problem per species);
+//   solve  U - dt/2 F(U) = W  by the pointwise quasi-Newton iteration
+//     U <- U - P[(I_s - dt/2 J_f(u_q))^{-1} (R G)_q],  G = U - dt/2 F(U) - W,
+//   from U = W + dt/2 F(U^n), until ||G||_2 <= tol max(1, ||W||_2) per instance.
+//
+// The paper solves the stage with Newton's method (Sec. 4, Example 3; Sec. 5:
+// the sparse basis couples every unknown); the pointwise iteration has the
+// same root.  Control stays on the device: a check kernel sets a per-instance
+// convergence flag that every later kernel of the step reads, so a step is a
+// fixed launch sequence (newton_max + 1 residual passes) that can be captured
+// in a graph; converged instances skip their work.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+#include "kernels.h"
+#include "krylov.h"
+#include "reaction.h"
+
+namespace sgdg {
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct IifWs {
+  KrylovWs kws;
+  double* rws;
+  double *v, *W, *G, *F;
+  double *part, *partw, *wnorm;
+  int32_t* conv;
+};
+
+size_t iif2_ws_bytes(const sgdg_plan* plan, int M, int nrhs) {
+  const size_t tot = (size_t)plan->total * nrhs;
+  size_t b = al256(krylov_ws_bytes(plan, M, nrhs));
+  b += al256((size_t)reaction_ws_doubles(plan) * nrhs * 8);
+  b += 4 * al256(tot * 8);
+  b += 2 * al256((size_t)nrhs * plan->nchunks * 8);
+  b += al256((size_t)nrhs * plan->ninst * 8);
+  b += al256((size_t)nrhs * plan->ninst * 4);
+  return b;
+}
+
+static IifWs carve(const sgdg_plan* plan, int M, int nrhs, void* base) {
+  const size_t tot = (size_t)plan->total * nrhs;
+  char* p = (char*)base;
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += al256(bytes);
+    return (void*)r;
+  };
+  IifWs w{};
+  void* kb = take(krylov_ws_bytes(plan, M, nrhs));
+  w.kws = krylov_carve(plan, M, nrhs, kb);
+  w.rws = (double*)take((size_t)reaction_ws_doubles(plan) * nrhs * 8);
+  w.v = (double*)take(tot * 8);
+  w.W = (double*)take(tot * 8);
+  w.G = (double*)take(tot * 8);
+  w.F = (double*)take(tot * 8);
+  w.part = (double*)take((size_t)nrhs * plan->nchunks * 8);
+  w.partw = (double*)take((size_t)nrhs * plan->nchunks * 8);
+  w.wnorm = (double*)take((size_t)nrhs * plan->ninst * 8);
+  w.conv = (int32_t*)take((size_t)nrhs * plan->ninst * 4);
+  return w;
+}
+
+// out = x + a y
+__global__ __launch_bounds__(256) void k_axpy(double* __restrict__ out, const double* __restrict__ x, double a,
+                                              const double* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = x[i] + a * y[i];
+}
+
+// U = W + dt2 F, per-chunk ||W||^2, reset of the convergence flags
+__global__ __launch_bounds__(CHUNK) void k_stage_init(DevTables T, int ninst, int nchunks, int64_t total, double dt2,
+                                                      double* __restrict__ U, const double* __restrict__ W,
+                                                      const double* __restrict__ F, double* __restrict__ partw,
+                                                      int32_t* __restrict__ conv) {
+  const int c = blockIdx.x, rhs = blockIdx.y, tid = threadIdx.x;
+  const Chunk ch = T.chunks[c];
+  double w2 = 0.0;
+  if (tid < ch.count) {
+    const int64_t gi = (int64_t)rhs * total + ch.start + tid;
+    const double w = W[gi];
+    U[gi] = w + dt2 * F[gi];
+    w2 = w * w;
+  }
+  for (int off = 32; off > 0; off >>= 1) w2 += __shfl_xor(w2, off, 64);
+  __shared__ double red[CHUNK / 64];
+  if ((tid & 63) == 0) red[tid >> 6] = w2;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < CHUNK / 64; ++w) t += red[w];
+    partw[(int64_t)rhs * nchunks + c] = t;
+    if (c == T.pchunk0[ch.inst * 2] ) conv[rhs * ninst + ch.inst] = 0;
+  }
+}
+
+// one workgroup per (rhs, instance): ||G||, convergence decision, statistics
+__global__ __launch_bounds__(64) void k_check(DevTables T, int ninst, int nchunks, int it, int newton_max, double tol,
+                                              const double* __restrict__ part, const double* __restrict__ partw,
+                                              double* __restrict__ wnorm, int32_t* __restrict__ conv,
+                                              sgdg_stats* __restrict__ stats) {
+  const int inst = blockIdx.x, rhs = blockIdx.y;
+  if (threadIdx.x != 0) return;
+  const int ci = rhs * ninst + inst;
+  if (conv[ci]) return;
+  const int S = T.inst[inst].S;
+  const int c0 = T.pchunk0[inst * 2];
+  int nc = T.pnchunk[inst * 2];
+  if (S > 1) nc += T.pnchunk[inst * 2 + 1];
+  if (it == 0) {
+    double t = 0.0;
+    for (int q = 0; q < nc; ++q) t += partw[(int64_t)rhs * nchunks + c0 + q];
+    wnorm[ci] = sqrt(t);
+  }
+  double t = 0.0;
+  for (int q = 0; q < nc; ++q) t += part[(int64_t)rhs * nchunks + c0 + q];
+  const double res = sqrt(t);
+  const bool fin = isfinite(res);
+  const bool ok = fin && res <= tol * fmax(1.0, wnorm[ci]);
+  const bool last = it >= newton_max;
+  if (ok || !fin || last) conv[ci] = 1;
+  if (stats)
+    for (int s = 0; s < S; ++s) {
+      sgdg_stats& st = stats[ci * 2 + s];
+      st.newton_iters = it;
+      st.residual = res;
+      if (!fin)
+        st.status = SGDG_ERR_NONFINITE;
+      else if (!ok && last && st.status == SGDG_OK)
+        st.status = SGDG_ERR_NOCONV;
+    }
+}
+
+static sgdg_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, what);
+  return SGDG_OK;
+}
+
+}  // namespace sgdg
+
+using namespace sgdg;
+
+extern "C" sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const double* U, double* F, void* workspace,
+                                     size_t workspace_bytes, void* stream) {
+  if (!plan) return fail(SGDG_ERR_ARG, "sgdg_reaction: null plan");
+  if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "sgdg_reaction: nrhs must be in 1..65535");
+  if (!U || !F || !workspace) return fail(SGDG_ERR_ARG, "sgdg_reaction: null device pointer");
+  if ((const void*)U == (const void*)F) return fail(SGDG_ERR_ARG, "sgdg_reaction: U and F must not alias");
+  if (workspace_bytes < iif2_ws_bytes(plan, 1, nrhs)) return fail(SGDG_ERR_ARG, "sgdg_reaction: workspace too small");
+  IifWs w = carve(plan, 1, nrhs, workspace);
+  RxArgs a{};
+  a.U = const_cast<double*>(U);
+  a.F = F;
+  a.rws = w.rws;
+  reaction_pass(plan, nrhs, RX_F, a, (hipStream_t)stream);
+  return check_launch("sgdg_reaction launch");
+}
+
+extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcache,
+                                 double newton_tol, int32_t newton_max, void* workspace, size_t workspace_bytes,
+                                 sgdg_stats* stats, void* stream) {
+  if (!plan) return fail(SGDG_ERR_ARG, "iif2_step: null plan");
+  if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "iif2_step: nrhs must be in 1..65535");
+  if (M < 1 || M > SGDG_MAX_M) return fail(SGDG_ERR_ARG, "iif2_step: M must be in 1..48");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SGDG_ERR_ARG, "iif2_step: dt must be positive");
+  if (!(newton_tol >= 0.0)) return fail(SGDG_ERR_ARG, "iif2_step: newton_tol must be >= 0");
+  if (newton_max < 0 || newton_max > 1000) return fail(SGDG_ERR_ARG, "iif2_step: newton_max must be in 0..1000");
+  if (!U || !workspace) return fail(SGDG_ERR_ARG, "iif2_step: null device pointer");
+  if (workspace_bytes < iif2_ws_bytes(plan, M, nrhs)) return fail(SGDG_ERR_ARG, "iif2_step: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  IifWs w = carve(plan, M, nrhs, workspace);
+  const double dt2 = 0.5 * dt;
+  const int64_t n = plan->total * (int64_t)nrhs;
+  double* F = Fcache ? Fcache : w.F;
+  RxArgs a{};
+  a.rws = w.rws;
+  a.dt2 = dt2;
+  if (!Fcache) {
+    a.U = U;
+    a.F = F;
+    reaction_pass(plan, nrhs, RX_F, a, s);
+  }
+  hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.v, U, dt2, F, n);
+  sgdg_status st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s);
+  if (st != SGDG_OK) return st;
+  const dim3 cgrid((unsigned)plan->nchunks, (unsigned)nrhs);
+  hipLaunchKernelGGL(k_stage_init, cgrid, dim3(CHUNK), 0, s, plan->dev, plan->ninst, plan->nchunks, plan->total, dt2, U,
+                     w.W, F, w.partw, w.conv);
+  a.U = U;
+  a.W = w.W;
+  a.F = F;
+  a.Gout = w.G;
+  a.G = w.G;
+  a.part = w.part;
+  a.conv = w.conv;
+  for (int it = 0; it <= newton_max; ++it) {
+    reaction_pass(plan, nrhs, RX_RESID, a, s);
+    hipLaunchKernelGGL(k_check, dim3((unsigned)plan->ninst, (unsigned)nrhs), dim3(64), 0, s, plan->dev, plan->ninst,
+                       plan->nchunks, it, newton_max, newton_tol, w.part, w.partw, w.wnorm, w.conv, stats);
+    if (it < newton_max) reaction_pass(plan, nrhs, RX_CORR, a, s);
+  }
+  return check_launch("iif2_step launch");
+}

@@ -1,0 +1,75 @@
+// Reaction transforms: plan-level tables and launchers (reaction.hip), used by iif2.hip.
+#pragma once
+
+#include "internal.h"
+
+namespace sgdg {
+
+// One level block of an r-dimensional sparse grid of level N (r = 1..d),
+// canonical order, extents c(l)(k+1).
+struct RBlk {
+  int64_t start;
+  int32_t size;
+  int32_t lsum;
+  int32_t lev[SGDG_MAX_D];
+};
+
+// Per-instance constants of the reaction transforms.
+struct RInst {
+  int32_t N, K1, S, nq, np1, n1, d, pad;
+  int64_t seg;    // offset of the instance in a plan vector
+  int64_t ndof;
+  int64_t E_off;  // into E: [(l * np1 + q) * K1 + p], value of level-l function at 1D point q
+  int64_t w_off;  // into w1: Gauss weight times h_N of 1D point q
+  int32_t blk_off[SGDG_MAX_D + 1];  // into rblk, r-dim grid
+  int32_t nblk[SGDG_MAX_D + 1];
+  int32_t id_off[SGDG_MAX_D + 1];   // into rid: (N+1)^r entries, -1 if |l|_1 > N
+  int32_t pad2;
+  int64_t gdof[SGDG_MAX_D + 1];     // DOFs of the r-dim grid
+  int64_t npre[SGDG_MAX_D + 1];     // np1^m
+  int64_t X_off[SGDG_MAX_D];        // per-rhs workspace offsets (doubles) of expansion outputs, m = 1..d-1
+  int64_t Y_off[SGDG_MAX_D];        // of contraction outputs, m = 0..d-1 (Y_0 only for d = 1)
+  double rx[2][4][4];
+};
+
+struct RTables {
+  RInst* inst = nullptr;
+  RBlk* rblk = nullptr;
+  int32_t* rid = nullptr;
+  double* E = nullptr;
+  double* w1 = nullptr;
+  int64_t* cum_x[SGDG_MAX_D] = {};  // per expansion stage m: cumulative output counts over instances (ninst+1)
+  int64_t* cum_y[SGDG_MAX_D] = {};  // per contraction stage m (>= 1)
+  int64_t* cum_line = nullptr;
+};
+
+struct RHost {
+  RTables dev;
+  std::vector<std::vector<int64_t>> cum_x, cum_y;
+  std::vector<int64_t> cum_line;
+  int64_t rws = 0;  // doubles of reaction workspace per right-hand side
+  int max_n1 = 0, max_np1 = 0;
+};
+
+enum RxMode { RX_F = 0, RX_RESID = 1, RX_CORR = 2 };
+
+// One reaction pass over nrhs right-hand sides.
+//   RX_F    : F = P f(R U)
+//   RX_RESID: F = P f(R U), G = U - dt2 F - W, per-chunk |G|^2 into part
+//   RX_CORR : U <- U - P[(I - dt2 J_f(R U))^{-1} R G]
+// Instances with conv[rhs * ninst + inst] != 0 are skipped (conv may be null).
+struct RxArgs {
+  double* U;
+  const double* G;
+  double* F;
+  double* Gout;
+  const double* W;
+  double* part;  // [rhs][chunk]
+  const int32_t* conv;
+  double dt2;
+  double* rws;  // reaction workspace base
+};
+void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s);
+int64_t reaction_ws_doubles(const sgdg_plan* plan);
+
+}  // namespace sgdg
