@@ -278,6 +278,7 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
       bc.val_off = op_val_off[o];
       bc.ncell = 1 << N;
       bc.k = hi.desc.k;
+      bc.nnzb = (int32_t)p->ops[o].src.size();
       bcsr.push_back(bc);
     }
     id.gblk_off = (int32_t)p->gblk.size();
@@ -318,8 +319,28 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
   }
   p->nchunks = (int32_t)p->chunks.size();
   p->nblocks = (int32_t)p->gblk.size();
-  p->chunks_by_k.assign(SGDG_MAX_K + 1, {});
-  for (int32_t c = 0; c < p->nchunks; ++c) p->chunks_by_k[p->inst[p->chunks[c].inst].desc.k].push_back(c);
+  // sweep kinds: k and whether the species segment plus its level-block table
+  // fit the LDS budget of the staged sweep
+  const int xbytes = prec == SGDG_FP64 ? 8 : (prec == SGDG_FP32_SWEEP ? 4 : 2);
+  p->chunk_lists.assign(2 * (SGDG_MAX_K + 1), {});
+  p->list_lds.assign(2 * (SGDG_MAX_K + 1), 0);
+  for (int32_t c = 0; c < p->nchunks; ++c) {
+    const HostInstance& hi = p->inst[p->chunks[c].inst];
+    int64_t ntab = 1;
+    for (int m = 0; m < d; ++m) ntab *= (hi.desc.n + 1);
+    // block table, row pointers and source cells of each distinct 1D operator, x segment
+    int64_t rows = 0;
+    for (int m = 0; m < d; ++m) {
+      bool seen = false;
+      for (int m2 = 0; m2 < m; ++m2) seen = seen || hi.dir_tab[m2] == hi.dir_tab[m];
+      if (!seen) rows += (int64_t)p->ops[hi.dir_tab[m]].cptr.size() + (int64_t)p->ops[hi.dir_tab[m]].src.size();
+    }
+    const int64_t lds = (((ntab + rows) * 4 + 15) & ~(int64_t)15) + hi.ndof * xbytes;
+    const int staged = lds <= APPLY_LDS_BYTES_HOST ? 1 : 0;
+    const int kind = hi.desc.k * 2 + staged;
+    p->chunk_lists[kind].push_back(c);
+    if (staged) p->list_lds[kind] = std::max(p->list_lds[kind], (int)lds);
+  }
 
   sgdg_status st = SGDG_OK;
   std::vector<float> valf(val_all.begin(), val_all.end());
@@ -344,10 +365,10 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
   }
   p->pchunk0 = pc0;
   p->pnchunk = pnc;
-  p->dev_chunk_lists.assign(SGDG_MAX_K + 1, nullptr);
-  for (int k = 1; k <= SGDG_MAX_K; ++k) {
-    if (p->chunks_by_k[k].empty()) continue;
-    if ((st = upload(p, p->chunks_by_k[k], &p->dev_chunk_lists[k])) != SGDG_OK) {
+  p->dev_chunk_lists.assign(p->chunk_lists.size(), nullptr);
+  for (size_t kind = 0; kind < p->chunk_lists.size(); ++kind) {
+    if (p->chunk_lists[kind].empty()) continue;
+    if ((st = upload(p, p->chunk_lists[kind], &p->dev_chunk_lists[kind])) != SGDG_OK) {
       sg_dg_destroy(p);
       return st;
     }

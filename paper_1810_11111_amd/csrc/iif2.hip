@@ -37,7 +37,8 @@ size_t iif2_ws_bytes(const sgdg_plan* plan, int M, int nrhs) {
   size_t b = al256(krylov_ws_bytes(plan, M, nrhs));
   b += al256((size_t)reaction_ws_doubles(plan) * nrhs * 8);
   b += 4 * al256(tot * 8);
-  b += 2 * al256((size_t)nrhs * plan->nchunks * 8);
+  b += al256((size_t)nrhs * reaction_final_fibres(plan) * 8);
+  b += al256((size_t)nrhs * plan->nchunks * 8);
   b += al256((size_t)nrhs * plan->ninst * 8);
   b += al256((size_t)nrhs * plan->ninst * 4);
   return b;
@@ -59,7 +60,7 @@ static IifWs carve(const sgdg_plan* plan, int M, int nrhs, void* base) {
   w.W = (double*)take(tot * 8);
   w.G = (double*)take(tot * 8);
   w.F = (double*)take(tot * 8);
-  w.part = (double*)take((size_t)nrhs * plan->nchunks * 8);
+  w.part = (double*)take((size_t)nrhs * reaction_final_fibres(plan) * 8);
   w.partw = (double*)take((size_t)nrhs * plan->nchunks * 8);
   w.wnorm = (double*)take((size_t)nrhs * plan->ninst * 8);
   w.conv = (int32_t*)take((size_t)nrhs * plan->ninst * 4);
@@ -100,12 +101,21 @@ __global__ __launch_bounds__(CHUNK) void k_stage_init(DevTables T, int ninst, in
 }
 
 // one workgroup per (rhs, instance): ||G||, convergence decision, statistics
-__global__ __launch_bounds__(64) void k_check(DevTables T, int ninst, int nchunks, int it, int newton_max, double tol,
+// fixed-order sum of a[i0 .. i0+n) by one 64-lane wave (lane-strided, then butterfly)
+__device__ __forceinline__ double wave_fixed_sum(const double* __restrict__ a, int64_t i0, int64_t n) {
+  double t = 0.0;
+  for (int64_t q = threadIdx.x; q < n; q += 64) t += a[i0 + q];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  return t;
+}
+
+__global__ __launch_bounds__(64) void k_check(DevTables T, const int64_t* __restrict__ cum_fin, int ninst,
+                                              int nchunks, int64_t nfin, int it, int newton_max, double tol,
                                               const double* __restrict__ part, const double* __restrict__ partw,
                                               double* __restrict__ wnorm, int32_t* __restrict__ conv,
                                               sgdg_stats* __restrict__ stats) {
   const int inst = blockIdx.x, rhs = blockIdx.y;
-  if (threadIdx.x != 0) return;
   const int ci = rhs * ninst + inst;
   if (conv[ci]) return;
   const int S = T.inst[inst].S;
@@ -113,12 +123,11 @@ __global__ __launch_bounds__(64) void k_check(DevTables T, int ninst, int nchunk
   int nc = T.pnchunk[inst * 2];
   if (S > 1) nc += T.pnchunk[inst * 2 + 1];
   if (it == 0) {
-    double t = 0.0;
-    for (int q = 0; q < nc; ++q) t += partw[(int64_t)rhs * nchunks + c0 + q];
-    wnorm[ci] = sqrt(t);
+    const double t = wave_fixed_sum(partw, (int64_t)rhs * nchunks + c0, nc);
+    if (threadIdx.x == 0) wnorm[ci] = sqrt(t);
   }
-  double t = 0.0;
-  for (int q = 0; q < nc; ++q) t += part[(int64_t)rhs * nchunks + c0 + q];
+  const double t = wave_fixed_sum(part, (int64_t)rhs * nfin + cum_fin[inst], cum_fin[inst + 1] - cum_fin[inst]);
+  if (threadIdx.x != 0) return;
   const double res = sqrt(t);
   const bool fin = isfinite(res);
   const bool ok = fin && res <= tol * fmax(1.0, wnorm[ci]);
@@ -152,6 +161,7 @@ extern "C" sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const 
   if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "sgdg_reaction: nrhs must be in 1..65535");
   if (!U || !F || !workspace) return fail(SGDG_ERR_ARG, "sgdg_reaction: null device pointer");
   if ((const void*)U == (const void*)F) return fail(SGDG_ERR_ARG, "sgdg_reaction: U and F must not alias");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "sgdg_reaction: (k+1) 2^N above 2048 per axis");
   if (workspace_bytes < iif2_ws_bytes(plan, 1, nrhs)) return fail(SGDG_ERR_ARG, "sgdg_reaction: workspace too small");
   IifWs w = carve(plan, 1, nrhs, workspace);
   RxArgs a{};
@@ -172,6 +182,7 @@ extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   if (!(newton_tol >= 0.0)) return fail(SGDG_ERR_ARG, "iif2_step: newton_tol must be >= 0");
   if (newton_max < 0 || newton_max > 1000) return fail(SGDG_ERR_ARG, "iif2_step: newton_max must be in 0..1000");
   if (!U || !workspace) return fail(SGDG_ERR_ARG, "iif2_step: null device pointer");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "iif2_step: (k+1) 2^N above 2048 per axis");
   if (workspace_bytes < iif2_ws_bytes(plan, M, nrhs)) return fail(SGDG_ERR_ARG, "iif2_step: workspace too small");
   hipStream_t s = (hipStream_t)stream;
   IifWs w = carve(plan, M, nrhs, workspace);
@@ -199,10 +210,12 @@ extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   a.G = w.G;
   a.part = w.part;
   a.conv = w.conv;
+  const int64_t nfin = reaction_final_fibres(plan);
   for (int it = 0; it <= newton_max; ++it) {
     reaction_pass(plan, nrhs, RX_RESID, a, s);
-    hipLaunchKernelGGL(k_check, dim3((unsigned)plan->ninst, (unsigned)nrhs), dim3(64), 0, s, plan->dev, plan->ninst,
-                       plan->nchunks, it, newton_max, newton_tol, w.part, w.partw, w.wnorm, w.conv, stats);
+    hipLaunchKernelGGL(k_check, dim3((unsigned)plan->ninst, (unsigned)nrhs), dim3(64), 0, s, plan->dev,
+                       ((const RHost*)plan->rdata)->dev.cum_fin, plan->ninst, plan->nchunks, nfin, it, newton_max,
+                       newton_tol, w.part, w.partw, w.wnorm, w.conv, stats);
     if (it < newton_max) reaction_pass(plan, nrhs, RX_CORR, a, s);
   }
   return check_launch("iif2_step launch");

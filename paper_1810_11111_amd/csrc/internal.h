@@ -62,6 +62,8 @@ struct BCsr {
   int64_t val_off;   // into val / valf (scalar index of block 0)
   int32_t ncell;
   int32_t k;
+  int32_t nnzb;      // number of cell blocks (length of src)
+  int32_t pad;
 };
 
 struct DevTables {
@@ -110,8 +112,11 @@ struct sgdg_plan {
   std::vector<sgdg::Op1D> ops;
   std::vector<sgdg::GBlock> gblk;
   std::vector<sgdg::Chunk> chunks;
-  std::vector<std::vector<int32_t>> chunks_by_k;  // chunk ids grouped by k (index k)
-  std::vector<int32_t*> dev_chunk_lists;          // device copies of chunks_by_k
+  // chunk ids grouped by sweep kind: index k*2 + staged (staged: the species
+  // segment and its block table fit the LDS budget of the staged sweep)
+  std::vector<std::vector<int32_t>> chunk_lists;
+  std::vector<int32_t*> dev_chunk_lists;
+  std::vector<int> list_lds;  // dynamic LDS bytes of the staged lists
   std::vector<sgdg::InstDev> instdev;
   std::vector<int32_t> pchunk0, pnchunk;  // host copies of the per-species chunk ranges
   sgdg::DevTables dev;
@@ -123,6 +128,7 @@ struct sgdg_plan {
 namespace sgdg {
 
 constexpr int CHUNK = 256;
+constexpr int APPLY_LDS_BYTES_HOST = 128 * 1024;  // same budget as the staged sweep kernel
 
 // error reporting
 sgdg_status fail(sgdg_status st, const std::string& msg);
@@ -143,6 +149,6 @@ double hier_value(const Basis1D& b, int level, int j, int p, double x, bool deri
 Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd);
 
 // enumeration helpers
-inline int level_count(int l) { return l == 0 ? 1 : (1 << (l - 1)); }
+__host__ __device__ inline int level_count(int l) { return l == 0 ? 1 : (1 << (l - 1)); }
 
 }  // namespace sgdg

@@ -56,18 +56,50 @@ __device__ __forceinline__ int find_block(const DevTables& T, const Chunk& ch, i
   return lo;
 }
 
-// y_g = (A x)_g for one output element g of a plan vector (x points at the
-// start of the plan vector).  Returns the accumulated value (already scaled by
-// -D_s).
-template <int D, int K, class P>
-__device__ __forceinline__ typename P::A apply_one(const DevTables& T, const Chunk& ch, int64_t g,
-                                                   const typename P::X* __restrict__ x) {
+// Source of the gathered x values: global memory with the plan's block
+// tables, or the problem's segment staged in LDS with its block-start table.
+template <class P>
+struct SrcGlobal {
+  const typename P::X* __restrict__ x;  // start of the plan vector
+  const int32_t* __restrict__ blkid;    // instance's (N+1)^d table into lstart
+  const int64_t* __restrict__ lstart;
+  int64_t seg;                          // start of the species segment
+  __device__ __forceinline__ int64_t block_base(int lin) const { return seg + lstart[blkid[lin]]; }
+  __device__ __forceinline__ typename P::A load(int64_t i) const { return P::load(x + i); }
+};
+template <class P>
+struct SrcLds {
+  const typename P::X* x;  // LDS copy of the species segment
+  const int32_t* bst;      // LDS: block start inside the segment per level tuple
+  __device__ __forceinline__ int64_t block_base(int lin) const { return bst[lin]; }
+  __device__ __forceinline__ typename P::A load(int64_t i) const { return P::load(x + i); }
+};
+
+// Row structure of the 1D operators: from global memory, or staged in LDS
+// (cptr / src of every direction copied to one LDS array).
+struct RowsGlobal {
+  const int32_t* cptr;
+  const int32_t* src;
+  __device__ __forceinline__ int rp(const BCsr& bc, int i, int t) const { return cptr[bc.cptr_off + t]; }
+  __device__ __forceinline__ int sc(const BCsr& bc, int i, int e) const { return src[bc.src_off + e]; }
+};
+struct RowsLds {
+  const int32_t* cptr[SGDG_MAX_D];  // LDS, per direction
+  const int32_t* src[SGDG_MAX_D];
+  __device__ __forceinline__ int rp(const BCsr& bc, int i, int t) const { return cptr[i][t]; }
+  __device__ __forceinline__ int sc(const BCsr& bc, int i, int e) const { return src[i][e]; }
+};
+
+// y_g = (A x)_g for one output element g of a plan vector.  Returns the
+// accumulated value (already scaled by -D_s).  Rows of B_i are walked in
+// ascending source cell order, so the block base of a source level is looked
+// up once per level, not per entry.
+template <int D, int K, class P, class Src, class Rows>
+__device__ __forceinline__ typename P::A apply_one(const DevTables& T, const GBlock& B, const InstDev& I, int64_t g,
+                                                   const Src& xs, const Rows& rows) {
   using A = typename P::A;
   using V = typename P::V;
   constexpr int K1 = K + 1;
-  const int bi = find_block(T, ch, g);
-  const GBlock& B = T.gblk[bi];
-  const InstDev& I = T.inst[B.inst];
   int ext[D], sh[D], t[D], lev[D];
   int L = (int)(g - B.start);
   {
@@ -93,7 +125,6 @@ __device__ __forceinline__ typename P::A apply_one(const DevTables& T, const Chu
   int linall = 0;
   for (int m = 0; m < D; ++m) linall += lev[m] * I.pow[m];
 
-  const int64_t seg = I.offset + (int64_t)B.species * I.ndof;
   const V* __restrict__ vals = P::vals(T);
   A acc = 0;
 #pragma unroll
@@ -109,25 +140,33 @@ __device__ __forceinline__ typename P::A apply_one(const DevTables& T, const Chu
     const int Blo = suf[i + 1];
     const int lin = linall - li * I.pow[i];
     const BCsr bc = T.bcsr[I.bcsr_off[i]];
-    const int e0 = T.cptr[bc.cptr_off + tcell];
-    const int e1 = T.cptr[bc.cptr_off + tcell + 1];
-    const int32_t* __restrict__ src = T.src + bc.src_off;
+    const int e0 = rows.rp(bc, i, tcell);
+    const int e1 = rows.rp(bc, i, tcell + 1);
     const V* __restrict__ vrow = vals + bc.val_off + pt * K1;
+    int cur_lc = -1;
+    int64_t bbase = 0;
+    int extc = K1;
     for (int e = e0; e < e1; ++e) {
-      const int sc = src[e];
+      const int sc = rows.sc(bc, i, e);
       if (sc >= lim) break;
       const int lc = sc == 0 ? 0 : 32 - __clz(sc);
+      if (lc != cur_lc) {
+        cur_lc = lc;
+        bbase = xs.block_base(lin + lc * I.pow[i]);
+        extc = lc == 0 ? K1 : (K1 << (lc - 1));
+      }
       const int jc = sc == 0 ? 0 : sc - (1 << (lc - 1));
-      const int extc = lc == 0 ? K1 : (K1 << (lc - 1));
-      const int sb = T.blkid[I.blkid_off + lin + lc * I.pow[i]];
-      const int64_t base = seg + T.lstart[sb] + (int64_t)(Ahi * extc + jc * K1) * S + Blo;
+      const int64_t base = bbase + (int64_t)(Ahi * extc + jc * K1) * S + Blo;
       const V* __restrict__ v = vrow + (int64_t)e * K1 * K1;
 #pragma unroll
-      for (int pc = 0; pc < K1; ++pc) acc += (A)v[pc] * P::load(x + base + (int64_t)pc * S);
+      for (int pc = 0; pc < K1; ++pc) acc += (A)v[pc] * xs.load(base + (int64_t)pc * S);
     }
   }
   return acc * (A)(-I.D[B.species]);
 }
+
+// LDS budget of the staged sweep (bytes for the x segment and the block table).
+constexpr int APPLY_LDS_BYTES = APPLY_LDS_BYTES_HOST;
 
 template <class P>
 void launch_apply(const sgdg_plan* plan, int nrhs, const void* x, void* y, int64_t xs, int64_t ys, hipStream_t s);

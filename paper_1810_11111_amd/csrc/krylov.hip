@@ -10,9 +10,10 @@
 // classical Gram-Schmidt applied twice (rounding-level equivalent of the
 // modified form), which needs three device-wide reductions per step instead
 // of j+1; each reduction is a kernel boundary (cheap inside a captured graph):
-//   k_apply_dots : w = A v_j (matrix-free sweep) and per-chunk <v_i, w>
-//   k_upd1       : h1 = sum of partials, w1 = w - V h1, per-chunk <v_i, w1>, |w1|^2
-//   k_upd2       : h2, w2 = w1 - V h2, |w2|^2 = |w1|^2 - |h2|^2, v_{j+1} = w2 / |w2|
+//   sweep   : w = A v_j (the same kernel as sg_dg_apply)
+//   k_dots1 : per-chunk <v_i, w>
+//   k_upd1  : h1 = sum of partials, w1 = w - V h1, per-chunk <v_i, w1>, |w1|^2
+//   k_upd2  : h2, w2 = w1 - V h2, |w2|^2 = |w1|^2 - |h2|^2, v_{j+1} = w2 / |w2|
 // Partial sums are reduced in a fixed order, so every workgroup of a problem
 // computes bit-identical Hessenberg entries and breakdown decisions.
 // Dot products, norms, H, exp(h H) and the final combination are FP64 in
@@ -100,33 +101,70 @@ __global__ __launch_bounds__(CHUNK) void k_norm(DevTables T, int nchunks, int ni
   (void)nrhs;
 }
 
-// w = A v_j and per-chunk partials <v_i, w>, i <= j.
-template <int D, int K, class P, class TV>
-__global__ __launch_bounds__(CHUNK) void k_apply_dots(DevTables T, const int32_t* __restrict__ list, int nchunks,
-                                                      int ninst, int64_t total, int M, int j,
-                                                      const typename P::X* __restrict__ xin, KrylovWs ws) {
-  const int c = list[blockIdx.x], rhs = blockIdx.y, tid = threadIdx.x, nrhs = gridDim.y;
-  const Chunk ch = T.chunks[c];
-  if (ws.done[prob_of(rhs, ninst, ch)]) return;
-  const int64_t g = ch.start + tid;
-  double w = 0.0;
-  if (tid < ch.count) {
-    const typename P::A acc = apply_one<D, K, P>(T, ch, g, xin + rhs * total);
-    ((typename P::Y*)ws.wy)[rhs * total + g] = (typename P::Y)acc;
-    w = (double)(typename P::Y)acc;
-  }
-  __shared__ double red[NW][SGDG_MAX_M + 2];
-  for (int i = 0; i <= j; ++i) {
-    double pr = tid < ch.count ? (double)vec<TV>(ws, i, nrhs, rhs, total)[g] * w : 0.0;
-    pr = wave_sum(pr);
-    if ((tid & 63) == 0) red[tid >> 6][i] = pr;
+// Deterministic chunk-level multi-dot: out[i] = sum over the chunk of
+// V_i[e] * wl[e] for i < J, plus out[J] = sum wl[e]^2 when with_norm.
+// Thread (i, s) of a J x S arrangement sums the elements e = s, s+S, ... so
+// the loads of one column are coalesced across slices.
+template <class TV>
+__device__ __forceinline__ void chunk_dots(const KrylovWs& ws, int J, bool with_norm, int nrhs, int rhs,
+                                           int64_t total, int64_t g0, int count, const double* wl, double* red,
+                                           double* out) {
+  const int tid = threadIdx.x;
+  const int cols = J + (with_norm ? 1 : 0);
+  const int S = CHUNK / cols;
+  if (tid < cols * S) {
+    const int i = tid / S, s = tid - i * S;
+    double acc = 0.0;
+    if (i < J) {
+      const TV* v = vec<TV>(ws, i, nrhs, rhs, total) + g0;
+      for (int e = s; e < count; e += S) acc += (double)v[e] * wl[e];
+    } else {
+      for (int e = s; e < count; e += S) acc += wl[e] * wl[e];
+    }
+    red[tid] = acc;
   }
   __syncthreads();
-  if (tid <= j) {
+  if (tid < cols) {
     double t = 0.0;
-    for (int q = 0; q < NW; ++q) t += red[q][tid];
-    ws.part1[((int64_t)rhs * nchunks + c) * (M + 2) + tid] = t;
+    for (int q = 0; q < S; ++q) t += red[tid * S + q];
+    out[tid] = t;
   }
+  __syncthreads();
+}
+
+// Deterministic reduction of per-chunk partials of one problem: h[i] = sum
+// over its nc chunks of part[c0 + q][i], i < cols.
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int64_t row0, int nc, int ld, int cols,
+                                                double* red, double* h) {
+  const int tid = threadIdx.x;
+  const int S = CHUNK / cols;
+  if (tid < cols * S) {
+    const int i = tid / S, s = tid - i * S;
+    double acc = 0.0;
+    for (int q = s; q < nc; q += S) acc += part[(row0 + q) * ld + i];
+    red[tid] = acc;
+  }
+  __syncthreads();
+  if (tid < cols) {
+    double t = 0.0;
+    for (int q = 0; q < S; ++q) t += red[tid * S + q];
+    h[tid] = t;
+  }
+  __syncthreads();
+}
+
+// per-chunk partials <v_i, w>, i <= j, of the sweep output w = A v_j
+template <class TV, class TY>
+__global__ __launch_bounds__(CHUNK) void k_dots1(DevTables T, int nchunks, int ninst, int64_t total, int M, int j,
+                                                 KrylovWs ws) {
+  const int c = blockIdx.x, rhs = blockIdx.y, tid = threadIdx.x, nrhs = gridDim.y;
+  const Chunk ch = T.chunks[c];
+  if (ws.done[prob_of(rhs, ninst, ch)]) return;
+  __shared__ double wl[CHUNK], red[CHUNK], out[SGDG_MAX_M + 2];
+  wl[tid] = tid < ch.count ? (double)((const TY*)ws.wy)[rhs * total + ch.start + tid] : 0.0;
+  __syncthreads();
+  chunk_dots<TV>(ws, j + 1, false, nrhs, rhs, total, ch.start, ch.count, wl, red, out);
+  if (tid <= j) ws.part1[((int64_t)rhs * nchunks + c) * (M + 2) + tid] = out[tid];
 }
 
 // h1 = <V, w>;  w1 = w - V h1;  partials <v_i, w1> and |w1|^2.
@@ -138,14 +176,8 @@ __global__ __launch_bounds__(CHUNK) void k_upd1(DevTables T, int nchunks, int ni
   const int p = prob_of(rhs, ninst, ch);
   if (ws.done[p]) return;
   const int c0 = T.pchunk0[ch.problem], nc = T.pnchunk[ch.problem];
-  __shared__ double h[SGDG_MAX_M + 2];
-  __shared__ double red[NW][SGDG_MAX_M + 2];
-  if (tid <= j) {
-    double t = 0.0;
-    for (int q = 0; q < nc; ++q) t += ws.part1[((int64_t)rhs * nchunks + c0 + q) * (M + 2) + tid];
-    h[tid] = t;
-  }
-  __syncthreads();
+  __shared__ double h[SGDG_MAX_M + 2], wl[CHUNK], red[CHUNK], out[SGDG_MAX_M + 2];
+  reduce_partials(ws.part1, (int64_t)rhs * nchunks + c0, nc, M + 2, j + 1, red, h);
   if (c == c0 && tid <= j) ws.H[(int64_t)p * (M + 1) * M + tid * M + j] = h[tid];
   const int64_t g = ch.start + tid;
   double w1 = 0.0;
@@ -155,21 +187,10 @@ __global__ __launch_bounds__(CHUNK) void k_upd1(DevTables T, int nchunks, int ni
     w1 = acc;
     ws.w1[rhs * total + g] = w1;
   }
-  for (int i = 0; i <= j; ++i) {
-    double pr = tid < ch.count ? (double)vec<TV>(ws, i, nrhs, rhs, total)[g] * w1 : 0.0;
-    pr = wave_sum(pr);
-    if ((tid & 63) == 0) red[tid >> 6][i] = pr;
-  }
-  {
-    double pr = wave_sum(w1 * w1);
-    if ((tid & 63) == 0) red[tid >> 6][j + 1] = pr;
-  }
+  wl[tid] = w1;
   __syncthreads();
-  if (tid <= j + 1) {
-    double t = 0.0;
-    for (int q = 0; q < NW; ++q) t += red[q][tid];
-    ws.part2[((int64_t)rhs * nchunks + c) * (M + 2) + tid] = t;
-  }
+  chunk_dots<TV>(ws, j + 1, true, nrhs, rhs, total, ch.start, ch.count, wl, red, out);
+  if (tid <= j + 1) ws.part2[((int64_t)rhs * nchunks + c) * (M + 2) + tid] = out[tid];
 }
 
 // h2 = <V, w1>;  w2 = w1 - V h2;  h_{j+1,j} = |w2|;  v_{j+1} = w2 / h_{j+1,j}.
@@ -181,14 +202,9 @@ __global__ __launch_bounds__(CHUNK) void k_upd2(DevTables T, int nchunks, int ni
   const int p = prob_of(rhs, ninst, ch);
   if (ws.done[p]) return;
   const int c0 = T.pchunk0[ch.problem], nc = T.pnchunk[ch.problem];
-  __shared__ double h[SGDG_MAX_M + 2];
+  __shared__ double h[SGDG_MAX_M + 2], red[CHUNK];
   __shared__ double hn_s;
-  if (tid <= j + 1) {
-    double t = 0.0;
-    for (int q = 0; q < nc; ++q) t += ws.part2[((int64_t)rhs * nchunks + c0 + q) * (M + 2) + tid];
-    h[tid] = t;
-  }
-  __syncthreads();
+  reduce_partials(ws.part2, (int64_t)rhs * nchunks + c0, nc, M + 2, j + 2, red, h);
   if (tid == 0) {
     double n2 = h[j + 1];
     for (int i = 0; i <= j; ++i) n2 -= h[i] * h[i];
@@ -227,12 +243,28 @@ __global__ __launch_bounds__(CHUNK) void k_upd2(DevTables T, int nchunks, int ni
 // ratio b_j / b_{j-1} = (m-j+1) / (j (2m-j+1)).
 constexpr int MM = SGDG_MAX_M;
 
+// C = A B (m x m in LDS, leading dimension MM); each thread owns a 2x2 tile.
+// Rows/columns at index m of an odd m are computed from unused LDS and never
+// stored.
 __device__ void mat_mul(double* C, const double* A, const double* B, int m) {
-  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-    const int r = e / m, c = e - r * m;
-    double acc = 0.0;
-    for (int q = 0; q < m; ++q) acc += A[r * MM + q] * B[q * MM + c];
-    C[r * MM + c] = acc;
+  const int nt = (m + 1) >> 1;
+  for (int t = threadIdx.x; t < nt * nt; t += blockDim.x) {
+    const int r = 2 * (t / nt), c = 2 * (t % nt);
+    double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+    for (int q = 0; q < m; ++q) {
+      const double a0 = A[r * MM + q], a1 = A[(r + 1) * MM + q];
+      const double2 bq = *reinterpret_cast<const double2*>(&B[q * MM + c]);
+      c00 += a0 * bq.x;
+      c01 += a0 * bq.y;
+      c10 += a1 * bq.x;
+      c11 += a1 * bq.y;
+    }
+    C[r * MM + c] = c00;
+    if (c + 1 < m) C[r * MM + c + 1] = c01;
+    if (r + 1 < m) {
+      C[(r + 1) * MM + c] = c10;
+      if (c + 1 < m) C[(r + 1) * MM + c + 1] = c11;
+    }
   }
   __syncthreads();
 }
@@ -252,7 +284,8 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
   const int m = ws.m[p];
   const double beta = ws.beta[p];
   const double* Hp = ws.H + (int64_t)p * (M + 1) * M;
-  __shared__ double Am[MM * MM], A2[MM * MM], A4[MM * MM], A6[MM * MM], Tm[MM * MM], Um[MM * MM], Vm[MM * MM];
+  __shared__ __align__(16) double Am[MM * MM], A2[MM * MM], A4[MM * MM], A6[MM * MM], Tm[MM * MM], Um[MM * MM],
+      Vm[MM * MM];
   __shared__ double b[14], fac[MM];
   __shared__ int deg_s, s_s, piv_s;
   __shared__ double nrm_s;
@@ -271,13 +304,16 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
     Am[r * MM + c] = r <= c + 1 ? hstep * Hp[r * M + c] : 0.0;
   }
   __syncthreads();
+  // ||A||_1: column sums in parallel, maximum by thread 0
+  if (tid < m) {
+    double cs = 0.0;
+    for (int r = 0; r < m; ++r) cs += fabs(Am[r * MM + tid]);
+    fac[tid] = cs;
+  }
+  __syncthreads();
   if (tid == 0) {
     double nrm = 0.0;
-    for (int c = 0; c < m; ++c) {
-      double cs = 0.0;
-      for (int r = 0; r < m; ++r) cs += fabs(Am[r * MM + c]);
-      nrm = fmax(nrm, cs);
-    }
+    for (int c = 0; c < m; ++c) nrm = fmax(nrm, fac[c]);
     const double th[5] = {1.495585217958292e-2, 2.539398330063230e-1, 9.504178996162932e-1, 2.097847961257068e0,
                           5.371920351148152e0};
     const int dg[5] = {3, 5, 7, 9, 13};
@@ -368,15 +404,21 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
   }
   __syncthreads();
   for (int k = 0; k < m; ++k) {
-    if (tid == 0) {
-      int piv = k;
-      double best = fabs(P[k * MM + k]);
-      for (int r = k + 1; r < m; ++r)
-        if (fabs(P[r * MM + k]) > best) {
-          best = fabs(P[r * MM + k]);
-          piv = r;
+    if (tid < 64) {
+      // pivot: largest |P[r][k]|, r >= k (lowest row on ties), by a wave reduction (m <= 48)
+      const int r = k + tid;
+      double best = r < m ? fabs(P[r * MM + k]) : -1.0;
+      int piv = r < m ? r : 1 << 30;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int op = __shfl_xor(piv, off, 64);
+        if (ob > best || (ob == best && op < piv)) {
+          best = ob;
+          piv = op;
         }
-      piv_s = piv;
+      }
+      if (tid == 0) piv_s = piv;
     }
     __syncthreads();
     const int piv = piv_s;
@@ -493,20 +535,6 @@ KrylovWs krylov_carve(const sgdg_plan* plan, int M, int nrhs, void* base) {
   return ws;
 }
 
-template <int D, class P, class TV>
-static void launch_apply_dots(const sgdg_plan* plan, int nrhs, int M, int j, const void* xin, const KrylovWs& ws,
-                              hipStream_t s) {
-#define SGDG_AD(KK)                                                                                               \
-  if (!plan->chunks_by_k[KK].empty())                                                                             \
-    hipLaunchKernelGGL((k_apply_dots<D, KK, P, TV>), dim3((unsigned)plan->chunks_by_k[KK].size(), (unsigned)nrhs), \
-                       dim3(CHUNK), 0, s, plan->dev, plan->dev_chunk_lists[KK], plan->nchunks, plan->ninst,      \
-                       plan->total, M, j, (const typename P::X*)xin, ws);
-  SGDG_AD(1)
-  SGDG_AD(2)
-  SGDG_AD(3)
-#undef SGDG_AD
-}
-
 template <class P, class TV, class TY>
 static void run_typed(const sgdg_plan* plan, int nrhs, double h, int M, const double* v, double* w,
                       const KrylovWs& ws, sgdg_stats* stats, hipStream_t s) {
@@ -515,14 +543,8 @@ static void run_typed(const sgdg_plan* plan, int nrhs, double h, int M, const do
   hipLaunchKernelGGL((k_norm<TV>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, v, ws);
   for (int j = 0; j < M; ++j) {
     const void* xin = ws.Vb ? (const void*)ws.Vb : (const void*)((const TV*)ws.V + (size_t)j * nrhs * plan->total);
-    switch (plan->d) {
-      case 1: launch_apply_dots<1, P, TV>(plan, nrhs, M, j, xin, ws, s); break;
-      case 2: launch_apply_dots<2, P, TV>(plan, nrhs, M, j, xin, ws, s); break;
-      case 3: launch_apply_dots<3, P, TV>(plan, nrhs, M, j, xin, ws, s); break;
-      case 4: launch_apply_dots<4, P, TV>(plan, nrhs, M, j, xin, ws, s); break;
-      case 5: launch_apply_dots<5, P, TV>(plan, nrhs, M, j, xin, ws, s); break;
-      default: launch_apply_dots<6, P, TV>(plan, nrhs, M, j, xin, ws, s); break;
-    }
+    launch_apply<P>(plan, nrhs, xin, ws.wy, plan->total, plan->total, s);
+    hipLaunchKernelGGL((k_dots1<TV, TY>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j, ws);
     hipLaunchKernelGGL((k_upd1<TV, TY>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j, ws);
     hipLaunchKernelGGL((k_upd2<TV>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j, ws);
   }

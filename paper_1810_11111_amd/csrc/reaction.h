@@ -19,8 +19,9 @@ struct RInst {
   int32_t N, K1, S, nq, np1, n1, d, pad;
   int64_t seg;    // offset of the instance in a plan vector
   int64_t ndof;
-  int64_t E_off;  // into E: [(l * np1 + q) * K1 + p], value of level-l function at 1D point q
-  int64_t w_off;  // into w1: Gauss weight times h_N of 1D point q
+  int64_t EL_off;    // into EL: [(L * np1 + q) * K1 + p] = level-L cell basis p at finest 1D Gauss point q
+  int64_t w_off;     // into w1: Gauss weight times h_N of 1D point q
+  int64_t mats_off;  // into mats: ML, MR, cL, cR (each 16 doubles, row length K1)
   int32_t blk_off[SGDG_MAX_D + 1];  // into rblk, r-dim grid
   int32_t nblk[SGDG_MAX_D + 1];
   int32_t id_off[SGDG_MAX_D + 1];   // into rid: (N+1)^r entries, -1 if |l|_1 > N
@@ -28,7 +29,7 @@ struct RInst {
   int64_t gdof[SGDG_MAX_D + 1];     // DOFs of the r-dim grid
   int64_t npre[SGDG_MAX_D + 1];     // np1^m
   int64_t X_off[SGDG_MAX_D];        // per-rhs workspace offsets (doubles) of expansion outputs, m = 1..d-1
-  int64_t Y_off[SGDG_MAX_D];        // of contraction outputs, m = 0..d-1 (Y_0 only for d = 1)
+  int64_t Y_off[SGDG_MAX_D];        // of contraction outputs, m = 1..d-1
   double rx[2][4][4];
 };
 
@@ -36,26 +37,32 @@ struct RTables {
   RInst* inst = nullptr;
   RBlk* rblk = nullptr;
   int32_t* rid = nullptr;
-  double* E = nullptr;
+  double* EL = nullptr;
   double* w1 = nullptr;
-  int64_t* cum_x[SGDG_MAX_D] = {};  // per expansion stage m: cumulative output counts over instances (ninst+1)
-  int64_t* cum_y[SGDG_MAX_D] = {};  // per contraction stage m (>= 1)
-  int64_t* cum_line = nullptr;
+  double* mats = nullptr;
+  int64_t* cum_x[SGDG_MAX_D] = {};  // expansion stage m: fibres per instance (prefix sums, ninst+1)
+  int64_t* cum_y[SGDG_MAX_D] = {};  // contraction stage m >= 1
+  int64_t* cum_line = nullptr;      // lines of the last axis
+  int64_t* cum_fin = nullptr;       // fibres of the final stage (partial residual sums)
 };
 
 struct RHost {
   RTables dev;
   std::vector<std::vector<int64_t>> cum_x, cum_y;
-  std::vector<int64_t> cum_line;
+  std::vector<int64_t> cum_line, cum_fin;
   int64_t rws = 0;  // doubles of reaction workspace per right-hand side
   int max_n1 = 0, max_np1 = 0;
+  bool supported = true;
 };
+
+bool reaction_supported(const sgdg_plan* plan);
+int64_t reaction_final_fibres(const sgdg_plan* plan);
 
 enum RxMode { RX_F = 0, RX_RESID = 1, RX_CORR = 2 };
 
 // One reaction pass over nrhs right-hand sides.
 //   RX_F    : F = P f(R U)
-//   RX_RESID: F = P f(R U), G = U - dt2 F - W, per-chunk |G|^2 into part
+//   RX_RESID: F = P f(R U), G = U - dt2 F - W, per-final-fibre |G|^2 into part
 //   RX_CORR : U <- U - P[(I - dt2 J_f(R U))^{-1} R G]
 // Instances with conv[rhs * ninst + inst] != 0 are skipped (conv may be null).
 struct RxArgs {
@@ -64,7 +71,7 @@ struct RxArgs {
   double* F;
   double* Gout;
   const double* W;
-  double* part;  // [rhs][chunk]
+  double* part;  // [rhs][final fibre]
   const int32_t* conv;
   double dt2;
   double* rws;  // reaction workspace base

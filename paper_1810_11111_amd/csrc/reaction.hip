@@ -3,20 +3,26 @@
 // Sec. 5 of the paper: u_h is reconstructed at the Gaussian points of the
 // finest-level mesh Omega_N and int f(u_h) v dx is done by that quadrature
 // (k+1 Gauss-Legendre points per axis in every finest cell; with this rule
-// P R = I on the sparse space).  R and P = R^T diag(W) are applied by sum
-// factorisation over the axes:
+// P R = I on the sparse space).  The paper names the cost of this step as the
+// dominant one and points at the special structure of the basis as the way to
+// cut it; here that structure is used directly.
 //
-//   expand stage m (m = 0..d-2): T_{m+1}[q_0..q_m][sparse grid of axes m+1..d-1]
-//       = sum over l_m <= N - |l_{>m}|, p of T_m[..][(l_m, l_{>m}); j(q_m), p, ..] E[l_m][q_m][p]
-//   line kernel (last axis): per line expand to its np1 points, apply f (or
-//       the per-point species-Jacobian solve of the implicit stage), contract
-//       back with the weights, all in LDS;
-//   contract stage m (m = d-2..0): the transpose, summing each coefficient
-//       over the points of its support; stage 0 writes plan vectors and fuses
-//       the mode's post-processing (residual G, correction of U).
-//
-// Every stage covers all instances, species and right-hand sides of the plan
-// in one launch.
+// R and P = R^T diag(W) are applied axis by axis ("unidirectional"), each
+// axis as a batch of independent 1D fibres.  A fibre along axis m with level
+// budget L = N - (levels of the other, not yet transformed axes) holds a 1D
+// hierarchical vector of levels 0..L:
+//   expand  : inverse fast multiwavelet transform to the 2^L level-L cells
+//             (two-scale relations), then (k+1)-term evaluation at each of the
+//             np1 = (k+1) 2^N Gauss points of the axis;
+//   contract: weights, projection of the np1 point values onto the 2^N finest
+//             cells, forward fast multiwavelet transform, levels <= L kept.
+// Both are O((k+1)^2 n) per fibre and uniform across lanes (a coefficient's
+// support is never summed point by point).  Stages: expand axes 0..d-2,
+// line kernel on the last axis (expand, pointwise f or per-point species
+// Jacobian solve, contract), contract axes d-2..0; the last contraction
+// writes plan vectors with the residual / correction post-processing fused.
+// One 64-lane workgroup per fibre, all intermediate work in LDS; every stage
+// covers all instances, species and right-hand sides in one launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,7 +38,6 @@
 namespace sgdg {
 
 sgdg_status plan_upload(sgdg_plan* p, const void* src, size_t bytes, void** out);
-static sgdg_status line_lds_attr(const RHost* rh);
 
 template <class T>
 static sgdg_status up(sgdg_plan* p, const std::vector<T>& v, T** out) {
@@ -61,18 +66,38 @@ static std::vector<std::vector<int>> grid_blocks(int r, int N) {
   return out;
 }
 
+constexpr int RX_THREADS = 64;
+constexpr int RX_MAX_N1 = 2048;
+
+static size_t fibre_lds_bytes(const RHost* rh) {
+  return (3 * (size_t)rh->max_n1 + (size_t)rh->max_np1 + 64) * sizeof(double);
+}
+static size_t line_lds_bytes(const RHost* rh) {
+  return (3 * (size_t)rh->max_n1 + 4 * (size_t)rh->max_np1 + 64) * sizeof(double);
+}
+static sgdg_status set_lds_attrs(const RHost* rh);
+
 sgdg_status reaction_build(sgdg_plan* plan) {
   RHost* rh = new RHost();
   plan->rdata = rh;
   const int d = plan->d;
+  // A fibre of a whole finest-grid line stays in LDS: (k+1) 2^N <= 2048.
+  // Larger plans are still valid for the sweep and the Krylov exponential;
+  // their reaction calls report SGDG_ERR_UNSUPPORTED.
+  for (const HostInstance& hi : plan->inst)
+    if (((hi.desc.k + 1) << hi.desc.n) > RX_MAX_N1) {
+      rh->supported = false;
+      return SGDG_OK;
+    }
   std::vector<RInst> ri;
   std::vector<RBlk> rblk;
   std::vector<int32_t> rid;
-  std::vector<double> E, w1;
+  std::vector<double> EL, w1, mats;
   int64_t ws = 0;
   rh->cum_x.assign(d, std::vector<int64_t>(1, 0));
   rh->cum_y.assign(d, std::vector<int64_t>(1, 0));
   rh->cum_line.assign(1, 0);
+  rh->cum_fin.assign(1, 0);
   for (int i = 0; i < plan->ninst; ++i) {
     const HostInstance& hi = plan->inst[i];
     const int N = hi.desc.n, K1 = hi.desc.k + 1, S = hi.desc.nspecies;
@@ -89,21 +114,31 @@ sgdg_status reaction_build(sgdg_plan* plan) {
     std::memcpy(r.rx, hi.desc.rx, sizeof(r.rx));
     rh->max_n1 = std::max(rh->max_n1, r.n1);
     rh->max_np1 = std::max(rh->max_np1, r.np1);
-    // 1D Gauss points and basis values
     std::vector<double> xg, wg;
     gauss01(r.nq, xg, wg);
     const Basis1D& bs = basis1d(hi.desc.k);
     const double h = std::ldexp(1.0, -N);
-    r.E_off = (int64_t)E.size();
+    r.EL_off = (int64_t)EL.size();
     r.w_off = (int64_t)w1.size();
+    r.mats_off = (int64_t)mats.size();
     for (int q = 0; q < r.np1; ++q) w1.push_back(wg[q % r.nq] * h);
-    for (int l = 0; l <= N; ++l)
+    // level-L cell basis 2^(L/2) phi_p(2^L x - c) at the finest Gauss points
+    double phi[16];
+    for (int L = 0; L <= N; ++L)
       for (int q = 0; q < r.np1; ++q) {
-        const int cell = q / r.nq;
-        const int j = l == 0 ? 0 : (cell >> (N - l + 1));
-        const double x = (cell + xg[q % r.nq]) * h;
-        for (int p = 0; p < K1; ++p) E.push_back(hier_value(bs, l, j, p, x, false));
+        const int cellN = q / r.nq;
+        const int cL = cellN >> (N - L);
+        const double xloc = ((cellN - ((int64_t)cL << (N - L))) + xg[q % r.nq]) * std::ldexp(1.0, L - N);
+        legendre01_all(hi.desc.k, xloc, phi, nullptr);
+        for (int p = 0; p < K1; ++p) EL.push_back(std::sqrt(std::ldexp(1.0, L)) * phi[p]);
       }
+    // two-scale matrices, rows padded to 16 entries each
+    const std::vector<double>* src[4] = {&bs.ML, &bs.MR, &bs.cL, &bs.cR};
+    for (int t = 0; t < 4; ++t) {
+      std::vector<double> pad(16, 0.0);
+      std::copy(src[t]->begin(), src[t]->end(), pad.begin());
+      mats.insert(mats.end(), pad.begin(), pad.end());
+    }
     // r-dimensional sparse grids, r = 1..d
     for (int rr = 1; rr <= d; ++rr) {
       auto blocks = grid_blocks(rr, N);
@@ -145,29 +180,28 @@ sgdg_status reaction_build(sgdg_plan* plan) {
       r.Y_off[m] = ws;
       ws += (int64_t)S * r.npre[m] * r.gdof[d - m];
     }
-    if (d == 1) {
-      r.Y_off[0] = ws;
-      ws += (int64_t)S * hi.ndof;
-    }
+    // fibres: expansion/contraction stage m runs over (species, prefix, column of the (d-m-1)-dim grid)
     for (int m = 0; m + 1 <= d - 1; ++m)
-      rh->cum_x[m].push_back(rh->cum_x[m].back() + (int64_t)S * r.npre[m + 1] * r.gdof[d - m - 1]);
-    for (int m = 1; m <= d - 1; ++m)
-      rh->cum_y[m].push_back(rh->cum_y[m].back() + (int64_t)S * r.npre[m] * r.gdof[d - m]);
+      rh->cum_x[m].push_back(rh->cum_x[m].back() + (int64_t)S * r.npre[m] * r.gdof[d - m - 1]);
+    for (int m = 1; m + 1 <= d - 1; ++m)
+      rh->cum_y[m].push_back(rh->cum_y[m].back() + (int64_t)S * r.npre[m] * r.gdof[d - m - 1]);
     rh->cum_line.push_back(rh->cum_line.back() + r.npre[d - 1]);
+    rh->cum_fin.push_back(rh->cum_fin.back() + (d >= 2 ? (int64_t)S * r.gdof[d - 1] : 1));
     ri.push_back(r);
   }
   rh->rws = ws;
-  if (rh->max_n1 > 2048) return fail(SGDG_ERR_UNSUPPORTED, "reaction: (k+1) 2^N above 2048 per axis");
   sgdg_status st;
   if ((st = up(plan, ri, &rh->dev.inst)) != SGDG_OK || (st = up(plan, rblk, &rh->dev.rblk)) != SGDG_OK ||
-      (st = up(plan, rid, &rh->dev.rid)) != SGDG_OK || (st = up(plan, E, &rh->dev.E)) != SGDG_OK ||
-      (st = up(plan, w1, &rh->dev.w1)) != SGDG_OK || (st = up(plan, rh->cum_line, &rh->dev.cum_line)) != SGDG_OK)
+      (st = up(plan, rid, &rh->dev.rid)) != SGDG_OK || (st = up(plan, EL, &rh->dev.EL)) != SGDG_OK ||
+      (st = up(plan, w1, &rh->dev.w1)) != SGDG_OK || (st = up(plan, mats, &rh->dev.mats)) != SGDG_OK ||
+      (st = up(plan, rh->cum_line, &rh->dev.cum_line)) != SGDG_OK ||
+      (st = up(plan, rh->cum_fin, &rh->dev.cum_fin)) != SGDG_OK)
     return st;
   for (int m = 0; m < d; ++m) {
     if ((st = up(plan, rh->cum_x[m], &rh->dev.cum_x[m])) != SGDG_OK) return st;
     if ((st = up(plan, rh->cum_y[m], &rh->dev.cum_y[m])) != SGDG_OK) return st;
   }
-  return line_lds_attr(rh);
+  return set_lds_attrs(rh);
 }
 
 void reaction_destroy(sgdg_plan* plan) {
@@ -176,8 +210,13 @@ void reaction_destroy(sgdg_plan* plan) {
 }
 
 int64_t reaction_ws_doubles(const sgdg_plan* plan) { return ((const RHost*)plan->rdata)->rws; }
+bool reaction_supported(const sgdg_plan* plan) { return ((const RHost*)plan->rdata)->supported; }
+int64_t reaction_final_fibres(const sgdg_plan* plan) {
+  const RHost* rh = (const RHost*)plan->rdata;
+  return rh->supported ? rh->cum_fin.back() : 0;
+}
 
-// ---------------------------------------------------------------- kernels
+// ---------------------------------------------------------------- device helpers
 
 __device__ __forceinline__ int find_inst(const int64_t* __restrict__ cum, int ninst, int64_t e) {
   int lo = 0, hi = ninst - 1;
@@ -203,66 +242,109 @@ __device__ __forceinline__ int find_rblk(const RBlk* __restrict__ b, int n, int6
   return lo;
 }
 
-__device__ __forceinline__ int cell_of_level(int q, int l, int N, int nq) { return l == 0 ? 0 : ((q / nq) >> (N - l + 1)); }
+__device__ __forceinline__ int off1(int l, int K1) { return l == 0 ? 0 : (K1 << (l - 1)); }
 
-// input vector of expansion stage 0 / the line kernel when d = 1 (plan vectors), per input z
+// two-scale matrices in LDS: M[0..15] ML[q][i] (child q from parent i), M[16..] MR,
+// M[32..] cL[p][q] (wavelet p on left child basis q), M[48..] cR; row length K1
+__device__ __forceinline__ void load_mats(const RTables& R, const RInst& I, double* M) {
+  for (int e = threadIdx.x; e < 64; e += blockDim.x) M[e] = R.mats[I.mats_off + e];
+}
+
+// inverse fast multiwavelet transform: hierarchical levels 0..L in h -> level-L
+// cell-Legendre coefficients (returned pointer, one of b0 / b1)
+__device__ double* ifwt(const double* h, double* b0, double* b1, int L, int K1, const double* M) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < K1; e += nt) b0[e] = h[e];
+  __syncthreads();
+  double* cur = b0;
+  double* nxt = b1;
+  for (int n = 1; n <= L; ++n) {
+    const double* dw = h + (K1 << (n - 1));
+    const int items = (K1 << n);
+    for (int e = tid; e < items; e += nt) {
+      const int c = e / K1, q = e - c * K1, j = c >> 1;
+      const double* Mq = (c & 1) ? M + 16 : M;
+      const double* Wq = (c & 1) ? M + 48 : M + 32;
+      double acc = 0.0;
+      for (int i = 0; i < K1; ++i) acc += Mq[q * K1 + i] * cur[j * K1 + i];
+      for (int p = 0; p < K1; ++p) acc += Wq[p * K1 + q] * dw[j * K1 + p];
+      nxt[e] = acc;
+    }
+    __syncthreads();
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  return cur;
+}
+
+// forward fast multiwavelet transform of level-N cell coefficients in s (s and
+// tmp are overwritten); emit(level, j, p, value) receives every hierarchical
+// coefficient (wavelets of levels N..1, then level 0).
+template <class Emit>
+__device__ void ffwt(double* s, double* tmp, int N, int K1, const double* M, Emit emit) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* cur = s;
+  double* nxt = tmp;
+  for (int n = N; n >= 1; --n) {
+    const int npar = 1 << (n - 1);
+    const int half = npar * K1;
+    for (int e = tid; e < 2 * half; e += nt) {
+      const int w = e >= half;
+      const int e2 = e - w * half;
+      const int j = e2 / K1, i = e2 - j * K1;
+      const double* sl = cur + (2 * j) * K1;
+      const double* sr = sl + K1;
+      double acc = 0.0;
+      if (!w) {
+        for (int q = 0; q < K1; ++q) acc += M[q * K1 + i] * sl[q] + M[16 + q * K1 + i] * sr[q];
+        nxt[j * K1 + i] = acc;
+      } else {
+        for (int q = 0; q < K1; ++q) acc += M[32 + i * K1 + q] * sl[q] + M[48 + i * K1 + q] * sr[q];
+        emit(n, j, i, acc);
+      }
+    }
+    __syncthreads();
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  for (int e = tid; e < K1; e += nt) emit(0, 0, e, cur[e]);
+  __syncthreads();
+}
+
+// value at finest point q of the level-L cell expansion s
+__device__ __forceinline__ double eval_pt(const double* s, const double* __restrict__ EL, int L, int N, int nq, int np1,
+                                          int K1, int q) {
+  const int c = (q / nq) >> (N - L);
+  const double* e = EL + ((int64_t)L * np1 + q) * K1;
+  double u = 0.0;
+  for (int p = 0; p < K1; ++p) u += s[c * K1 + p] * e[p];
+  return u;
+}
+
+// weighted point values g (weights already applied) -> level-N cell coefficients in out
+__device__ __forceinline__ void project_cells(const double* g, const double* __restrict__ EL, int N, int nq, int np1,
+                                              int K1, double* out) {
+  const int ncell = 1 << N;
+  const double* e = EL + (int64_t)N * np1 * K1;
+  for (int t = threadIdx.x; t < ncell * K1; t += blockDim.x) {
+    const int c = t / K1, p = t - c * K1;
+    double acc = 0.0;
+    for (int gq = 0; gq < nq; ++gq) acc += g[c * nq + gq] * e[(c * nq + gq) * K1 + p];
+    out[t] = acc;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ const double* plan_in(const RxArgs& a, int z, int64_t rhs_total) {
   return (z == 0 ? (const double*)a.U : a.G) + rhs_total;
 }
 
-__global__ __launch_bounds__(256) void k_rx_expand(RTables R, int ninst, int m, int64_t total, RxArgs a,
-                                                   int64_t rws) {
-  const int z = blockIdx.z, rhs = blockIdx.y;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t* cum = R.cum_x[m];
-  if (e >= cum[ninst]) return;
-  const int inst = find_inst(cum, ninst, e);
-  if (a.conv && a.conv[rhs * ninst + inst]) return;
-  const RInst& I = R.inst[inst];
-  const int d = I.d, r = d - m, N = I.N, K1 = I.K1, S = I.S, np1 = I.np1;
-  int64_t le = e - cum[inst];
-  const int64_t nout = I.npre[m + 1] * I.gdof[r - 1];
-  const int s = (int)(le / nout);
-  le -= (int64_t)s * nout;
-  const int64_t pre1 = le / I.gdof[r - 1];
-  const int64_t eo = le - pre1 * I.gdof[r - 1];
-  const int qm = (int)(pre1 % np1);
-  const int64_t pre0 = pre1 / np1;
-  const RBlk* ob = R.rblk + I.blk_off[r - 1];
-  const int bo = find_rblk(ob, I.nblk[r - 1], eo);
-  const RBlk B = ob[bo];
-  const int64_t rest = eo - B.start;
-  const int64_t Sb = B.size;
-  int lin = 0, pw = 1;
-  for (int t = r - 2; t >= 0; --t) {
-    lin += B.lev[t] * pw;
-    pw *= (N + 1);
-  }
-  // pw = (N+1)^(r-1): weight of the leading axis (axis m) in the r-dim id table
-  const int32_t* __restrict__ id = R.rid + I.id_off[r];
-  const RBlk* ib = R.rblk + I.blk_off[r];
-  const double* __restrict__ in;
-  double* xr = a.rws + (int64_t)rhs * rws;
-  if (m == 0)
-    in = plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof;
-  else
-    in = xr + I.X_off[m] + (((int64_t)z * S + s) * I.npre[m] + pre0) * I.gdof[r];
-  const double* __restrict__ E = R.E + I.E_off;
-  double acc = 0.0;
-  for (int l = 0; l <= N - B.lsum; ++l) {
-    const int bi = id[l * pw + lin];
-    const int64_t base = ib[bi].start;
-    const int j = cell_of_level(qm, l, N, I.nq);
-    const double* ev = E + ((int64_t)l * np1 + qm) * K1;
-    for (int p = 0; p < K1; ++p) acc += in[base + (int64_t)(j * K1 + p) * Sb + rest] * ev[p];
-  }
-  xr[I.X_off[m + 1] + (((int64_t)z * S + s) * I.npre[m + 1] + pre1) * I.gdof[r - 1] + eo] = acc;
-}
-
 __device__ __forceinline__ void rx_f(const double (*c)[4][4], int S, const double* u, double* f) {
   const double u0 = u[0], u1 = S > 1 ? u[1] : 0.0;
-  double p0[4] = {1.0, u0, u0 * u0, u0 * u0 * u0};
-  double p1[4] = {1.0, u1, u1 * u1, u1 * u1 * u1};
+  const double p0[4] = {1.0, u0, u0 * u0, u0 * u0 * u0};
+  const double p1[4] = {1.0, u1, u1 * u1, u1 * u1 * u1};
   for (int s = 0; s < S; ++s) {
     double acc = 0.0;
     for (int aa = 0; aa < 4; ++aa)
@@ -273,8 +355,8 @@ __device__ __forceinline__ void rx_f(const double (*c)[4][4], int S, const doubl
 
 __device__ __forceinline__ void rx_jac(const double (*c)[4][4], int S, const double* u, double J[2][2]) {
   const double u0 = u[0], u1 = S > 1 ? u[1] : 0.0;
-  double p0[4] = {1.0, u0, u0 * u0, u0 * u0 * u0};
-  double p1[4] = {1.0, u1, u1 * u1, u1 * u1 * u1};
+  const double p0[4] = {1.0, u0, u0 * u0, u0 * u0 * u0};
+  const double p1[4] = {1.0, u1, u1 * u1, u1 * u1 * u1};
   for (int s = 0; s < S; ++s) {
     double j0 = 0.0, j1 = 0.0;
     for (int aa = 0; aa < 4; ++aa)
@@ -287,190 +369,221 @@ __device__ __forceinline__ void rx_jac(const double (*c)[4][4], int S, const dou
   }
 }
 
-// One workgroup per line along the last axis: expand, pointwise map, contract.
-__global__ __launch_bounds__(256) void k_rx_line(RTables R, int ninst, int mode, int64_t total, RxArgs a, int64_t rws,
-                                                 int max_n1, int max_np1) {
+// post-processing of one output coefficient of the final stage; returns G^2 (RESID) or 0
+__device__ __forceinline__ double finish(const RxArgs& a, int mode, int64_t gi, double v) {
+  if (mode == RX_F) {
+    a.F[gi] = v;
+  } else if (mode == RX_RESID) {
+    a.F[gi] = v;
+    const double G = a.U[gi] - a.dt2 * v - a.W[gi];
+    a.Gout[gi] = G;
+    return G * G;
+  } else {
+    a.U[gi] -= v;
+  }
+  return 0.0;
+}
+
+__device__ __forceinline__ double block_sum64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------- kernels
+
+// expansion stage m: fibres along axis m, grid (fibres, rhs, input)
+__global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, int ninst, int m, int64_t total, RxArgs a,
+                                                          int64_t rws, int max_n1) {
+  extern __shared__ double lds[];
+  const int z = blockIdx.z, rhs = blockIdx.y;
+  const int64_t f = blockIdx.x;
+  const int64_t* cum = R.cum_x[m];
+  const int inst = find_inst(cum, ninst, f);
+  if (a.conv && a.conv[rhs * ninst + inst]) return;
+  const RInst& I = R.inst[inst];
+  const int d = I.d, r = d - m, N = I.N, K1 = I.K1, S = I.S, np1 = I.np1, nq = I.nq;
+  int64_t le = f - cum[inst];
+  const int64_t per_s = I.npre[m] * I.gdof[r - 1];
+  const int s = (int)(le / per_s);
+  le -= (int64_t)s * per_s;
+  const int64_t pre0 = le / I.gdof[r - 1];
+  const int64_t eo = le - pre0 * I.gdof[r - 1];
+  const RBlk* ob = R.rblk + I.blk_off[r - 1];
+  const RBlk B = ob[find_rblk(ob, I.nblk[r - 1], eo)];
+  const int64_t rest = eo - B.start, Sb = B.size;
+  const int L = N - B.lsum;
+  int lin = 0, pw = 1;
+  for (int t = r - 2; t >= 0; --t) {
+    lin += B.lev[t] * pw;
+    pw *= (N + 1);
+  }
+  double* h = lds;
+  double* b0 = lds + max_n1;
+  double* b1 = lds + 2 * max_n1;
+  double* M = lds + 3 * max_n1;
+  const int32_t* __restrict__ id = R.rid + I.id_off[r];
+  const RBlk* ib = R.rblk + I.blk_off[r];
+  double* xr = a.rws + (int64_t)rhs * rws;
+  const double* __restrict__ in =
+      m == 0 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof
+             : xr + I.X_off[m] + (((int64_t)z * S + s) * I.npre[m] + pre0) * I.gdof[r];
+  load_mats(R, I, M);
+  for (int l = 0; l <= L; ++l) {
+    const int64_t base = ib[id[l * pw + lin]].start + rest;
+    const int cnt = level_count(l) * K1;
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) h[off1(l, K1) + t] = in[base + (int64_t)t * Sb];
+  }
+  __syncthreads();
+  const double* sc = ifwt(h, b0, b1, L, K1, M);
+  const double* __restrict__ EL = R.EL + I.EL_off;
+  double* out = xr + I.X_off[m + 1] + (((int64_t)z * S + s) * I.npre[m + 1] + pre0 * np1) * I.gdof[r - 1] + eo;
+  for (int q = threadIdx.x; q < np1; q += blockDim.x)
+    out[(int64_t)q * I.gdof[r - 1]] = eval_pt(sc, EL, L, N, nq, np1, K1, q);
+}
+
+// one workgroup per line of the last axis: expand (all species and inputs),
+// pointwise map, contract; for d = 1 the line is the whole instance and the
+// plan vectors are read and finished directly
+__global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, int ninst, int mode, int64_t total, RxArgs a,
+                                                        int64_t rws, int max_n1, int max_np1, int64_t nfin) {
   extern __shared__ double lds[];
   const int rhs = blockIdx.y;
   const int64_t gl = blockIdx.x;
-  if (gl >= R.cum_line[ninst]) return;
   const int inst = find_inst(R.cum_line, ninst, gl);
   if (a.conv && a.conv[rhs * ninst + inst]) return;
   const RInst& I = R.inst[inst];
   const int d = I.d, N = I.N, K1 = I.K1, S = I.S, np1 = I.np1, n1 = I.n1, nq = I.nq;
   const int64_t pre = gl - R.cum_line[inst];
   const int nin = mode == RX_CORR ? 2 : 1;
-  double* coef = lds;                      // [z][s][max_n1]
-  double* fq = lds + 4 * (int64_t)max_n1;  // [s][max_np1]
+  double* h = lds;
+  double* b0 = lds + max_n1;
+  double* b1 = lds + 2 * max_n1;
+  double* pts = lds + 3 * max_n1;  // [z*2+s][max_np1]
+  double* M = pts + 4 * max_np1;
   double* xr = a.rws + (int64_t)rhs * rws;
+  const double* __restrict__ EL = R.EL + I.EL_off;
+  const double* __restrict__ w1 = R.w1 + I.w_off;
+  load_mats(R, I, M);
   for (int z = 0; z < nin; ++z)
     for (int s = 0; s < S; ++s) {
-      const double* in;
-      if (d == 1)
-        in = plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof;
-      else
-        in = xr + I.X_off[d - 1] + (((int64_t)z * S + s) * I.npre[d - 1] + pre) * n1;
-      for (int i = threadIdx.x; i < n1; i += blockDim.x) coef[(z * 2 + s) * max_n1 + i] = in[i];
+      const double* in = d == 1 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof
+                                : xr + I.X_off[d - 1] + (((int64_t)z * S + s) * I.npre[d - 1] + pre) * n1;
+      for (int i = threadIdx.x; i < n1; i += blockDim.x) h[i] = in[i];
+      __syncthreads();
+      const double* sc = ifwt(h, b0, b1, N, K1, M);
+      for (int q = threadIdx.x; q < np1; q += blockDim.x) pts[(z * 2 + s) * max_np1 + q] = eval_pt(sc, EL, N, N, nq, np1, K1, q);
+      __syncthreads();
     }
-  __syncthreads();
-  const double* __restrict__ E = R.E + I.E_off;
-  const double* __restrict__ w1 = R.w1 + I.w_off;
   for (int q = threadIdx.x; q < np1; q += blockDim.x) {
-    double u[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int l = 0; l <= N; ++l) {
-      const int j = cell_of_level(q, l, N, nq);
-      const int o = (l == 0 ? 0 : (K1 << (l - 1))) + j * K1;
-      const double* ev = E + ((int64_t)l * np1 + q) * K1;
-      for (int p = 0; p < K1; ++p)
-        for (int z = 0; z < nin; ++z)
-          for (int s = 0; s < S; ++s) u[z][s] += coef[(z * 2 + s) * max_n1 + o + p] * ev[p];
-    }
+    double u[2] = {pts[q], S > 1 ? pts[max_np1 + q] : 0.0};
     double out[2];
     if (mode == RX_CORR) {
+      const double g0 = pts[2 * max_np1 + q], g1 = S > 1 ? pts[3 * max_np1 + q] : 0.0;
       double J[2][2];
-      rx_jac(I.rx, S, u[0], J);
+      rx_jac(I.rx, S, u, J);
       if (S == 1) {
-        out[0] = u[1][0] / (1.0 - a.dt2 * J[0][0]);
+        out[0] = g0 / (1.0 - a.dt2 * J[0][0]);
       } else {
-        const double A = 1.0 - a.dt2 * J[0][0], B = -a.dt2 * J[0][1];
+        const double A = 1.0 - a.dt2 * J[0][0], Bq = -a.dt2 * J[0][1];
         const double C = -a.dt2 * J[1][0], D = 1.0 - a.dt2 * J[1][1];
-        const double det = A * D - B * C;
-        out[0] = (D * u[1][0] - B * u[1][1]) / det;
-        out[1] = (A * u[1][1] - C * u[1][0]) / det;
+        const double det = A * D - Bq * C;
+        out[0] = (D * g0 - Bq * g1) / det;
+        out[1] = (A * g1 - C * g0) / det;
       }
     } else {
-      rx_f(I.rx, S, u[0], out);
+      rx_f(I.rx, S, u, out);
     }
-    for (int s = 0; s < S; ++s) fq[s * max_np1 + q] = w1[q] * out[s];
+    for (int s = 0; s < S; ++s) pts[s * max_np1 + q] = w1[q] * out[s];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-    const int c1 = i / K1, p = i - c1 * K1;
-    const int l = c1 == 0 ? 0 : 32 - __clz(c1);
-    const int j = c1 == 0 ? 0 : c1 - (1 << (l - 1));
-    const int qs = l == 0 ? 0 : (j << (N - l + 1)) * nq;
-    const int qe = l == 0 ? np1 : ((j + 1) << (N - l + 1)) * nq;
-    double acc[2] = {0.0, 0.0};
-    for (int q = qs; q < qe; ++q) {
-      const double ev = E[((int64_t)l * np1 + q) * K1 + p];
-      for (int s = 0; s < S; ++s) acc[s] += fq[s * max_np1 + q] * ev;
+  double g2 = 0.0;
+  for (int s = 0; s < S; ++s) {
+    project_cells(pts + s * max_np1, EL, N, nq, np1, K1, b0);
+    if (d == 1) {
+      const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)s * I.ndof;
+      ffwt(b0, b1, N, K1, M, [&](int n, int j, int p, double v) {
+        g2 += finish(a, mode, base + off1(n, K1) + j * K1 + p, v);
+      });
+    } else {
+      double* out = xr + I.Y_off[d - 1] + ((int64_t)s * I.npre[d - 1] + pre) * n1;
+      ffwt(b0, b1, N, K1, M, [&](int n, int j, int p, double v) { out[off1(n, K1) + j * K1 + p] = v; });
     }
-    for (int s = 0; s < S; ++s) {
-      if (d == 1)
-        xr[I.Y_off[0] + (int64_t)s * I.ndof + i] = acc[s];
-      else
-        xr[I.Y_off[d - 1] + ((int64_t)s * I.npre[d - 1] + pre) * n1 + i] = acc[s];
-    }
+  }
+  if (d == 1 && mode == RX_RESID) {
+    g2 = block_sum64(g2);
+    if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + R.cum_fin[inst]] = g2;
   }
 }
 
-// contraction stage m >= 1: Y_m from Y_{m+1}
-__global__ __launch_bounds__(256) void k_rx_contract(RTables R, int ninst, int m, RxArgs a, int64_t rws) {
+// contraction stage m (m >= 1 writes Y_m; m == 0 finishes plan vectors)
+__global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, int ninst, int m, int mode, int64_t total,
+                                                            RxArgs a, int64_t rws, int max_n1, int64_t nfin) {
+  extern __shared__ double lds[];
   const int rhs = blockIdx.y;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t* cum = R.cum_y[m];
-  if (e >= cum[ninst]) return;
-  const int inst = find_inst(cum, ninst, e);
+  const int64_t f = blockIdx.x;
+  const int64_t* cum = m == 0 ? R.cum_fin : R.cum_y[m];
+  const int inst = find_inst(cum, ninst, f);
   if (a.conv && a.conv[rhs * ninst + inst]) return;
   const RInst& I = R.inst[inst];
   const int d = I.d, r = d - m, N = I.N, K1 = I.K1, np1 = I.np1, nq = I.nq;
-  int64_t le = e - cum[inst];
-  const int64_t nout = I.npre[m] * I.gdof[r];
-  const int s = (int)(le / nout);
-  le -= (int64_t)s * nout;
-  const int64_t pre0 = le / I.gdof[r];
-  const int64_t eo = le - pre0 * I.gdof[r];
-  const RBlk* bb = R.rblk + I.blk_off[r];
-  const RBlk B = bb[find_rblk(bb, I.nblk[r], eo)];
-  const int64_t L = eo - B.start;
-  // sub-block of axes m+1.. in the (r-1)-dim grid
-  int lin = 0;
-  for (int t = 1; t < r; ++t) lin = lin * (N + 1) + B.lev[t];
-  const RBlk Bs = R.rblk[I.blk_off[r - 1] + R.rid[I.id_off[r - 1] + lin]];
-  const int64_t Ss = Bs.size;
-  const int tm = (int)(L / Ss);
-  const int64_t rest = L - (int64_t)tm * Ss;
-  const int j = tm / K1, p = tm - j * K1, l = B.lev[0];
-  const int qs = l == 0 ? 0 : (j << (N - l + 1)) * nq;
-  const int qe = l == 0 ? np1 : ((j + 1) << (N - l + 1)) * nq;
+  int64_t le = f - cum[inst];
+  const int64_t per_s = I.npre[m] * I.gdof[r - 1];
+  const int s = (int)(le / per_s);
+  le -= (int64_t)s * per_s;
+  const int64_t pre0 = le / I.gdof[r - 1];
+  const int64_t eo = le - pre0 * I.gdof[r - 1];
+  const RBlk* ob = R.rblk + I.blk_off[r - 1];
+  const RBlk B = ob[find_rblk(ob, I.nblk[r - 1], eo)];
+  const int64_t rest = eo - B.start, Sb = B.size;
+  const int L = N - B.lsum;
+  int lin = 0, pw = 1;
+  for (int t = r - 2; t >= 0; --t) {
+    lin += B.lev[t] * pw;
+    pw *= (N + 1);
+  }
+  double* g = lds;
+  double* b0 = lds + max_n1;
+  double* b1 = lds + 2 * max_n1;
+  double* M = lds + 3 * max_n1;
   double* xr = a.rws + (int64_t)rhs * rws;
-  const double* __restrict__ in = xr + I.Y_off[m + 1] + ((int64_t)s * I.npre[m + 1] + pre0 * np1) * I.gdof[r - 1] +
-                                  Bs.start + rest;
-  const double* __restrict__ E = R.E + I.E_off;
+  const double* __restrict__ EL = R.EL + I.EL_off;
   const double* __restrict__ w1 = R.w1 + I.w_off;
-  double acc = 0.0;
-  for (int q = qs; q < qe; ++q) acc += w1[q] * E[((int64_t)l * np1 + q) * K1 + p] * in[(int64_t)q * I.gdof[r - 1]];
-  xr[I.Y_off[m] + ((int64_t)s * I.npre[m] + pre0) * I.gdof[r] + eo] = acc;
-}
-
-// final stage over plan chunks: contraction of axis 0 (or pass-through for d = 1) and post-processing
-__global__ __launch_bounds__(CHUNK) void k_rx_final(DevTables T, RTables R, int ninst, int nchunks, int mode,
-                                                    int64_t total, RxArgs a, int64_t rws) {
-  const int c = blockIdx.x, rhs = blockIdx.y, tid = threadIdx.x;
-  const Chunk ch = T.chunks[c];
-  const int inst = ch.inst, s = ch.species;
-  if (a.conv && a.conv[rhs * ninst + inst]) return;
-  const RInst& I = R.inst[inst];
-  const int d = I.d, N = I.N, K1 = I.K1, np1 = I.np1, nq = I.nq;
-  double* xr = a.rws + (int64_t)rhs * rws;
-  double acc = 0.0;
-  const int64_t g = ch.start + tid;
-  if (tid < ch.count) {
-    const int64_t eo = g - I.seg - (int64_t)s * I.ndof;
-    if (d == 1) {
-      acc = xr[I.Y_off[0] + (int64_t)s * I.ndof + eo];
-    } else {
-      const RBlk* bb = R.rblk + I.blk_off[d];
-      const RBlk B = bb[find_rblk(bb, I.nblk[d], eo)];
-      const int64_t L = eo - B.start;
-      int lin = 0;
-      for (int t = 1; t < d; ++t) lin = lin * (N + 1) + B.lev[t];
-      const RBlk Bs = R.rblk[I.blk_off[d - 1] + R.rid[I.id_off[d - 1] + lin]];
-      const int64_t Ss = Bs.size;
-      const int tm = (int)(L / Ss);
-      const int64_t rest = L - (int64_t)tm * Ss;
-      const int j = tm / K1, p = tm - j * K1, l = B.lev[0];
-      const int qs = l == 0 ? 0 : (j << (N - l + 1)) * nq;
-      const int qe = l == 0 ? np1 : ((j + 1) << (N - l + 1)) * nq;
-      const double* __restrict__ in = xr + I.Y_off[1] + (int64_t)s * I.npre[1] * I.gdof[d - 1] + Bs.start + rest;
-      const double* __restrict__ E = R.E + I.E_off;
-      const double* __restrict__ w1 = R.w1 + I.w_off;
-      for (int q = qs; q < qe; ++q) acc += w1[q] * E[((int64_t)l * np1 + q) * K1 + p] * in[(int64_t)q * I.gdof[d - 1]];
-    }
-  }
-  const int64_t gi = (int64_t)rhs * total + g;
-  double g2 = 0.0;
-  if (tid < ch.count) {
-    if (mode == RX_F) {
-      a.F[gi] = acc;
-    } else if (mode == RX_RESID) {
-      a.F[gi] = acc;
-      const double G = a.U[gi] - a.dt2 * acc - a.W[gi];
-      a.Gout[gi] = G;
-      g2 = G * G;
-    } else {
-      a.U[gi] -= acc;
-    }
-  }
-  if (mode == RX_RESID) {
-    for (int off = 32; off > 0; off >>= 1) g2 += __shfl_xor(g2, off, 64);
-    __shared__ double red[CHUNK / 64];
-    if ((tid & 63) == 0) red[tid >> 6] = g2;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int w = 0; w < CHUNK / 64; ++w) t += red[w];
-      a.part[(int64_t)rhs * nchunks + c] = t;
+  load_mats(R, I, M);
+  const double* __restrict__ in = xr + I.Y_off[m + 1] + ((int64_t)s * I.npre[m + 1] + pre0 * np1) * I.gdof[r - 1] + eo;
+  for (int q = threadIdx.x; q < np1; q += blockDim.x) g[q] = w1[q] * in[(int64_t)q * I.gdof[r - 1]];
+  __syncthreads();
+  project_cells(g, EL, N, nq, np1, K1, b0);
+  const int32_t* __restrict__ id = R.rid + I.id_off[r];
+  const RBlk* ib = R.rblk + I.blk_off[r];
+  if (m > 0) {
+    double* out = xr + I.Y_off[m] + ((int64_t)s * I.npre[m] + pre0) * I.gdof[r] + rest;
+    ffwt(b0, b1, N, K1, M, [&](int n, int j, int p, double v) {
+      if (n <= L) out[ib[id[n * pw + lin]].start + (int64_t)(j * K1 + p) * Sb] = v;
+    });
+  } else {
+    const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)s * I.ndof + rest;
+    double g2 = 0.0;
+    ffwt(b0, b1, N, K1, M, [&](int n, int j, int p, double v) {
+      if (n <= L) g2 += finish(a, mode, base + ib[id[n * pw + lin]].start + (int64_t)(j * K1 + p) * Sb, v);
+    });
+    if (mode == RX_RESID) {
+      g2 = block_sum64(g2);
+      if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + f] = g2;
     }
   }
 }
 
-static size_t line_lds_bytes(const RHost* rh) { return (4 * (size_t)rh->max_n1 + 2 * (size_t)rh->max_np1) * sizeof(double); }
-
-static sgdg_status line_lds_attr(const RHost* rh) {
+static sgdg_status set_lds_attrs(const RHost* rh) {
   hipError_t e = hipFuncSetAttribute((const void*)k_rx_line, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)line_lds_bytes(rh));
-  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(line kernel LDS)");
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_rx_expand, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fibre_lds_bytes(rh));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_rx_contract, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fibre_lds_bytes(rh));
+  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(reaction kernels LDS)");
   return SGDG_OK;
 }
 
@@ -478,22 +591,18 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
   const RHost* rh = (const RHost*)plan->rdata;
   const int d = plan->d, ninst = plan->ninst;
   const int nin = mode == RX_CORR ? 2 : 1;
-  for (int m = 0; m + 1 <= d - 1; ++m) {
-    const int64_t n = rh->cum_x[m].back();
-    if (n == 0) continue;
-    hipLaunchKernelGGL(k_rx_expand, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs, (unsigned)nin), dim3(256), 0, s,
-                       rh->dev, ninst, m, plan->total, a, rh->rws);
+  const size_t fl = fibre_lds_bytes(rh), ll = line_lds_bytes(rh);
+  const int64_t nfin = rh->cum_fin.back();
+  for (int m = 0; m + 1 <= d - 1; ++m)
+    hipLaunchKernelGGL(k_rx_expand, dim3((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin),
+                       dim3(RX_THREADS), fl, s, rh->dev, ninst, m, plan->total, a, rh->rws, rh->max_n1);
+  hipLaunchKernelGGL(k_rx_line, dim3((unsigned)rh->cum_line.back(), (unsigned)nrhs), dim3(RX_THREADS), ll, s, rh->dev,
+                     ninst, (int)mode, plan->total, a, rh->rws, rh->max_n1, rh->max_np1, nfin);
+  for (int m = d - 2; m >= 0; --m) {
+    const int64_t nf = m == 0 ? nfin : rh->cum_y[m].back();
+    hipLaunchKernelGGL(k_rx_contract, dim3((unsigned)nf, (unsigned)nrhs), dim3(RX_THREADS), fl, s, rh->dev, ninst, m,
+                       (int)mode, plan->total, a, rh->rws, rh->max_n1, nfin);
   }
-  const size_t lds = line_lds_bytes(rh);
-  hipLaunchKernelGGL(k_rx_line, dim3((unsigned)rh->cum_line.back(), (unsigned)nrhs), dim3(256), lds, s, rh->dev, ninst,
-                     (int)mode, plan->total, a, rh->rws, rh->max_n1, rh->max_np1);
-  for (int m = d - 2; m >= 1; --m) {
-    const int64_t n = rh->cum_y[m].back();
-    hipLaunchKernelGGL(k_rx_contract, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, s, rh->dev,
-                       ninst, m, a, rh->rws);
-  }
-  hipLaunchKernelGGL(k_rx_final, dim3((unsigned)plan->nchunks, (unsigned)nrhs), dim3(CHUNK), 0, s, plan->dev, rh->dev,
-                     ninst, plan->nchunks, (int)mode, plan->total, a, rh->rws);
 }
 
 }  // namespace sgdg
