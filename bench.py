@@ -232,11 +232,13 @@ def main():
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
                        "traffic": traffic_record("apply_kernel_lds", wl.name),
-                       "kernel": "apply_kernel_lds<2,2,PrecF64> (operator sweep, y = A x)",
+                       "kernel": "apply_kernel_lds<2,2,PrecF64,true,void> (operator sweep, y = A x)",
                        "avg_us": avg * 1e6, "bytes_per_launch": nbytes,
                        "launches_per_step": wl.M * 1,
                        "note": "algorithmic bytes = read x + write y, 8 B each per DOF; the working set "
-                               "(166 KB) is cache resident, so this launch is latency bound"}
+                               "(166 KB) is cache resident, so this launch is latency bound; traffic = "
+                               "FETCH_SIZE + WRITE_SIZE per launch scaled by a 256 MiB copy (each XCD's L2 "
+                               "fetches the staged operator tables once)"}
     if not args.no_big:
         log("[bench] out-of-cache sweep d=3 N=16 k=1")
         big = [I.Instance(3, 16, 1, [1.0], I.rx_zeros(1))]

@@ -10,136 +10,233 @@
 // no read-modify-write of y); rows of B_i are stored as cell blocks so a
 // group of K+1 consecutive source entries shares one index decode.
 //
-// Two variants: when a species segment (and its level-block table) fits in
-// LDS, every workgroup first stages the whole segment there and gathers from
-// LDS (small problems are latency bound: the gathers then cost LDS latency,
-// not L2 latency); otherwise the gathers read global memory.
+// Three tiers, chosen per species segment when the plan is built: when the
+// segment, its level-block table and the row tables fit in LDS, every
+// workgroup first stages them there and gathers from LDS (small problems are
+// latency bound: a gather then costs LDS latency, not L2 latency), and when the
+// block values fit as well they are staged too; otherwise the gathers read
+// global memory.  The staged kernels give each output APPLY_G lanes, which
+// quadruples the waves per compute unit for latency hiding.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "internal.h"
 #include "kernels.h"
 
 namespace sgdg {
 
-template <int D, int K, class P>
-__global__ __launch_bounds__(CHUNK) void apply_kernel(DevTables T, const int32_t* __restrict__ list,
-                                                      const typename P::X* __restrict__ x, typename P::Y* __restrict__ y,
-                                                      int64_t xstride, int64_t ystride) {
-  const Chunk ch = T.chunks[list[blockIdx.x]];
-  const int tid = threadIdx.x;
-  if (tid >= ch.count) return;
-  const int64_t g = ch.start + tid;
-  const int64_t rhs = blockIdx.y;
-  const GBlock& B = T.gblk[find_block(T, ch, g)];
-  const InstDev& I = T.inst[B.inst];
-  SrcGlobal<P> xs{x + rhs * xstride, T.blkid + I.blkid_off, T.lstart, I.offset + (int64_t)B.species * I.ndof};
-  RowsGlobal rows{T.cptr, T.src};
-  y[rhs * ystride + g] = (typename P::Y)apply_one<D, K, P>(T, B, I, g, xs, rows);
+// Chunk-level inner products of the Arnoldi form (DotArgs): wl holds the
+// chunk's sweep output (zero past its end); wave w takes basis vectors
+// i = w, w + nwaves, ...; the order of every sum is fixed.
+template <class TV>
+__device__ __forceinline__ void chunk_dots_out(const DotArgs& da, int c, int rhs, const Chunk& ch, const double* wl) {
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int i = wv; i <= da.j; i += nw) {
+    const TV* v = (const TV*)da.V + ((int64_t)i * da.nrhs + rhs) * da.total + ch.start;
+    double s = 0.0;
+    for (int q = ln; q < ch.count; q += 64) s += (double)v[q] * wl[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (ln == 0) da.part[((int64_t)rhs * da.nchunks + c) * da.ld + i] = s;
+  }
 }
 
-// Staged variant: one 64-lane workgroup per quarter chunk, so a small problem
-// spreads over four times as many compute units (the gathers are bound by
-// per-CU load throughput, not by the staging copy).
-constexpr int SUB = 4;
-
-template <int D, int K, class P>
-__global__ __launch_bounds__(CHUNK / SUB) void apply_kernel_lds(DevTables T, const int32_t* __restrict__ list,
-                                                                const typename P::X* __restrict__ x,
-                                                                typename P::Y* __restrict__ y, int64_t xstride,
-                                                                int64_t ystride) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const Chunk ch = T.chunks[list[blockIdx.x / SUB]];
-  const int sub = blockIdx.x % SUB;
+template <int D, int K, class P, class TV>
+__global__ __launch_bounds__(CHUNK) void apply_kernel(DevTables T, const int32_t* __restrict__ list,
+                                                      const typename P::X* __restrict__ x, typename P::Y* __restrict__ y,
+                                                      int64_t xstride, int64_t ystride, DotArgs da) {
+  const int c = list[blockIdx.x];
+  const Chunk ch = T.chunks[c];
   const int tid = threadIdx.x;
+  const int64_t rhs = blockIdx.y;
+  const bool active = tid < ch.count;
+  typename P::Y out = 0;
+  if (active) {
+    const int64_t g = ch.start + tid;
+    const GBlock& B = T.gblk[find_block(T, ch, g)];
+    const InstDev& I = T.inst[B.inst];
+    SrcGlobal<P> xs{x + rhs * xstride, T.blkid + I.blkid_off, T.lstart, I.offset + (int64_t)B.species * I.ndof};
+    RowsGlobal rows{T.cptr, T.src};
+    ValsGlobal<P> vs{P::vals(T)};
+    out = (typename P::Y)apply_one<D, K, 1, P>(T, B, I, g, 0, xs, rows, vs);
+    y[rhs * ystride + g] = out;
+  }
+  if constexpr (!std::is_void_v<TV>) {
+    __shared__ double wl[CHUNK];
+    wl[tid] = active ? (double)out : 0.0;
+    __syncthreads();
+    chunk_dots_out<TV>(da, c, (int)rhs, ch, wl);
+  }
+}
+
+// Staged variant: the workgroup copies the problem's level-block table, the
+// row tables of its distinct 1D operators, its x segment and (STAGE_VALS) the
+// block values into LDS, then APPLY_G lanes share each output element and
+// split its row entries; their partial sums are combined in a fixed order.
+template <int D, int K, class P, bool STAGE_VALS, class TV>
+__global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, const int32_t* __restrict__ list,
+                                                                   const typename P::X* __restrict__ x,
+                                                                   typename P::Y* __restrict__ y, int64_t xstride,
+                                                                   int64_t ystride, DotArgs da) {
+  using V = typename P::V;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int cid = list[blockIdx.x];
+  const Chunk ch = T.chunks[cid];
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
   const int64_t rhs = blockIdx.y;
   const InstDev& I = T.inst[ch.inst];
   const int64_t seg = I.offset + (int64_t)ch.species * I.ndof;
   int ntab = 1;
   for (int m = 0; m < D; ++m) ntab *= (I.N + 1);
   int32_t* bst = (int32_t*)smem;
-  for (int i = tid; i < ntab; i += blockDim.x) {
+  for (int i = tid; i < ntab; i += nthr) {
     const int b = T.blkid[I.blkid_off + i];
     bst[i] = b >= 0 ? (int32_t)T.lstart[b] : -1;
   }
   // row pointers and source cells of each distinct 1D operator of the instance
+  // (directions sharing an operator share its LDS copy; every array index
+  // below is a compile-time constant after unrolling, so the pointer tables
+  // stay in registers)
   RowsLds rows;
+  ValsLds<P> vl;
+  unsigned dup = 0;  // bit i: direction i reuses an earlier direction's operator
   int32_t* rp = bst + ntab;
+#pragma unroll
   for (int i = 0; i < D; ++i) {
     const BCsr bc = T.bcsr[I.bcsr_off[i]];
-    int same = -1;
+#pragma unroll
     for (int i2 = 0; i2 < i; ++i2)
-      if (T.bcsr[I.bcsr_off[i2]].cptr_off == bc.cptr_off) same = i2;
-    if (same >= 0) {
-      rows.cptr[i] = rows.cptr[same];
-      rows.src[i] = rows.src[same];
-      continue;
-    }
+      if (!((dup >> i) & 1u) && T.bcsr[I.bcsr_off[i2]].cptr_off == bc.cptr_off) {
+        rows.cptr[i] = rows.cptr[i2];
+        rows.src[i] = rows.src[i2];
+        dup |= 1u << i;
+      }
+    if ((dup >> i) & 1u) continue;
     rows.cptr[i] = rp;
-    for (int t = tid; t <= bc.ncell; t += blockDim.x) rp[t] = T.cptr[bc.cptr_off + t];
+    for (int t = tid; t <= bc.ncell; t += nthr) rp[t] = T.cptr[bc.cptr_off + t];
     rp += bc.ncell + 1;
     rows.src[i] = rp;
-    for (int t = tid; t < bc.nnzb; t += blockDim.x) rp[t] = T.src[bc.src_off + t];
+    for (int t = tid; t < bc.nnzb; t += nthr) rp[t] = T.src[bc.src_off + t];
     rp += bc.nnzb;
   }
-  typename P::X* xl = (typename P::X*)(smem + ((((unsigned char*)rp - smem) + 15) & ~15));
+  unsigned char* cur = smem + ((((unsigned char*)rp - smem) + 15) & ~15);
+  typename P::X* xl = (typename P::X*)cur;
   const typename P::X* __restrict__ xg = x + rhs * xstride + seg;
-  for (int64_t i = tid; i < I.ndof; i += blockDim.x) xl[i] = xg[i];
-  __syncthreads();
-  const int e = sub * (CHUNK / SUB) + tid;
-  if (e >= ch.count) return;
-  const int64_t g = ch.start + e;
-  const GBlock& B = T.gblk[find_block(T, ch, g)];
-  SrcLds<P> xs{xl, bst};
-  y[rhs * ystride + g] = (typename P::Y)apply_one<D, K, P>(T, B, I, g, xs, rows);
-}
-
-template <int D, int K, class P>
-static void launch_kind(const sgdg_plan* plan, int nrhs, const void* x, void* y, int64_t xs, int64_t ys,
-                        hipStream_t s) {
-  const int kg = K * 2 + 0, ks = K * 2 + 1;
-  if (!plan->chunk_lists[kg].empty())
-    hipLaunchKernelGGL((apply_kernel<D, K, P>), dim3((unsigned)plan->chunk_lists[kg].size(), (unsigned)nrhs),
-                       dim3(CHUNK), 0, s, plan->dev, plan->dev_chunk_lists[kg], (const typename P::X*)x,
-                       (typename P::Y*)y, xs, ys);
-  if (!plan->chunk_lists[ks].empty()) {
-    const int lds = plan->list_lds[ks];
-    static std::atomic<int> attr_set{0};
-    if (attr_set.load() < lds) {
-      hipFuncSetAttribute((const void*)apply_kernel_lds<D, K, P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          APPLY_LDS_BYTES);
-      attr_set.store(APPLY_LDS_BYTES);
+  for (int64_t i = tid; i < I.ndof; i += nthr) xl[i] = xg[i];
+  cur += (I.ndof * (int64_t)sizeof(typename P::X) + 15) & ~15;
+  if constexpr (STAGE_VALS) {
+    const V* __restrict__ vals = P::vals(T);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const BCsr bc = T.bcsr[I.bcsr_off[i]];
+#pragma unroll
+      for (int i2 = 0; i2 < i; ++i2)
+        if (T.bcsr[I.bcsr_off[i2]].cptr_off == bc.cptr_off) vl.v[i] = vl.v[i2];
+      if ((dup >> i) & 1u) continue;
+      V* dst = (V*)cur;
+      const int64_t nv = (int64_t)bc.nnzb * (K + 1) * (K + 1);
+      for (int64_t t = tid; t < nv; t += nthr) dst[t] = vals[bc.val_off + t];
+      vl.v[i] = dst;
+      cur += (nv * (int64_t)sizeof(V) + 15) & ~15;
     }
-    hipLaunchKernelGGL((apply_kernel_lds<D, K, P>),
-                       dim3((unsigned)plan->chunk_lists[ks].size() * SUB, (unsigned)nrhs), dim3(CHUNK / SUB), lds, s,
-                       plan->dev, plan->dev_chunk_lists[ks], (const typename P::X*)x, (typename P::Y*)y, xs, ys);
+  }
+  __syncthreads();
+  const int e = tid / APPLY_G;
+  const int lane = tid % APPLY_G;
+  const bool active = e < ch.count;
+  typename P::A acc = 0;
+  if (active) {
+    const int64_t g = ch.start + e;
+    const GBlock& B = T.gblk[find_block(T, ch, g)];
+    SrcLds<P> xs{xl, bst};
+    if constexpr (STAGE_VALS)
+      acc = apply_one<D, K, APPLY_G, P>(T, B, I, g, lane, xs, rows, vl);
+    else
+      acc = apply_one<D, K, APPLY_G, P>(T, B, I, g, lane, xs, rows, ValsGlobal<P>{P::vals(T)});
+  }
+  // fixed-order combination of the lane partials: (l0 + l1) + (l2 + l3)
+#pragma unroll
+  for (int o = 1; o < APPLY_G; o <<= 1) acc += __shfl_xor(acc, o, APPLY_G);
+  const typename P::Y out = (typename P::Y)acc;
+  if (active && lane == 0) y[rhs * ystride + ch.start + e] = out;
+  if constexpr (!std::is_void_v<TV>) {
+    __syncthreads();  // the staged tables are dead; reuse the LDS for the chunk output
+    double* wl = (double*)smem;
+    if (lane == 0) wl[e] = active ? (double)out : 0.0;
+    __syncthreads();
+    chunk_dots_out<TV>(da, cid, (int)rhs, ch, wl);
   }
 }
 
-template <int D, class P>
+template <int D, int K, class P, bool SV, class TV>
+static void launch_staged(const sgdg_plan* plan, int kind, int nrhs, const void* x, void* y, int64_t xs, int64_t ys,
+                          const DotArgs& da, hipStream_t s) {
+  // the Arnoldi form reuses the LDS for one chunk of output (CHUNK doubles)
+  const int lds = std::max(plan->list_lds[kind], std::is_void_v<TV> ? 0 : (int)(CHUNK * sizeof(double)));
+  static std::atomic<int> attr_set{0};
+  if (attr_set.load() < lds) {
+    hipFuncSetAttribute((const void*)apply_kernel_lds<D, K, P, SV, TV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        APPLY_LDS_BYTES);
+    attr_set.store(APPLY_LDS_BYTES);
+  }
+  hipLaunchKernelGGL((apply_kernel_lds<D, K, P, SV, TV>),
+                     dim3((unsigned)plan->chunk_lists[kind].size(), (unsigned)nrhs), dim3(CHUNK * APPLY_G), lds, s,
+                     plan->dev, plan->dev_chunk_lists[kind], (const typename P::X*)x, (typename P::Y*)y, xs, ys, da);
+}
+
+template <int D, int K, class P, class TV>
+static void launch_kind(const sgdg_plan* plan, int nrhs, const void* x, void* y, int64_t xs, int64_t ys,
+                        const DotArgs& da, hipStream_t s) {
+  const int k0 = K * SWEEP_TIERS;
+  if (!plan->chunk_lists[k0].empty())
+    hipLaunchKernelGGL((apply_kernel<D, K, P, TV>), dim3((unsigned)plan->chunk_lists[k0].size(), (unsigned)nrhs),
+                       dim3(CHUNK), 0, s, plan->dev, plan->dev_chunk_lists[k0], (const typename P::X*)x,
+                       (typename P::Y*)y, xs, ys, da);
+  if (!plan->chunk_lists[k0 + 1].empty()) launch_staged<D, K, P, false, TV>(plan, k0 + 1, nrhs, x, y, xs, ys, da, s);
+  if (!plan->chunk_lists[k0 + 2].empty()) launch_staged<D, K, P, true, TV>(plan, k0 + 2, nrhs, x, y, xs, ys, da, s);
+}
+
+template <int D, class P, class TV>
 static void launch_apply_d(const sgdg_plan* plan, int nrhs, const void* x, void* y, int64_t xs, int64_t ys,
-                           hipStream_t s) {
-  launch_kind<D, 1, P>(plan, nrhs, x, y, xs, ys, s);
-  launch_kind<D, 2, P>(plan, nrhs, x, y, xs, ys, s);
-  launch_kind<D, 3, P>(plan, nrhs, x, y, xs, ys, s);
+                           const DotArgs& da, hipStream_t s) {
+  launch_kind<D, 1, P, TV>(plan, nrhs, x, y, xs, ys, da, s);
+  launch_kind<D, 2, P, TV>(plan, nrhs, x, y, xs, ys, da, s);
+  launch_kind<D, 3, P, TV>(plan, nrhs, x, y, xs, ys, da, s);
+}
+
+template <class P, class TV>
+static void launch_any(const sgdg_plan* plan, int nrhs, const void* x, void* y, int64_t xs, int64_t ys,
+                       const DotArgs& da, hipStream_t s) {
+  switch (plan->d) {
+    case 1: launch_apply_d<1, P, TV>(plan, nrhs, x, y, xs, ys, da, s); break;
+    case 2: launch_apply_d<2, P, TV>(plan, nrhs, x, y, xs, ys, da, s); break;
+    case 3: launch_apply_d<3, P, TV>(plan, nrhs, x, y, xs, ys, da, s); break;
+    case 4: launch_apply_d<4, P, TV>(plan, nrhs, x, y, xs, ys, da, s); break;
+    case 5: launch_apply_d<5, P, TV>(plan, nrhs, x, y, xs, ys, da, s); break;
+    case 6: launch_apply_d<6, P, TV>(plan, nrhs, x, y, xs, ys, da, s); break;
+  }
 }
 
 template <class P>
 void launch_apply(const sgdg_plan* plan, int nrhs, const void* x, void* y, int64_t xs, int64_t ys, hipStream_t s) {
-  switch (plan->d) {
-    case 1: launch_apply_d<1, P>(plan, nrhs, x, y, xs, ys, s); break;
-    case 2: launch_apply_d<2, P>(plan, nrhs, x, y, xs, ys, s); break;
-    case 3: launch_apply_d<3, P>(plan, nrhs, x, y, xs, ys, s); break;
-    case 4: launch_apply_d<4, P>(plan, nrhs, x, y, xs, ys, s); break;
-    case 5: launch_apply_d<5, P>(plan, nrhs, x, y, xs, ys, s); break;
-    case 6: launch_apply_d<6, P>(plan, nrhs, x, y, xs, ys, s); break;
-  }
+  launch_any<P, void>(plan, nrhs, x, y, xs, ys, DotArgs{}, s);
+}
+
+template <class P, class TV>
+void launch_apply_dots(const sgdg_plan* plan, int nrhs, const void* x, void* y, const DotArgs& da, hipStream_t s) {
+  launch_any<P, TV>(plan, nrhs, x, y, plan->total, plan->total, da, s);
 }
 
 template void launch_apply<PrecF64>(const sgdg_plan*, int, const void*, void*, int64_t, int64_t, hipStream_t);
 template void launch_apply<PrecF32>(const sgdg_plan*, int, const void*, void*, int64_t, int64_t, hipStream_t);
 template void launch_apply<PrecBF16>(const sgdg_plan*, int, const void*, void*, int64_t, int64_t, hipStream_t);
+template void launch_apply_dots<PrecF64, double>(const sgdg_plan*, int, const void*, void*, const DotArgs&, hipStream_t);
+template void launch_apply_dots<PrecF32, float>(const sgdg_plan*, int, const void*, void*, const DotArgs&, hipStream_t);
+template void launch_apply_dots<PrecBF16, float>(const sgdg_plan*, int, const void*, void*, const DotArgs&, hipStream_t);
 
 }  // namespace sgdg
 

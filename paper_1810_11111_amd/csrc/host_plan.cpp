@@ -319,27 +319,33 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
   }
   p->nchunks = (int32_t)p->chunks.size();
   p->nblocks = (int32_t)p->gblk.size();
-  // sweep kinds: k and whether the species segment plus its level-block table
-  // fit the LDS budget of the staged sweep
+  // sweep kinds: k and how much of the problem fits the LDS budget of the
+  // staged sweeps (block table + row tables + x segment, then block values)
   const int xbytes = prec == SGDG_FP64 ? 8 : (prec == SGDG_FP32_SWEEP ? 4 : 2);
-  p->chunk_lists.assign(2 * (SGDG_MAX_K + 1), {});
-  p->list_lds.assign(2 * (SGDG_MAX_K + 1), 0);
+  const int vbytes = prec == SGDG_FP64 ? 8 : 4;
+  p->chunk_lists.assign(SWEEP_TIERS * (SGDG_MAX_K + 1), {});
+  p->list_lds.assign(SWEEP_TIERS * (SGDG_MAX_K + 1), 0);
+  auto al16 = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
   for (int32_t c = 0; c < p->nchunks; ++c) {
     const HostInstance& hi = p->inst[p->chunks[c].inst];
     int64_t ntab = 1;
     for (int m = 0; m < d; ++m) ntab *= (hi.desc.n + 1);
-    // block table, row pointers and source cells of each distinct 1D operator, x segment
-    int64_t rows = 0;
+    // block table, row pointers and source cells of each distinct 1D operator
+    int64_t rows = 0, vals = 0;
     for (int m = 0; m < d; ++m) {
       bool seen = false;
       for (int m2 = 0; m2 < m; ++m2) seen = seen || hi.dir_tab[m2] == hi.dir_tab[m];
-      if (!seen) rows += (int64_t)p->ops[hi.dir_tab[m]].cptr.size() + (int64_t)p->ops[hi.dir_tab[m]].src.size();
+      if (seen) continue;
+      const Op1D& op = p->ops[hi.dir_tab[m]];
+      rows += (int64_t)op.cptr.size() + (int64_t)op.src.size();
+      vals += al16((int64_t)op.val.size() * vbytes);
     }
-    const int64_t lds = (((ntab + rows) * 4 + 15) & ~(int64_t)15) + hi.ndof * xbytes;
-    const int staged = lds <= APPLY_LDS_BYTES_HOST ? 1 : 0;
-    const int kind = hi.desc.k * 2 + staged;
+    const int64_t lds1 = al16((ntab + rows) * 4) + al16(hi.ndof * xbytes);
+    const int64_t lds2 = lds1 + vals;
+    const int tier = lds2 <= APPLY_LDS_BYTES_HOST ? 2 : (lds1 <= APPLY_LDS_BYTES_HOST ? 1 : 0);
+    const int kind = hi.desc.k * SWEEP_TIERS + tier;
     p->chunk_lists[kind].push_back(c);
-    if (staged) p->list_lds[kind] = std::max(p->list_lds[kind], (int)lds);
+    if (tier > 0) p->list_lds[kind] = std::max(p->list_lds[kind], (int)(tier == 2 ? lds2 : lds1));
   }
 
   sgdg_status st = SGDG_OK;

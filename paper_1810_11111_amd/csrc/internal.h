@@ -112,8 +112,9 @@ struct sgdg_plan {
   std::vector<sgdg::Op1D> ops;
   std::vector<sgdg::GBlock> gblk;
   std::vector<sgdg::Chunk> chunks;
-  // chunk ids grouped by sweep kind: index k*2 + staged (staged: the species
-  // segment and its block table fit the LDS budget of the staged sweep)
+  // chunk ids grouped by sweep kind: index k * SWEEP_TIERS + tier, tier 0 =
+  // gathers from global memory, 1 = x segment and row tables staged in LDS,
+  // 2 = block values staged as well
   std::vector<std::vector<int32_t>> chunk_lists;
   std::vector<int32_t*> dev_chunk_lists;
   std::vector<int> list_lds;  // dynamic LDS bytes of the staged lists
@@ -128,7 +129,9 @@ struct sgdg_plan {
 namespace sgdg {
 
 constexpr int CHUNK = 256;
-constexpr int APPLY_LDS_BYTES_HOST = 128 * 1024;  // same budget as the staged sweep kernel
+constexpr int APPLY_LDS_BYTES_HOST = 160 * 1024;  // same budget as the staged sweep kernels
+constexpr int SWEEP_TIERS = 3;
+constexpr int APPLY_G = 4;  // lanes per output element in the staged sweeps
 
 // error reporting
 sgdg_status fail(sgdg_status st, const std::string& msg);

@@ -90,13 +90,27 @@ struct RowsLds {
   __device__ __forceinline__ int sc(const BCsr& bc, int i, int e) const { return src[i][e]; }
 };
 
-// y_g = (A x)_g for one output element g of a plan vector.  Returns the
-// accumulated value (already scaled by -D_s).  Rows of B_i are walked in
-// ascending source cell order, so the block base of a source level is looked
-// up once per level, not per entry.
-template <int D, int K, class P, class Src, class Rows>
+// Block values of the 1D operators: global table, or each direction's table
+// staged in LDS.
+template <class P>
+struct ValsGlobal {
+  const typename P::V* __restrict__ v;
+  __device__ __forceinline__ const typename P::V* row(const BCsr& bc, int i) const { return v + bc.val_off; }
+};
+template <class P>
+struct ValsLds {
+  const typename P::V* v[SGDG_MAX_D];
+  __device__ __forceinline__ const typename P::V* row(const BCsr& bc, int i) const { return v[i]; }
+};
+
+// Partial y_g = (A x)_g for one output element g of a plan vector, from the
+// row entries e = e0 + lane, e0 + lane + G, ... of every direction (G lanes
+// share one output; the caller sums the G partials).  Already scaled by
+// -D_s.  Rows of B_i are walked in ascending source cell order, so the block
+// base of a source level is looked up once per level, not per entry.
+template <int D, int K, int G, class P, class Src, class Rows, class Vals>
 __device__ __forceinline__ typename P::A apply_one(const DevTables& T, const GBlock& B, const InstDev& I, int64_t g,
-                                                   const Src& xs, const Rows& rows) {
+                                                   int lane, const Src& xs, const Rows& rows, const Vals& vs) {
   using A = typename P::A;
   using V = typename P::V;
   constexpr int K1 = K + 1;
@@ -125,7 +139,6 @@ __device__ __forceinline__ typename P::A apply_one(const DevTables& T, const GBl
   int linall = 0;
   for (int m = 0; m < D; ++m) linall += lev[m] * I.pow[m];
 
-  const V* __restrict__ vals = P::vals(T);
   A acc = 0;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
@@ -142,11 +155,11 @@ __device__ __forceinline__ typename P::A apply_one(const DevTables& T, const GBl
     const BCsr bc = T.bcsr[I.bcsr_off[i]];
     const int e0 = rows.rp(bc, i, tcell);
     const int e1 = rows.rp(bc, i, tcell + 1);
-    const V* __restrict__ vrow = vals + bc.val_off + pt * K1;
+    const V* __restrict__ vrow = vs.row(bc, i) + pt * K1;
     int cur_lc = -1;
     int64_t bbase = 0;
     int extc = K1;
-    for (int e = e0; e < e1; ++e) {
+    for (int e = e0 + lane; e < e1; e += G) {
       const int sc = rows.sc(bc, i, e);
       if (sc >= lim) break;
       const int lc = sc == 0 ? 0 : 32 - __clz(sc);
@@ -165,10 +178,24 @@ __device__ __forceinline__ typename P::A apply_one(const DevTables& T, const GBl
   return acc * (A)(-I.D[B.species]);
 }
 
-// LDS budget of the staged sweep (bytes for the x segment and the block table).
+// LDS budget of the staged sweeps (block table, row tables, x segment and,
+// when they fit, the block values).
 constexpr int APPLY_LDS_BYTES = APPLY_LDS_BYTES_HOST;
 
 template <class P>
 void launch_apply(const sgdg_plan* plan, int nrhs, const void* x, void* y, int64_t xs, int64_t ys, hipStream_t s);
+
+// Arnoldi form of the sweep: after y = A x of a chunk, the same workgroup
+// writes the chunk's partial inner products <v_i, y>, i = 0..j, of the basis
+// vectors V (element type TV, [i][rhs][total]) to part[(rhs * nchunks + chunk)
+// * ld + i].
+struct DotArgs {
+  const void* V;
+  double* part;
+  int32_t j, ld, nchunks, nrhs;
+  int64_t total;
+};
+template <class P, class TV>
+void launch_apply_dots(const sgdg_plan* plan, int nrhs, const void* x, void* y, const DotArgs& da, hipStream_t s);
 
 }  // namespace sgdg

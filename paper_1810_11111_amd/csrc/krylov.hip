@@ -10,8 +10,8 @@
 // classical Gram-Schmidt applied twice (rounding-level equivalent of the
 // modified form), which needs three device-wide reductions per step instead
 // of j+1; each reduction is a kernel boundary (cheap inside a captured graph):
-//   sweep   : w = A v_j (the same kernel as sg_dg_apply)
-//   k_dots1 : per-chunk <v_i, w>
+//   sweep   : w = A v_j (the sg_dg_apply kernels) and, in the same
+//             workgroups, the per-chunk partials <v_i, w>
 //   k_upd1  : h1 = sum of partials, w1 = w - V h1, per-chunk <v_i, w1>, |w1|^2
 //   k_upd2  : h2, w2 = w1 - V h2, |w2|^2 = |w1|^2 - |h2|^2, v_{j+1} = w2 / |w2|
 // Partial sums are reduced in a fixed order, so every workgroup of a problem
@@ -153,20 +153,6 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
   __syncthreads();
 }
 
-// per-chunk partials <v_i, w>, i <= j, of the sweep output w = A v_j
-template <class TV, class TY>
-__global__ __launch_bounds__(CHUNK) void k_dots1(DevTables T, int nchunks, int ninst, int64_t total, int M, int j,
-                                                 KrylovWs ws) {
-  const int c = blockIdx.x, rhs = blockIdx.y, tid = threadIdx.x, nrhs = gridDim.y;
-  const Chunk ch = T.chunks[c];
-  if (ws.done[prob_of(rhs, ninst, ch)]) return;
-  __shared__ double wl[CHUNK], red[CHUNK], out[SGDG_MAX_M + 2];
-  wl[tid] = tid < ch.count ? (double)((const TY*)ws.wy)[rhs * total + ch.start + tid] : 0.0;
-  __syncthreads();
-  chunk_dots<TV>(ws, j + 1, false, nrhs, rhs, total, ch.start, ch.count, wl, red, out);
-  if (tid <= j) ws.part1[((int64_t)rhs * nchunks + c) * (M + 2) + tid] = out[tid];
-}
-
 // h1 = <V, w>;  w1 = w - V h1;  partials <v_i, w1> and |w1|^2.
 template <class TV, class TY>
 __global__ __launch_bounds__(CHUNK) void k_upd1(DevTables T, int nchunks, int ninst, int64_t total, int M, int j,
@@ -242,29 +228,31 @@ __global__ __launch_bounds__(CHUNK) void k_upd2(DevTables T, int nchunks, int ni
 // [m/m] Pade coefficients b_j = (2m-j)! m! / ((2m)! j! (m-j)!) from the
 // ratio b_j / b_{j-1} = (m-j+1) / (j (2m-j+1)).
 constexpr int MM = SGDG_MAX_M;
+constexpr int LDM = MM + 2;  // row stride of the LDS matrices: 16 consecutive rows hit distinct banks
 
-// C = A B (m x m in LDS, leading dimension MM); each thread owns a 2x2 tile.
-// Rows/columns at index m of an odd m are computed from unused LDS and never
-// stored.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// C = A B for m x m matrices in LDS (row stride LDM) on the FP64 matrix
+// cores: the matrices are zero-padded to mp = 16 ceil(m / 16) and every wave
+// computes 16 x 16 output tiles with v_mfma_f64_16x16x4f64 (A fragment: lane l
+// holds A[l % 16][l / 16], B fragment: B[l / 16][l % 16], accumulator element v
+// of lane l is C[4 v + l / 16][l % 16], as measured on gfx950).  The padding of A and B must be zero;
+// the padding of C is written as zero.  C must not alias A or B.
 __device__ void mat_mul(double* C, const double* A, const double* B, int m) {
-  const int nt = (m + 1) >> 1;
-  for (int t = threadIdx.x; t < nt * nt; t += blockDim.x) {
-    const int r = 2 * (t / nt), c = 2 * (t % nt);
-    double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
-    for (int q = 0; q < m; ++q) {
-      const double a0 = A[r * MM + q], a1 = A[(r + 1) * MM + q];
-      const double2 bq = *reinterpret_cast<const double2*>(&B[q * MM + c]);
-      c00 += a0 * bq.x;
-      c01 += a0 * bq.y;
-      c10 += a1 * bq.x;
-      c11 += a1 * bq.y;
+  const int mp = (m + 15) & ~15;
+  const int nt = mp >> 4;
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < nt * nt; t += nw) {
+    const int ti = (t / nt) << 4, tj = (t % nt) << 4;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < mp; k0 += 4) {
+      const double a = A[(ti + li) * LDM + k0 + lk];
+      const double b = B[(k0 + lk) * LDM + tj + li];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
-    C[r * MM + c] = c00;
-    if (c + 1 < m) C[r * MM + c + 1] = c01;
-    if (r + 1 < m) {
-      C[(r + 1) * MM + c] = c10;
-      if (c + 1 < m) C[(r + 1) * MM + c + 1] = c11;
-    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) C[(ti + 4 * v + lk) * LDM + tj + li] = acc[v];
   }
   __syncthreads();
 }
@@ -284,8 +272,8 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
   const int m = ws.m[p];
   const double beta = ws.beta[p];
   const double* Hp = ws.H + (int64_t)p * (M + 1) * M;
-  __shared__ __align__(16) double Am[MM * MM], A2[MM * MM], A4[MM * MM], A6[MM * MM], Tm[MM * MM], Um[MM * MM],
-      Vm[MM * MM];
+  __shared__ __align__(16) double Am[MM * LDM], A2[MM * LDM], A4[MM * LDM], A6[MM * LDM], Tm[MM * LDM],
+      Um[MM * LDM], Vm[MM * LDM];
   __shared__ double b[14], fac[MM];
   __shared__ int deg_s, s_s, piv_s;
   __shared__ double nrm_s;
@@ -298,16 +286,19 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
     }
     return;
   }
-  // only the Hessenberg part of H is ever written (rows <= column + 1)
-  for (int e = tid; e < m * m; e += blockDim.x) {
-    const int r = e / m, c = e - r * m;
-    Am[r * MM + c] = r <= c + 1 ? hstep * Hp[r * M + c] : 0.0;
+  // only the Hessenberg part of H is ever written (rows <= column + 1); every
+  // work matrix starts zero on the padded square used by mat_mul
+  const int mp = (m + 15) & ~15;
+  for (int e = tid; e < mp * mp; e += blockDim.x) {
+    const int r = e / mp, c = e - r * mp, q = r * LDM + c;
+    Am[q] = (r < m && c < m && r <= c + 1) ? hstep * Hp[r * M + c] : 0.0;
+    A2[q] = A4[q] = A6[q] = Tm[q] = Um[q] = Vm[q] = 0.0;
   }
   __syncthreads();
   // ||A||_1: column sums in parallel, maximum by thread 0
   if (tid < m) {
     double cs = 0.0;
-    for (int r = 0; r < m; ++r) cs += fabs(Am[r * MM + tid]);
+    for (int r = 0; r < m; ++r) cs += fabs(Am[r * LDM + tid]);
     fac[tid] = cs;
   }
   __syncthreads();
@@ -334,7 +325,7 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
   const int deg = deg_s, s = s_s;
   if (s > 0) {
     const double sc = ldexp(1.0, -s);
-    for (int e = tid; e < m * m; e += blockDim.x) Am[(e / m) * MM + e % m] *= sc;
+    for (int e = tid; e < m * m; e += blockDim.x) Am[(e / m) * LDM + e % m] *= sc;
     __syncthreads();
   }
   mat_mul(A2, Am, Am, m);
@@ -344,20 +335,20 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
     // U = A [A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I]
     // V =    A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
     for (int e = tid; e < m * m; e += blockDim.x) {
-      const int q = (e / m) * MM + e % m;
+      const int q = (e / m) * LDM + e % m;
       Tm[q] = b[13] * A6[q] + b[11] * A4[q] + b[9] * A2[q];
     }
     __syncthreads();
     mat_mul(Um, A6, Tm, m);
     for (int e = tid; e < m * m; e += blockDim.x) {
-      const int r = e / m, c = e % m, q = r * MM + c;
+      const int r = e / m, c = e % m, q = r * LDM + c;
       Um[q] += b[7] * A6[q] + b[5] * A4[q] + b[3] * A2[q] + (r == c ? b[1] : 0.0);
       Tm[q] = b[12] * A6[q] + b[10] * A4[q] + b[8] * A2[q];
     }
     __syncthreads();
     mat_mul(Vm, A6, Tm, m);
     for (int e = tid; e < m * m; e += blockDim.x) {
-      const int r = e / m, c = e % m, q = r * MM + c;
+      const int r = e / m, c = e % m, q = r * LDM + c;
       Vm[q] += b[6] * A6[q] + b[4] * A4[q] + b[2] * A2[q] + (r == c ? b[0] : 0.0);
       Tm[q] = Um[q];
     }
@@ -367,7 +358,7 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
     // U = A (sum over odd j of b_j A^(j-1)), V = sum over even j of b_j A^j, powers A2, A4, A6, A8 = A4 A4
     if (deg == 9) mat_mul(Vm, A4, A4, m);  // A8 kept in Vm until consumed
     for (int e = tid; e < m * m; e += blockDim.x) {
-      const int r = e / m, c = e % m, q = r * MM + c;
+      const int r = e / m, c = e % m, q = r * LDM + c;
       const double I = (r == c) ? 1.0 : 0.0;
       double u = b[1] * I + b[3] * A2[q];
       double v = b[0] * I + b[2] * A2[q];
@@ -389,82 +380,77 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
     __syncthreads();
     mat_mul(Um, Am, Tm, m);
     for (int e = tid; e < m * m; e += blockDim.x) {
-      const int q = (e / m) * MM + e % m;
+      const int q = (e / m) * LDM + e % m;
       Vm[q] = A2[q];
     }
     __syncthreads();
   }
-  // solve (V - U) R = (V + U) by Gaussian elimination with partial pivoting
-  double* P = A4;
-  double* Q = A6;
+  // solve (V - U) R = (V + U) by Gauss-Jordan elimination with partial
+  // pivoting on the augmented rows [P | Q]; one step per column, written to a
+  // second buffer pair so that every step needs a single barrier.  Columns of
+  // P at or left of the pivot column are not carried (they are unit vectors).
+  double* P0 = A4;
+  double* Q0 = A6;
+  double* P1 = Tm;
+  double* Q1 = A2;
   for (int e = tid; e < m * m; e += blockDim.x) {
-    const int q = (e / m) * MM + e % m;
-    P[q] = Vm[q] - Um[q];
-    Q[q] = Vm[q] + Um[q];
+    const int q = (e / m) * LDM + e % m;
+    P0[q] = Vm[q] - Um[q];
+    Q0[q] = Vm[q] + Um[q];
   }
   __syncthreads();
   for (int k = 0; k < m; ++k) {
-    if (tid < 64) {
-      // pivot: largest |P[r][k]|, r >= k (lowest row on ties), by a wave reduction (m <= 48)
-      const int r = k + tid;
-      double best = r < m ? fabs(P[r * MM + k]) : -1.0;
-      int piv = r < m ? r : 1 << 30;
+    // pivot: largest |P[r][k]| for r >= k, lowest row on ties; every wave
+    // finds it on its own (lane r holds row r, m <= 64), so no extra barrier
+    int piv;
+    {
+      const int r = k + (tid & 63);
+      double best = r < m ? fabs(P0[r * LDM + k]) : -1.0;
+      int pr = r < m ? r : 1 << 30;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         const double ob = __shfl_xor(best, off, 64);
-        const int op = __shfl_xor(piv, off, 64);
-        if (ob > best || (ob == best && op < piv)) {
+        const int op = __shfl_xor(pr, off, 64);
+        if (ob > best || (ob == best && op < pr)) {
           best = ob;
-          piv = op;
+          pr = op;
         }
       }
-      if (tid == 0) piv_s = piv;
+      piv = pr;
+    }
+    const double inv = 1.0 / P0[piv * LDM + k];
+    const int ncp = m - k - 1, nc = ncp + m;
+    for (int e = tid; e < m * nc; e += blockDim.x) {
+      const int r = e / nc, cc = e - r * nc;
+      const bool inP = cc < ncp;
+      const int c = inP ? k + 1 + cc : cc - ncp;
+      const double* X0 = inP ? P0 : Q0;
+      double* X1 = inP ? P1 : Q1;
+      const int sr = r == k ? piv : (r == piv ? k : r);  // row k and the pivot row trade places
+      const double pv = X0[piv * LDM + c] * inv;
+      X1[r * LDM + c] = r == k ? pv : X0[sr * LDM + c] - P0[sr * LDM + k] * pv;
     }
     __syncthreads();
-    const int piv = piv_s;
-    if (piv != k) {
-      for (int c = tid; c < m; c += blockDim.x) {
-        double t = P[k * MM + c];
-        P[k * MM + c] = P[piv * MM + c];
-        P[piv * MM + c] = t;
-        t = Q[k * MM + c];
-        Q[k * MM + c] = Q[piv * MM + c];
-        Q[piv * MM + c] = t;
-      }
-      __syncthreads();
-    }
-    for (int r = k + 1 + tid; r < m; r += blockDim.x) fac[r] = P[r * MM + k] / P[k * MM + k];
-    __syncthreads();
-    const int rows = m - k - 1;
-    for (int e = tid; e < rows * m; e += blockDim.x) {
-      const int r = k + 1 + e / m, c = e % m;
-      const double f = fac[r];
-      if (c > k) P[r * MM + c] -= f * P[k * MM + c];
-      Q[r * MM + c] -= f * Q[k * MM + c];
-    }
-    __syncthreads();
-  }
-  for (int k = m - 1; k >= 0; --k) {
-    for (int c = tid; c < m; c += blockDim.x) {
-      double acc = Q[k * MM + c];
-      for (int r = k + 1; r < m; ++r) acc -= P[k * MM + r] * Q[r * MM + c];
-      Q[k * MM + c] = acc / P[k * MM + k];
-    }
-    __syncthreads();
+    double* t = P0;
+    P0 = P1;
+    P1 = t;
+    t = Q0;
+    Q0 = Q1;
+    Q1 = t;
   }
   // square s times
-  double* R = Q;
-  double* Rn = Tm;
+  double* R = Q0;
+  double* Rn = Um;
   for (int q = 0; q < s; ++q) {
     mat_mul(Rn, R, R, m);
     double* t = R;
     R = Rn;
     Rn = t;
   }
-  for (int i = tid; i < M; i += blockDim.x) ws.y[(int64_t)p * M + i] = i < m ? R[i * MM] : 0.0;
+  for (int i = tid; i < M; i += blockDim.x) ws.y[(int64_t)p * M + i] = i < m ? R[i * LDM] : 0.0;
   if (stats && tid == 0) {
     bool fin = isfinite(beta);
-    for (int i = 0; i < m; ++i) fin = fin && isfinite(R[i * MM]);
+    for (int i = 0; i < m; ++i) fin = fin && isfinite(R[i * LDM]);
     stats[p].krylov_m = m;
     stats[p].h_next = Hp[m * M + (m - 1)];
     stats[p].status = fin ? SGDG_OK : SGDG_ERR_NONFINITE;
@@ -543,8 +529,9 @@ static void run_typed(const sgdg_plan* plan, int nrhs, double h, int M, const do
   hipLaunchKernelGGL((k_norm<TV>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, v, ws);
   for (int j = 0; j < M; ++j) {
     const void* xin = ws.Vb ? (const void*)ws.Vb : (const void*)((const TV*)ws.V + (size_t)j * nrhs * plan->total);
-    launch_apply<P>(plan, nrhs, xin, ws.wy, plan->total, plan->total, s);
-    hipLaunchKernelGGL((k_dots1<TV, TY>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j, ws);
+    // sweep w = A v_j fused with the chunk partials <v_i, w>, i <= j
+    const DotArgs da{ws.V, ws.part1, j, M + 2, plan->nchunks, nrhs, plan->total};
+    launch_apply_dots<P, TV>(plan, nrhs, xin, ws.wy, da, s);
     hipLaunchKernelGGL((k_upd1<TV, TY>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j, ws);
     hipLaunchKernelGGL((k_upd2<TV>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j, ws);
   }

@@ -21,7 +21,8 @@
 // line kernel on the last axis (expand, pointwise f or per-point species
 // Jacobian solve, contract), contract axes d-2..0; the last contraction
 // writes plan vectors with the residual / correction post-processing fused.
-// One 64-lane workgroup per fibre, all intermediate work in LDS; every stage
+// One workgroup per fibre (128 lanes; 256 for the lines of the last axis),
+// all intermediate work in LDS, the polynomial degree a template constant; every stage
 // covers all instances, species and right-hand sides in one launch.
 #include <hip/hip_runtime.h>
 
@@ -66,14 +67,16 @@ static std::vector<std::vector<int>> grid_blocks(int r, int N) {
   return out;
 }
 
-constexpr int RX_THREADS = 64;
+constexpr int RX_THREADS_FIB = 128;   // expansion / contraction fibres
+constexpr int RX_THREADS_LINE = 256;  // lines of the last axis
 constexpr int RX_MAX_N1 = 2048;
+constexpr int RX_TAIL = 64 + 16;  // two-scale matrices + per-wave partial sums
 
 static size_t fibre_lds_bytes(const RHost* rh) {
-  return (3 * (size_t)rh->max_n1 + (size_t)rh->max_np1 + 64) * sizeof(double);
+  return (3 * (size_t)rh->max_n1 + (size_t)rh->max_np1 + RX_TAIL) * sizeof(double);
 }
 static size_t line_lds_bytes(const RHost* rh) {
-  return (3 * (size_t)rh->max_n1 + 4 * (size_t)rh->max_np1 + 64) * sizeof(double);
+  return (3 * (size_t)rh->max_n1 + 4 * (size_t)rh->max_np1 + RX_TAIL) * sizeof(double);
 }
 static sgdg_status set_lds_attrs(const RHost* rh);
 
@@ -242,6 +245,16 @@ __device__ __forceinline__ int find_rblk(const RBlk* __restrict__ b, int n, int6
   return lo;
 }
 
+// a[m] for a small kernel-argument array without a dynamic index (which would
+// move the argument struct to scratch memory)
+__device__ __forceinline__ const int64_t* pick(const int64_t* const (&a)[SGDG_MAX_D], int m) {
+  const int64_t* r = a[0];
+#pragma unroll
+  for (int i = 1; i < SGDG_MAX_D; ++i)
+    if (m == i) r = a[i];
+  return r;
+}
+
 __device__ __forceinline__ int off1(int l, int K1) { return l == 0 ? 0 : (K1 << (l - 1)); }
 
 // two-scale matrices in LDS: M[0..15] ML[q][i] (child q from parent i), M[16..] MR,
@@ -252,7 +265,8 @@ __device__ __forceinline__ void load_mats(const RTables& R, const RInst& I, doub
 
 // inverse fast multiwavelet transform: hierarchical levels 0..L in h -> level-L
 // cell-Legendre coefficients (returned pointer, one of b0 / b1)
-__device__ double* ifwt(const double* h, double* b0, double* b1, int L, int K1, const double* M) {
+template <int K1>
+__device__ __forceinline__ double* ifwt(const double* h, double* b0, double* b1, int L, const double* M) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < K1; e += nt) b0[e] = h[e];
   __syncthreads();
@@ -266,7 +280,9 @@ __device__ double* ifwt(const double* h, double* b0, double* b1, int L, int K1, 
       const double* Mq = (c & 1) ? M + 16 : M;
       const double* Wq = (c & 1) ? M + 48 : M + 32;
       double acc = 0.0;
+#pragma unroll
       for (int i = 0; i < K1; ++i) acc += Mq[q * K1 + i] * cur[j * K1 + i];
+#pragma unroll
       for (int p = 0; p < K1; ++p) acc += Wq[p * K1 + q] * dw[j * K1 + p];
       nxt[e] = acc;
     }
@@ -281,8 +297,8 @@ __device__ double* ifwt(const double* h, double* b0, double* b1, int L, int K1, 
 // forward fast multiwavelet transform of level-N cell coefficients in s (s and
 // tmp are overwritten); emit(level, j, p, value) receives every hierarchical
 // coefficient (wavelets of levels N..1, then level 0).
-template <class Emit>
-__device__ void ffwt(double* s, double* tmp, int N, int K1, const double* M, Emit emit) {
+template <int K1, class Emit>
+__device__ __forceinline__ void ffwt(double* s, double* tmp, int N, const double* M, Emit emit) {
   const int tid = threadIdx.x, nt = blockDim.x;
   double* cur = s;
   double* nxt = tmp;
@@ -297,9 +313,11 @@ __device__ void ffwt(double* s, double* tmp, int N, int K1, const double* M, Emi
       const double* sr = sl + K1;
       double acc = 0.0;
       if (!w) {
+#pragma unroll
         for (int q = 0; q < K1; ++q) acc += M[q * K1 + i] * sl[q] + M[16 + q * K1 + i] * sr[q];
         nxt[j * K1 + i] = acc;
       } else {
+#pragma unroll
         for (int q = 0; q < K1; ++q) acc += M[32 + i * K1 + q] * sl[q] + M[48 + i * K1 + q] * sr[q];
         emit(n, j, i, acc);
       }
@@ -313,25 +331,28 @@ __device__ void ffwt(double* s, double* tmp, int N, int K1, const double* M, Emi
   __syncthreads();
 }
 
-// value at finest point q of the level-L cell expansion s
-__device__ __forceinline__ double eval_pt(const double* s, const double* __restrict__ EL, int L, int N, int nq, int np1,
-                                          int K1, int q) {
-  const int c = (q / nq) >> (N - L);
+// value at finest point q of the level-L cell expansion s (K1 Gauss points per cell)
+template <int K1>
+__device__ __forceinline__ double eval_pt(const double* s, const double* __restrict__ EL, int L, int N, int np1, int q) {
+  const int c = (q / K1) >> (N - L);
   const double* e = EL + ((int64_t)L * np1 + q) * K1;
   double u = 0.0;
+#pragma unroll
   for (int p = 0; p < K1; ++p) u += s[c * K1 + p] * e[p];
   return u;
 }
 
 // weighted point values g (weights already applied) -> level-N cell coefficients in out
-__device__ __forceinline__ void project_cells(const double* g, const double* __restrict__ EL, int N, int nq, int np1,
-                                              int K1, double* out) {
+template <int K1>
+__device__ __forceinline__ void project_cells(const double* g, const double* __restrict__ EL, int N, int np1,
+                                              double* out) {
   const int ncell = 1 << N;
   const double* e = EL + (int64_t)N * np1 * K1;
   for (int t = threadIdx.x; t < ncell * K1; t += blockDim.x) {
     const int c = t / K1, p = t - c * K1;
     double acc = 0.0;
-    for (int gq = 0; gq < nq; ++gq) acc += g[c * nq + gq] * e[(c * nq + gq) * K1 + p];
+#pragma unroll
+    for (int gq = 0; gq < K1; ++gq) acc += g[c * K1 + gq] * e[(c * K1 + gq) * K1 + p];
     out[t] = acc;
   }
   __syncthreads();
@@ -345,10 +366,14 @@ __device__ __forceinline__ void rx_f(const double (*c)[4][4], int S, const doubl
   const double u0 = u[0], u1 = S > 1 ? u[1] : 0.0;
   const double p0[4] = {1.0, u0, u0 * u0, u0 * u0 * u0};
   const double p1[4] = {1.0, u1, u1 * u1, u1 * u1 * u1};
-  for (int s = 0; s < S; ++s) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
     double acc = 0.0;
-    for (int aa = 0; aa < 4; ++aa)
-      for (int bb = 0; bb < 4; ++bb) acc += c[s][aa][bb] * p0[aa] * p1[bb];
+    if (s < S)
+#pragma unroll
+      for (int aa = 0; aa < 4; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) acc += c[s][aa][bb] * p0[aa] * p1[bb];
     f[s] = acc;
   }
 }
@@ -357,13 +382,17 @@ __device__ __forceinline__ void rx_jac(const double (*c)[4][4], int S, const dou
   const double u0 = u[0], u1 = S > 1 ? u[1] : 0.0;
   const double p0[4] = {1.0, u0, u0 * u0, u0 * u0 * u0};
   const double p1[4] = {1.0, u1, u1 * u1, u1 * u1 * u1};
-  for (int s = 0; s < S; ++s) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
     double j0 = 0.0, j1 = 0.0;
-    for (int aa = 0; aa < 4; ++aa)
-      for (int bb = 0; bb < 4; ++bb) {
-        if (aa > 0) j0 += c[s][aa][bb] * aa * p0[aa - 1] * p1[bb];
-        if (bb > 0) j1 += c[s][aa][bb] * bb * p0[aa] * p1[bb - 1];
-      }
+    if (s < S)
+#pragma unroll
+      for (int aa = 0; aa < 4; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+          if (aa > 0) j0 += c[s][aa][bb] * aa * p0[aa - 1] * p1[bb];
+          if (bb > 0) j1 += c[s][aa][bb] * bb * p0[aa] * p1[bb - 1];
+        }
     J[s][0] = j0;
     J[s][1] = j1;
   }
@@ -384,33 +413,41 @@ __device__ __forceinline__ double finish(const RxArgs& a, int mode, int64_t gi, 
   return 0.0;
 }
 
-__device__ __forceinline__ double block_sum64(double v) {
+// Sum over the workgroup in a fixed order (wave sums, then waves in index
+// order); the result is valid in thread 0.  wsum: LDS scratch of one double
+// per wave.
+__device__ __forceinline__ double block_sum(double v, double* wsum) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) wsum[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) t += wsum[i];
+  return t;
 }
 
 // ---------------------------------------------------------------- kernels
 
 // expansion stage m: fibres along axis m, grid (fibres, rhs, input)
-__global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, int ninst, int m, int64_t total, RxArgs a,
-                                                          int64_t rws, int max_n1) {
-  extern __shared__ double lds[];
+template <int K1>
+__device__ void rx_expand_body(const RTables& R, int inst, int m, int64_t total, const RxArgs& a, int64_t rws,
+                               int max_n1, double* lds) {
   const int z = blockIdx.z, rhs = blockIdx.y;
   const int64_t f = blockIdx.x;
-  const int64_t* cum = R.cum_x[m];
-  const int inst = find_inst(cum, ninst, f);
-  if (a.conv && a.conv[rhs * ninst + inst]) return;
+  const int64_t* cum = pick(R.cum_x, m);
   const RInst& I = R.inst[inst];
-  const int d = I.d, r = d - m, N = I.N, K1 = I.K1, S = I.S, np1 = I.np1, nq = I.nq;
+  const int d = I.d, r = d - m, N = I.N, S = I.S, np1 = I.np1;
   int64_t le = f - cum[inst];
-  const int64_t per_s = I.npre[m] * I.gdof[r - 1];
+  const int64_t gd_in = I.gdof[r], gd_out = I.gdof[r - 1];
+  const int64_t per_s = I.npre[m] * gd_out;
   const int s = (int)(le / per_s);
   le -= (int64_t)s * per_s;
-  const int64_t pre0 = le / I.gdof[r - 1];
-  const int64_t eo = le - pre0 * I.gdof[r - 1];
+  const int64_t pre0 = le / gd_out;
+  const int64_t eo = le - pre0 * gd_out;
   const RBlk* ob = R.rblk + I.blk_off[r - 1];
-  const RBlk B = ob[find_rblk(ob, I.nblk[r - 1], eo)];
+  const RBlk& B = ob[find_rblk(ob, I.nblk[r - 1], eo)];
   const int64_t rest = eo - B.start, Sb = B.size;
   const int L = N - B.lsum;
   int lin = 0, pw = 1;
@@ -427,7 +464,9 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, int ninst, 
   double* xr = a.rws + (int64_t)rhs * rws;
   const double* __restrict__ in =
       m == 0 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof
-             : xr + I.X_off[m] + (((int64_t)z * S + s) * I.npre[m] + pre0) * I.gdof[r];
+             : xr + I.X_off[m] + (((int64_t)z * S + s) * I.npre[m] + pre0) * gd_in;
+  double* out = xr + I.X_off[m + 1] + (((int64_t)z * S + s) * I.npre[m + 1] + pre0 * np1) * gd_out + eo;
+  const double* __restrict__ EL = R.EL + I.EL_off;
   load_mats(R, I, M);
   for (int l = 0; l <= L; ++l) {
     const int64_t base = ib[id[l * pw + lin]].start + rest;
@@ -435,25 +474,32 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, int ninst, 
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) h[off1(l, K1) + t] = in[base + (int64_t)t * Sb];
   }
   __syncthreads();
-  const double* sc = ifwt(h, b0, b1, L, K1, M);
-  const double* __restrict__ EL = R.EL + I.EL_off;
-  double* out = xr + I.X_off[m + 1] + (((int64_t)z * S + s) * I.npre[m + 1] + pre0 * np1) * I.gdof[r - 1] + eo;
-  for (int q = threadIdx.x; q < np1; q += blockDim.x)
-    out[(int64_t)q * I.gdof[r - 1]] = eval_pt(sc, EL, L, N, nq, np1, K1, q);
+  const double* sc = ifwt<K1>(h, b0, b1, L, M);
+  for (int q = threadIdx.x; q < np1; q += blockDim.x) out[(int64_t)q * gd_out] = eval_pt<K1>(sc, EL, L, N, np1, q);
+}
+
+__global__ __launch_bounds__(RX_THREADS_FIB) void k_rx_expand(RTables R, int ninst, int m, int64_t total, RxArgs a,
+                                                              int64_t rws, int max_n1) {
+  extern __shared__ double lds[];
+  const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
+  if (a.conv && a.conv[blockIdx.y * ninst + inst]) return;
+  switch (R.inst[inst].K1) {
+    case 2: rx_expand_body<2>(R, inst, m, total, a, rws, max_n1, lds); break;
+    case 3: rx_expand_body<3>(R, inst, m, total, a, rws, max_n1, lds); break;
+    default: rx_expand_body<4>(R, inst, m, total, a, rws, max_n1, lds); break;
+  }
 }
 
 // one workgroup per line of the last axis: expand (all species and inputs),
 // pointwise map, contract; for d = 1 the line is the whole instance and the
 // plan vectors are read and finished directly
-__global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, int ninst, int mode, int64_t total, RxArgs a,
-                                                        int64_t rws, int max_n1, int max_np1, int64_t nfin) {
-  extern __shared__ double lds[];
+template <int K1>
+__device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total, const RxArgs& a, int64_t rws,
+                             int max_n1, int max_np1, int64_t nfin, double* lds) {
   const int rhs = blockIdx.y;
   const int64_t gl = blockIdx.x;
-  const int inst = find_inst(R.cum_line, ninst, gl);
-  if (a.conv && a.conv[rhs * ninst + inst]) return;
   const RInst& I = R.inst[inst];
-  const int d = I.d, N = I.N, K1 = I.K1, S = I.S, np1 = I.np1, n1 = I.n1, nq = I.nq;
+  const int d = I.d, N = I.N, S = I.S, np1 = I.np1, n1 = I.n1;
   const int64_t pre = gl - R.cum_line[inst];
   const int nin = mode == RX_CORR ? 2 : 1;
   double* h = lds;
@@ -461,18 +507,23 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, int ninst, in
   double* b1 = lds + 2 * max_n1;
   double* pts = lds + 3 * max_n1;  // [z*2+s][max_np1]
   double* M = pts + 4 * max_np1;
+  double* wsum = M + 64;
   double* xr = a.rws + (int64_t)rhs * rws;
   const double* __restrict__ EL = R.EL + I.EL_off;
   const double* __restrict__ w1 = R.w1 + I.w_off;
+  const double dt2 = a.dt2;
   load_mats(R, I, M);
-  for (int z = 0; z < nin; ++z)
+#pragma unroll
+  for (int z = 0; z < 2; ++z)
     for (int s = 0; s < S; ++s) {
+      if (z >= nin) break;
       const double* in = d == 1 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof
                                 : xr + I.X_off[d - 1] + (((int64_t)z * S + s) * I.npre[d - 1] + pre) * n1;
       for (int i = threadIdx.x; i < n1; i += blockDim.x) h[i] = in[i];
       __syncthreads();
-      const double* sc = ifwt(h, b0, b1, N, K1, M);
-      for (int q = threadIdx.x; q < np1; q += blockDim.x) pts[(z * 2 + s) * max_np1 + q] = eval_pt(sc, EL, N, N, nq, np1, K1, q);
+      const double* sc = ifwt<K1>(h, b0, b1, N, M);
+      double* pz = pts + (z * 2 + s) * max_np1;
+      for (int q = threadIdx.x; q < np1; q += blockDim.x) pz[q] = eval_pt<K1>(sc, EL, N, N, np1, q);
       __syncthreads();
     }
   for (int q = threadIdx.x; q < np1; q += blockDim.x) {
@@ -483,10 +534,10 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, int ninst, in
       double J[2][2];
       rx_jac(I.rx, S, u, J);
       if (S == 1) {
-        out[0] = g0 / (1.0 - a.dt2 * J[0][0]);
+        out[0] = g0 / (1.0 - dt2 * J[0][0]);
       } else {
-        const double A = 1.0 - a.dt2 * J[0][0], Bq = -a.dt2 * J[0][1];
-        const double C = -a.dt2 * J[1][0], D = 1.0 - a.dt2 * J[1][1];
+        const double A = 1.0 - dt2 * J[0][0], Bq = -dt2 * J[0][1];
+        const double C = -dt2 * J[1][0], D = 1.0 - dt2 * J[1][1];
         const double det = A * D - Bq * C;
         out[0] = (D * g0 - Bq * g1) / det;
         out[1] = (A * g1 - C * g0) / det;
@@ -494,47 +545,59 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, int ninst, in
     } else {
       rx_f(I.rx, S, u, out);
     }
-    for (int s = 0; s < S; ++s) pts[s * max_np1 + q] = w1[q] * out[s];
+    pts[q] = w1[q] * out[0];
+    if (S > 1) pts[max_np1 + q] = w1[q] * out[1];
   }
   __syncthreads();
   double g2 = 0.0;
   for (int s = 0; s < S; ++s) {
-    project_cells(pts + s * max_np1, EL, N, nq, np1, K1, b0);
+    project_cells<K1>(pts + s * max_np1, EL, N, np1, b0);
     if (d == 1) {
       const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)s * I.ndof;
-      ffwt(b0, b1, N, K1, M, [&](int n, int j, int p, double v) {
+      ffwt<K1>(b0, b1, N, M, [&](int n, int j, int p, double v) {
         g2 += finish(a, mode, base + off1(n, K1) + j * K1 + p, v);
       });
     } else {
       double* out = xr + I.Y_off[d - 1] + ((int64_t)s * I.npre[d - 1] + pre) * n1;
-      ffwt(b0, b1, N, K1, M, [&](int n, int j, int p, double v) { out[off1(n, K1) + j * K1 + p] = v; });
+      ffwt<K1>(b0, b1, N, M, [&](int n, int j, int p, double v) { out[off1(n, K1) + j * K1 + p] = v; });
     }
   }
   if (d == 1 && mode == RX_RESID) {
-    g2 = block_sum64(g2);
+    g2 = block_sum(g2, wsum);
     if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + R.cum_fin[inst]] = g2;
   }
 }
 
-// contraction stage m (m >= 1 writes Y_m; m == 0 finishes plan vectors)
-__global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, int ninst, int m, int mode, int64_t total,
-                                                            RxArgs a, int64_t rws, int max_n1, int64_t nfin) {
+__global__ __launch_bounds__(RX_THREADS_LINE) void k_rx_line(RTables R, int ninst, int mode, int64_t total, RxArgs a,
+                                                             int64_t rws, int max_n1, int max_np1, int64_t nfin) {
   extern __shared__ double lds[];
+  const int inst = find_inst(R.cum_line, ninst, blockIdx.x);
+  if (a.conv && a.conv[blockIdx.y * ninst + inst]) return;
+  switch (R.inst[inst].K1) {
+    case 2: rx_line_body<2>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, lds); break;
+    case 3: rx_line_body<3>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, lds); break;
+    default: rx_line_body<4>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, lds); break;
+  }
+}
+
+// contraction stage m (m >= 1 writes Y_m; m == 0 finishes plan vectors)
+template <int K1>
+__device__ void rx_contract_body(const RTables& R, int inst, int m, int mode, int64_t total, const RxArgs& a,
+                                 int64_t rws, int max_n1, int64_t nfin, double* lds) {
   const int rhs = blockIdx.y;
   const int64_t f = blockIdx.x;
-  const int64_t* cum = m == 0 ? R.cum_fin : R.cum_y[m];
-  const int inst = find_inst(cum, ninst, f);
-  if (a.conv && a.conv[rhs * ninst + inst]) return;
+  const int64_t* cum = m == 0 ? R.cum_fin : pick(R.cum_y, m);
   const RInst& I = R.inst[inst];
-  const int d = I.d, r = d - m, N = I.N, K1 = I.K1, np1 = I.np1, nq = I.nq;
+  const int d = I.d, r = d - m, N = I.N, np1 = I.np1;
   int64_t le = f - cum[inst];
-  const int64_t per_s = I.npre[m] * I.gdof[r - 1];
+  const int64_t gd_in = I.gdof[r - 1], gd_out = I.gdof[r];
+  const int64_t per_s = I.npre[m] * gd_in;
   const int s = (int)(le / per_s);
   le -= (int64_t)s * per_s;
-  const int64_t pre0 = le / I.gdof[r - 1];
-  const int64_t eo = le - pre0 * I.gdof[r - 1];
+  const int64_t pre0 = le / gd_in;
+  const int64_t eo = le - pre0 * gd_in;
   const RBlk* ob = R.rblk + I.blk_off[r - 1];
-  const RBlk B = ob[find_rblk(ob, I.nblk[r - 1], eo)];
+  const RBlk& B = ob[find_rblk(ob, I.nblk[r - 1], eo)];
   const int64_t rest = eo - B.start, Sb = B.size;
   const int L = N - B.lsum;
   int lin = 0, pw = 1;
@@ -546,31 +609,44 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, int ninst
   double* b0 = lds + max_n1;
   double* b1 = lds + 2 * max_n1;
   double* M = lds + 3 * max_n1;
+  double* wsum = M + 64;
   double* xr = a.rws + (int64_t)rhs * rws;
   const double* __restrict__ EL = R.EL + I.EL_off;
   const double* __restrict__ w1 = R.w1 + I.w_off;
   load_mats(R, I, M);
-  const double* __restrict__ in = xr + I.Y_off[m + 1] + ((int64_t)s * I.npre[m + 1] + pre0 * np1) * I.gdof[r - 1] + eo;
-  for (int q = threadIdx.x; q < np1; q += blockDim.x) g[q] = w1[q] * in[(int64_t)q * I.gdof[r - 1]];
+  const double* __restrict__ in = xr + I.Y_off[m + 1] + ((int64_t)s * I.npre[m + 1] + pre0 * np1) * gd_in + eo;
+  for (int q = threadIdx.x; q < np1; q += blockDim.x) g[q] = w1[q] * in[(int64_t)q * gd_in];
   __syncthreads();
-  project_cells(g, EL, N, nq, np1, K1, b0);
+  project_cells<K1>(g, EL, N, np1, b0);
   const int32_t* __restrict__ id = R.rid + I.id_off[r];
   const RBlk* ib = R.rblk + I.blk_off[r];
   if (m > 0) {
-    double* out = xr + I.Y_off[m] + ((int64_t)s * I.npre[m] + pre0) * I.gdof[r] + rest;
-    ffwt(b0, b1, N, K1, M, [&](int n, int j, int p, double v) {
+    double* out = xr + I.Y_off[m] + ((int64_t)s * I.npre[m] + pre0) * gd_out + rest;
+    ffwt<K1>(b0, b1, N, M, [&](int n, int j, int p, double v) {
       if (n <= L) out[ib[id[n * pw + lin]].start + (int64_t)(j * K1 + p) * Sb] = v;
     });
   } else {
     const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)s * I.ndof + rest;
     double g2 = 0.0;
-    ffwt(b0, b1, N, K1, M, [&](int n, int j, int p, double v) {
+    ffwt<K1>(b0, b1, N, M, [&](int n, int j, int p, double v) {
       if (n <= L) g2 += finish(a, mode, base + ib[id[n * pw + lin]].start + (int64_t)(j * K1 + p) * Sb, v);
     });
     if (mode == RX_RESID) {
-      g2 = block_sum64(g2);
+      g2 = block_sum(g2, wsum);
       if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + f] = g2;
     }
+  }
+}
+
+__global__ __launch_bounds__(RX_THREADS_FIB) void k_rx_contract(RTables R, int ninst, int m, int mode, int64_t total,
+                                                                RxArgs a, int64_t rws, int max_n1, int64_t nfin) {
+  extern __shared__ double lds[];
+  const int inst = find_inst(m == 0 ? R.cum_fin : pick(R.cum_y, m), ninst, blockIdx.x);
+  if (a.conv && a.conv[blockIdx.y * ninst + inst]) return;
+  switch (R.inst[inst].K1) {
+    case 2: rx_contract_body<2>(R, inst, m, mode, total, a, rws, max_n1, nfin, lds); break;
+    case 3: rx_contract_body<3>(R, inst, m, mode, total, a, rws, max_n1, nfin, lds); break;
+    default: rx_contract_body<4>(R, inst, m, mode, total, a, rws, max_n1, nfin, lds); break;
   }
 }
 
@@ -595,12 +671,12 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
   const int64_t nfin = rh->cum_fin.back();
   for (int m = 0; m + 1 <= d - 1; ++m)
     hipLaunchKernelGGL(k_rx_expand, dim3((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin),
-                       dim3(RX_THREADS), fl, s, rh->dev, ninst, m, plan->total, a, rh->rws, rh->max_n1);
-  hipLaunchKernelGGL(k_rx_line, dim3((unsigned)rh->cum_line.back(), (unsigned)nrhs), dim3(RX_THREADS), ll, s, rh->dev,
+                       dim3(RX_THREADS_FIB), fl, s, rh->dev, ninst, m, plan->total, a, rh->rws, rh->max_n1);
+  hipLaunchKernelGGL(k_rx_line, dim3((unsigned)rh->cum_line.back(), (unsigned)nrhs), dim3(RX_THREADS_LINE), ll, s, rh->dev,
                      ninst, (int)mode, plan->total, a, rh->rws, rh->max_n1, rh->max_np1, nfin);
   for (int m = d - 2; m >= 0; --m) {
     const int64_t nf = m == 0 ? nfin : rh->cum_y[m].back();
-    hipLaunchKernelGGL(k_rx_contract, dim3((unsigned)nf, (unsigned)nrhs), dim3(RX_THREADS), fl, s, rh->dev, ninst, m,
+    hipLaunchKernelGGL(k_rx_contract, dim3((unsigned)nf, (unsigned)nrhs), dim3(RX_THREADS_FIB), fl, s, rh->dev, ninst, m,
                        (int)mode, plan->total, a, rh->rws, rh->max_n1, nfin);
   }
 }
