@@ -238,6 +238,24 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // holds A[l % 16][l / 16], B fragment: B[l / 16][l % 16], accumulator element v
 // of lane l is C[4 v + l / 16][l % 16], as measured on gfx950).  The padding of A and B must be zero;
 // the padding of C is written as zero.  C must not alias A or B.
+// one 16 x 16 output tile with NK = mp / 4 steps; all fragments are loaded
+// before the dependent MFMA chain starts
+template <int NK>
+__device__ __forceinline__ void mfma_tile(double* __restrict__ C, const double* __restrict__ A,
+                                          const double* __restrict__ B, int ti, int tj, int li, int lk) {
+  double a[NK], b[NK];
+#pragma unroll
+  for (int q = 0; q < NK; ++q) {
+    a[q] = A[(ti + li) * LDM + 4 * q + lk];
+    b[q] = B[(4 * q + lk) * LDM + tj + li];
+  }
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < NK; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) C[(ti + 4 * v + lk) * LDM + tj + li] = acc[v];
+}
+
 __device__ void mat_mul(double* C, const double* A, const double* B, int m) {
   const int mp = (m + 15) & ~15;
   const int nt = mp >> 4;
@@ -245,16 +263,43 @@ __device__ void mat_mul(double* C, const double* A, const double* B, int m) {
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   for (int t = wave; t < nt * nt; t += nw) {
     const int ti = (t / nt) << 4, tj = (t % nt) << 4;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < mp; k0 += 4) {
-      const double a = A[(ti + li) * LDM + k0 + lk];
-      const double b = B[(k0 + lk) * LDM + tj + li];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) C[(ti + 4 * v + lk) * LDM + tj + li] = acc[v];
+    if (nt == 1)
+      mfma_tile<4>(C, A, B, ti, tj, li, lk);
+    else if (nt == 2)
+      mfma_tile<8>(C, A, B, ti, tj, li, lk);
+    else
+      mfma_tile<12>(C, A, B, ti, tj, li, lk);
   }
   __syncthreads();
+}
+
+// One Gauss-Jordan step for row r of the augmented system [P | Q] (row k and
+// the pivot row trade places; the pivot row is normalised, every other row
+// loses its multiple of it).  Columns c = g, g + ngrp, ... (at most U per
+// thread); all loads are issued before the stores.
+template <int U>
+__device__ __forceinline__ void gj_row(const double* __restrict__ P0, const double* __restrict__ Q0,
+                                       double* __restrict__ P1, double* __restrict__ Q1, int m, int k, int piv,
+                                       int r, int g, int ngrp) {
+  const int sr = r == k ? piv : (r == piv ? k : r);
+  const double inv = 1.0 / P0[piv * LDM + k];
+  const double f = P0[sr * LDM + k];
+  double pp[U], ps[U], qp[U], qs[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int cp = k + 1 + g + u * ngrp, cq = g + u * ngrp;
+    pp[u] = cp < m ? P0[piv * LDM + cp] : 0.0;
+    ps[u] = cp < m ? P0[sr * LDM + cp] : 0.0;
+    qp[u] = cq < m ? Q0[piv * LDM + cq] : 0.0;
+    qs[u] = cq < m ? Q0[sr * LDM + cq] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int cp = k + 1 + g + u * ngrp, cq = g + u * ngrp;
+    const double vp = pp[u] * inv, vq = qp[u] * inv;
+    if (cp < m) P1[r * LDM + cp] = r == k ? vp : ps[u] - f * vp;
+    if (cq < m) Q1[r * LDM + cq] = r == k ? vq : qs[u] - f * vq;
+  }
 }
 
 __device__ void pade_coeffs(int deg, double* b) {
@@ -399,36 +444,30 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
     Q0[q] = Vm[q] + Um[q];
   }
   __syncthreads();
+  // thread -> (row, column group): rows r < m in the low bits, columns
+  // strided by the number of groups (no integer division in the loop)
+  const int rsh = m <= 32 ? 5 : 6;
+  const int my_r = tid & ((1 << rsh) - 1), my_g = tid >> rsh, ngrp = blockDim.x >> rsh;
   for (int k = 0; k < m; ++k) {
-    // pivot: largest |P[r][k]| for r >= k, lowest row on ties; every wave
-    // finds it on its own (lane r holds row r, m <= 64), so no extra barrier
+    // pivot: largest |P[r][k]| for r >= k; every wave finds it on its own (lane
+    // r - k holds row r, m <= 64) with one 32-bit key per lane: the magnitude
+    // rounded to FP32 with its low 6 mantissa bits replaced by 63 - lane, so the
+    // maximum key is the largest magnitude and, among magnitudes equal to ~17
+    // bits, the lowest row
     int piv;
     {
-      const int r = k + (tid & 63);
-      double best = r < m ? fabs(P0[r * LDM + k]) : -1.0;
-      int pr = r < m ? r : 1 << 30;
+      const int lane = tid & 63, r = k + lane;
+      unsigned key = 0u;
+      if (r < m) key = (__float_as_uint((float)fabs(P0[r * LDM + k])) & ~63u) | (unsigned)(63 - lane);
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int op = __shfl_xor(pr, off, 64);
-        if (ob > best || (ob == best && op < pr)) {
-          best = ob;
-          pr = op;
-        }
-      }
-      piv = pr;
+      for (int off = 32; off > 0; off >>= 1) key = max(key, (unsigned)__shfl_xor((int)key, off, 64));
+      piv = k + 63 - (int)(key & 63u);
     }
-    const double inv = 1.0 / P0[piv * LDM + k];
-    const int ncp = m - k - 1, nc = ncp + m;
-    for (int e = tid; e < m * nc; e += blockDim.x) {
-      const int r = e / nc, cc = e - r * nc;
-      const bool inP = cc < ncp;
-      const int c = inP ? k + 1 + cc : cc - ncp;
-      const double* X0 = inP ? P0 : Q0;
-      double* X1 = inP ? P1 : Q1;
-      const int sr = r == k ? piv : (r == piv ? k : r);  // row k and the pivot row trade places
-      const double pv = X0[piv * LDM + c] * inv;
-      X1[r * LDM + c] = r == k ? pv : X0[sr * LDM + c] - P0[sr * LDM + k] * pv;
+    if (my_r < m) {
+      if (rsh == 5)
+        gj_row<4>(P0, Q0, P1, Q1, m, k, piv, my_r, my_g, ngrp);
+      else
+        gj_row<12>(P0, Q0, P1, Q1, m, k, piv, my_r, my_g, ngrp);
     }
     __syncthreads();
     double* t = P0;
