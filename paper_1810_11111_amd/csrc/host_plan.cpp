@@ -325,6 +325,7 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
   const int vbytes = prec == SGDG_FP64 ? 8 : 4;
   p->chunk_lists.assign(SWEEP_TIERS * (SGDG_MAX_K + 1), {});
   p->list_lds.assign(SWEEP_TIERS * (SGDG_MAX_K + 1), 0);
+  p->list_fixed.assign(SWEEP_TIERS * (SGDG_MAX_K + 1), 0);
   auto al16 = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
   for (int32_t c = 0; c < p->nchunks; ++c) {
     const HostInstance& hi = p->inst[p->chunks[c].inst];
@@ -345,7 +346,11 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
     const int tier = lds2 <= APPLY_LDS_BYTES_HOST ? 2 : (lds1 <= APPLY_LDS_BYTES_HOST ? 1 : 0);
     const int kind = hi.desc.k * SWEEP_TIERS + tier;
     p->chunk_lists[kind].push_back(c);
-    if (tier > 0) p->list_lds[kind] = std::max(p->list_lds[kind], (int)(tier == 2 ? lds2 : lds1));
+    if (tier > 0) {
+      p->list_lds[kind] = std::max(p->list_lds[kind], (int)(tier == 2 ? lds2 : lds1));
+      const int64_t fixed = al16((ntab + rows) * 4) + (tier == 2 ? vals : 0);
+      p->list_fixed[kind] = std::max(p->list_fixed[kind], (int)fixed);
+    }
   }
 
   sgdg_status st = SGDG_OK;

@@ -117,7 +117,8 @@ struct sgdg_plan {
   // 2 = block values staged as well
   std::vector<std::vector<int32_t>> chunk_lists;
   std::vector<int32_t*> dev_chunk_lists;
-  std::vector<int> list_lds;  // dynamic LDS bytes of the staged lists
+  std::vector<int> list_lds;    // dynamic LDS bytes of the staged lists
+  std::vector<int> list_fixed;  // of which tables and block values (all but the x segment), maximum over the list
   std::vector<sgdg::InstDev> instdev;
   std::vector<int32_t> pchunk0, pnchunk;  // host copies of the per-species chunk ranges
   sgdg::DevTables dev;

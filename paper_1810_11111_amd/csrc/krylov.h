@@ -5,6 +5,9 @@
 
 namespace sgdg {
 
+// happy breakdown: h_{j+1,j} <= KRYLOV_BREAKDOWN_REL * ||A_s||_inf ends the Arnoldi process
+constexpr double KRYLOV_BREAKDOWN_REL = 1e-12;
+
 // Device-side view of a Krylov workspace (one carve-up of a caller buffer).
 struct KrylovWs {
   void* V;           // (M+1) basis vectors: [i][rhs][total], FP64 or FP32
@@ -18,10 +21,18 @@ struct KrylovWs {
   double* beta;      // [problem]
   int32_t* m;        // [problem]: Krylov dimension reached
   int32_t* done;     // [problem]: no further Arnoldi steps
+  uint32_t* bar;     // persistent Arnoldi: [0] arrivals, [1] generation, [2] error flag
 };
 
 size_t krylov_ws_bytes(const sgdg_plan* plan, int M, int nrhs);
 KrylovWs krylov_carve(const sgdg_plan* plan, int M, int nrhs, void* base);
+
+// Persistent Arnoldi (arnoldi.hip): all M steps of every problem in one
+// launch with grid-wide barriers, when enabled by SGDG_ARNOLDI=persistent,
+// the plan's chunks are all in one staged sweep list and the grid fits the
+// device at one workgroup per compute unit.  Returns false (and launches
+// nothing) otherwise.
+bool arnoldi_persistent(const sgdg_plan* plan, int nrhs, int M, const KrylovWs& ws, hipStream_t s);
 
 // w = exp(h A) v for nrhs plan vectors (v, w FP64, may alias).
 sgdg_status krylov_run(const sgdg_plan* plan, int nrhs, double h, int M, const double* v, double* w,

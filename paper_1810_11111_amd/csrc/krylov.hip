@@ -29,7 +29,6 @@
 namespace sgdg {
 
 constexpr int NW = CHUNK / 64;
-constexpr double BREAKDOWN_REL = 1e-12;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -62,6 +61,10 @@ __global__ __launch_bounds__(CHUNK) void k_init(DevTables T, int nchunks, int ni
     double t = 0.0;
     for (int w = 0; w < NW; ++w) t += red[w];
     ws.part1[((int64_t)rhs * nchunks + c) * (M + 2)] = t;
+    if (c == 0 && rhs == 0) {
+      ws.bar[0] = 0u;
+      ws.bar[2] = 0u;
+    }
     if (c == T.pchunk0[ch.problem]) {
       const int p = prob_of(rhs, ninst, ch);
       ws.done[p] = 0;
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(CHUNK) void k_upd2(DevTables T, int nchunks, int ni
   if (c == c0 && tid == 0) Hp[(j + 1) * M + j] = hn;
   const InstDev& I = T.inst[ch.inst];
   const int Mp = (int)min((int64_t)M, I.ndof);
-  const bool stop = !(hn > BREAKDOWN_REL * I.anorm[ch.species]) || (j + 1 >= Mp);
+  const bool stop = !(hn > KRYLOV_BREAKDOWN_REL * I.anorm[ch.species]) || (j + 1 >= Mp);
   if (stop) {
     if (c == c0 && tid == 0) {
       ws.m[p] = j + 1;
@@ -492,7 +495,7 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
     for (int i = 0; i < m; ++i) fin = fin && isfinite(R[i * LDM]);
     stats[p].krylov_m = m;
     stats[p].h_next = Hp[m * M + (m - 1)];
-    stats[p].status = fin ? SGDG_OK : SGDG_ERR_NONFINITE;
+    stats[p].status = ws.bar[2] ? SGDG_ERR_HIP : (fin ? SGDG_OK : SGDG_ERR_NONFINITE);
   }
 }
 
@@ -532,6 +535,7 @@ size_t krylov_ws_bytes(const sgdg_plan* plan, int M, int nrhs) {
   b += align256(np * M * 8);                                              // y
   b += align256(np * 8);                                                  // beta
   b += 2 * align256(np * 4);                                              // m, done
+  b += align256(64);                                                      // barrier words
   return b;
 }
 
@@ -557,6 +561,7 @@ KrylovWs krylov_carve(const sgdg_plan* plan, int M, int nrhs, void* base) {
   ws.beta = (double*)take(np * 8);
   ws.m = (int32_t*)take(np * 4);
   ws.done = (int32_t*)take(np * 4);
+  ws.bar = (uint32_t*)take(64);
   return ws;
 }
 
@@ -566,13 +571,16 @@ static void run_typed(const sgdg_plan* plan, int nrhs, double h, int M, const do
   const dim3 grid((unsigned)plan->nchunks, (unsigned)nrhs), blk(CHUNK);
   hipLaunchKernelGGL(k_init, grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, v, ws);
   hipLaunchKernelGGL((k_norm<TV>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, v, ws);
-  for (int j = 0; j < M; ++j) {
-    const void* xin = ws.Vb ? (const void*)ws.Vb : (const void*)((const TV*)ws.V + (size_t)j * nrhs * plan->total);
-    // sweep w = A v_j fused with the chunk partials <v_i, w>, i <= j
-    const DotArgs da{ws.V, ws.part1, j, M + 2, plan->nchunks, nrhs, plan->total};
-    launch_apply_dots<P, TV>(plan, nrhs, xin, ws.wy, da, s);
-    hipLaunchKernelGGL((k_upd1<TV, TY>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j, ws);
-    hipLaunchKernelGGL((k_upd2<TV>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j, ws);
+  if (!arnoldi_persistent(plan, nrhs, M, ws, s)) {
+    for (int j = 0; j < M; ++j) {
+      const void* xin = ws.Vb ? (const void*)ws.Vb : (const void*)((const TV*)ws.V + (size_t)j * nrhs * plan->total);
+      // sweep w = A v_j fused with the chunk partials <v_i, w>, i <= j
+      const DotArgs da{ws.V, ws.part1, j, M + 2, plan->nchunks, nrhs, plan->total};
+      launch_apply_dots<P, TV>(plan, nrhs, xin, ws.wy, da, s);
+      hipLaunchKernelGGL((k_upd1<TV, TY>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j,
+                         ws);
+      hipLaunchKernelGGL((k_upd2<TV>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j, ws);
+    }
   }
   hipLaunchKernelGGL(k_expm, dim3((unsigned)(nrhs * plan->ninst * 2)), dim3(256), 0, s, plan->dev, plan->ninst, M, h, ws,
                      stats);

@@ -100,6 +100,35 @@ def test_expv_fp64_random(d, N, k, D, h, M, seed):
             assert np.linalg.norm(W[r, seg]) <= np.linalg.norm(V[r, seg]) * (1 + 1e-12)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_expv_persistent_and_multi_kernel_forms_agree(prec, monkeypatch):
+    """SGDG_ARNOLDI=persistent runs the Arnoldi process of a plan whose chunks
+    all fit the LDS-staged sweep in one cooperative launch; the default is the
+    launch-per-pass form.  Both follow the same arithmetic (CGS2, FP64
+    reductions); they may differ only by the order of partial sums."""
+    sg = lib()
+    wl = I.schnakenberg_d2(N=6, k=2)
+    inst = wl.instances[0]
+    say("expv persistent vs multi", prec)
+    plan = sg.Plan([inst], prec)
+    V = I.smooth_random(plan.total, 21, 3)
+    monkeypatch.delenv("SGDG_ARNOLDI", raising=False)
+    Wm, stm = _run(plan, wl.dt, wl.M, V, nrhs=3)
+    monkeypatch.setenv("SGDG_ARNOLDI", "persistent")
+    Wp, stp = _run(plan, wl.dt, wl.M, V, nrhs=3)
+    assert np.array_equal(stm["krylov_m"], stp["krylov_m"]) and np.all(stp["status"][: 3 * 2] == 0)
+    if prec == "fp64":
+        _compare(plan, [inst], wl.dt, wl.M, V, Wp, stp, fp64_tol, nrhs=3)
+        _compare(plan, [inst], wl.dt, wl.M, V, Wm, stm, fp64_tol, nrhs=3)
+    nd = plan.info(0)[0]
+    an = [plan.norm_inf(0, s) for s in range(2)]
+    for r in range(3):
+        for s in range(2):
+            seg = slice(s * nd, (s + 1) * nd)
+            tol = {"fp64": 2 * fp64_tol(wl.dt, an[s]), "fp32": 1e-4, "bf16": 3e-2}[prec] * np.linalg.norm(V[r, seg])
+            assert np.linalg.norm(Wp[r, seg] - Wm[r, seg]) <= tol, (prec, r, s)
+
+
 def test_expv_schnakenberg_full_size():
     """The benchmark workload's Krylov call: d=2 N=7 k=2, two species, M=30, dt=0.05."""
     sg = lib()
