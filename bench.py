@@ -9,8 +9,10 @@ uniform +-0.01 noise on every coefficient.  One step = one iif2_step call
 captured HIP graph; inputs are resident in HBM before timing starts.
 
 Prints ONE JSON line with the IIF2 throughput in DOF-steps/s (FP64 path),
-the FP32- and BF16-sweep variants with their L2 error against the FP64
-result, the roofline of the dominant kernel and the CPU oracle baseline.
+the FP32- and BF16-sweep variants with their L2 difference to the FP64
+result, the roofline of the dominant kernel, the out-of-cache sweep, a
+64-instance batched run (FP64 and FP32 sweeps), and the CPU oracle baseline
+with the L2 error of each precision against the oracle after the same steps.
 """
 from __future__ import annotations
 
@@ -156,14 +158,24 @@ def traffic_record(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, U0, budget_s=20.0):
-    """The oracle (numpy/scipy FP64) on the same workload: as many steps as fit in the budget."""
-    from oracle import iif
+def cpu_baseline(wl, budget_s=20.0):
+    """The oracle (numpy/scipy FP64) on the same workload: as many steps as fit in
+    the budget, from the oracle's own projection of the initial data.  Returns
+    the record, that initial state and the oracle state after the steps run."""
+    from oracle import iif, project
     from threadpoolctl import threadpool_info
 
     inst = wl.instances[0]
     prob = iif.Problem(inst.d, inst.N, inst.k, inst.D, inst.rx, wl.dt, wl.M)
-    U = U0.reshape(inst.species, -1).copy()
+    U0 = []
+    for terms, mults, add in wl.initial_condition(0, prob.ndof):
+        v = np.zeros(prob.ndof)
+        for (amp, fac), mult in zip(terms, mults):
+            pr = project.project_separable(inst.d, inst.N, inst.k, amp, fac)
+            v += pr * (1.0 + mult) if mult is not None else pr
+        U0.append(v + add if add is not None else v)
+    U0 = np.array(U0)
+    U = U0.copy()
     Fn = prob.F(U)
     t0 = time.perf_counter()
     n = 0
@@ -172,8 +184,25 @@ def cpu_baseline(wl, U0, budget_s=20.0):
         n += 1
     secs = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return {"value": prob.ndof * inst.species * n / secs, "unit": "DOF-steps/s", "cores": int(threads),
-            "kind": "oracle", "sample": f"first {n} of {wl.steps} IIF2 steps of the same workload ({secs:.1f} s)"}
+    rec = {"value": prob.ndof * inst.species * n / secs, "unit": "DOF-steps/s", "cores": int(threads),
+           "kind": "oracle", "sample": f"first {n} of {wl.steps} IIF2 steps of the same workload ({secs:.1f} s)"}
+    return rec, U0.ravel(), n, U.ravel()
+
+
+def gpu_trajectory(sg, torch, wl, prec, U0, steps):
+    """`steps` eager IIF2 steps of the library from U0 (untimed)."""
+    plan = sg.Plan(wl.instances, prec)
+    Ud = torch.from_numpy(U0.copy()).cuda()
+    F = torch.zeros_like(Ud)
+    _, ib = plan.workspace_size(wl.M, 1)
+    ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
+    plan.reaction(Ud, F, ws)
+    for _ in range(steps):
+        plan.iif2_step(wl.dt, wl.M, Ud, F, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX)
+    torch.cuda.synchronize()
+    U = Ud.cpu().numpy()
+    plan.close()
+    return U
 
 
 def main():
@@ -185,6 +214,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 legs")
     ap.add_argument("--eager", action="store_true", help="launch steps eagerly instead of replaying a graph")
     ap.add_argument("--no-big", action="store_true", help="skip the out-of-cache sweep measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance Gray-Scott batch")
+    ap.add_argument("--batched-steps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
@@ -246,9 +277,39 @@ def main():
         out["apply_out_of_cache"] = {"workload": "sweep d=3 N=16 k=1 (24.6M DOF, 197 MB per FP64 vector)",
                                      "dof": tot_b, "avg_ms": avg_b * 1e3, "achieved_gbs": nbytes_b / avg_b / 1e9,
                                      "frac_of_peak": nbytes_b / avg_b / 1e9 / HBM_PEAK_GBS}
+    if not args.no_batched:
+        # 64 independent Gray-Scott instances (levels 5-8, k 1-2) in one plan: every
+        # launch of the step covers all of them; FP64 and FP32 sweeps
+        bw = I.gray_scott_batch()
+        bplan = sg.Plan(bw.instances, "fp64")
+        bU0 = build_ic(bplan, bw)
+        bdofs = dof_per_step(bplan, bw)
+        bplan.close()
+        batched = {"workload": f"{bw.name} ({len(bw.instances)} instances, d=2, N 5-8, k 1-2, M={bw.M}, "
+                               f"dt={bw.dt})", "dof_per_step": bdofs, "steps": args.batched_steps}
+        ref = None
+        for prec in ("fp64", "fp32"):
+            log(f"[bench] batched {prec}")
+            s2, Ub, stb, _ = run_steps(sg, torch, bw, prec, bU0, args.batched_steps, 3, graph=not args.eager)
+            ent = {"value": bdofs * args.batched_steps / s2, "ms_per_step": 1e3 * s2 / args.batched_steps,
+                   "status_ok": bool(np.all(stb["status"][: 2 * len(bw.instances)] == 0))}
+            if ref is None:
+                ref = Ub
+            else:
+                ent["rel_l2_vs_fp64"] = float(np.linalg.norm(Ub - ref) / np.linalg.norm(ref))
+            batched[prec] = ent
+        out["batched"] = batched
     if not args.no_cpu:
         log("[bench] cpu oracle")
-        out["cpu_baseline"] = cpu_baseline(wl, U0)
+        rec, U0o, n, Uo = cpu_baseline(wl)
+        out["cpu_baseline"] = rec
+        # the same steps on the GPU from the oracle's initial state: L2 error of
+        # each precision against the FP64 oracle
+        err = {"steps": n, "ic_rel_diff_library_vs_oracle": float(np.linalg.norm(U0 - U0o) / np.linalg.norm(U0o))}
+        for prec in ("fp64", "fp32", "bf16"):
+            Ug = gpu_trajectory(sg, torch, wl, prec, U0o, n)
+            err[prec] = float(np.linalg.norm(Ug - Uo) / np.linalg.norm(Uo))
+        out["rel_l2_vs_oracle"] = err
     print(json.dumps(out), flush=True)
 
 
