@@ -1,4 +1,4 @@
-"""IIF2 time stepping with the implicit reaction stage.
+"""IIF2 and IIF3 time stepping with the implicit reaction stage.
 
 Paper: Sec. 3, integrating-factor form (3.2), the r-th order family (3.3)
 with Lagrange coefficients (3.4), and IIF2 (3.5):
@@ -22,6 +22,9 @@ Readings:
   (same input, same value).
 * One Krylov exponential per species (the diffusion operator of a system is
   block diagonal, species s scaled by D_s).
+* IIF3 (3.6): terms under one exponential share a Krylov evaluation, the
+  stage coefficient is alpha_1 dt = 5 dt / 12 with initial guess
+  W + alpha_1 dt F(U^n), and the first step is one IIF2 step (start-up).
 """
 from __future__ import annotations
 
@@ -73,12 +76,14 @@ class Problem:
         return reaction.F(self.quad, self.rx, U)
 
 
-def implicit_stage(prob: Problem, W, Fn, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT):
-    """Pointwise quasi-Newton solve of U - dt/2 F(U) = W.
+def implicit_stage(prob: Problem, W, Fn, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT, coef=None):
+    """Pointwise quasi-Newton solve of U - c F(U) = W, c = coef (default dt/2,
+    the IIF2 stage; IIF3 uses c = alpha_1 dt = 5 dt / 12).  Initial guess
+    W + c F(U^n).
 
     Returns (U, F(U), info) with info = {iters, residual, converged}.
     """
-    dt2 = 0.5 * prob.dt
+    dt2 = 0.5 * prob.dt if coef is None else float(coef)
     S = prob.S
     U = W + dt2 * Fn
     wnorm = float(np.linalg.norm(W))
@@ -132,15 +137,16 @@ def implicit_stage_newton_dense(prob: Problem, W, Fn, tol=1e-14, max_iter=30):
     return U
 
 
-def expv_species(prob: Problem, v, dense: bool = False):
-    """exp(A_s dt) v_s for every species (Krylov with M, or dense)."""
+def expv_species(prob: Problem, v, dense: bool = False, h=None):
+    """exp(A_s h) v_s for every species (Krylov with M, or dense); h = dt by default."""
+    h = prob.dt if h is None else float(h)
     out, infos = [], []
     for s in range(prob.S):
         if dense:
-            out.append(krylov.dense_expv(prob.A[s], prob.dt, v[s]))
+            out.append(krylov.dense_expv(prob.A[s], h, v[s]))
             infos.append({"m": -1})
         else:
-            w, info = krylov.expv(prob.A[s], prob.dt, v[s], prob.M, prob.anorm[s])
+            w, info = krylov.expv(prob.A[s], h, v[s], prob.M, prob.anorm[s])
             out.append(w)
             infos.append(info)
     return np.array(out), infos
@@ -164,3 +170,43 @@ def iif2_run(prob: Problem, U0, steps: int, dense=False, tol=TOL_DEFAULT, max_it
         U, Fn, info = iif2_step(prob, U, Fn, dense, tol, max_iter)
         infos.append(info)
     return U, Fn, infos
+
+
+def iif3_step(prob: Problem, U, Fn, Fnm1, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT):
+    """One IIF3 step (3.6), the r = 3 member of (3.3) with the coefficients (3.4):
+
+        U^{n+1} = e^{A dt} U^n + dt (alpha_1 F(U^{n+1}) + alpha_0 e^{A dt} F(U^n)
+                                     + alpha_{-1} e^{2 A dt} F(U^{n-1})),
+        alpha_1 = 5/12, alpha_0 = 2/3, alpha_{-1} = -1/12.
+
+    Reading: terms under the same exponential share one Krylov evaluation (as
+    in IIF2, (3.5)): W = exp(A dt)(U^n + alpha_0 dt F^n) + exp(2 A dt)(alpha_{-1}
+    dt F^{n-1}), each by its own Arnoldi process with h = dt and h = 2 dt; the
+    implicit stage solves U - alpha_1 dt F(U) = W.
+    Returns (U^{n+1}, F(U^{n+1}), info)."""
+    al = iif_alpha(3)
+    dt = prob.dt
+    W, kinfo = expv_species(prob, U + al[0] * dt * Fn, dense, h=dt)
+    W2, kinfo2 = expv_species(prob, al[1] * dt * Fnm1, dense, h=2.0 * dt)
+    U1, F1, ninfo = implicit_stage(prob, W + W2, Fn, tol, max_iter, coef=al[-1] * dt)
+    ninfo["krylov"] = kinfo
+    ninfo["krylov2"] = kinfo2
+    return U1, F1, ninfo
+
+
+def iif3_run(prob: Problem, U0, steps: int, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT):
+    """`steps` steps of IIF3 from U0; the first step, which has no F(U^{n-1}),
+    is one IIF2 step (reading: the paper does not state its start-up).
+    Returns (U, F(U), F(U^{n-1}) of the last step, infos)."""
+    U = np.array(U0, dtype=np.float64).reshape(prob.S, prob.ndof)
+    Fn = prob.F(U)
+    Fp = None
+    infos = []
+    for n in range(steps):
+        if n == 0:
+            U1, F1, info = iif2_step(prob, U, Fn, dense, tol, max_iter)
+        else:
+            U1, F1, info = iif3_step(prob, U, Fn, Fp, dense, tol, max_iter)
+        U, Fp, Fn = U1, Fn, F1
+        infos.append(info)
+    return U, Fn, Fp, infos

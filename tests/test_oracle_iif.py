@@ -101,3 +101,62 @@ def test_example4_matches_table7(golden_dir):
         assert abs(verr[i] / g["v_error"][i] - 1) < 0.15, (verr, g["v_error"])
         assert abs(verr[i] / uerr[i] / (b - c) - 1) < 0.02
     assert all(1.7 < np.log2(uerr[i] / uerr[i + 1]) < 2.3 for i in range(2))
+
+
+def _ode_error(scheme, dt, T=1.0, u0=0.8):
+    """Spatially constant state, f = -u^2: A keeps constants (exp(A dt) is the
+    identity on them, Krylov breaks down at m = 1), so the scheme reduces to
+    its scalar form for u' = -u^2, u(t) = u0 / (1 + u0 t)."""
+    prob = iif.Problem(2, 3, 1, [1.0], I.rx_quadratic(-1.0), dt, 8)
+    U0 = np.zeros((1, prob.ndof))
+    U0[0, 0] = u0
+    steps = int(round(T / dt))
+    if scheme == 2:
+        U, _, _ = iif.iif2_run(prob, U0, steps, tol=1e-15)
+    else:
+        U, _, _, _ = iif.iif3_run(prob, U0, steps, tol=1e-15)
+    assert np.abs(U[0, 1:]).max() < 1e-14
+    return abs(U[0, 0] - u0 / (1.0 + u0 * T))
+
+
+def test_iif3_is_third_order_and_iif2_second_order_in_time():
+    """(3.3)-(3.6): IIF3 (with one IIF2 start-up step) converges at order 3 and
+    IIF2 at order 2; a wrong coefficient or exponential shift in the IIF3
+    combination drops its order."""
+    e3 = [_ode_error(3, dt) for dt in (0.1, 0.05, 0.025)]
+    e2 = [_ode_error(2, dt) for dt in (0.1, 0.05, 0.025)]
+    r3 = [np.log2(e3[i] / e3[i + 1]) for i in range(2)]
+    r2 = [np.log2(e2[i] / e2[i + 1]) for i in range(2)]
+    assert all(2.8 < r < 3.3 for r in r3), r3
+    assert all(1.8 < r < 2.2 for r in r2), r2
+    assert e3[-1] < e2[-1] / 10
+
+
+def test_iif3_zero_reaction_is_repeated_exponential():
+    d, N, k = 2, 4, 1
+    prob = iif.Problem(d, N, k, [0.1], I.rx_zeros(1), 0.01, 12)
+    U0 = np.random.default_rng(3).uniform(-1, 1, (1, prob.ndof))
+    U, _, _, infos = iif.iif3_run(prob, U0, 3)
+    v = U0[0]
+    for _ in range(3):
+        v, _ = krylov.expv(prob.A[0], prob.dt, v, 12, prob.anorm[0])
+    assert np.abs(U[0] - v).max() < 1e-14
+    assert infos[1]["krylov2"][0]["m"] == 0  # exp(2 A dt) of the zero vector
+
+
+def test_iif3_stage_root_with_dense_exponentials():
+    """The IIF3 stage solves U - (5/12) dt F(U) = W with W from the two
+    exponentials; with dense exponentials the result satisfies (3.6) exactly."""
+    from scipy.linalg import expm
+
+    d, N, k = 2, 3, 1
+    dt = 0.02
+    prob = iif.Problem(d, N, k, [0.5], I.rx_quadratic(-1.0), dt, 10)
+    U0 = project.project_terms(d, N, k, [(0.5, [I.SIN, I.SIN]), (0.3, [I.ONE, I.ONE])])[None]
+    Um1 = 0.9 * U0
+    Fn, Fm1 = prob.F(U0), prob.F(Um1)
+    U1, F1, info = iif.iif3_step(prob, U0, Fn, Fm1, dense=True, tol=1e-15)
+    E = expm(dt * prob.A[0].toarray() if hasattr(prob.A[0], "toarray") else dt * prob.A[0])
+    rhs = E @ U0[0] + dt * (5 / 12 * F1[0] + 2 / 3 * (E @ Fn[0]) - 1 / 12 * (E @ (E @ Fm1[0])))
+    assert info["converged"]
+    assert np.abs(U1[0] - rhs).max() < 1e-13 * max(1.0, np.abs(rhs).max())
