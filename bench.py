@@ -106,6 +106,47 @@ def run_steps(sg, torch, wl, prec, U0, steps, warmup, graph=True):
     return secs, U, stats, done + max(0, warmup - done)
 
 
+def run_steps_iif3(sg, torch, wl, U0, steps, warmup):
+    """IIF3 (Sec. 3, eq. 3.6) on the workload: one IIF2 start-up step, then
+    IIF3 steps replayed from a captured graph.  Returns (seconds, stats)."""
+    plan = sg.Plan(wl.instances, "fp64")
+    Ud = torch.from_numpy(U0.copy()).cuda()
+    Fc = torch.zeros_like(Ud)
+    _, ib = plan.workspace_size(wl.M, 1)
+    ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
+    st = torch.zeros(len(wl.instances) * 2 * sg.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    plan.reaction(Ud, Fc, ws)
+    Fp = Fc.clone()
+    plan.iif2_step(wl.dt, wl.M, Ud, Fc, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX, stats=st)
+
+    def step():
+        plan.iif3_step(wl.dt, wl.M, Ud, Fc, Fp, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX, stats=st)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for _ in range(max(0, warmup - 2)):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3
+    stats = sg.stats_array(st)
+    del g
+    plan.close()
+    return secs, stats
+
+
 def kernel_source_hash():
     """Hash of the sweep kernel sources (traffic counters are only valid for this code)."""
     h = hashlib.sha256()
@@ -215,6 +256,7 @@ def main():
     ap.add_argument("--eager", action="store_true", help="launch steps eagerly instead of replaying a graph")
     ap.add_argument("--no-big", action="store_true", help="skip the out-of-cache sweep measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance Gray-Scott batch")
+    ap.add_argument("--no-iif3", action="store_true", help="skip the IIF3 leg")
     ap.add_argument("--batched-steps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -255,6 +297,12 @@ def main():
             mixed[prec] = {"value": ndps * args.steps / s2, "ms_per_step": 1e3 * s2 / args.steps,
                            "rel_l2_vs_fp64": rel, "status_ok": bool(np.all(stp["status"][:2] == 0))}
         out["mixed"] = mixed
+    if not args.no_iif3:
+        log("[bench] iif3")
+        s3, st3 = run_steps_iif3(sg, torch, wl, U0, args.steps, args.warmup)
+        out["iif3"] = {"value": ndps * args.steps / s3, "ms_per_step": 1e3 * s3 / args.steps,
+                       "status_ok": bool(np.all(st3["status"][: 2 * len(wl.instances)] == 0)),
+                       "note": "same workload with IIF3 (eq. 3.6): two Krylov exponentials per step"}
     # roofline of the dominant kernel: the operator sweep (the same kernel the
     # step launches for every Krylov vector), timed live on the workload plan
     log("[bench] sweep timing")

@@ -138,7 +138,7 @@ sgdg_status sg_dg_info(const sgdg_plan* plan, int32_t inst, int64_t* ndof, int64
 /* Entries of one plan vector (sum over instances of nspecies * ndof). */
 sgdg_status sg_dg_total(const sgdg_plan* plan, int64_t* total);
 
-/* Device workspace (bytes) needed by krylov_expv and by iif2_step for Krylov
+/* Device workspace (bytes) needed by krylov_expv and by iif2_step / iif3_step for Krylov
  * dimension M (1..48) and nrhs right-hand sides.                            */
 sgdg_status sg_dg_workspace_size(const sgdg_plan* plan, int32_t M, int32_t nrhs, size_t* krylov_bytes,
                                  size_t* iif2_bytes);
@@ -202,6 +202,20 @@ sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const double* U, 
  * first step) and F(U') on return; NULL recomputes it every step.
  * workspace: at least iif2_bytes.  stats: device array or NULL.             */
 sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcache,
+                      double newton_tol, int32_t newton_max, void* workspace, size_t workspace_bytes,
+                      sgdg_stats* stats, void* stream);
+
+/* One IIF3 step (Sec. 3, eq. 3.6; coefficients 5/12, 2/3, -1/12 of eq. 3.4):
+ *   W = exp(A dt)(U + 2/3 dt F(U)) + exp(2 A dt)(-1/12 dt F(U^{n-1}))
+ * (each exponential by its own Krylov process of dimension M), then the
+ * implicit stage of iif2_step with coefficient 5/12 dt in place of dt/2, from
+ * U = W + 5/12 dt F(U).  U: device FP64 plan vectors, updated in place.
+ * Fcur: F(U^n) on entry, F(U^{n+1}) on return.  Fprev: F(U^{n-1}) on entry,
+ * F(U^n) on return.  The three must not alias.  A run starts with one
+ * iif2_step (the scheme needs F at two earlier levels), then F(U^0) becomes
+ * Fprev.  workspace: at least iif2_bytes.  stats: as iif2_step (the Krylov
+ * entries describe the exp(A dt) process).  Errors as iif2_step.            */
+sgdg_status iif3_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcur, double* Fprev,
                       double newton_tol, int32_t newton_max, void* workspace, size_t workspace_bytes,
                       sgdg_stats* stats, void* stream);
 

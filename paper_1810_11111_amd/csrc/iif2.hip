@@ -1,4 +1,5 @@
-// IIF2 time step (Sec. 3, eq. 3.5) with the implicit reaction stage.
+// IIF2 and IIF3 time steps (Sec. 3, eqs. 3.5 and 3.6) with the implicit
+// reaction stage.
 //
 //   v = U^n + dt/2 F(U^n);  W = exp(A dt) v  (one Krylov problem per species);
 //   solve  U - dt/2 F(U) = W  by the pointwise quasi-Newton iteration
@@ -11,6 +12,10 @@
 // convergence flag that every later kernel of the step reads, so a step is a
 // fixed launch sequence (newton_max + 1 residual passes) that can be captured
 // in a graph; converged instances skip their work.
+//
+// IIF3 (eq. 3.6, coefficients of eq. 3.4: 5/12, 2/3, -1/12):
+//   W = exp(A dt)(U^n + 2/3 dt F^n) + exp(2 A dt)(-1/12 dt F^{n-1}),
+//   solve U - 5/12 dt F(U) = W the same way from U = W + 5/12 dt F^n.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -27,7 +32,7 @@ static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct IifWs {
   KrylovWs kws;
   double* rws;
-  double *v, *W, *G, *F;
+  double *v, *W, *G, *F, *W2;
   double *part, *partw, *wnorm;
   int32_t* conv;
 };
@@ -36,7 +41,7 @@ size_t iif2_ws_bytes(const sgdg_plan* plan, int M, int nrhs) {
   const size_t tot = (size_t)plan->total * nrhs;
   size_t b = al256(krylov_ws_bytes(plan, M, nrhs));
   b += al256((size_t)reaction_ws_doubles(plan) * nrhs * 8);
-  b += 4 * al256(tot * 8);
+  b += 5 * al256(tot * 8);
   b += al256((size_t)nrhs * reaction_final_fibres(plan) * 8);
   b += al256((size_t)nrhs * plan->nchunks * 8);
   b += al256((size_t)nrhs * plan->ninst * 8);
@@ -60,6 +65,7 @@ static IifWs carve(const sgdg_plan* plan, int M, int nrhs, void* base) {
   w.W = (double*)take(tot * 8);
   w.G = (double*)take(tot * 8);
   w.F = (double*)take(tot * 8);
+  w.W2 = (double*)take(tot * 8);
   w.part = (double*)take((size_t)nrhs * reaction_final_fibres(plan) * 8);
   w.partw = (double*)take((size_t)nrhs * plan->nchunks * 8);
   w.wnorm = (double*)take((size_t)nrhs * plan->ninst * 8);
@@ -72,6 +78,19 @@ __global__ __launch_bounds__(256) void k_axpy(double* __restrict__ out, const do
                                               const double* __restrict__ y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = x[i] + a * y[i];
+}
+
+// out = a y
+__global__ __launch_bounds__(256) void k_scale(double* __restrict__ out, double a, const double* __restrict__ y,
+                                               int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * y[i];
+}
+
+// out = y
+__global__ __launch_bounds__(256) void k_copy(double* __restrict__ out, const double* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = y[i];
 }
 
 // U = W + dt2 F, per-chunk ||W||^2, reset of the convergence flags
@@ -145,6 +164,33 @@ __global__ __launch_bounds__(64) void k_check(DevTables T, const int64_t* __rest
     }
 }
 
+// U - c F(U) = W from U = W + c F (F holds F(U^n) on entry and F(U) of the
+// accepted iterate on return)
+static void implicit_stage(const sgdg_plan* plan, int nrhs, double c, double* U, double* F, const IifWs& w,
+                           double newton_tol, int newton_max, sgdg_stats* stats, hipStream_t s) {
+  const dim3 cgrid((unsigned)plan->nchunks, (unsigned)nrhs);
+  hipLaunchKernelGGL(k_stage_init, cgrid, dim3(CHUNK), 0, s, plan->dev, plan->ninst, plan->nchunks, plan->total, c, U,
+                     w.W, F, w.partw, w.conv);
+  RxArgs a{};
+  a.rws = w.rws;
+  a.dt2 = c;
+  a.U = U;
+  a.W = w.W;
+  a.F = F;
+  a.Gout = w.G;
+  a.G = w.G;
+  a.part = w.part;
+  a.conv = w.conv;
+  const int64_t nfin = reaction_final_fibres(plan);
+  for (int it = 0; it <= newton_max; ++it) {
+    reaction_pass(plan, nrhs, RX_RESID, a, s);
+    hipLaunchKernelGGL(k_check, dim3((unsigned)plan->ninst, (unsigned)nrhs), dim3(64), 0, s, plan->dev,
+                       ((const RHost*)plan->rdata)->dev.cum_fin, plan->ninst, plan->nchunks, nfin, it, newton_max,
+                       newton_tol, w.part, w.partw, w.wnorm, w.conv, stats);
+    if (it < newton_max) reaction_pass(plan, nrhs, RX_CORR, a, s);
+  }
+}
+
 static sgdg_status check_launch(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, what);
@@ -200,23 +246,37 @@ extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.v, U, dt2, F, n);
   sgdg_status st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s);
   if (st != SGDG_OK) return st;
-  const dim3 cgrid((unsigned)plan->nchunks, (unsigned)nrhs);
-  hipLaunchKernelGGL(k_stage_init, cgrid, dim3(CHUNK), 0, s, plan->dev, plan->ninst, plan->nchunks, plan->total, dt2, U,
-                     w.W, F, w.partw, w.conv);
-  a.U = U;
-  a.W = w.W;
-  a.F = F;
-  a.Gout = w.G;
-  a.G = w.G;
-  a.part = w.part;
-  a.conv = w.conv;
-  const int64_t nfin = reaction_final_fibres(plan);
-  for (int it = 0; it <= newton_max; ++it) {
-    reaction_pass(plan, nrhs, RX_RESID, a, s);
-    hipLaunchKernelGGL(k_check, dim3((unsigned)plan->ninst, (unsigned)nrhs), dim3(64), 0, s, plan->dev,
-                       ((const RHost*)plan->rdata)->dev.cum_fin, plan->ninst, plan->nchunks, nfin, it, newton_max,
-                       newton_tol, w.part, w.partw, w.wnorm, w.conv, stats);
-    if (it < newton_max) reaction_pass(plan, nrhs, RX_CORR, a, s);
-  }
+  implicit_stage(plan, nrhs, dt2, U, F, w, newton_tol, newton_max, stats, s);
   return check_launch("iif2_step launch");
+}
+
+extern "C" sgdg_status iif3_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcur,
+                                 double* Fprev, double newton_tol, int32_t newton_max, void* workspace,
+                                 size_t workspace_bytes, sgdg_stats* stats, void* stream) {
+  if (!plan) return fail(SGDG_ERR_ARG, "iif3_step: null plan");
+  if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "iif3_step: nrhs must be in 1..65535");
+  if (M < 1 || M > SGDG_MAX_M) return fail(SGDG_ERR_ARG, "iif3_step: M must be in 1..48");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SGDG_ERR_ARG, "iif3_step: dt must be positive");
+  if (!(newton_tol >= 0.0)) return fail(SGDG_ERR_ARG, "iif3_step: newton_tol must be >= 0");
+  if (newton_max < 0 || newton_max > 1000) return fail(SGDG_ERR_ARG, "iif3_step: newton_max must be in 0..1000");
+  if (!U || !Fcur || !Fprev || !workspace) return fail(SGDG_ERR_ARG, "iif3_step: null device pointer");
+  if (U == Fcur || U == Fprev || Fcur == Fprev) return fail(SGDG_ERR_ARG, "iif3_step: U, Fcur and Fprev must not alias");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "iif3_step: (k+1) 2^N above 2048 per axis");
+  if (workspace_bytes < iif2_ws_bytes(plan, M, nrhs)) return fail(SGDG_ERR_ARG, "iif3_step: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  IifWs w = carve(plan, M, nrhs, workspace);
+  const int64_t n = plan->total * (int64_t)nrhs;
+  const dim3 vg((unsigned)((n + 255) / 256)), vb(256);
+  // exp(2 A dt)(-1/12 dt F^{n-1}); F^{n-1} is then replaced by F^n
+  hipLaunchKernelGGL(k_scale, vg, vb, 0, s, w.v, -dt / 12.0, Fprev, n);
+  sgdg_status st = krylov_run(plan, nrhs, 2.0 * dt, M, w.v, w.W2, w.kws, stats, s);
+  if (st != SGDG_OK) return st;
+  hipLaunchKernelGGL(k_copy, vg, vb, 0, s, Fprev, Fcur, n);
+  // exp(A dt)(U^n + 2/3 dt F^n), plus the first term
+  hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.v, U, 2.0 * dt / 3.0, Fcur, n);
+  st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s);
+  if (st != SGDG_OK) return st;
+  hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.W, w.W, 1.0, w.W2, n);
+  implicit_stage(plan, nrhs, 5.0 * dt / 12.0, U, Fcur, w, newton_tol, newton_max, stats, s);
+  return check_launch("iif3_step launch");
 }

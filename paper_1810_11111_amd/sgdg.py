@@ -67,6 +67,7 @@ _sigs = {
     "krylov_expv": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _sz, _vp, _vp], C.c_int),
     "sgdg_reaction": ([_vp, _i32, _vp, _vp, _vp, _sz, _vp], C.c_int),
     "iif2_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
+    "iif3_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
 }
 EXPORTED = sorted(_sigs)
 for _name, (_args, _res) in _sigs.items():
@@ -207,6 +208,12 @@ class Plan:
         _check(_lib.iif2_step(self._h, nrhs, float(dt), M, _ptr(U), _ptr(Fcache), float(newton_tol), newton_max,
                               _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(stats),
                               _stream(stream)), "iif2_step")
+
+    def iif3_step(self, dt, M, U, Fcur, Fprev, workspace, newton_tol=1e-14, newton_max=50, stats=None, nrhs=1,
+                  stream=None):
+        _check(_lib.iif3_step(self._h, nrhs, float(dt), M, _ptr(U), _ptr(Fcur), _ptr(Fprev), float(newton_tol),
+                              newton_max, _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(stats),
+                              _stream(stream)), "iif3_step")
 
 
 def stats_array(stats_tensor):

@@ -282,3 +282,73 @@ def test_example4_matches_table7_on_gpu(golden_dir):
     ue = project.l2_error(Ug[0, :nd], fu * P, fu ** 2 * 0.25)
     ve = project.l2_error(Ug[0, nd:], fv * P, fv ** 2 * 0.25)
     assert abs(ue / g["u_error"][0] - 1) < 0.15 and abs(ve / g["v_error"][0] - 1) < 0.15, (ue, ve)
+
+
+# ----------------------------------------------------------------------------- IIF3
+
+def _run_gpu3(plan, wl, U0vec, steps, newton_max=12, tol=1e-14, dt=None):
+    """One iif2_step start-up, then iif3_step (Sec. 3, eq. 3.6)."""
+    import torch
+
+    dt = wl.dt if dt is None else dt
+    Ud = to_dev(U0vec.reshape(1, -1).copy())
+    ws = _ws(plan, wl.M, 1)
+    st = _stats(plan, 1)
+    Fc = torch.zeros_like(Ud)
+    plan.reaction(Ud, Fc, ws)
+    Fp = Fc.clone()
+    for n in range(steps):
+        if n == 0:
+            plan.iif2_step(dt, wl.M, Ud, Fc, ws, newton_tol=tol, newton_max=newton_max, stats=st)
+        else:
+            plan.iif3_step(dt, wl.M, Ud, Fc, Fp, ws, newton_tol=tol, newton_max=newton_max, stats=st)
+    torch.cuda.synchronize()
+    return Ud.cpu().numpy()[0], Fc.cpu().numpy()[0], Fp.cpu().numpy()[0], lib().stats_array(st)
+
+
+@pytest.mark.parametrize("name,kw,steps", [
+    ("schnakenberg_d2", dict(N=5, k=2, steps=4), 4),
+    ("heat_linear_d2", dict(), 5),
+    ("quadratic_d4", dict(N=3, steps=3), 3),
+])
+def test_iif3_matches_oracle(name, kw, steps):
+    """Two Krylov exponentials (h = dt and 2 dt) per step and the 5/12 dt stage."""
+    sg = lib()
+    wl = getattr(I, name)(**kw)
+    inst = wl.instances[0]
+    say("iif3", name, kw, steps)
+    plan = sg.Plan([inst], "fp64")
+    nd = plan.info(0)[0]
+    U0 = _ic_oracle(wl, 0, inst, nd)
+    Ug, Fg, Fpg, st = _run_gpu3(plan, wl, U0.ravel(), steps)
+    prob = _oracle_problem(inst, wl.dt, wl.M)
+    Ur, Fr, Fpr, infos = iif.iif3_run(prob, U0, steps, tol=1e-14)
+    Ug, Fg, Fpg = (a.reshape(inst.species, nd) for a in (Ug, Fg, Fpg))
+    for s in range(inst.species):
+        vnorm = np.linalg.norm(U0[s]) + np.linalg.norm(Ur[s])
+        tol = _step_tol(inst, 2 * wl.dt, vnorm, s, steps, prob.anorm[s])
+        err = np.linalg.norm(Ug[s] - Ur[s])
+        assert err <= tol, f"species {s}: err {err:.3e} > {tol:.3e}"
+        assert st[s]["status"] == 0 and st[s]["krylov_m"] == infos[-1]["krylov"][s]["m"]
+        ftol = tol * max(1.0, np.abs(Fr[s]).max() / max(np.abs(Ur[s]).max(), 1e-300)) * 10
+        assert np.linalg.norm(Fg[s] - Fr[s]) <= ftol and np.linalg.norm(Fpg[s] - Fpr[s]) <= ftol
+
+
+def test_iif3_third_order_on_constant_state():
+    """Spatially constant state, f = -u^2 (A keeps constants): the library's
+    IIF3 converges at third order to u0 / (1 + u0 t) -- a closed form, not the
+    oracle."""
+    sg = lib()
+    inst = I.Instance(2, 3, 1, [1.0], I.rx_quadratic(-1.0))
+    say("iif3 third order")
+    plan = sg.Plan([inst], "fp64")
+    wl = type("StepParams", (), {"M": 8, "dt": None})
+    errs = []
+    for dt in (0.1, 0.05, 0.025):
+        U0 = np.zeros(plan.total)
+        U0[0] = 0.8
+        Ug, _, _, st = _run_gpu3(plan, wl, U0, int(round(1.0 / dt)), dt=dt, tol=1e-15)
+        assert np.abs(Ug[1:]).max() <= 1e-14 and st[0]["status"] == 0
+        errs.append(abs(Ug[0] - 0.8 / 1.8))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(2.8 < r < 3.3 for r in rates), rates
