@@ -323,8 +323,11 @@ def main():
         big = [I.Instance(3, 16, 1, [1.0], I.rx_zeros(1))]
         avg_b, nbytes_b, tot_b = time_sweep(sg, torch, big, "fp64", reps=10)
         out["apply_out_of_cache"] = {"workload": "sweep d=3 N=16 k=1 (24.6M DOF, 197 MB per FP64 vector)",
+                                     "kernel": "apply_kernel<3,1,PrecF64,void> (global gathers)",
                                      "dof": tot_b, "avg_ms": avg_b * 1e3, "achieved_gbs": nbytes_b / avg_b / 1e9,
-                                     "frac_of_peak": nbytes_b / avg_b / 1e9 / HBM_PEAK_GBS}
+                                     "frac_of_peak": nbytes_b / avg_b / 1e9 / HBM_PEAK_GBS,
+                                     "bytes_per_launch": nbytes_b,
+                                     "traffic": traffic_record("apply_kernel", "sweep_d3_n16_k1")}
     if not args.no_batched:
         # 64 independent Gray-Scott instances (levels 5-8, k 1-2) in one plan: every
         # launch of the step covers all of them; FP64 and FP32 sweeps
