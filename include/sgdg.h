@@ -219,6 +219,16 @@ sgdg_status iif3_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M,
                       double newton_tol, int32_t newton_max, void* workspace, size_t workspace_bytes,
                       sgdg_stats* stats, void* stream);
 
+/* One explicit Runge-Kutta step of dU/dt = A U + F(U) (Sec. 4, Table 1: the
+ * RK2 and RK3 comparators whose step limit shows the stiffness of A).  order 2:
+ * U1 = U + dt L(U), U <- (U + U1 + dt L(U1)) / 2; order 3 (Shu-Osher): U1 as
+ * before, U2 = 3/4 U + 1/4 (U1 + dt L(U1)), U <- 1/3 U + 2/3 (U2 + dt L(U2)),
+ * L(U) = A U + F(U).  FP64 plans only (SGDG_ERR_UNSUPPORTED otherwise).  U:
+ * device FP64 plan vectors, updated in place.  workspace: at least
+ * iif2_bytes for M = 1.  Errors: SGDG_ERR_ARG, _UNSUPPORTED, _HIP.          */
+sgdg_status rk_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t order, double* U, void* workspace,
+                    size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,5 +1,5 @@
 // IIF2 and IIF3 time steps (Sec. 3, eqs. 3.5 and 3.6) with the implicit
-// reaction stage.
+// reaction stage, and the explicit SSP Runge-Kutta comparators of Sec. 4.
 //
 //   v = U^n + dt/2 F(U^n);  W = exp(A dt) v  (one Krylov problem per species);
 //   solve  U - dt/2 F(U) = W  by the pointwise quasi-Newton iteration
@@ -85,6 +85,14 @@ __global__ __launch_bounds__(256) void k_scale(double* __restrict__ out, double 
                                                int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a * y[i];
+}
+
+// out = a x + b y + c z
+__global__ __launch_bounds__(256) void k_lin3(double* __restrict__ out, double a, const double* __restrict__ x, double b,
+                                              const double* __restrict__ y, double c, const double* __restrict__ z,
+                                              int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * x[i] + b * y[i] + c * z[i];
 }
 
 // out = y
@@ -279,4 +287,47 @@ extern "C" sgdg_status iif3_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.W, w.W, 1.0, w.W2, n);
   implicit_stage(plan, nrhs, 5.0 * dt / 12.0, U, Fcur, w, newton_tol, newton_max, stats, s);
   return check_launch("iif3_step launch");
+}
+
+// L(V) = A V + F(V) into out (tmp: F(V)); FP64 plans
+static void rk_rhs(const sgdg_plan* plan, int nrhs, const double* V, double* out, double* tmp, const IifWs& w,
+                   hipStream_t s) {
+  launch_apply<PrecF64>(plan, nrhs, V, out, plan->total, plan->total, s);
+  RxArgs a{};
+  a.rws = w.rws;
+  a.U = const_cast<double*>(V);
+  a.F = tmp;
+  reaction_pass(plan, nrhs, RX_F, a, s);
+  const int64_t n = plan->total * (int64_t)nrhs;
+  hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, out, 1.0, tmp, n);
+}
+
+extern "C" sgdg_status rk_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t order, double* U,
+                               void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan) return fail(SGDG_ERR_ARG, "rk_step: null plan");
+  if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "rk_step: nrhs must be in 1..65535");
+  if (order != 2 && order != 3) return fail(SGDG_ERR_ARG, "rk_step: order must be 2 or 3");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SGDG_ERR_ARG, "rk_step: dt must be positive");
+  if (!U || !workspace) return fail(SGDG_ERR_ARG, "rk_step: null device pointer");
+  if (plan->prec != SGDG_FP64) return fail(SGDG_ERR_UNSUPPORTED, "rk_step: FP64 plans only");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "rk_step: (k+1) 2^N above 2048 per axis");
+  if (workspace_bytes < iif2_ws_bytes(plan, 1, nrhs)) return fail(SGDG_ERR_ARG, "rk_step: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  IifWs w = carve(plan, 1, nrhs, workspace);
+  const int64_t n = plan->total * (int64_t)nrhs;
+  const dim3 vg((unsigned)((n + 255) / 256)), vb(256);
+  // stage 1: v = U + dt L(U)
+  rk_rhs(plan, nrhs, U, w.G, w.F, w, s);
+  hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.v, U, dt, w.G, n);
+  rk_rhs(plan, nrhs, w.v, w.G, w.F, w, s);
+  if (order == 2) {
+    // U = 1/2 U + 1/2 (v + dt L(v))
+    hipLaunchKernelGGL(k_lin3, vg, vb, 0, s, U, 0.5, U, 0.5, w.v, 0.5 * dt, w.G, n);
+  } else {
+    // W = 3/4 U + 1/4 (v + dt L(v));  U = 1/3 U + 2/3 (W + dt L(W))
+    hipLaunchKernelGGL(k_lin3, vg, vb, 0, s, w.W, 0.75, U, 0.25, w.v, 0.25 * dt, w.G, n);
+    rk_rhs(plan, nrhs, w.W, w.G, w.F, w, s);
+    hipLaunchKernelGGL(k_lin3, vg, vb, 0, s, U, 1.0 / 3.0, U, 2.0 / 3.0, w.W, 2.0 / 3.0 * dt, w.G, n);
+  }
+  return check_launch("rk_step launch");
 }

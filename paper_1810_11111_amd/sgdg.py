@@ -68,6 +68,7 @@ _sigs = {
     "sgdg_reaction": ([_vp, _i32, _vp, _vp, _vp, _sz, _vp], C.c_int),
     "iif2_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
     "iif3_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
+    "rk_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _sz, _vp], C.c_int),
 }
 EXPORTED = sorted(_sigs)
 for _name, (_args, _res) in _sigs.items():
@@ -214,6 +215,10 @@ class Plan:
         _check(_lib.iif3_step(self._h, nrhs, float(dt), M, _ptr(U), _ptr(Fcur), _ptr(Fprev), float(newton_tol),
                               newton_max, _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(stats),
                               _stream(stream)), "iif3_step")
+
+    def rk_step(self, dt, order, U, workspace, nrhs=1, stream=None):
+        _check(_lib.rk_step(self._h, nrhs, float(dt), order, _ptr(U), _ptr(workspace),
+                            workspace.numel() * workspace.element_size(), _stream(stream)), "rk_step")
 
 
 def stats_array(stats_tensor):

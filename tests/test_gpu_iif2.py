@@ -352,3 +352,61 @@ def test_iif3_third_order_on_constant_state():
         errs.append(abs(Ug[0] - 0.8 / 1.8))
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert all(2.8 < r < 3.3 for r in rates), rates
+
+
+# ----------------------------------------------------------------------------- explicit RK comparator
+
+def _run_rk(plan, U0vec, dt, order, steps):
+    import torch
+
+    Ud = to_dev(U0vec.reshape(1, -1).copy())
+    ws = _ws(plan, 1, 1)
+    for _ in range(steps):
+        plan.rk_step(dt, order, Ud, ws)
+    torch.cuda.synchronize()
+    return Ud.cpu().numpy()[0]
+
+
+@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("name,kw,dt", [
+    ("schnakenberg_d2", dict(N=4, k=2), 2e-6),
+    ("quadratic_d4", dict(N=3), 2e-5),
+])
+def test_rk_step_matches_oracle(order, name, kw, dt):
+    """SSP RK2 / RK3 (Sec. 4 comparators): sweep + reaction + stage combinations."""
+    from oracle import rk
+
+    sg = lib()
+    wl = getattr(I, name)(**kw)
+    inst = wl.instances[0]
+    say("rk", order, name, kw)
+    plan = sg.Plan([inst], "fp64")
+    nd = plan.info(0)[0]
+    U0 = _ic_oracle(wl, 0, inst, nd)
+    Ug = _run_rk(plan, U0.ravel(), dt, order, 5).reshape(inst.species, nd)
+    prob = _oracle_problem(inst, dt, 1)
+    Ur = U0.copy()
+    for _ in range(5):
+        Ur = rk.rk_step(prob, Ur, dt, order)
+    for s in range(inst.species):
+        # five steps of sums of O(1) terms with |dt A| < z_s: a few hundred ulps of the state
+        assert np.linalg.norm(Ug[s] - Ur[s]) <= 1e-13 * max(1.0, np.linalg.norm(Ur[s])), s
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_rk_stability_limit_on_gpu(order):
+    """dt just below z_s / |lambda_0(A)| stays bounded, just above grows (Table 1)."""
+    from oracle import rk
+
+    sg = lib()
+    inst = I.Instance(2, 4, 1, [1.0], I.rx_zeros(1))
+    say("rk stability", order)
+    plan = sg.Plan([inst], "fp64")
+    prob = _oracle_problem(inst, 1.0, 1)
+    lam0 = np.linalg.eigvalsh(prob.A[0].toarray()).min()
+    dt0 = rk.real_stability_limit(order) / abs(lam0)
+    U0 = I.smooth_random(plan.total, 6, 1)[0]
+    for fac, grows in ((0.98, False), (1.03, True)):
+        U = _run_rk(plan, U0, fac * dt0, order, 400)
+        ratio = np.linalg.norm(U) / np.linalg.norm(U0)
+        assert (ratio > 10.0) == grows, (fac, ratio)
