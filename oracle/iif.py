@@ -22,6 +22,9 @@ Readings:
   (same input, same value).
 * One Krylov exponential per species (the diffusion operator of a system is
   block diagonal, species s scaled by D_s).
+* A forcing term of (1.1) (Examples 2 and 3) enters F as its L2 projection
+  S(t) evaluated at the time level of each F (F^{n+1} = P f(R U^{n+1}) +
+  S(t^{n+1}) in the stage).
 * IIF3 (3.6): terms under one exponential share a Krylov evaluation, the
   stage coefficient is alpha_1 dt = 5 dt / 12 with initial guess
   W + alpha_1 dt F(U^n), and the first step is one IIF2 step (start-up).
@@ -60,13 +63,14 @@ def iif_alpha(r: int):
 class Problem:
     """One instance: operator, quadrature, reaction and step parameters."""
 
-    def __init__(self, d, N, k, D, rx, dt, M, sigma=20.0, kappas=None, nq=None):
+    def __init__(self, d, N, k, D, rx, dt, M, sigma=20.0, kappas=None, nq=None, bc="periodic"):
         self.d, self.N, self.k = d, N, k
         self.D = list(D)
         self.S = len(self.D)
         self.rx = np.asarray(rx, dtype=np.float64)
         self.dt, self.M = float(dt), int(M)
-        A1 = assemble_A(d, N, k, sigma, kappas, 1.0)
+        self.bc = bc
+        A1 = assemble_A(d, N, k, sigma, kappas, 1.0, bc)
         self.A = [Ds * A1 for Ds in self.D]
         self.anorm = [inf_norm(a) for a in self.A]
         self.quad = reaction.Quadrature(d, N, k, nq)
@@ -76,14 +80,18 @@ class Problem:
         return reaction.F(self.quad, self.rx, U)
 
 
-def implicit_stage(prob: Problem, W, Fn, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT, coef=None):
-    """Pointwise quasi-Newton solve of U - c F(U) = W, c = coef (default dt/2,
-    the IIF2 stage; IIF3 uses c = alpha_1 dt = 5 dt / 12).  Initial guess
-    W + c F(U^n).
+def implicit_stage(prob: Problem, W, Fn, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT, coef=None, S=None):
+    """Pointwise quasi-Newton solve of U - c (F(U) + S) = W, c = coef (default
+    dt/2, the IIF2 stage; IIF3 uses c = alpha_1 dt = 5 dt / 12), S a source
+    vector at the new time level (projection of a forcing term, or None).
+    Initial guess W + c F^n, F^n the full right-hand side of the old level.
 
-    Returns (U, F(U), info) with info = {iters, residual, converged}.
+    Returns (U, F(U) + S, info) with info = {iters, residual, converged}.
     """
     dt2 = 0.5 * prob.dt if coef is None else float(coef)
+    if S is not None:
+        U, FU, info = implicit_stage(prob, W + dt2 * np.asarray(S), Fn, tol, max_iter, coef=dt2)
+        return U, FU + S, info
     S = prob.S
     U = W + dt2 * Fn
     wnorm = float(np.linalg.norm(W))
@@ -152,27 +160,32 @@ def expv_species(prob: Problem, v, dense: bool = False, h=None):
     return np.array(out), infos
 
 
-def iif2_step(prob: Problem, U, Fn, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT):
-    """One IIF2 step (3.5).  Returns (U^{n+1}, F(U^{n+1}), info)."""
+def iif2_step(prob: Problem, U, Fn, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT, S_next=None):
+    """One IIF2 step (3.5).  Fn: the right-hand side at the old level (reaction
+    plus source); S_next: source vector at the new level or None.
+    Returns (U^{n+1}, F(U^{n+1}) + S_next, info)."""
     v = U + 0.5 * prob.dt * Fn
     W, kinfo = expv_species(prob, v, dense)
-    U1, F1, ninfo = implicit_stage(prob, W, Fn, tol, max_iter)
+    U1, F1, ninfo = implicit_stage(prob, W, Fn, tol, max_iter, S=S_next)
     ninfo["krylov"] = kinfo
     return U1, F1, ninfo
 
 
-def iif2_run(prob: Problem, U0, steps: int, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT):
-    """`steps` IIF2 steps from U0 (species, ndof).  Returns (U, F(U), infos)."""
+def iif2_run(prob: Problem, U0, steps: int, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT, source=None):
+    """`steps` IIF2 steps from U0 (species, ndof); source(t) -> (species, ndof)
+    array or None (time-dependent forcing, F = P f(R U) + source(t)).
+    Returns (U, F(U), infos)."""
     U = np.array(U0, dtype=np.float64).reshape(prob.S, prob.ndof)
-    Fn = prob.F(U)
+    Fn = prob.F(U) + (source(0.0) if source else 0.0)
     infos = []
-    for _ in range(steps):
-        U, Fn, info = iif2_step(prob, U, Fn, dense, tol, max_iter)
+    for n in range(steps):
+        Sn = source((n + 1) * prob.dt) if source else None
+        U, Fn, info = iif2_step(prob, U, Fn, dense, tol, max_iter, S_next=Sn)
         infos.append(info)
     return U, Fn, infos
 
 
-def iif3_step(prob: Problem, U, Fn, Fnm1, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT):
+def iif3_step(prob: Problem, U, Fn, Fnm1, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT, S_next=None):
     """One IIF3 step (3.6), the r = 3 member of (3.3) with the coefficients (3.4):
 
         U^{n+1} = e^{A dt} U^n + dt (alpha_1 F(U^{n+1}) + alpha_0 e^{A dt} F(U^n)
@@ -188,25 +201,26 @@ def iif3_step(prob: Problem, U, Fn, Fnm1, dense=False, tol=TOL_DEFAULT, max_iter
     dt = prob.dt
     W, kinfo = expv_species(prob, U + al[0] * dt * Fn, dense, h=dt)
     W2, kinfo2 = expv_species(prob, al[1] * dt * Fnm1, dense, h=2.0 * dt)
-    U1, F1, ninfo = implicit_stage(prob, W + W2, Fn, tol, max_iter, coef=al[-1] * dt)
+    U1, F1, ninfo = implicit_stage(prob, W + W2, Fn, tol, max_iter, coef=al[-1] * dt, S=S_next)
     ninfo["krylov"] = kinfo
     ninfo["krylov2"] = kinfo2
     return U1, F1, ninfo
 
 
-def iif3_run(prob: Problem, U0, steps: int, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT):
+def iif3_run(prob: Problem, U0, steps: int, dense=False, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFAULT, source=None):
     """`steps` steps of IIF3 from U0; the first step, which has no F(U^{n-1}),
     is one IIF2 step (reading: the paper does not state its start-up).
     Returns (U, F(U), F(U^{n-1}) of the last step, infos)."""
     U = np.array(U0, dtype=np.float64).reshape(prob.S, prob.ndof)
-    Fn = prob.F(U)
+    Fn = prob.F(U) + (source(0.0) if source else 0.0)
     Fp = None
     infos = []
     for n in range(steps):
+        Sn = source((n + 1) * prob.dt) if source else None
         if n == 0:
-            U1, F1, info = iif2_step(prob, U, Fn, dense, tol, max_iter)
+            U1, F1, info = iif2_step(prob, U, Fn, dense, tol, max_iter, S_next=Sn)
         else:
-            U1, F1, info = iif3_step(prob, U, Fn, Fp, dense, tol, max_iter)
+            U1, F1, info = iif3_step(prob, U, Fn, Fp, dense, tol, max_iter, S_next=Sn)
         U, Fp, Fn = U1, Fn, F1
         infos.append(info)
     return U, Fn, Fp, infos

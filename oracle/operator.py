@@ -33,10 +33,16 @@ from .basis import dlegendre01, gauss01, legendre01, to_cell_legendre
 from .sparsegrid import enumerate_dofs
 
 
-def full_grid_sipg(N: int, k: int, sigma: float = 20.0, kappa=None, nquad: int = 12):
-    """1D SIPG matrix B_full[v, u] = B(u, v) on 2^N periodic cells, cell-Legendre basis.
+def full_grid_sipg(N: int, k: int, sigma: float = 20.0, kappa=None, nquad: int = 12, bc: str = "periodic"):
+    """1D SIPG matrix B_full[v, u] = B(u, v) on 2^N cells, cell-Legendre basis.
 
     Cell c basis: h^{-1/2} phi_q((x - c h)/h), h = 2^-N.
+    bc = "periodic": the face at x = 0 joins the last and the first cell.
+    bc = "dirichlet" (zero boundary values): on a boundary face the jump is
+    the one-sided trace times the outward normal and the average of the
+    flux is its one-sided value (the convention stated after eq. 2.11), so the
+    face at x = 0 acts on cell 0 with [u] = -u(0+), {u'} = u'(0+), and the face
+    at x = 1 on the last cell with [u] = u(1-), {u'} = u'(1-).
     """
     nc = 2 ** N
     h = 2.0 ** (-N)
@@ -56,7 +62,15 @@ def full_grid_sipg(N: int, k: int, sigma: float = 20.0, kappa=None, nquad: int =
     v1 = np.array([legendre01(q, 1.0) for q in range(k + 1)])
     d0 = np.array([dlegendre01(q, 0.0) for q in range(k + 1)])
     d1 = np.array([dlegendre01(q, 1.0) for q in range(k + 1)])
-    for e in range(nc):
+    if bc == "dirichlet":
+        for xe, c, jump, der in ((0.0, 0, -v0 / np.sqrt(h), d0 / h ** 1.5), (1.0, nc - 1, v1 / np.sqrt(h), d1 / h ** 1.5)):
+            ke = float(kap(np.array([xe]))[0])
+            loc = -ke * np.outer(jump, der) - ke * np.outer(der, jump) + (sigma / h) * np.outer(jump, jump)
+            s = slice(c * (k + 1), (c + 1) * (k + 1))
+            B[s, s] += loc
+    elif bc != "periodic":
+        raise ValueError(bc)
+    for e in range(1 if bc == "dirichlet" else 0, nc):
         L, R = (e - 1) % nc, e
         xe = e * h
         ke = float(kap(np.array([xe]))[0])
@@ -74,7 +88,7 @@ def full_grid_sipg(N: int, k: int, sigma: float = 20.0, kappa=None, nquad: int =
     return B
 
 
-def hier_operator_1d(N: int, k: int, sigma: float = 20.0, kappa=None, drop_rel: float = 1e-13):
+def hier_operator_1d(N: int, k: int, sigma: float = 20.0, kappa=None, drop_rel: float = 1e-13, bc: str = "periodic"):
     """1D operator in the hierarchical basis (levels 0..N): Bh = T B_full T^T.
 
     Entries below drop_rel * max|Bh| are rounding noise of exact zeros (a
@@ -82,15 +96,16 @@ def hier_operator_1d(N: int, k: int, sigma: float = 20.0, kappa=None, drop_rel: 
     jumps on its support) and are set to zero.
     """
     T = to_cell_legendre(N, k)
-    Bh = T @ full_grid_sipg(N, k, sigma, kappa) @ T.T
+    Bh = T @ full_grid_sipg(N, k, sigma, kappa, bc=bc) @ T.T
     Bh[np.abs(Bh) < drop_rel * np.abs(Bh).max()] = 0.0
     return Bh
 
 
-def assemble_A(d: int, N: int, k: int, sigma: float = 20.0, kappas=None, D: float = 1.0):
+def assemble_A(d: int, N: int, k: int, sigma: float = 20.0, kappas=None, D: float = 1.0, bc: str = "periodic"):
     """Explicit sparse A (scipy CSR, canonical DOF order) for one species.
 
-    kappas: None (k_ii = 1) or a list of d callables k_ii(x).
+    kappas: None (k_ii = 1) or a list of d callables k_ii(x); bc: "periodic" or
+    "dirichlet" (zero boundary values on every face of the cube).
     """
     _, _, _, r1d = enumerate_dofs(d, N, k)
     n1 = (k + 1) * 2 ** N
@@ -105,7 +120,7 @@ def assemble_A(d: int, N: int, k: int, sigma: float = 20.0, kappas=None, D: floa
         kap = None if kappas is None else kappas[i]
         ck = id(kap) if kap is not None else None
         if ck not in cache:
-            cache[ck] = hier_operator_1d(N, k, sigma, kap)
+            cache[ck] = hier_operator_1d(N, k, sigma, kap, bc=bc)
         Bh = cache[ck]
         ri = r1d[:, i]
         for r in np.unique(ri):

@@ -37,6 +37,9 @@ Workloads (d-dimensional periodic unit cube, sigma = 20, nq = k+1):
                    dt=0.005, 100 steps, M=40; batch variant: 16 right-hand sides
                    with amplitudes U[0.1, 1]
 
+  example2 / example3  Examples 2 and 3 of Sec. 4 (periodic with forcing;
+                   zero Dirichlet with u^2 and forcing), analytic data, no seed
+
 Seeds: numpy default_rng(1810_11111 + index), index = 1..5 in the order above.
 """
 from __future__ import annotations
@@ -118,11 +121,12 @@ def fourier_mode_terms(amp: float, freqs, phase: float):
 class Instance:
     """One independent problem: grid, species, reaction, diffusion, kappa."""
 
-    def __init__(self, d, N, k, D, rx, kdiag=None):
+    def __init__(self, d, N, k, D, rx, kdiag=None, bc=0):
         self.d, self.N, self.k = int(d), int(N), int(k)
         self.D = [float(x) for x in D]
         self.rx = np.asarray(rx, dtype=np.float64)
         self.kdiag = kdiag  # None or (a0, a1, f): k_ii(x) = a0 + a1 sin(2 pi f x), every axis
+        self.bc = int(bc)  # 0: periodic, 1: zero Dirichlet on every face
 
     @property
     def species(self):
@@ -130,12 +134,15 @@ class Instance:
 
 
 class Workload:
-    def __init__(self, name, instances, dt, steps, M, prec, ics):
+    def __init__(self, name, instances, dt, steps, M, prec, ics, sources=None):
         self.name = name
         self.instances = instances
         self.dt, self.steps, self.M = float(dt), int(steps), int(M)
         self.prec = prec
         self._ics = ics  # callable(inst_index, ndof) -> list over species of (terms, mult, add)
+        # forcing of species 0: list of (amp, [factor per axis], rate), meaning
+        # sum amp * exp(-rate t) * prod_m g_m(x_m); each side projects it itself
+        self.sources = sources or []
 
     def initial_condition(self, inst: int, ndof: int):
         return self._ics(inst, ndof)
@@ -203,6 +210,40 @@ def quadratic_d4(N=6, nrhs=1, steps=100):
     insts = [Instance(4, N, 1, [1.0], rx_quadratic(-1.0)) for _ in amps]
     return Workload("quadratic_d4", insts, 0.005, steps, 40, "fp64",
                     lambda i, n: [([(float(amps[i]), [SIN] * 4)], [None], None)])
+
+
+def _sin2_terms(d: int, amp: float):
+    """amp * prod_m sin^2(2 pi x_m) = amp * prod_m (1 - cos(4 pi x_m)) / 2 as 2^d separable terms."""
+    terms = []
+    for mask in range(2 ** d):
+        coef = amp * (-1.0) ** bin(mask).count("1") / 2.0 ** d
+        terms.append((coef, [("cos", 2.0, 0.0) if (mask >> m) & 1 else ONE for m in range(d)]))
+    return terms
+
+
+def example2(d=2, N=5, k=1):
+    """Sec. 4, Example 2: u_t = kap Lap u + u - exp(-t) prod sin(2 pi x_i), periodic,
+    u(x, 0) = prod sin(2 pi x_i), exact exp(-t) prod sin(2 pi x_i); kap = 1/(8 pi^2)
+    (2D) or 1/(12 pi^2) (3D); dt = h_N, T = 1 (2D) or 0.4 (3D), M = 25."""
+    kap = 1.0 / (8.0 * math.pi ** 2) if d == 2 else 1.0 / (12.0 * math.pi ** 2)
+    inst = Instance(d, N, k, [kap], rx_linear(1.0))
+    dt = 2.0 ** -N
+    T = 1.0 if d == 2 else 0.4
+    return Workload(f"example2_d{d}", [inst], dt, int(round(T / dt)), 25, "fp64",
+                    lambda i, n: [([(1.0, [SIN] * d)], [None], None)], sources=[(-1.0, [SIN] * d, 1.0)])
+
+
+def example3(d=2, N=5, k=1):
+    """Sec. 4, Example 3: u_t = kap Lap u + u^2 - exp(-2t) prod sin^2(2 pi x_i), zero
+    Dirichlet boundary, u(x, 0) = prod sin(2 pi x_i), exact exp(-t) prod sin(2 pi x_i);
+    kap as Example 2; dt = h_N, T = 1 (2D) or 0.2 (3D), M = 25."""
+    kap = 1.0 / (8.0 * math.pi ** 2) if d == 2 else 1.0 / (12.0 * math.pi ** 2)
+    inst = Instance(d, N, k, [kap], rx_quadratic(1.0), bc=1)
+    dt = 2.0 ** -N
+    T = 1.0 if d == 2 else 0.2
+    src = [(a, f, 2.0) for a, f in _sin2_terms(d, -1.0)]
+    return Workload(f"example3_d{d}", [inst], dt, int(round(T / dt)), 25, "fp64",
+                    lambda i, n: [([(1.0, [SIN] * d)], [None], None)], sources=src)
 
 
 def smooth_random(n: int, seed: int, nrhs: int = 1):
