@@ -80,7 +80,7 @@ typedef struct {
   double a0, a1, freq, phase;
 } sgdg_kdiag;
 
-/* One instance (Sec. 2.1 scheme on [0,1]^d, periodic boundary). */
+/* One instance (Sec. 2.1 scheme on [0,1]^d). */
 typedef struct {
   int32_t d;          /* space dimension, 1..6                                  */
   int32_t n;          /* sparse-grid level N >= 0 (|l|_1 <= N), 2^N finest cells */
@@ -91,6 +91,11 @@ typedef struct {
   const sgdg_kdiag* kdiag; /* NULL: k_ii = 1; else d entries, read during build only */
   /* Reaction f_s(u0, u1) = sum_{a,b=0..3} rx[s][a][b] u0^a u1^b (degree <= 3 used). */
   double rx[2][4][4];
+  /* Boundary: 0 periodic; 1 zero Dirichlet on every face (boundary faces take
+   * the one-sided trace times the outward normal as jump and the one-sided
+   * flux as average, the convention stated after eq. 2.11).                */
+  int32_t bc;
+  int32_t pad;
 } sgdg_desc;
 
 /* A separable 1D factor of initial data, for sg_dg_project. */
@@ -184,12 +189,13 @@ sgdg_status sg_dg_apply(const sgdg_plan* plan, int32_t nrhs, const void* x, void
 sgdg_status krylov_expv(const sgdg_plan* plan, int32_t nrhs, double h, int32_t M, const double* v, double* w,
                         void* workspace, size_t workspace_bytes, sgdg_stats* stats, void* stream);
 
-/* F(U) = P f(R U) (Sec. 5: reconstruction at the Gauss points of the finest
- * mesh, pointwise f, Gauss quadrature back to the sparse space).  U, F:
- * device FP64 plan vectors (nrhs*total), not aliased; workspace as for
- * iif2_step.                                                                */
-sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const double* U, double* F, void* workspace,
-                          size_t workspace_bytes, void* stream);
+/* F(U) = P f(R U) + S (Sec. 5: reconstruction at the Gauss points of the
+ * finest mesh, pointwise f, Gauss quadrature back to the sparse space; S the
+ * projected forcing of the time level, device plan vectors, or NULL).  U, F,
+ * S: device FP64 plan vectors (nrhs*total); F must not alias U or S;
+ * workspace as for iif2_step.                                              */
+sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const double* U, double* F, const double* S,
+                          void* workspace, size_t workspace_bytes, void* stream);
 
 /* One IIF2 step (Sec. 3, eq. 3.5):
  *   W = exp(A dt) (U + dt/2 F(U));  solve U' - dt/2 F(U') = W;  U <- U'.
@@ -200,10 +206,13 @@ sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const double* U, 
  * iterate).  U: device FP64 plan vectors, updated in place.  Fcache: device
  * FP64 plan vectors holding F(U) on entry (computed by sgdg_reaction for the
  * first step) and F(U') on return; NULL recomputes it every step.
- * workspace: at least iif2_bytes.  stats: device array or NULL.             */
+ * S_next: projected forcing at the new time level (F = P f(R U) + S), device
+ * plan vectors or NULL; a source needs Fcache (the old level's F includes
+ * its own source).  workspace: at least iif2_bytes.  stats: device array or
+ * NULL.                                                                    */
 sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcache,
-                      double newton_tol, int32_t newton_max, void* workspace, size_t workspace_bytes,
-                      sgdg_stats* stats, void* stream);
+                      const double* S_next, double newton_tol, int32_t newton_max, void* workspace,
+                      size_t workspace_bytes, sgdg_stats* stats, void* stream);
 
 /* One IIF3 step (Sec. 3, eq. 3.6; coefficients 5/12, 2/3, -1/12 of eq. 3.4):
  *   W = exp(A dt)(U + 2/3 dt F(U)) + exp(2 A dt)(-1/12 dt F(U^{n-1}))
@@ -213,11 +222,12 @@ sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M,
  * Fcur: F(U^n) on entry, F(U^{n+1}) on return.  Fprev: F(U^{n-1}) on entry,
  * F(U^n) on return.  The three must not alias.  A run starts with one
  * iif2_step (the scheme needs F at two earlier levels), then F(U^0) becomes
- * Fprev.  workspace: at least iif2_bytes.  stats: as iif2_step (the Krylov
- * entries describe the exp(A dt) process).  Errors as iif2_step.            */
+ * Fprev.  S_next: forcing at the new level as for iif2_step.  workspace: at
+ * least iif2_bytes.  stats: as iif2_step (the Krylov entries describe the
+ * exp(A dt) process).  Errors as iif2_step.                                 */
 sgdg_status iif3_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcur, double* Fprev,
-                      double newton_tol, int32_t newton_max, void* workspace, size_t workspace_bytes,
-                      sgdg_stats* stats, void* stream);
+                      const double* S_next, double newton_tol, int32_t newton_max, void* workspace,
+                      size_t workspace_bytes, sgdg_stats* stats, void* stream);
 
 /* One explicit Runge-Kutta step of dU/dt = A U + F(U) (Sec. 4, Table 1: the
  * RK2 and RK3 comparators whose step limit shows the stiffness of A).  order 2:

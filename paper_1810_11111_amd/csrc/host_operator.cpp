@@ -3,7 +3,11 @@
 // Bilinear form (Sec. 2.1, eq. 2.10, jumps/averages eq. 2.11) of one axis:
 //   B(u, v) = int k(x) u' v' dx
 //             + sum over faces e of Omega_N: -{k u'}[v] - {k v'}[u] + (sigma/h_N)[u][v],
-// periodic (the face at x = 0 joins the last and first cell), h_N = 2^-N.
+// periodic (the face at x = 0 joins the last and first cell) or zero
+// Dirichlet (the face at x = 0 acts on the first cell with [u] = -u(0+),
+// {k u'} = k u'(0+); the face at x = 1 on the last cell with [u] = u(1-),
+// {k u'} = k u'(1-): trace times outward normal and one-sided flux, the
+// boundary convention stated after eq. 2.11), h_N = 2^-N.
 //
 // Route: for every source hierarchical function, its restriction to the
 // finest cells is obtained by two-scale refinement of the Alpert / Legendre
@@ -41,7 +45,7 @@ inline double kval(const sgdg_kdiag& kd, double x) { return kd.a0 + kd.a1 * std:
 
 }  // namespace
 
-Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd) {
+Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd, int bc) {
   const Basis1D& bs = basis1d(k);
   const int K1 = k + 1, K2 = K1 * K1;
   const long nc = 1L << N;
@@ -90,6 +94,19 @@ Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd) {
     }
   }
 
+  // zero-Dirichlet boundary face matrices (K1 x K1, on one cell): x = 0 acts on
+  // cell 0 (jump -v0/sqrt(h), flux d0/h^1.5), x = 1 on cell nc-1 (v1, d1)
+  std::vector<double> FB0(K2), FB1(K2);
+  {
+    const double k0 = kval(kd, 0.0), k1 = kval(kd, 1.0), sh = std::sqrt(h), h15 = h * sh;
+    for (int a = 0; a < K1; ++a)
+      for (int b = 0; b < K1; ++b) {
+        const double ja0 = -v0[a] / sh, jb0 = -v0[b] / sh, da0 = d0[a] / h15, db0 = d0[b] / h15;
+        const double ja1 = v1[a] / sh, jb1 = v1[b] / sh, da1 = d1[a] / h15, db1 = d1[b] / h15;
+        FB0[a * K1 + b] = -k0 * ja0 * db0 - k0 * da0 * jb0 + sigma / h * ja0 * jb0;
+        FB1[a * K1 + b] = -k1 * ja1 * db1 - k1 * da1 * jb1 + sigma / h * ja1 * jb1;
+      }
+  }
   const double scale_est = sigma * std::ldexp(1.0, 2 * N);
   std::map<std::pair<int32_t, int32_t>, std::vector<double>> blocks;  // (target cell, source cell) -> [pt][ps]
 
@@ -178,6 +195,22 @@ Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd) {
     for (long f = 0; f < nf; ++f) {
       long e = full ? f : a0 + f;
       long em = ((e % nc) + nc) % nc;
+      if (bc == 1 && em == 0) {
+        // the two boundary faces: each couples one end cell with itself
+        for (int p = 0; p < K1; ++p)
+          for (int side = 0; side < 2; ++side) {
+            const long c = side == 0 ? 0 : nc - 1;
+            const double* FB = side == 0 ? FB0.data() : FB1.data();
+            double u[16];
+            for (int q = 0; q < K1; ++q) u[q] = gval(c, p, q);
+            for (int a = 0; a < K1; ++a) {
+              double acc = 0;
+              for (int b = 0; b < K1; ++b) acc += FB[a * K1 + b] * u[b];
+              if (acc != 0.0) addres(c, p, a, acc);
+            }
+          }
+        continue;
+      }
       const double* Fp = constk ? Fconst.data() : &Fall[em * 4 * K2];
       long L = em - 1, R = em;
       for (int p = 0; p < K1; ++p) {
@@ -266,6 +299,7 @@ Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd) {
   op.N = N;
   op.k = k;
   op.sigma = sigma;
+  op.bc = bc;
   op.kd = {kd.a0, kd.a1, kd.freq, kd.phase};
   op.cptr.assign(nc + 1, 0);
   for (auto& kv : blocks) {

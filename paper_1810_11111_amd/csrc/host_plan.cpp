@@ -113,6 +113,7 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
     if (ds.n < 0 || ds.n > 20) return fail(SGDG_ERR_ARG, "sg_dg_build: level N must be in 0..20");
     if (ds.k < 1 || ds.k > SGDG_MAX_K) return fail(SGDG_ERR_ARG, "sg_dg_build: degree k must be in 1..3");
     if (ds.nspecies < 1 || ds.nspecies > 2) return fail(SGDG_ERR_ARG, "sg_dg_build: nspecies must be 1 or 2");
+    if (ds.bc != 0 && ds.bc != 1) return fail(SGDG_ERR_ARG, "sg_dg_build: bc must be 0 (periodic) or 1 (zero Dirichlet)");
     for (int s = 0; s < ds.nspecies; ++s)
       if (!(ds.D[s] > 0.0) || !std::isfinite(ds.D[s])) return fail(SGDG_ERR_ARG, "sg_dg_build: D_s must be positive");
     if (ds.kdiag)
@@ -158,18 +159,18 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
     for (int m = 0; m < d; ++m) np *= (int64_t)K1 << N;
     hi.npoints = np;
     offset += hi.desc.nspecies * hi.ndof;
-    // 1D operators per direction, shared between identical (N, k, sigma, kdiag)
+    // 1D operators per direction, shared between identical (N, k, sigma, bc, kdiag)
     for (int m = 0; m < d; ++m) {
       const sgdg_kdiag& kd = hi.kdiag[m];
       int found = -1;
       for (size_t o = 0; o < p->ops.size(); ++o) {
         const Op1D& op = p->ops[o];
-        if (op.N == N && op.k == hi.desc.k && op.sigma == hi.desc.sigma && op.kd[0] == kd.a0 && op.kd[1] == kd.a1 &&
-            op.kd[2] == kd.freq && op.kd[3] == kd.phase)
+        if (op.N == N && op.k == hi.desc.k && op.sigma == hi.desc.sigma && op.bc == hi.desc.bc && op.kd[0] == kd.a0 &&
+            op.kd[1] == kd.a1 && op.kd[2] == kd.freq && op.kd[3] == kd.phase)
           found = (int)o;
       }
       if (found < 0) {
-        p->ops.push_back(build_op1d(N, hi.desc.k, hi.desc.sigma, kd));
+        p->ops.push_back(build_op1d(N, hi.desc.k, hi.desc.sigma, kd, hi.desc.bc));
         found = (int)p->ops.size() - 1;
       }
       hi.dir_tab.push_back(found);

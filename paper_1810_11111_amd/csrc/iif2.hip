@@ -172,11 +172,16 @@ __global__ __launch_bounds__(64) void k_check(DevTables T, const int64_t* __rest
     }
 }
 
-// U - c F(U) = W from U = W + c F (F holds F(U^n) on entry and F(U) of the
-// accepted iterate on return)
-static void implicit_stage(const sgdg_plan* plan, int nrhs, double c, double* U, double* F, const IifWs& w,
-                           double newton_tol, int newton_max, sgdg_stats* stats, hipStream_t s) {
+// U - c (F(U) + S) = W from U = W + c F (F holds the full right-hand side of
+// the old level on entry and F(U) + S of the accepted iterate on return; S
+// may be null)
+static void implicit_stage(const sgdg_plan* plan, int nrhs, double c, double* U, double* F, const double* S,
+                           const IifWs& w, double newton_tol, int newton_max, sgdg_stats* stats, hipStream_t s) {
   const dim3 cgrid((unsigned)plan->nchunks, (unsigned)nrhs);
+  const int64_t n = plan->total * (int64_t)nrhs;
+  const dim3 vg((unsigned)((n + 255) / 256)), vb(256);
+  // a source S at the new level: U - c (P f(R U) + S) = W  <=>  U - c P f(R U) = W + c S
+  if (S) hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.W, w.W, c, S, n);
   hipLaunchKernelGGL(k_stage_init, cgrid, dim3(CHUNK), 0, s, plan->dev, plan->ninst, plan->nchunks, plan->total, c, U,
                      w.W, F, w.partw, w.conv);
   RxArgs a{};
@@ -197,6 +202,7 @@ static void implicit_stage(const sgdg_plan* plan, int nrhs, double c, double* U,
                        newton_tol, w.part, w.partw, w.wnorm, w.conv, stats);
     if (it < newton_max) reaction_pass(plan, nrhs, RX_CORR, a, s);
   }
+  if (S) hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, F, F, 1.0, S, n);  // F(U) of the new level includes S
 }
 
 static sgdg_status check_launch(const char* what) {
@@ -209,12 +215,13 @@ static sgdg_status check_launch(const char* what) {
 
 using namespace sgdg;
 
-extern "C" sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const double* U, double* F, void* workspace,
-                                     size_t workspace_bytes, void* stream) {
+extern "C" sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const double* U, double* F, const double* S,
+                                     void* workspace, size_t workspace_bytes, void* stream) {
   if (!plan) return fail(SGDG_ERR_ARG, "sgdg_reaction: null plan");
   if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "sgdg_reaction: nrhs must be in 1..65535");
   if (!U || !F || !workspace) return fail(SGDG_ERR_ARG, "sgdg_reaction: null device pointer");
-  if ((const void*)U == (const void*)F) return fail(SGDG_ERR_ARG, "sgdg_reaction: U and F must not alias");
+  if ((const void*)U == (const void*)F || (const void*)S == (const void*)F)
+    return fail(SGDG_ERR_ARG, "sgdg_reaction: F must not alias U or S");
   if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "sgdg_reaction: (k+1) 2^N above 2048 per axis");
   if (workspace_bytes < iif2_ws_bytes(plan, 1, nrhs)) return fail(SGDG_ERR_ARG, "sgdg_reaction: workspace too small");
   IifWs w = carve(plan, 1, nrhs, workspace);
@@ -223,12 +230,16 @@ extern "C" sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const 
   a.F = F;
   a.rws = w.rws;
   reaction_pass(plan, nrhs, RX_F, a, (hipStream_t)stream);
+  if (S) {
+    const int64_t n = plan->total * (int64_t)nrhs;
+    hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, F, F, 1.0, S, n);
+  }
   return check_launch("sgdg_reaction launch");
 }
 
 extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcache,
-                                 double newton_tol, int32_t newton_max, void* workspace, size_t workspace_bytes,
-                                 sgdg_stats* stats, void* stream) {
+                                 const double* S_next, double newton_tol, int32_t newton_max, void* workspace,
+                                 size_t workspace_bytes, sgdg_stats* stats, void* stream) {
   if (!plan) return fail(SGDG_ERR_ARG, "iif2_step: null plan");
   if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "iif2_step: nrhs must be in 1..65535");
   if (M < 1 || M > SGDG_MAX_M) return fail(SGDG_ERR_ARG, "iif2_step: M must be in 1..48");
@@ -236,6 +247,7 @@ extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   if (!(newton_tol >= 0.0)) return fail(SGDG_ERR_ARG, "iif2_step: newton_tol must be >= 0");
   if (newton_max < 0 || newton_max > 1000) return fail(SGDG_ERR_ARG, "iif2_step: newton_max must be in 0..1000");
   if (!U || !workspace) return fail(SGDG_ERR_ARG, "iif2_step: null device pointer");
+  if (S_next && !Fcache) return fail(SGDG_ERR_ARG, "iif2_step: a source needs the F cache (F of the old level)");
   if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "iif2_step: (k+1) 2^N above 2048 per axis");
   if (workspace_bytes < iif2_ws_bytes(plan, M, nrhs)) return fail(SGDG_ERR_ARG, "iif2_step: workspace too small");
   hipStream_t s = (hipStream_t)stream;
@@ -254,13 +266,13 @@ extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.v, U, dt2, F, n);
   sgdg_status st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s);
   if (st != SGDG_OK) return st;
-  implicit_stage(plan, nrhs, dt2, U, F, w, newton_tol, newton_max, stats, s);
+  implicit_stage(plan, nrhs, dt2, U, F, S_next, w, newton_tol, newton_max, stats, s);
   return check_launch("iif2_step launch");
 }
 
 extern "C" sgdg_status iif3_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcur,
-                                 double* Fprev, double newton_tol, int32_t newton_max, void* workspace,
-                                 size_t workspace_bytes, sgdg_stats* stats, void* stream) {
+                                 double* Fprev, const double* S_next, double newton_tol, int32_t newton_max,
+                                 void* workspace, size_t workspace_bytes, sgdg_stats* stats, void* stream) {
   if (!plan) return fail(SGDG_ERR_ARG, "iif3_step: null plan");
   if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "iif3_step: nrhs must be in 1..65535");
   if (M < 1 || M > SGDG_MAX_M) return fail(SGDG_ERR_ARG, "iif3_step: M must be in 1..48");
@@ -285,7 +297,7 @@ extern "C" sgdg_status iif3_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s);
   if (st != SGDG_OK) return st;
   hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.W, w.W, 1.0, w.W2, n);
-  implicit_stage(plan, nrhs, 5.0 * dt / 12.0, U, Fcur, w, newton_tol, newton_max, stats, s);
+  implicit_stage(plan, nrhs, 5.0 * dt / 12.0, U, Fcur, S_next, w, newton_tol, newton_max, stats, s);
   return check_launch("iif3_step launch");
 }
 

@@ -99,6 +99,7 @@ struct Op1D {  // host cell-block CSR
   std::vector<double> val;  // nnzb * (k+1)^2
   std::vector<double> kd;   // kdiag descriptor used (a0,a1,freq,phase), for sharing
   double sigma;
+  int bc;                   // 0 periodic, 1 zero Dirichlet
 };
 
 }  // namespace sgdg
@@ -150,7 +151,7 @@ const Basis1D& basis1d(int k);
 double hier_value(const Basis1D& b, int level, int j, int p, double x, bool deriv);
 
 // 1D operator (host_operator.cpp)
-Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd);
+Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd, int bc);
 
 // enumeration helpers
 __host__ __device__ inline int level_count(int l) { return l == 0 ? 1 : (1 << (l - 1)); }

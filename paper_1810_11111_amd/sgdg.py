@@ -35,7 +35,7 @@ class Desc(C.Structure):
     _fields_ = [
         ("d", C.c_int32), ("n", C.c_int32), ("k", C.c_int32), ("nspecies", C.c_int32),
         ("sigma", C.c_double), ("D", C.c_double * 2), ("kdiag", C.POINTER(Kdiag)),
-        ("rx", C.c_double * 32),
+        ("rx", C.c_double * 32), ("bc", C.c_int32), ("pad", C.c_int32),
     ]
 
 
@@ -65,9 +65,9 @@ _sigs = {
     "sg_dg_norm_inf": ([_vp, _i32, _i32, C.POINTER(_f64)], C.c_int),
     "sg_dg_apply": ([_vp, _i32, _vp, _vp, _vp], C.c_int),
     "krylov_expv": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _sz, _vp, _vp], C.c_int),
-    "sgdg_reaction": ([_vp, _i32, _vp, _vp, _vp, _sz, _vp], C.c_int),
-    "iif2_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
-    "iif3_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
+    "sgdg_reaction": ([_vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
+    "iif2_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
+    "iif3_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
     "rk_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _sz, _vp], C.c_int),
 }
 EXPORTED = sorted(_sigs)
@@ -111,6 +111,7 @@ def make_desc(inst):
     for i, v in enumerate(rx.ravel()):
         d.rx[i] = float(v)
     d.kdiag = None
+    d.bc = int(getattr(inst, "bc", 0))
     return d
 
 
@@ -200,21 +201,21 @@ class Plan:
                                 workspace.numel() * workspace.element_size(), _ptr(stats), _stream(stream)),
                "krylov_expv")
 
-    def reaction(self, U, F, workspace, nrhs=1, stream=None):
-        _check(_lib.sgdg_reaction(self._h, nrhs, _ptr(U), _ptr(F), _ptr(workspace),
+    def reaction(self, U, F, workspace, nrhs=1, stream=None, source=None):
+        _check(_lib.sgdg_reaction(self._h, nrhs, _ptr(U), _ptr(F), _ptr(source), _ptr(workspace),
                                   workspace.numel() * workspace.element_size(), _stream(stream)), "sgdg_reaction")
 
     def iif2_step(self, dt, M, U, Fcache, workspace, newton_tol=1e-14, newton_max=50, stats=None, nrhs=1,
-                  stream=None):
-        _check(_lib.iif2_step(self._h, nrhs, float(dt), M, _ptr(U), _ptr(Fcache), float(newton_tol), newton_max,
-                              _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(stats),
+                  stream=None, source=None):
+        _check(_lib.iif2_step(self._h, nrhs, float(dt), M, _ptr(U), _ptr(Fcache), _ptr(source), float(newton_tol),
+                              newton_max, _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(stats),
                               _stream(stream)), "iif2_step")
 
     def iif3_step(self, dt, M, U, Fcur, Fprev, workspace, newton_tol=1e-14, newton_max=50, stats=None, nrhs=1,
-                  stream=None):
-        _check(_lib.iif3_step(self._h, nrhs, float(dt), M, _ptr(U), _ptr(Fcur), _ptr(Fprev), float(newton_tol),
-                              newton_max, _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(stats),
-                              _stream(stream)), "iif3_step")
+                  stream=None, source=None):
+        _check(_lib.iif3_step(self._h, nrhs, float(dt), M, _ptr(U), _ptr(Fcur), _ptr(Fprev), _ptr(source),
+                              float(newton_tol), newton_max, _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _ptr(stats), _stream(stream)), "iif3_step")
 
     def rk_step(self, dt, order, U, workspace, nrhs=1, stream=None):
         _check(_lib.rk_step(self._h, nrhs, float(dt), order, _ptr(U), _ptr(workspace),

@@ -29,7 +29,8 @@ def _kappas(inst):
 
 
 def _oracle_problem(inst, dt, M):
-    return iif.Problem(inst.d, inst.N, inst.k, inst.D, inst.rx, dt, M, kappas=_kappas(inst))
+    return iif.Problem(inst.d, inst.N, inst.k, inst.D, inst.rx, dt, M, kappas=_kappas(inst),
+                       bc="dirichlet" if getattr(inst, "bc", 0) else "periodic")
 
 
 def _ic_oracle(wl, i, inst, ndof):
@@ -410,3 +411,105 @@ def test_rk_stability_limit_on_gpu(order):
         U = _run_rk(plan, U0, fac * dt0, order, 400)
         ratio = np.linalg.norm(U) / np.linalg.norm(U0)
         assert (ratio > 10.0) == grows, (fac, ratio)
+
+
+# ----------------------------------------------------------------------------- zero Dirichlet and forcing (Examples 2, 3)
+
+def _run_forced(plan, wl, U0vec, steps, scheme, S0, rate, tol=1e-13):
+    """IIF2 (scheme 2) or one IIF2 start-up + IIF3 (scheme 3) with the forcing
+    S(t) = exp(-rate t) S0 passed at the new level of every step."""
+    import torch
+
+    dt = wl.dt
+    Ud = to_dev(U0vec.reshape(1, -1).copy())
+    ws = _ws(plan, wl.M, 1)
+    st = _stats(plan, 1)
+    Fc = torch.zeros_like(Ud)
+    plan.reaction(Ud, Fc, ws, source=to_dev(S0.reshape(1, -1)))
+    Fp = Fc.clone()
+    for n in range(steps):
+        Sn = to_dev((math.exp(-rate * (n + 1) * dt) * S0).reshape(1, -1))
+        if scheme == 2 or n == 0:
+            plan.iif2_step(dt, wl.M, Ud, Fc, ws, newton_tol=tol, newton_max=20, stats=st, source=Sn)
+        else:
+            plan.iif3_step(dt, wl.M, Ud, Fc, Fp, ws, newton_tol=tol, newton_max=20, stats=st, source=Sn)
+    torch.cuda.synchronize()
+    return Ud.cpu().numpy()[0], lib().stats_array(st)
+
+
+def _example_setup(wl, plan):
+    inst = wl.instances[0]
+    S0_lib = np.zeros(plan.total)
+    S0_orc = np.zeros(plan.total)
+    for a, f, _ in wl.sources:
+        S0_lib += plan.project(0, a, f)
+        S0_orc += project.project_separable(inst.d, inst.N, inst.k, a, f)
+    rate = wl.sources[0][2]
+    return S0_lib, S0_orc, rate
+
+
+@pytest.mark.parametrize("d,N,k", [(2, 4, 1), (2, 3, 2), (3, 3, 1)])
+def test_apply_dirichlet_matches_explicit_operator(d, N, k):
+    from oracle import operator
+
+    sg = lib()
+    inst = I.Instance(d, N, k, [1.0], I.rx_zeros(1), bc=1)
+    say("apply dirichlet", d, N, k)
+    plan = sg.Plan([inst], "fp64")
+    X = I.smooth_random(plan.total, 31, 1)[0]
+    import torch
+
+    yd = torch.zeros(plan.total, dtype=torch.float64, device="cuda")
+    plan.apply(to_dev(X), yd)
+    torch.cuda.synchronize()
+    A = operator.assemble_A(d, N, k, bc="dirichlet")
+    ref = A @ X
+    scale = np.abs(A) @ np.abs(X)
+    assert np.abs(yd.cpu().numpy() - ref).max() <= 1e-13 * scale.max()
+
+
+@pytest.mark.parametrize("example,N,k,scheme,steps", [
+    (I.example2, 4, 1, 2, 16),
+    (I.example3, 4, 1, 2, 16),
+    (I.example3, 3, 2, 3, 8),
+])
+def test_forced_examples_match_oracle(example, N, k, scheme, steps):
+    """Examples 2 (periodic) and 3 (zero Dirichlet) of Sec. 4, full time range
+    at N = 3 or 4: the forcing enters at each new level."""
+    sg = lib()
+    wl = example(2, N, k)
+    inst = wl.instances[0]
+    say("forced", wl.name, N, k, scheme)
+    plan = sg.Plan([inst], "fp64")
+    nd = plan.info(0)[0]
+    S0_lib, S0_orc, rate = _example_setup(wl, plan)
+    assert np.abs(S0_lib - S0_orc).max() <= 1e-14
+    U0 = _ic_oracle(wl, 0, inst, nd)
+    Ug, st = _run_forced(plan, wl, U0.ravel(), steps, scheme, S0_orc, rate)
+    prob = _oracle_problem(inst, wl.dt, wl.M)
+    src = lambda t: (math.exp(-rate * t) * S0_orc)[None]  # noqa: E731
+    run = iif.iif2_run if scheme == 2 else iif.iif3_run
+    Ur = run(prob, U0, steps, tol=1e-13, source=src)[0]
+    tol = _step_tol(inst, 2 * wl.dt, np.linalg.norm(U0) + np.linalg.norm(Ur), 0, steps, prob.anorm[0])
+    assert np.linalg.norm(Ug - Ur[0]) <= tol and st[0]["status"] == 0
+
+
+@pytest.mark.parametrize("example", [I.example2, I.example3])
+def test_forced_examples_converge_on_gpu(example):
+    """P1 IIF2, dt = h_N, T = 1: L2 error against the exact solution
+    exp(-t) prod sin(2 pi x_i) falls at about second order (Tables 5, 6)."""
+    sg = lib()
+    errs = []
+    for N in (3, 4, 5):
+        wl = example(2, N, 1)
+        inst = wl.instances[0]
+        say("forced rates", wl.name, N)
+        plan = sg.Plan([inst], "fp64")
+        S0_lib, _, rate = _example_setup(wl, plan)
+        U0 = plan.project(0, 1.0, [I.SIN, I.SIN])
+        Ug, st = _run_forced(plan, wl, U0, wl.steps, 2, S0_lib, rate)
+        T = wl.steps * wl.dt
+        errs.append(project.l2_error(Ug, math.exp(-T) * U0, math.exp(-2 * T) * 0.25))
+        assert st[0]["status"] == 0
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[-1] < 0.05 and all(1.4 < r < 2.8 for r in rates), (errs, rates)
