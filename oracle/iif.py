@@ -25,6 +25,9 @@ Readings:
 * A forcing term of (1.1) (Examples 2 and 3) enters F as its L2 projection
   S(t) evaluated at the time level of each F (F^{n+1} = P f(R U^{n+1}) +
   S(t^{n+1}) in the stage).
+* Local implicit stage (variant, not the paper's scheme): the stage solved
+  pointwise at the Gauss points, u - c f(u) = R W, then U = P u; Newton per
+  point from u = w, stop at |g| <= 1e-15 max(1, |w|) or 30 corrections.
 * IIF3 (3.6): terms under one exponential share a Krylov evaluation, the
   stage coefficient is alpha_1 dt = 5 dt / 12 with initial guess
   W + alpha_1 dt F(U^n), and the first step is one IIF2 step (start-up).
@@ -117,6 +120,78 @@ def implicit_stage(prob: Problem, W, Fn, tol=TOL_DEFAULT, max_iter=MAX_ITER_DEFA
             dq = [(d * Gq[0] - b * Gq[1]) / det, (a * Gq[1] - c * Gq[0]) / det]
         U = U - np.array([prob.quad.P(dq[s]) for s in range(S)])
         it += 1
+
+
+LOCAL_TOL = 1e-15
+LOCAL_MAX_ITER = 30
+
+
+def solve_pointwise(rx, wq, coef, tol=LOCAL_TOL, max_iter=LOCAL_MAX_ITER):
+    """Solve u - c f(u) = w independently at every point (s x s Newton, s <= 2),
+    from u = w, until |u - c f(u) - w| <= tol * max(1, |w|) at the point (max
+    norm over species) or max_iter corrections.  wq: list over species of
+    point arrays.  Returns the list of solutions."""
+    S = len(wq)
+    u = [np.array(w, dtype=np.float64) for w in wq]
+    wmag = np.maximum(1.0, np.max(np.abs(np.array(wq)), axis=0))
+    active = np.ones(u[0].shape, dtype=bool)
+    for _ in range(max_iter + 1):
+        f = reaction.f_eval(rx, u)
+        g = [u[s] - coef * f[s] - wq[s] for s in range(S)]
+        gmax = np.max(np.abs(np.array(g)), axis=0)
+        active &= ~(gmax <= tol * wmag)
+        if not active.any():
+            break
+        J = reaction.f_jac(rx, u)
+        if S == 1:
+            du = [g[0] / (1.0 - coef * J[0][0])]
+        else:
+            a, b = 1.0 - coef * J[0][0], -coef * J[0][1]
+            c, d = -coef * J[1][0], 1.0 - coef * J[1][1]
+            det = a * d - b * c
+            du = [(d * g[0] - b * g[1]) / det, (a * g[1] - c * g[0]) / det]
+        for s in range(S):
+            u[s] = np.where(active, u[s] - du[s], u[s])
+    return u
+
+
+def implicit_stage_local(prob: Problem, W, coef=None, S=None):
+    """Local implicit stage (the "local implicit property" of IIF schemes that
+    Sec. 5 names as future work for the sparse-grid method): instead of the
+    Galerkin root of U - c P f(R U) = W, solve the reaction problem
+    u - c f(u) = R W independently at every Gauss point of Omega_N and project,
+    U = P u.  A different scheme (collocation of the stage): equal to the
+    Galerkin stage for linear f, close to it (at quadrature-error level) for
+    nonlinear f.  Returns (U, F(U) + S)."""
+    c = 0.5 * prob.dt if coef is None else float(coef)
+    W = np.asarray(W, dtype=np.float64)
+    if S is not None:
+        W = W + c * np.asarray(S)
+    wq = [prob.quad.R(W[s]) for s in range(prob.S)]
+    uq = solve_pointwise(prob.rx, wq, c)
+    U = np.array([prob.quad.P(uq[s]) for s in range(prob.S)])
+    F = prob.F(U) + (S if S is not None else 0.0)
+    return U, F
+
+
+def iif2_step_local(prob: Problem, U, Fn, dense=False, S_next=None):
+    """IIF2 (3.5) with the local implicit stage.  Returns (U^{n+1}, F^{n+1}, info)."""
+    v = U + 0.5 * prob.dt * Fn
+    W, kinfo = expv_species(prob, v, dense)
+    U1, F1 = implicit_stage_local(prob, W, 0.5 * prob.dt, S_next)
+    return U1, F1, {"krylov": kinfo}
+
+
+def iif2_run_local(prob: Problem, U0, steps: int, dense=False, source=None):
+    """`steps` IIF2 steps with the local implicit stage.  Returns (U, F(U), infos)."""
+    U = np.array(U0, dtype=np.float64).reshape(prob.S, prob.ndof)
+    Fn = prob.F(U) + (source(0.0) if source else 0.0)
+    infos = []
+    for n in range(steps):
+        Sn = source((n + 1) * prob.dt) if source else None
+        U, Fn, info = iif2_step_local(prob, U, Fn, dense, S_next=Sn)
+        infos.append(info)
+    return U, Fn, infos
 
 
 def implicit_stage_newton_dense(prob: Problem, W, Fn, tol=1e-14, max_iter=30):

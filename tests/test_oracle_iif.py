@@ -160,3 +160,50 @@ def test_iif3_stage_root_with_dense_exponentials():
     rhs = E @ U0[0] + dt * (5 / 12 * F1[0] + 2 / 3 * (E @ Fn[0]) - 1 / 12 * (E @ (E @ Fm1[0])))
     assert info["converged"]
     assert np.abs(U1[0] - rhs).max() < 1e-13 * max(1.0, np.abs(rhs).max())
+
+
+def test_local_stage_equals_galerkin_for_linear_reaction():
+    """f = lambda u: pointwise u = w / (1 - c lambda), and P R = I on the sparse
+    space, so the local stage is the Galerkin stage W / (1 - c lambda)."""
+    prob = iif.Problem(2, 3, 1, [1.0], I.rx_linear(-2.0), 0.05, 10)
+    W = np.random.default_rng(7).uniform(-1, 1, (1, prob.ndof))
+    U, _ = iif.implicit_stage_local(prob, W)
+    assert np.abs(U - W / (1 + 0.05)).max() < 1e-14
+
+
+def test_local_stage_solves_the_pointwise_problem():
+    prob = iif.Problem(2, 3, 2, [0.01, 1.0], I.rx_schnakenberg(0.1, 0.9), 0.2, 10)
+    rng = np.random.default_rng(8)
+    W = np.zeros((2, prob.ndof))
+    W[0, 0], W[1, 0] = 1.0, 0.9
+    W += rng.uniform(-0.05, 0.05, W.shape)
+    c = 0.1
+    wq = [prob.quad.R(W[s]) for s in range(2)]
+    uq = iif.solve_pointwise(prob.rx, wq, c)
+    f = iif.reaction.f_eval(prob.rx, uq)
+    for s in range(2):
+        assert np.abs(uq[s] - c * f[s] - wq[s]).max() < 1e-14
+    # close to, but not equal to, the Galerkin root (a different scheme)
+    Ul, _ = iif.implicit_stage_local(prob, W, c)
+    Ug, _, _ = iif.implicit_stage(prob, W, prob.F(W), tol=1e-15, coef=c)
+    diff = np.abs(Ul - Ug).max()
+    assert 1e-10 < diff < 1e-3, diff
+
+
+def test_local_stage_example3_second_order():
+    """Example 3 (zero Dirichlet, u^2, forcing) with the local stage, P1 IIF2:
+    still second order in the L2 error."""
+    import math
+
+    errs = []
+    for N in (3, 4, 5):
+        wl = I.example3(2, N, 1)
+        inst = wl.instances[0]
+        prob = iif.Problem(inst.d, N, 1, inst.D, inst.rx, wl.dt, wl.M, bc="dirichlet")
+        U0 = project.project_terms(2, N, 1, [(1.0, [I.SIN, I.SIN])])[None]
+        S0 = sum(project.project_separable(2, N, 1, a, f) for a, f, _ in wl.sources)
+        U, _, _ = iif.iif2_run_local(prob, U0, wl.steps, source=lambda t: (math.exp(-2 * t) * S0)[None])
+        T = wl.steps * wl.dt
+        errs.append(project.l2_error(U[0], math.exp(-T) * U0[0], math.exp(-2 * T) * 0.25))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[-1] < 0.05 and all(1.4 < r < 2.8 for r in rates), (errs, rates)
