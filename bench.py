@@ -59,8 +59,9 @@ def dof_per_step(plan, wl):
     return sum(plan.info(i)[0] * inst.species for i, inst in enumerate(wl.instances))
 
 
-def run_steps(sg, torch, wl, prec, U0, steps, warmup, graph=True):
-    """Returns (seconds for `steps` steps, final U (numpy), stats)."""
+def run_steps(sg, torch, wl, prec, U0, steps, warmup, graph=True, local=False):
+    """Returns (seconds for `steps` steps, final U (numpy), stats).  local: the
+    stage solved pointwise (iif2_step_local) instead of the Galerkin stage."""
     plan = sg.Plan(wl.instances, prec)
     Ud = torch.from_numpy(U0.copy()).cuda()
     F = torch.zeros_like(Ud)
@@ -70,7 +71,10 @@ def run_steps(sg, torch, wl, prec, U0, steps, warmup, graph=True):
     plan.reaction(Ud, F, ws)
 
     def step():
-        plan.iif2_step(wl.dt, wl.M, Ud, F, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX, stats=st)
+        if local:
+            plan.iif2_step_local(wl.dt, wl.M, Ud, F, ws, stats=st)
+        else:
+            plan.iif2_step(wl.dt, wl.M, Ud, F, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX, stats=st)
 
     torch.cuda.synchronize()
     g = None
@@ -257,6 +261,7 @@ def main():
     ap.add_argument("--no-big", action="store_true", help="skip the out-of-cache sweep measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance Gray-Scott batch")
     ap.add_argument("--no-iif3", action="store_true", help="skip the IIF3 leg")
+    ap.add_argument("--no-local", action="store_true", help="skip the local-stage variant")
     ap.add_argument("--batched-steps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -297,6 +302,15 @@ def main():
             mixed[prec] = {"value": ndps * args.steps / s2, "ms_per_step": 1e3 * s2 / args.steps,
                            "rel_l2_vs_fp64": rel, "status_ok": bool(np.all(stp["status"][:2] == 0))}
         out["mixed"] = mixed
+    if not args.no_local:
+        log("[bench] local stage")
+        sl, Ul, stl, _ = run_steps(sg, torch, wl, "fp64", U0, args.steps, args.warmup, graph=not args.eager,
+                                   local=True)
+        out["iif2_local_stage"] = {
+            "value": ndps * args.steps / sl, "ms_per_step": 1e3 * sl / args.steps,
+            "status_ok": bool(np.all(stl["status"][: 2 * len(wl.instances)] == 0)),
+            "rel_l2_vs_galerkin_stage": float(np.linalg.norm(Ul - U64) / np.linalg.norm(U64)),
+            "note": "variant: implicit stage solved pointwise at the Gauss points (local implicit property)"}
     if not args.no_iif3:
         log("[bench] iif3")
         s3, st3 = run_steps_iif3(sg, torch, wl, U0, args.steps, args.warmup)

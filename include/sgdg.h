@@ -229,6 +229,17 @@ sgdg_status iif3_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M,
                       const double* S_next, double newton_tol, int32_t newton_max, void* workspace,
                       size_t workspace_bytes, sgdg_stats* stats, void* stream);
 
+/* One IIF2 step with the local implicit stage (a variant, not the paper's
+ * scheme: the "local implicit property" Sec. 5 names as future work).  As
+ * iif2_step, except that the stage is solved independently at every Gauss
+ * point of Omega_N, u - dt/2 f(u) = R W (Newton per point from u = w, at most
+ * 30 corrections, |g| <= 1e-15 max(1, |w|)), and projected, U = P u; no
+ * global iteration.  Equal to iif2_step for linear f.  Fcache is required.
+ * stats: Krylov entries only.                                               */
+sgdg_status iif2_step_local(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcache,
+                            const double* S_next, void* workspace, size_t workspace_bytes, sgdg_stats* stats,
+                            void* stream);
+
 /* One explicit Runge-Kutta step of dU/dt = A U + F(U) (Sec. 4, Table 1: the
  * RK2 and RK3 comparators whose step limit shows the stiffness of A).  order 2:
  * U1 = U + dt L(U), U <- (U + U1 + dt L(U1)) / 2; order 3 (Shu-Osher): U1 as

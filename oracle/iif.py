@@ -135,12 +135,12 @@ def solve_pointwise(rx, wq, coef, tol=LOCAL_TOL, max_iter=LOCAL_MAX_ITER):
     u = [np.array(w, dtype=np.float64) for w in wq]
     wmag = np.maximum(1.0, np.max(np.abs(np.array(wq)), axis=0))
     active = np.ones(u[0].shape, dtype=bool)
-    for _ in range(max_iter + 1):
+    for it in range(max_iter + 1):
         f = reaction.f_eval(rx, u)
         g = [u[s] - coef * f[s] - wq[s] for s in range(S)]
         gmax = np.max(np.abs(np.array(g)), axis=0)
         active &= ~(gmax <= tol * wmag)
-        if not active.any():
+        if not active.any() or it == max_iter:
             break
         J = reaction.f_jac(rx, u)
         if S == 1:

@@ -343,3 +343,41 @@ extern "C" sgdg_status rk_step(const sgdg_plan* plan, int32_t nrhs, double dt, i
   }
   return check_launch("rk_step launch");
 }
+
+extern "C" sgdg_status iif2_step_local(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U,
+                                       double* Fcache, const double* S_next, void* workspace, size_t workspace_bytes,
+                                       sgdg_stats* stats, void* stream) {
+  if (!plan) return fail(SGDG_ERR_ARG, "iif2_step_local: null plan");
+  if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "iif2_step_local: nrhs must be in 1..65535");
+  if (M < 1 || M > SGDG_MAX_M) return fail(SGDG_ERR_ARG, "iif2_step_local: M must be in 1..48");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SGDG_ERR_ARG, "iif2_step_local: dt must be positive");
+  if (!U || !Fcache || !workspace) return fail(SGDG_ERR_ARG, "iif2_step_local: null device pointer");
+  if (U == Fcache) return fail(SGDG_ERR_ARG, "iif2_step_local: U and Fcache must not alias");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "iif2_step_local: (k+1) 2^N above 2048 per axis");
+  if (workspace_bytes < iif2_ws_bytes(plan, M, nrhs))
+    return fail(SGDG_ERR_ARG, "iif2_step_local: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  IifWs w = carve(plan, M, nrhs, workspace);
+  const double c = 0.5 * dt;
+  const int64_t n = plan->total * (int64_t)nrhs;
+  const dim3 vg((unsigned)((n + 255) / 256)), vb(256);
+  hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.v, U, c, Fcache, n);
+  sgdg_status st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s);
+  if (st != SGDG_OK) return st;
+  if (S_next) hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.W, w.W, c, S_next, n);
+  // U = P u, u - c f(u) = R W at every Gauss point
+  RxArgs a{};
+  a.rws = w.rws;
+  a.dt2 = c;
+  a.U = w.W;
+  a.Gout = U;
+  reaction_pass(plan, nrhs, RX_LOCAL, a, s);
+  // F of the new level
+  RxArgs b{};
+  b.rws = w.rws;
+  b.U = U;
+  b.F = Fcache;
+  reaction_pass(plan, nrhs, RX_F, b, s);
+  if (S_next) hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, Fcache, Fcache, 1.0, S_next, n);
+  return check_launch("iif2_step_local launch");
+}

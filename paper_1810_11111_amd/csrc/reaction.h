@@ -58,12 +58,17 @@ struct RHost {
 bool reaction_supported(const sgdg_plan* plan);
 int64_t reaction_final_fibres(const sgdg_plan* plan);
 
-enum RxMode { RX_F = 0, RX_RESID = 1, RX_CORR = 2 };
+enum RxMode { RX_F = 0, RX_RESID = 1, RX_CORR = 2, RX_LOCAL = 3 };
+
+// local implicit stage: per-point Newton on u - dt2 f(u) = w
+constexpr double RX_LOCAL_TOL = 1e-15;
+constexpr int RX_LOCAL_MAX_ITER = 30;
 
 // One reaction pass over nrhs right-hand sides.
 //   RX_F    : F = P f(R U)
 //   RX_RESID: F = P f(R U), G = U - dt2 F - W, per-final-fibre |G|^2 into part
 //   RX_CORR : U <- U - P[(I - dt2 J_f(R U))^{-1} R G]
+//   RX_LOCAL: Gout = P u, u solving u - dt2 f(u) = R U at every point (U holds W)
 // Instances with conv[rhs * ninst + inst] != 0 are skipped (conv may be null).
 struct RxArgs {
   double* U;

@@ -407,6 +407,8 @@ __device__ __forceinline__ double finish(const RxArgs& a, int mode, int64_t gi, 
     const double G = a.U[gi] - a.dt2 * v - a.W[gi];
     a.Gout[gi] = G;
     return G * G;
+  } else if (mode == RX_LOCAL) {
+    a.Gout[gi] = v;
   } else {
     a.U[gi] -= v;
   }
@@ -542,6 +544,30 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
         out[0] = (D * g0 - Bq * g1) / det;
         out[1] = (A * g1 - C * g0) / det;
       }
+    } else if (mode == RX_LOCAL) {
+      // u - dt2 f(u) = w at this point, Newton from u = w (at most RX_LOCAL_MAX_ITER corrections)
+      const double w0 = u[0], w1v = u[1];
+      const double wmag = fmax(1.0, fmax(fabs(w0), fabs(w1v)));
+      double x[2] = {w0, w1v};
+      for (int it = 0; it <= RX_LOCAL_MAX_ITER; ++it) {
+        double f[2];
+        rx_f(I.rx, S, x, f);
+        const double g0 = x[0] - dt2 * f[0] - w0, g1 = S > 1 ? x[1] - dt2 * f[1] - w1v : 0.0;
+        if (fmax(fabs(g0), fabs(g1)) <= RX_LOCAL_TOL * wmag || it == RX_LOCAL_MAX_ITER) break;
+        double J[2][2];
+        rx_jac(I.rx, S, x, J);
+        if (S == 1) {
+          x[0] -= g0 / (1.0 - dt2 * J[0][0]);
+        } else {
+          const double A = 1.0 - dt2 * J[0][0], Bq = -dt2 * J[0][1];
+          const double C = -dt2 * J[1][0], D = 1.0 - dt2 * J[1][1];
+          const double det = A * D - Bq * C;
+          x[0] -= (D * g0 - Bq * g1) / det;
+          x[1] -= (A * g1 - C * g0) / det;
+        }
+      }
+      out[0] = x[0];
+      out[1] = x[1];
     } else {
       rx_f(I.rx, S, u, out);
     }

@@ -69,6 +69,7 @@ _sigs = {
     "iif2_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
     "iif3_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
     "rk_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _sz, _vp], C.c_int),
+    "iif2_step_local": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _vp, _sz, _vp, _vp], C.c_int),
 }
 EXPORTED = sorted(_sigs)
 for _name, (_args, _res) in _sigs.items():
@@ -216,6 +217,11 @@ class Plan:
         _check(_lib.iif3_step(self._h, nrhs, float(dt), M, _ptr(U), _ptr(Fcur), _ptr(Fprev), _ptr(source),
                               float(newton_tol), newton_max, _ptr(workspace),
                               workspace.numel() * workspace.element_size(), _ptr(stats), _stream(stream)), "iif3_step")
+
+    def iif2_step_local(self, dt, M, U, Fcache, workspace, stats=None, nrhs=1, stream=None, source=None):
+        _check(_lib.iif2_step_local(self._h, nrhs, float(dt), M, _ptr(U), _ptr(Fcache), _ptr(source),
+                                    _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(stats),
+                                    _stream(stream)), "iif2_step_local")
 
     def rk_step(self, dt, order, U, workspace, nrhs=1, stream=None):
         _check(_lib.rk_step(self._h, nrhs, float(dt), order, _ptr(U), _ptr(workspace),

@@ -513,3 +513,70 @@ def test_forced_examples_converge_on_gpu(example):
         assert st[0]["status"] == 0
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert errs[-1] < 0.05 and all(1.4 < r < 2.8 for r in rates), (errs, rates)
+
+
+# ----------------------------------------------------------------------------- local implicit stage (variant)
+
+def _run_local(plan, wl, U0vec, steps, S0=None, rate=0.0):
+    import torch
+
+    Ud = to_dev(U0vec.reshape(1, -1).copy())
+    ws = _ws(plan, wl.M, 1)
+    st = _stats(plan, 1)
+    Fc = torch.zeros_like(Ud)
+    plan.reaction(Ud, Fc, ws, source=None if S0 is None else to_dev(S0.reshape(1, -1)))
+    for n in range(steps):
+        Sn = None if S0 is None else to_dev((math.exp(-rate * (n + 1) * wl.dt) * S0).reshape(1, -1))
+        plan.iif2_step_local(wl.dt, wl.M, Ud, Fc, ws, stats=st, source=Sn)
+    torch.cuda.synchronize()
+    return Ud.cpu().numpy()[0], lib().stats_array(st)
+
+
+@pytest.mark.parametrize("name,kw,steps", [
+    ("schnakenberg_d2", dict(N=5, k=2), 5),
+    ("schnakenberg_d2", dict(), 2),
+    ("quadratic_d4", dict(N=3), 3),
+])
+def test_local_stage_matches_oracle(name, kw, steps):
+    """iif2_step_local: pointwise Newton at the Gauss points, then P."""
+    sg = lib()
+    wl = getattr(I, name)(**kw)
+    inst = wl.instances[0]
+    say("iif2 local", name, kw, steps)
+    plan = sg.Plan([inst], "fp64")
+    nd = plan.info(0)[0]
+    U0 = _ic_oracle(wl, 0, inst, nd)
+    Ug, st = _run_local(plan, wl, U0.ravel(), steps)
+    prob = _oracle_problem(inst, wl.dt, wl.M)
+    Ur, _, _ = iif.iif2_run_local(prob, U0, steps)
+    Ug = Ug.reshape(inst.species, nd)
+    for s in range(inst.species):
+        tol = _step_tol(inst, wl.dt, np.linalg.norm(U0[s]) + np.linalg.norm(Ur[s]), s, steps, prob.anorm[s])
+        assert np.linalg.norm(Ug[s] - Ur[s]) <= tol, (s, np.linalg.norm(Ug[s] - Ur[s]), tol)
+        assert st[s]["status"] == 0
+
+
+def test_local_stage_example3_on_gpu():
+    """Example 3 (zero Dirichlet, forcing) with the local stage: parity with the
+    oracle over the full time range at N = 4, and second order N = 3..5."""
+    sg = lib()
+    errs = []
+    for N in (3, 4, 5):
+        wl = I.example3(2, N, 1)
+        inst = wl.instances[0]
+        say("iif2 local example3", N)
+        plan = sg.Plan([inst], "fp64")
+        S0_lib, S0_orc, rate = _example_setup(wl, plan)
+        U0 = plan.project(0, 1.0, [I.SIN, I.SIN])
+        Ug, _ = _run_local(plan, wl, U0, wl.steps, S0_lib, rate)
+        T = wl.steps * wl.dt
+        errs.append(project.l2_error(Ug, math.exp(-T) * U0, math.exp(-2 * T) * 0.25))
+        if N == 4:
+            prob = _oracle_problem(inst, wl.dt, wl.M)
+            U0o = project.project_terms(2, N, 1, [(1.0, [I.SIN, I.SIN])])[None]
+            Ugo, _ = _run_local(plan, wl, U0o.ravel(), wl.steps, S0_orc, rate)
+            Ur, _, _ = iif.iif2_run_local(prob, U0o, wl.steps, source=lambda t: (math.exp(-rate * t) * S0_orc)[None])
+            tol = _step_tol(inst, wl.dt, 2 * np.linalg.norm(U0o), 0, wl.steps, prob.anorm[0])
+            assert np.linalg.norm(Ugo - Ur[0]) <= tol
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[-1] < 0.05 and all(1.4 < r < 2.8 for r in rates), (errs, rates)
