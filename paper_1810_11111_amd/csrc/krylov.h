@@ -13,14 +13,15 @@ struct KrylovWs {
   void* V;           // (M+1) basis vectors: [i][rhs][total], FP64 or FP32
   uint16_t* Vb;      // BF16 sweep copy of the current basis vector (BF16 plans)
   void* wy;          // sweep output [rhs][total]: FP64 or FP32
-  double* w1;        // FP64 vector after the first Gram-Schmidt pass
   double* part1;     // per-chunk partial sums [rhs][chunk][M+2]
-  double* part2;
-  double* H;         // [problem][(M+1) x M], problem = (rhs*ninst + inst)*2 + species
+  double* part2;     // part2 / part3: the pair that carries <v_i, x_{j+1}> between steps
+  double* part3;
+  double* H;         // [problem][(M+1) x M], problem = (rhs*ninst + inst)*2 + species (persistent form)
+  double* lg;        // [problem][M+1][2M+1]: per-step (s, c, alpha) of the launch-per-step form
   double* y;         // [problem][M]: first column of exp(h H_m)
   double* beta;      // [problem]
   int32_t* m;        // [problem]: Krylov dimension reached
-  int32_t* done;     // [problem]: no further Arnoldi steps
+  int32_t* done;     // [problem]: 0, or 1 + the first Arnoldi step that no longer runs
   uint32_t* bar;     // persistent Arnoldi: [0] arrivals, [1] generation, [2] error flag
 };
 

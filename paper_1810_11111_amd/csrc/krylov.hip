@@ -8,14 +8,23 @@
 // GPU form.  Every (right-hand side, instance, species) is an independent
 // problem; all problems advance in lockstep over j.  Orthogonalisation is
 // classical Gram-Schmidt applied twice (rounding-level equivalent of the
-// modified form), which needs three device-wide reductions per step instead
-// of j+1; each reduction is a kernel boundary (cheap inside a captured graph):
-//   sweep   : w = A v_j (the sg_dg_apply kernels) and, in the same
-//             workgroups, the per-chunk partials <v_i, w>
-//   k_upd1  : h1 = sum of partials, w1 = w - V h1, per-chunk <v_i, w1>, |w1|^2
-//   k_upd2  : h2, w2 = w1 - V h2, |w2|^2 = |w1|^2 - |h2|^2, v_{j+1} = w2 / |w2|
-// Partial sums are reduced in a fixed order, so every workgroup of a problem
-// computes bit-identical Hessenberg entries and breakdown decisions.
+// modified form) with the second pass delayed by one step, so that a step
+// needs one device-wide reduction besides the sweep; each reduction is a
+// kernel boundary (cheap inside a captured graph):
+//   sweep : w = A x_j (the sg_dg_apply kernels) and, in the same workgroups,
+//           the per-chunk partials <v_i, w> (i < j) and <x_j, w>, where slot j
+//           of the basis holds x_j, the once-orthogonalised residual of the
+//           previous step
+//   k_upd : reorthogonalise and normalise x_j into v_j with the partials of
+//           <v_i, x_j> and |x_j|^2 left by the previous step, form
+//           x_{j+1} = (A v_j minus its projection on v_0..v_j), and leave the
+//           partials of <v_i, x_{j+1}> and |x_{j+1}|^2 for the next step
+// A v_j is never formed: w = A x_j and x_j = V c + alpha v_j give
+// A v_j = (w - A V c) / alpha, and A V c lies in the span of v_0..v_j, so only
+// the Hessenberg column needs it; the per-step scalars (s, c, alpha) are
+// logged and k_expm assembles H from them.  Partial sums are reduced in a
+// fixed order, so every workgroup of a problem computes bit-identical scalars
+// and breakdown decisions.
 // Dot products, norms, H, exp(h H) and the final combination are FP64 in
 // every precision mode; the basis is stored in the sweep precision.
 #include <hip/hip_runtime.h>
@@ -34,6 +43,27 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// maximum over the wave, returned to every lane: DPP steps within each row
+// of 16 lanes (quad xor 1, quad xor 2, half-row mirror, row mirror), then the
+// four row maxima read as scalars
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0), b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32), d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(a, b), max(c, d));
+}
+
+// the FP64 value of lane l (l uniform)
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 __device__ __forceinline__ int prob_of(int rhs, int ninst, const Chunk& ch) { return (rhs * ninst + ch.inst) * 2 + ch.species; }
@@ -104,37 +134,6 @@ __global__ __launch_bounds__(CHUNK) void k_norm(DevTables T, int nchunks, int ni
   (void)nrhs;
 }
 
-// Deterministic chunk-level multi-dot: out[i] = sum over the chunk of
-// V_i[e] * wl[e] for i < J, plus out[J] = sum wl[e]^2 when with_norm.
-// Thread (i, s) of a J x S arrangement sums the elements e = s, s+S, ... so
-// the loads of one column are coalesced across slices.
-template <class TV>
-__device__ __forceinline__ void chunk_dots(const KrylovWs& ws, int J, bool with_norm, int nrhs, int rhs,
-                                           int64_t total, int64_t g0, int count, const double* wl, double* red,
-                                           double* out) {
-  const int tid = threadIdx.x;
-  const int cols = J + (with_norm ? 1 : 0);
-  const int S = CHUNK / cols;
-  if (tid < cols * S) {
-    const int i = tid / S, s = tid - i * S;
-    double acc = 0.0;
-    if (i < J) {
-      const TV* v = vec<TV>(ws, i, nrhs, rhs, total) + g0;
-      for (int e = s; e < count; e += S) acc += (double)v[e] * wl[e];
-    } else {
-      for (int e = s; e < count; e += S) acc += wl[e] * wl[e];
-    }
-    red[tid] = acc;
-  }
-  __syncthreads();
-  if (tid < cols) {
-    double t = 0.0;
-    for (int q = 0; q < S; ++q) t += red[tid * S + q];
-    out[tid] = t;
-  }
-  __syncthreads();
-}
-
 // Deterministic reduction of per-chunk partials of one problem: h[i] = sum
 // over its nc chunks of part[c0 + q][i], i < cols.
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int64_t row0, int nc, int ld, int cols,
@@ -156,71 +155,151 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
   __syncthreads();
 }
 
-// h1 = <V, w>;  w1 = w - V h1;  partials <v_i, w1> and |w1|^2.
-template <class TV, class TY>
-__global__ __launch_bounds__(CHUNK) void k_upd1(DevTables T, int nchunks, int ninst, int64_t total, int M, int j,
-                                                KrylovWs ws) {
-  const int c = blockIdx.x, rhs = blockIdx.y, tid = threadIdx.x, nrhs = gridDim.y;
-  const Chunk ch = T.chunks[c];
-  const int p = prob_of(rhs, ninst, ch);
-  if (ws.done[p]) return;
-  const int c0 = T.pchunk0[ch.problem], nc = T.pnchunk[ch.problem];
-  __shared__ double h[SGDG_MAX_M + 2], wl[CHUNK], red[CHUNK], out[SGDG_MAX_M + 2];
-  reduce_partials(ws.part1, (int64_t)rhs * nchunks + c0, nc, M + 2, j + 1, red, h);
-  if (c == c0 && tid <= j) ws.H[(int64_t)p * (M + 1) * M + tid * M + j] = h[tid];
-  const int64_t g = ch.start + tid;
-  double w1 = 0.0;
-  if (tid < ch.count) {
-    double acc = (double)((const TY*)ws.wy)[rhs * total + g];
-    for (int i = 0; i <= j; ++i) acc -= h[i] * (double)vec<TV>(ws, i, nrhs, rhs, total)[g];
-    w1 = acc;
-    ws.w1[rhs * total + g] = w1;
+// Deterministic reduction of two partial arrays of one problem at once (both
+// sets of loads in flight together): ha[i] = sum over its nc chunks of
+// pa[c0 + q][i] for i < na, hb[i] likewise from pb for i < nb.
+__device__ __forceinline__ void reduce_partials2(const double* __restrict__ pa, int na, const double* __restrict__ pb,
+                                                 int nb, int64_t row0, int nc, int ld, double* red, double* ha,
+                                                 double* hb) {
+  const int tid = threadIdx.x;
+  const int cols = na + nb;
+  const int S = CHUNK / cols;
+  if (tid < cols * S) {
+    const int i = tid / S, s = tid - i * S;
+    const double* src = i < na ? pa + i : pb + (i - na);
+    double acc = 0.0;
+    for (int q = s; q < nc; q += S) acc += src[(row0 + q) * ld];
+    red[tid] = acc;
   }
-  wl[tid] = w1;
   __syncthreads();
-  chunk_dots<TV>(ws, j + 1, true, nrhs, rhs, total, ch.start, ch.count, wl, red, out);
-  if (tid <= j + 1) ws.part2[((int64_t)rhs * nchunks + c) * (M + 2) + tid] = out[tid];
+  if (tid < cols) {
+    double t = 0.0;
+    for (int q = 0; q < S; ++q) t += red[tid * S + q];
+    if (tid < na)
+      ha[tid] = t;
+    else
+      hb[tid - na] = t;
+  }
+  __syncthreads();
 }
 
-// h2 = <V, w1>;  w2 = w1 - V h2;  h_{j+1,j} = |w2|;  v_{j+1} = w2 / h_{j+1,j}.
+// Chunk partials against x = ul (LDS): out[i] = <v_i, x> for i < J (basis
+// from memory), out[J] = <vl, x> (vl in LDS), out[J + 1] = |x|^2.
 template <class TV>
-__global__ __launch_bounds__(CHUNK) void k_upd2(DevTables T, int nchunks, int ninst, int64_t total, int M, int j,
-                                                KrylovWs ws) {
+__device__ __forceinline__ void chunk_dots_next(const KrylovWs& ws, int J, int nrhs, int rhs, int64_t total,
+                                                int64_t g0, int count, const double* vl, const double* ul,
+                                                double* red, double* out) {
+  const int tid = threadIdx.x;
+  const int cols = J + 2;
+  const int S = CHUNK / cols;
+  if (tid < cols * S) {
+    const int i = tid / S, s = tid - i * S;
+    double acc = 0.0;
+    if (i < J) {
+      const TV* v = vec<TV>(ws, i, nrhs, rhs, total) + g0;
+      for (int e = s; e < count; e += S) acc += (double)v[e] * ul[e];
+    } else {
+      const double* a = i == J ? vl : ul;
+      for (int e = s; e < count; e += S) acc += a[e] * ul[e];
+    }
+    red[tid] = acc;
+  }
+  __syncthreads();
+  if (tid < cols) {
+    double t = 0.0;
+    for (int q = 0; q < S; ++q) t += red[tid * S + q];
+    out[tid] = t;
+  }
+  __syncthreads();
+}
+
+// Arnoldi step j after the sweep (see the header).  With s'_i the reduced
+// sweep partials and c_i, n the partials left by step j-1 (none for j = 0,
+// where x_0 = v_0):
+//   alpha = h_{j,j-1} = sqrt(n - |c|^2)  (breakdown: alpha <= rel ||A||),
+//   v_j = (x_j - sum_{i<j} c_i v_i) / alpha,
+//   s_i = s'_i (i < j),  s_j = <v_j, w> = (s'_j - c . s'_{0..j-1}) / alpha,
+//   x_{j+1} = (w - sum_{i<=j} s_i v_i) / alpha,
+// then the partials <v_i, x_{j+1}> (i <= j) and |x_{j+1}|^2 into the other
+// buffer of the pair (the one read here may still be read by other
+// workgroups).  The chunk's first workgroup logs (s, c, alpha).
+// done[p] = 1 + the first step that no longer runs for problem p.
+template <class TV, class TY>
+__global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int ninst, int64_t total, int M, int j,
+                                               KrylovWs ws) {
   const int c = blockIdx.x, rhs = blockIdx.y, tid = threadIdx.x, nrhs = gridDim.y;
   const Chunk ch = T.chunks[c];
   const int p = prob_of(rhs, ninst, ch);
-  if (ws.done[p]) return;
+  const int dn = ws.done[p];
+  if (dn && j >= dn - 1) return;
   const int c0 = T.pchunk0[ch.problem], nc = T.pnchunk[ch.problem];
-  __shared__ double h[SGDG_MAX_M + 2], red[CHUNK];
-  __shared__ double hn_s;
-  reduce_partials(ws.part2, (int64_t)rhs * nchunks + c0, nc, M + 2, j + 2, red, h);
+  __shared__ double sv[SGDG_MAX_M + 1], cv[SGDG_MAX_M + 1], red[CHUNK], vl[CHUNK], ul[CHUNK], out[SGDG_MAX_M + 2];
+  __shared__ double alpha_s;
+  __shared__ int stop_s;
+  const double* pin = (j & 1) ? ws.part3 : ws.part2;
+  double* pout = (j & 1) ? ws.part2 : ws.part3;
+  reduce_partials2(ws.part1, j + 1, pin, j ? j + 1 : 0, (int64_t)rhs * nchunks + c0, nc, M + 2, red, sv, cv);
+  const InstDev& I = T.inst[ch.inst];
   if (tid == 0) {
-    double n2 = h[j + 1];
-    for (int i = 0; i <= j; ++i) n2 -= h[i] * h[i];
-    hn_s = sqrt(fmax(n2, 0.0));
+    double a = 1.0;
+    int stop = 0;
+    if (j > 0) {
+      double n2 = cv[j];
+      for (int i = 0; i < j; ++i) n2 -= cv[i] * cv[i];
+      a = sqrt(fmax(n2, 0.0));
+      stop = !(a > KRYLOV_BREAKDOWN_REL * I.anorm[ch.species]);
+      double t = sv[j];
+      for (int i = 0; i < j; ++i) t -= cv[i] * sv[i];
+      sv[j] = stop ? 0.0 : t / a;
+    }
+    alpha_s = a;
+    stop_s = stop;
   }
   __syncthreads();
-  const double hn = hn_s;
-  double* Hp = ws.H + (int64_t)p * (M + 1) * M;
-  if (c == c0 && tid <= j) Hp[tid * M + j] += h[tid];
-  if (c == c0 && tid == 0) Hp[(j + 1) * M + j] = hn;
-  const InstDev& I = T.inst[ch.inst];
+  const double a = alpha_s;
+  const bool stop = stop_s != 0;
   const int Mp = (int)min((int64_t)M, I.ndof);
-  const bool stop = !(hn > KRYLOV_BREAKDOWN_REL * I.anorm[ch.species]) || (j + 1 >= Mp);
-  if (stop) {
-    if (c == c0 && tid == 0) {
-      ws.m[p] = j + 1;
-      ws.done[p] = 1;
+  const bool last = j + 1 >= Mp;
+  if (c == c0) {
+    double* L = ws.lg + ((int64_t)p * (M + 1) + j) * (2 * M + 1);
+    if (tid <= j) L[tid] = sv[tid];
+    if (tid < j) L[M + tid] = cv[tid];
+    if (tid == 0) {
+      L[2 * M] = a;
+      if (stop || last) {
+        ws.m[p] = stop ? j : j + 1;
+        ws.done[p] = j + 2;
+      }
     }
-    return;
   }
-  if (tid >= ch.count) return;
+  if (stop) return;
   const int64_t g = ch.start + tid;
-  double acc = ws.w1[rhs * total + g];
-  for (int i = 0; i <= j; ++i) acc -= h[i] * (double)vec<TV>(ws, i, nrhs, rhs, total)[g];
-  const double x = acc / hn;
-  ((TV*)ws.V)[((int64_t)(j + 1) * nrhs + rhs) * total + g] = (TV)x;
-  if (ws.Vb) ws.Vb[rhs * total + g] = f_to_bf16((float)x);
+  double vr = 0.0, ur = 0.0;
+  if (tid < ch.count) {
+    TV* Vj = (TV*)ws.V + ((int64_t)j * nrhs + rhs) * total;
+    double xa = (double)Vj[g];
+    double wa = (double)((const TY*)ws.wy)[rhs * total + g];
+    for (int i = 0; i < j; ++i) {
+      const double vi = (double)vec<TV>(ws, i, nrhs, rhs, total)[g];
+      xa -= cv[i] * vi;
+      wa -= sv[i] * vi;
+    }
+    const TV vt = (TV)(xa / a);
+    vr = (double)vt;
+    if (j > 0) Vj[g] = vt;
+    const double u = (wa - sv[j] * vr) / a;
+    const TV ut = (TV)u;
+    ur = (double)ut;
+    if (!last) {
+      ((TV*)ws.V)[((int64_t)(j + 1) * nrhs + rhs) * total + g] = ut;
+      if (ws.Vb) ws.Vb[rhs * total + g] = f_to_bf16((float)ut);
+    }
+  }
+  vl[tid] = vr;
+  ul[tid] = ur;
+  __syncthreads();
+  chunk_dots_next<TV>(ws, j, nrhs, rhs, total, ch.start, ch.count, vl, ul, red, out);
+  if (tid <= j + 1) pout[((int64_t)rhs * nchunks + c) * (M + 2) + tid] = out[tid];
 }
 
 // ---- exp(h H_m) e_1: Pade approximation with scaling and squaring ---------
@@ -231,7 +310,7 @@ __global__ __launch_bounds__(CHUNK) void k_upd2(DevTables T, int nchunks, int ni
 // [m/m] Pade coefficients b_j = (2m-j)! m! / ((2m)! j! (m-j)!) from the
 // ratio b_j / b_{j-1} = (m-j+1) / (j (2m-j+1)).
 constexpr int MM = SGDG_MAX_M;
-constexpr int LDM = MM + 2;  // row stride of the LDS matrices: 16 consecutive rows hit distinct banks
+constexpr int LDM = MM + 1;  // odd row stride (in doubles): row-per-lane accesses spread over all LDS banks
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -283,18 +362,19 @@ __device__ void mat_mul(double* C, const double* A, const double* B, int m) {
 template <int U>
 __device__ __forceinline__ void gj_row(const double* __restrict__ P0, const double* __restrict__ Q0,
                                        double* __restrict__ P1, double* __restrict__ Q1, int m, int k, int piv,
-                                       int r, int g, int ngrp) {
+                                       double inv, int r, int g, int ngrp) {
   const int sr = r == k ? piv : (r == piv ? k : r);
-  const double inv = 1.0 / P0[piv * LDM + k];
   const double f = P0[sr * LDM + k];
   double pp[U], ps[U], qp[U], qs[U];
+  // column indices clamped into the matrix, so that no load is conditional
+  // (values past column m - 1 are loaded but never stored)
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int cp = k + 1 + g + u * ngrp, cq = g + u * ngrp;
-    pp[u] = cp < m ? P0[piv * LDM + cp] : 0.0;
-    ps[u] = cp < m ? P0[sr * LDM + cp] : 0.0;
-    qp[u] = cq < m ? Q0[piv * LDM + cq] : 0.0;
-    qs[u] = cq < m ? Q0[sr * LDM + cq] : 0.0;
+    const int cp = min(k + 1 + g + u * ngrp, m - 1), cq = min(g + u * ngrp, m - 1);
+    pp[u] = P0[piv * LDM + cp];
+    ps[u] = P0[sr * LDM + cp];
+    qp[u] = Q0[piv * LDM + cq];
+    qs[u] = Q0[sr * LDM + cq];
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -310,11 +390,116 @@ __device__ void pade_coeffs(int deg, double* b) {
   for (int jj = 1; jj <= deg; ++jj) b[jj] = b[jj - 1] * (double)(deg - jj + 1) / ((double)jj * (double)(2 * deg - jj + 1));
 }
 
-__global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, double hstep, KrylovWs ws,
-                                              sgdg_stats* __restrict__ stats) {
+// Row i of H = G R^{-1} by forward substitution, the row held in registers
+// (NB >= m unrolls every index to a constant; no loads are conditional: S and
+// R are zero-padded and R[j][j] = 1 for j >= m, so the columns past m - 1 hold
+// harmless values that are never used):
+//   H[i][j] = (G[i][j] - sum_{k<j} H[i][k] R[k][j]) / R[j][j],
+//   G[i][j] = S[i][j] + R[j][j] R[i][j+1].
+template <int NB>
+__device__ __forceinline__ void hess_row(int i, const double* __restrict__ Sm, const double* __restrict__ Rm,
+                                         const double* __restrict__ rinv, double* __restrict__ Hs) {
+  double h[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    double g = Sm[i * LDM + j] + Rm[j * LDM + j] * Rm[i * LDM + j + 1];
+    double g2 = 0.0;
+#pragma unroll
+    for (int k = 0; k + 1 < j; k += 2) {
+      g -= h[k] * Rm[k * LDM + j];
+      g2 -= h[k + 1] * Rm[(k + 1) * LDM + j];
+    }
+    if (j & 1) g -= h[j - 1] * Rm[(j - 1) * LDM + j];
+    h[j] = (g + g2) * rinv[j];
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) Hs[i * LDM + j] = h[j];
+}
+
+// H_m (m x m, row stride LDM) from the per-step log of k_upd.  With x_j the
+// vector swept in step j, the log gives x_j = V R[:, j] (R upper triangular:
+// column j holds c^(j) above the diagonal alpha_j, alpha_0 = 1) and
+// A x_j = V s^(j) + alpha_j x_{j+1}, so A V R = V G with
+// G[:, j] = s^(j) + alpha_j R[:, j+1], and H = G R^{-1}: every row of H by
+// forward substitution, one row per thread.  R[:, m] comes from the log of
+// step m when the process broke down there, else from the partials of
+// <v_i, x_m>, |x_m|^2 that step m-1 left.  Returns h_{m,m-1} = alpha_m.
+__device__ __forceinline__ double hess_from_log(const DevTables& T, const KrylovWs& ws, int p, int rhs, int problem,
+                                                int nchunks, int M, int m, double* __restrict__ Hs,
+                                                double* __restrict__ Sm, double* __restrict__ Rm,
+                                                double* __restrict__ rinv, double* red, double* hv) {
+  const int tid = threadIdx.x;
+  const int ldl = 2 * M + 1;
+  const double* L = ws.lg + (int64_t)p * (M + 1) * ldl;
+  const int Mp = (int)min((int64_t)M, T.inst[problem >> 1].ndof);
+  const bool brk = m < Mp;
+  __shared__ double hn_s;
+  const int mp = (m + 15) & ~15;
+  // zero S and R on mp x (mp + 1), unit diagonal of R past m - 1
+  for (int e = tid; e < mp * (mp + 1); e += blockDim.x) {
+    const int r = e / (mp + 1), c = e - r * (mp + 1);
+    Sm[r * LDM + c] = 0.0;
+    Rm[r * LDM + c] = (r == c && r >= m) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int n = (brk ? m + 1 : m) * ldl;
+  // all loads of the log (and of the partials below) in flight before any is used
+  constexpr int LOGQ = ((SGDG_MAX_M + 1) * (2 * SGDG_MAX_M + 1) + 255) / 256;
+  double xs[LOGQ];
+#pragma unroll
+  for (int q = 0; q < LOGQ; ++q) {
+    const int e = tid + q * 256;
+    xs[q] = e < n ? L[e] : 0.0;
+  }
+  if (!brk) {
+    const double* part = (m & 1) ? ws.part3 : ws.part2;
+    reduce_partials(part, (int64_t)rhs * nchunks + T.pchunk0[problem], T.pnchunk[problem], M + 2, m + 1, red, hv);
+    if (tid < m) Rm[tid * LDM + m] = hv[tid];
+    if (tid == 0) {
+      double n2 = hv[m];
+      for (int i = 0; i < m; ++i) n2 -= hv[i] * hv[i];
+      hn_s = sqrt(fmax(n2, 0.0));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < LOGQ; ++q) {
+    const int e = tid + q * 256;
+    if (e >= n) break;
+    const int j = e / ldl, i = e - j * ldl;
+    const double x = xs[q];
+    if (j == m) {
+      if (i >= M && i < M + m) Rm[(i - M) * LDM + m] = x;
+      if (i == 2 * M) hn_s = x;
+    } else if (i < M) {
+      if (i <= j) Sm[i * LDM + j] = x;
+    } else if (i < 2 * M) {
+      if (i - M < j) Rm[(i - M) * LDM + j] = x;
+    } else {
+      Rm[j * LDM + j] = j ? x : 1.0;
+    }
+  }
+  if (tid < mp) rinv[tid] = tid < m ? 1.0 / (tid ? Rm[tid * LDM + tid] : 1.0) : 1.0;
+  __syncthreads();
+  if (tid < m) {
+    if (mp == 16)
+      hess_row<16>(tid, Sm, Rm, rinv, Hs);
+    else if (mp == 32)
+      hess_row<32>(tid, Sm, Rm, rinv, Hs);
+    else
+      hess_row<48>(tid, Sm, Rm, rinv, Hs);
+  }
+  __syncthreads();
+  return hn_s;
+}
+
+// from_log: H from the k_upd log (launch-per-step form), else from ws.H
+// (persistent form).
+__global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int nchunks, int M, double hstep, int from_log,
+                                              KrylovWs ws, sgdg_stats* __restrict__ stats) {
   const int p = blockIdx.x;
   const int species = p & 1;
   const int inst = (p >> 1) % ninst;
+  const int rhs = (p >> 1) / ninst;
   const int tid = threadIdx.x;
   if (species >= T.inst[inst].S) return;
   const int m = ws.m[p];
@@ -336,10 +521,13 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
   }
   // only the Hessenberg part of H is ever written (rows <= column + 1); every
   // work matrix starts zero on the padded square used by mat_mul
+  double hnext = 0.0;
+  if (from_log) hnext = hess_from_log(T, ws, p, rhs, inst * 2 + species, nchunks, M, m, Tm, A2, A4, fac, Vm, Um);
   const int mp = (m + 15) & ~15;
   for (int e = tid; e < mp * mp; e += blockDim.x) {
     const int r = e / mp, c = e - r * mp, q = r * LDM + c;
-    Am[q] = (r < m && c < m && r <= c + 1) ? hstep * Hp[r * M + c] : 0.0;
+    const bool in = r < m && c < m && r <= c + 1;
+    Am[q] = in ? hstep * (from_log ? Tm[q] : Hp[r * M + c]) : 0.0;
     A2[q] = A4[q] = A6[q] = Tm[q] = Um[q] = Vm[q] = 0.0;
   }
   __syncthreads();
@@ -456,21 +644,25 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
     // r - k holds row r, m <= 64) with one 32-bit key per lane: the magnitude
     // rounded to FP32 with its low 6 mantissa bits replaced by 63 - lane, so the
     // maximum key is the largest magnitude and, among magnitudes equal to ~17
-    // bits, the lowest row
+    // bits, the lowest row.  Every lane also forms the reciprocal of its entry
+    // (inf for a zero, which is never chosen unless the system is singular);
+    // the pivot's is then read from its lane.
     int piv;
+    double inv;
     {
       const int lane = tid & 63, r = k + lane;
-      unsigned key = 0u;
-      if (r < m) key = (__float_as_uint((float)fabs(P0[r * LDM + k])) & ~63u) | (unsigned)(63 - lane);
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) key = max(key, (unsigned)__shfl_xor((int)key, off, 64));
-      piv = k + 63 - (int)(key & 63u);
+      const double x = r < m ? P0[r * LDM + k] : 0.0;
+      const unsigned key = r < m ? (__float_as_uint((float)fabs(x)) & ~63u) | (unsigned)(63 - lane) : 0u;
+      const double rx = 1.0 / x;
+      const int pl = 63 - (int)(wave_max_u32(key) & 63u);
+      piv = k + pl;
+      inv = readlane_f64(rx, pl);
     }
     if (my_r < m) {
       if (rsh == 5)
-        gj_row<4>(P0, Q0, P1, Q1, m, k, piv, my_r, my_g, ngrp);
+        gj_row<4>(P0, Q0, P1, Q1, m, k, piv, inv, my_r, my_g, ngrp);
       else
-        gj_row<12>(P0, Q0, P1, Q1, m, k, piv, my_r, my_g, ngrp);
+        gj_row<12>(P0, Q0, P1, Q1, m, k, piv, inv, my_r, my_g, ngrp);
     }
     __syncthreads();
     double* t = P0;
@@ -494,7 +686,7 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int M, dou
     bool fin = isfinite(beta);
     for (int i = 0; i < m; ++i) fin = fin && isfinite(R[i * LDM]);
     stats[p].krylov_m = m;
-    stats[p].h_next = Hp[m * M + (m - 1)];
+    stats[p].h_next = from_log ? hnext : Hp[m * M + (m - 1)];
     stats[p].status = ws.bar[2] ? SGDG_ERR_HIP : (fin ? SGDG_OK : SGDG_ERR_NONFINITE);
   }
 }
@@ -529,9 +721,9 @@ size_t krylov_ws_bytes(const sgdg_plan* plan, int M, int nrhs) {
   b += align256((size_t)(M + 1) * tot * sweep_bytes(plan->prec));        // V
   b += align256(plan->prec == SGDG_BF16_SWEEP ? tot * 2 : 0);             // Vb
   b += align256(tot * sweep_bytes(plan->prec));                           // wy
-  b += align256(tot * 8);                                                 // w1
-  b += 2 * align256((size_t)nrhs * plan->nchunks * (M + 2) * 8);          // part1, part2
+  b += 3 * align256((size_t)nrhs * plan->nchunks * (M + 2) * 8);          // part1, part2, part3
   b += align256(np * (M + 1) * M * 8);                                    // H
+  b += align256(np * (M + 1) * (2 * M + 1) * 8);                          // step log
   b += align256(np * M * 8);                                              // y
   b += align256(np * 8);                                                  // beta
   b += 2 * align256(np * 4);                                              // m, done
@@ -553,10 +745,11 @@ KrylovWs krylov_carve(const sgdg_plan* plan, int M, int nrhs, void* base) {
   void* vb = take(plan->prec == SGDG_BF16_SWEEP ? tot * 2 : 0);
   ws.Vb = plan->prec == SGDG_BF16_SWEEP ? (uint16_t*)vb : nullptr;
   ws.wy = take(tot * sweep_bytes(plan->prec));
-  ws.w1 = (double*)take(tot * 8);
   ws.part1 = (double*)take((size_t)nrhs * plan->nchunks * (M + 2) * 8);
   ws.part2 = (double*)take((size_t)nrhs * plan->nchunks * (M + 2) * 8);
+  ws.part3 = (double*)take((size_t)nrhs * plan->nchunks * (M + 2) * 8);
   ws.H = (double*)take(np * (M + 1) * M * 8);
+  ws.lg = (double*)take(np * (M + 1) * (2 * M + 1) * 8);
   ws.y = (double*)take(np * M * 8);
   ws.beta = (double*)take(np * 8);
   ws.m = (int32_t*)take(np * 4);
@@ -571,19 +764,19 @@ static void run_typed(const sgdg_plan* plan, int nrhs, double h, int M, const do
   const dim3 grid((unsigned)plan->nchunks, (unsigned)nrhs), blk(CHUNK);
   hipLaunchKernelGGL(k_init, grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, v, ws);
   hipLaunchKernelGGL((k_norm<TV>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, v, ws);
-  if (!arnoldi_persistent(plan, nrhs, M, ws, s)) {
+  const bool persistent = arnoldi_persistent(plan, nrhs, M, ws, s);
+  if (!persistent) {
     for (int j = 0; j < M; ++j) {
       const void* xin = ws.Vb ? (const void*)ws.Vb : (const void*)((const TV*)ws.V + (size_t)j * nrhs * plan->total);
-      // sweep w = A v_j fused with the chunk partials <v_i, w>, i <= j
+      // sweep w = A x_j fused with the chunk partials <v_i, w>, i < j, and <x_j, w>
       const DotArgs da{ws.V, ws.part1, j, M + 2, plan->nchunks, nrhs, plan->total};
       launch_apply_dots<P, TV>(plan, nrhs, xin, ws.wy, da, s);
-      hipLaunchKernelGGL((k_upd1<TV, TY>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j,
+      hipLaunchKernelGGL((k_upd<TV, TY>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j,
                          ws);
-      hipLaunchKernelGGL((k_upd2<TV>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j, ws);
     }
   }
-  hipLaunchKernelGGL(k_expm, dim3((unsigned)(nrhs * plan->ninst * 2)), dim3(256), 0, s, plan->dev, plan->ninst, M, h, ws,
-                     stats);
+  hipLaunchKernelGGL(k_expm, dim3((unsigned)(nrhs * plan->ninst * 2)), dim3(256), 0, s, plan->dev, plan->ninst,
+                     plan->nchunks, M, h, persistent ? 0 : 1, ws, stats);
   hipLaunchKernelGGL((k_comb<TV>), grid, blk, 0, s, plan->dev, plan->ninst, plan->total, M, ws, w);
 }
 

@@ -104,8 +104,9 @@ def test_expv_fp64_random(d, N, k, D, h, M, seed):
 def test_expv_persistent_and_multi_kernel_forms_agree(prec, monkeypatch):
     """SGDG_ARNOLDI=persistent runs the Arnoldi process of a plan whose chunks
     all fit the LDS-staged sweep in one cooperative launch; the default is the
-    launch-per-pass form.  Both follow the same arithmetic (CGS2, FP64
-    reductions); they may differ only by the order of partial sums."""
+    launch-per-pass form.  Both orthogonalise by classical Gram-Schmidt
+    applied twice with FP64 reductions (the launch-per-pass form delays the
+    second pass by one step), so they agree to rounding."""
     sg = lib()
     wl = I.schnakenberg_d2(N=6, k=2)
     inst = wl.instances[0]
@@ -194,6 +195,23 @@ def test_expv_breakdown_eigenvector_zero_and_clamp():
     assert st2[0]["krylov_m"] <= plan2.total
     ref = krylov.dense_expv(_A(small), 1e-3, v[0])
     assert np.linalg.norm(W2[0] - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_expv_breakdown_at_intermediate_step():
+    """v in a three-dimensional invariant subspace: the process stops with
+    m = 3 (h_{3,2} at rounding level) and exp(hA)v is exact there."""
+    sg = lib()
+    inst = I.Instance(2, 3, 1, [1.0], I.rx_zeros(1))
+    plan = sg.Plan([inst], "fp64")
+    lam, Q = np.linalg.eigh(_A(inst).toarray())
+    picks = [4, 9, 20]
+    v = Q[:, picks] @ np.array([0.7, -0.4, 0.5])
+    say("expv breakdown at m = 3")
+    W, st = _run(plan, 0.01, 12, v[None])
+    assert st[0]["krylov_m"] == 3 and st[0]["status"] == 0
+    assert st[0]["h_next"] <= 1e-12 * plan.norm_inf(0, 0)
+    ref = Q[:, picks] @ (np.exp(0.01 * lam[picks]) * np.array([0.7, -0.4, 0.5]))
+    assert np.linalg.norm(W[0] - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
 def test_expv_nonfinite_is_reported():
