@@ -44,6 +44,44 @@ __device__ __forceinline__ void chunk_dots_out(const DotArgs& da, int c, int rhs
   }
 }
 
+// The staged kernel's form of the same products: 16 waves, so wave w takes
+// i = w, w + 16, w + 32 (i <= j <= SGDG_MAX_M - 1); the basis entries are
+// loaded into registers at kernel start (pre_basis) so that their latency
+// overlaps the staging and the sweep.  Same summation order as above.
+constexpr int PRE_W = CHUNK * APPLY_G / 64;
+constexpr int PRE_I = (SGDG_MAX_M + PRE_W - 1) / PRE_W;
+constexpr int PRE_Q = CHUNK / 64;
+static_assert(PRE_W == 16, "the staged kernel has 16 waves");
+
+template <class TV>
+__device__ __forceinline__ void pre_basis(const DotArgs& da, int rhs, const Chunk& ch, double (&vp)[PRE_I][PRE_Q]) {
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+  for (int a = 0; a < PRE_I; ++a) {
+    const int i = wv + a * PRE_W;
+#pragma unroll
+    for (int b = 0; b < PRE_Q; ++b)  // clamped indices: no load sits under a branch; the excess is masked later
+      vp[a][b] = (double)((const TV*)da.V + ((int64_t)min(i, da.j) * da.nrhs + rhs) * da.total +
+                          ch.start)[min(ln + 64 * b, ch.count - 1)];
+  }
+}
+
+__device__ __forceinline__ void chunk_dots_pre(const DotArgs& da, int c, int rhs, const Chunk& ch,
+                                               const double (&vp)[PRE_I][PRE_Q], const double* wl) {
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+  for (int a = 0; a < PRE_I; ++a) {
+    const int i = wv + a * PRE_W;
+    if (i > da.j) break;
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < PRE_Q; ++b) s += (ln + 64 * b < ch.count ? vp[a][b] : 0.0) * wl[ln + 64 * b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (ln == 0) da.part[((int64_t)rhs * da.nchunks + c) * da.ld + i] = s;
+  }
+}
+
 template <int D, int K, class P, class TV>
 __global__ __launch_bounds__(CHUNK) void apply_kernel(DevTables T, const int32_t* __restrict__ list,
                                                       const typename P::X* __restrict__ x, typename P::Y* __restrict__ y,
@@ -90,6 +128,8 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
   const int64_t rhs = blockIdx.y;
   const InstDev& I = T.inst[ch.inst];
   const int64_t seg = I.offset + (int64_t)ch.species * I.ndof;
+  double vpre[PRE_I][PRE_Q];
+  if constexpr (!std::is_void_v<TV>) pre_basis<TV>(da, (int)rhs, ch, vpre);
   int ntab = 1;
   for (int m = 0; m < D; ++m) ntab *= (I.N + 1);
   int32_t* bst = (int32_t*)smem;
@@ -168,7 +208,7 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
     double* wl = (double*)smem;
     if (lane == 0) wl[e] = active ? (double)out : 0.0;
     __syncthreads();
-    chunk_dots_out<TV>(da, cid, (int)rhs, ch, wl);
+    chunk_dots_pre(da, cid, (int)rhs, ch, vpre, wl);
   }
 }
 

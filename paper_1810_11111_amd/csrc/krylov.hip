@@ -155,58 +155,43 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
   __syncthreads();
 }
 
-// Deterministic reduction of two partial arrays of one problem at once (both
-// sets of loads in flight together): ha[i] = sum over its nc chunks of
-// pa[c0 + q][i] for i < na, hb[i] likewise from pb for i < nb.
-__device__ __forceinline__ void reduce_partials2(const double* __restrict__ pa, int na, const double* __restrict__ pb,
-                                                 int nb, int64_t row0, int nc, int ld, double* red, double* ha,
-                                                 double* hb) {
-  const int tid = threadIdx.x;
-  const int cols = na + nb;
-  const int S = CHUNK / cols;
-  if (tid < cols * S) {
-    const int i = tid / S, s = tid - i * S;
-    const double* src = i < na ? pa + i : pb + (i - na);
-    double acc = 0.0;
-    for (int q = s; q < nc; q += S) acc += src[(row0 + q) * ld];
-    red[tid] = acc;
-  }
-  __syncthreads();
-  if (tid < cols) {
-    double t = 0.0;
-    for (int q = 0; q < S; ++q) t += red[tid * S + q];
-    if (tid < na)
-      ha[tid] = t;
-    else
-      hb[tid - na] = t;
-  }
-  __syncthreads();
-}
-
 // Chunk partials against x = ul (LDS): out[i] = <v_i, x> for i < J (basis
-// from memory), out[J] = <vl, x> (vl in LDS), out[J + 1] = |x|^2.
-template <class TV>
+// from memory), out[J] = <vl, x> (vl in LDS), out[J + 1] = |x|^2, J < JB.
+// Thread (i, s) of a (JB + 2) x S arrangement sums the elements s, s + S, ...
+// of column i in that order; the trip count is a compile-time constant, so
+// all of a thread's loads are in flight together (indices clamped, excess
+// masked).
+template <class TV, int JB>
 __device__ __forceinline__ void chunk_dots_next(const KrylovWs& ws, int J, int nrhs, int rhs, int64_t total,
                                                 int64_t g0, int count, const double* vl, const double* ul,
                                                 double* red, double* out) {
+  constexpr int CJ = JB + 2, S = CHUNK / CJ, NE = (CHUNK + S - 1) / S;
   const int tid = threadIdx.x;
-  const int cols = J + 2;
-  const int S = CHUNK / cols;
-  if (tid < cols * S) {
-    const int i = tid / S, s = tid - i * S;
-    double acc = 0.0;
+  const int i = tid / S, s = tid - i * S;
+  if (i < J + 2) {
+    double raw[NE];
     if (i < J) {
       const TV* v = vec<TV>(ws, i, nrhs, rhs, total) + g0;
-      for (int e = s; e < count; e += S) acc += (double)v[e] * ul[e];
+#pragma unroll
+      for (int q = 0; q < NE; ++q) raw[q] = (double)v[min(s + q * S, count - 1)];
     } else {
       const double* a = i == J ? vl : ul;
-      for (int e = s; e < count; e += S) acc += a[e] * ul[e];
+#pragma unroll
+      for (int q = 0; q < NE; ++q) raw[q] = a[min(s + q * S, CHUNK - 1)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = s + q * S;
+      if (e < count) acc += raw[q] * ul[e];
     }
     red[tid] = acc;
   }
   __syncthreads();
-  if (tid < cols) {
+  if (tid < J + 2) {
     double t = 0.0;
+#pragma unroll
     for (int q = 0; q < S; ++q) t += red[tid * S + q];
     out[tid] = t;
   }
@@ -224,7 +209,7 @@ __device__ __forceinline__ void chunk_dots_next(const KrylovWs& ws, int J, int n
 // buffer of the pair (the one read here may still be read by other
 // workgroups).  The chunk's first workgroup logs (s, c, alpha).
 // done[p] = 1 + the first step that no longer runs for problem p.
-template <class TV, class TY>
+template <class TV, class TY, int JB>
 __global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int ninst, int64_t total, int M, int j,
                                                KrylovWs ws) {
   const int c = blockIdx.x, rhs = blockIdx.y, tid = threadIdx.x, nrhs = gridDim.y;
@@ -238,22 +223,68 @@ __global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int nin
   __shared__ int stop_s;
   const double* pin = (j & 1) ? ws.part3 : ws.part2;
   double* pout = (j & 1) ? ws.part2 : ws.part3;
-  reduce_partials2(ws.part1, j + 1, pin, j ? j + 1 : 0, (int64_t)rhs * nchunks + c0, nc, M + 2, red, sv, cv);
-  const InstDev& I = T.inst[ch.inst];
-  if (tid == 0) {
-    double a = 1.0;
-    int stop = 0;
-    if (j > 0) {
-      double n2 = cv[j];
-      for (int i = 0; i < j; ++i) n2 -= cv[i] * cv[i];
-      a = sqrt(fmax(n2, 0.0));
-      stop = !(a > KRYLOV_BREAKDOWN_REL * I.anorm[ch.species]);
-      double t = sv[j];
-      for (int i = 0; i < j; ++i) t -= cv[i] * sv[i];
-      sv[j] = stop ? 0.0 : t / a;
+  // Every load of the step is issued before the first wait: this thread's
+  // share of the partial sums (thread (col, slice) of a cols x S arrangement
+  // takes chunks slice, slice + S, ...), then x_j, w and v_i (i < j <= JB) of
+  // its element.  No load sits under a branch (indices are clamped into range
+  // and unused values discarded), so the waits can count them: loads return
+  // in order, and the reduction waits only for its own.
+  const int na = j + 1, nb = j ? j + 1 : 0, cols = na + nb, S = CHUNK / cols;
+  const int pc = min(tid / S, cols - 1), ps = tid - (tid / S) * S;
+  const bool pact = tid < cols * S;
+  const double* psrc = pc < na ? ws.part1 + pc : pin + (pc - na);
+  const int64_t row0 = (int64_t)rhs * nchunks + c0;
+  constexpr int QMAX = 8;
+  const bool few = nc <= QMAX * S;
+  double pq[QMAX];
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) pq[q] = psrc[(row0 + min(ps + q * S, nc - 1)) * (M + 2)];
+  const bool act = tid < ch.count;
+  const int64_t g = ch.start + min(tid, ch.count - 1);
+  TV* Vj = (TV*)ws.V + ((int64_t)j * nrhs + rhs) * total;
+  const double x0 = (double)Vj[g];
+  const double w0 = (double)((const TY*)ws.wy)[rhs * total + g];
+  double vv[JB];
+#pragma unroll
+  for (int i = 0; i < JB; ++i) vv[i] = (double)vec<TV>(ws, max(min(i, j - 1), 0), nrhs, rhs, total)[g];
+  __builtin_amdgcn_sched_barrier(0);  // keep the sums below every load
+  {
+    // the same summation order on both paths (the padded terms are zeros)
+    double acc = 0.0;
+    if (few) {
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) acc += ps + q * S < nc ? pq[q] : 0.0;
+    } else if (pact) {
+      for (int q = ps; q < nc; q += S) acc += psrc[(row0 + q) * (M + 2)];
     }
-    alpha_s = a;
-    stop_s = stop;
+    if (pact) red[tid] = acc;
+  }
+  __syncthreads();
+  if (tid < cols) {
+    double t = 0.0;
+    for (int q = 0; q < S; ++q) t += red[tid * S + q];
+    if (tid < na)
+      sv[tid] = t;
+    else
+      cv[tid - na] = t;
+  }
+  __syncthreads();
+  const InstDev& I = T.inst[ch.inst];
+  if (tid < 64) {
+    // |c|^2 and c . s' (i < j) by one wave, fixed-order butterfly sums
+    const double ci = tid < j ? cv[tid] : 0.0;
+    const double cc = wave_sum(ci * ci), cs = wave_sum(ci * (tid < j ? sv[tid] : 0.0));
+    if (tid == 0) {
+      double a = 1.0;
+      int stop = 0;
+      if (j > 0) {
+        a = sqrt(fmax(cv[j] - cc, 0.0));
+        stop = !(a > KRYLOV_BREAKDOWN_REL * I.anorm[ch.species]);
+        sv[j] = stop ? 0.0 : (sv[j] - cs) / a;
+      }
+      alpha_s = a;
+      stop_s = stop;
+    }
   }
   __syncthreads();
   const double a = alpha_s;
@@ -273,17 +304,15 @@ __global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int nin
     }
   }
   if (stop) return;
-  const int64_t g = ch.start + tid;
   double vr = 0.0, ur = 0.0;
-  if (tid < ch.count) {
-    TV* Vj = (TV*)ws.V + ((int64_t)j * nrhs + rhs) * total;
-    double xa = (double)Vj[g];
-    double wa = (double)((const TY*)ws.wy)[rhs * total + g];
-    for (int i = 0; i < j; ++i) {
-      const double vi = (double)vec<TV>(ws, i, nrhs, rhs, total)[g];
-      xa -= cv[i] * vi;
-      wa -= sv[i] * vi;
-    }
+  if (act) {
+    double xa = x0, wa = w0;
+#pragma unroll
+    for (int i = 0; i < JB; ++i)
+      if (i < j) {
+        xa -= cv[i] * vv[i];
+        wa -= sv[i] * vv[i];
+      }
     const TV vt = (TV)(xa / a);
     vr = (double)vt;
     if (j > 0) Vj[g] = vt;
@@ -298,7 +327,7 @@ __global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int nin
   vl[tid] = vr;
   ul[tid] = ur;
   __syncthreads();
-  chunk_dots_next<TV>(ws, j, nrhs, rhs, total, ch.start, ch.count, vl, ul, red, out);
+  chunk_dots_next<TV, JB>(ws, j, nrhs, rhs, total, ch.start, ch.count, vl, ul, red, out);
   if (tid <= j + 1) pout[((int64_t)rhs * nchunks + c) * (M + 2) + tid] = out[tid];
 }
 
@@ -771,8 +800,18 @@ static void run_typed(const sgdg_plan* plan, int nrhs, double h, int M, const do
       // sweep w = A x_j fused with the chunk partials <v_i, w>, i < j, and <x_j, w>
       const DotArgs da{ws.V, ws.part1, j, M + 2, plan->nchunks, nrhs, plan->total};
       launch_apply_dots<P, TV>(plan, nrhs, xin, ws.wy, da, s);
-      hipLaunchKernelGGL((k_upd<TV, TY>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j,
-                         ws);
+      if (j < 8)
+        hipLaunchKernelGGL((k_upd<TV, TY, 8>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M,
+                           j, ws);
+      else if (j < 16)
+        hipLaunchKernelGGL((k_upd<TV, TY, 16>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M,
+                           j, ws);
+      else if (j < 32)
+        hipLaunchKernelGGL((k_upd<TV, TY, 32>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M,
+                           j, ws);
+      else
+        hipLaunchKernelGGL((k_upd<TV, TY, SGDG_MAX_M>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst,
+                           plan->total, M, j, ws);
     }
   }
   hipLaunchKernelGGL(k_expm, dim3((unsigned)(nrhs * plan->ninst * 2)), dim3(256), 0, s, plan->dev, plan->ninst,
