@@ -90,24 +90,72 @@ __global__ __launch_bounds__(CHUNK) void apply_kernel(DevTables T, const int32_t
   const Chunk ch = T.chunks[c];
   const int tid = threadIdx.x;
   const int64_t rhs = blockIdx.y;
-  const bool active = tid < ch.count;
-  typename P::Y out = 0;
+  // chunks of heavy (coarse-level) rows give each output several lanes
+  const int G = ch.g / APPLY_G;
+  const int e = tid / G, lane = tid - e * G;
+  const bool active = e < ch.count;
+  typename P::A acc = 0;
   if (active) {
-    const int64_t g = ch.start + tid;
+    const int64_t g = ch.start + e;
     const GBlock& B = T.gblk[find_block(T, ch, g)];
     const InstDev& I = T.inst[B.inst];
     SrcGlobal<P> xs{x + rhs * xstride, T.blkid + I.blkid_off, T.lstart, I.offset + (int64_t)B.species * I.ndof};
     RowsGlobal rows{T.cptr, T.src};
     ValsGlobal<P> vs{P::vals(T)};
-    out = (typename P::Y)apply_one<D, K, 1, P>(T, B, I, g, 0, xs, rows, vs);
-    y[rhs * ystride + g] = out;
+    acc = apply_one<D, K, P>(T, B, I, g, lane, G, xs, rows, vs);
   }
+  for (int o = 1; o < G; o <<= 1) acc += __shfl_xor(acc, o, 64);
+  const typename P::Y out = (typename P::Y)acc;
+  if (active && lane == 0) y[rhs * ystride + ch.start + e] = out;
   if constexpr (!std::is_void_v<TV>) {
     __shared__ double wl[CHUNK];
-    wl[tid] = active ? (double)out : 0.0;
+    wl[tid] = 0.0;
+    __syncthreads();
+    if (active && lane == 0) wl[e] = (double)out;
     __syncthreads();
     chunk_dots_out<TV>(da, c, (int)rhs, ch, wl);
   }
+}
+
+constexpr int64_t lds_al256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+// Direct global -> LDS copy (global_load_lds: one instruction moves 16 bytes
+// per lane of a wave, lane l's bytes landing at the wave's LDS address + 16 l;
+// 4-byte variant for the unaligned ends) of nbytes (a multiple of 4) from a
+// 4-byte aligned src into the 16-byte aligned LDS region dst, which must hold
+// nbytes + 16 bytes.  The copy keeps src's position within its 16-byte line,
+// so the returned LDS pointer of the array is dst + (src mod 16).  Pieces of
+// 64 lines go to the waves in turn; lanes past the end are inactive, so
+// nothing outside the array is read.  Nothing waits here: the caller waits for
+// vmcnt(0) and synchronises before the LDS is read.
+__device__ __forceinline__ void* dma_copy(void* dst, const void* src, int64_t nbytes, int wave, int nwave, int lane) {
+  const uintptr_t s = (uintptr_t)src, s_al = s & ~(uintptr_t)15, e = s + (uintptr_t)nbytes;
+  unsigned char* base = (unsigned char*)dst;  // LDS image of global address t: base + (t - s_al)
+  const uintptr_t a = (s + 15) & ~(uintptr_t)15, b = e & ~(uintptr_t)15;
+  if (nbytes <= 0) return base + (s - s_al);
+  if (a >= b) {
+    // no whole 16-byte line inside: at most 7 dwords, one 4-byte instruction
+    const int n = (int)(nbytes >> 2);
+    if (wave == 0 && lane < n)
+      __builtin_amdgcn_global_load_lds((const void*)(s + 4 * (uintptr_t)lane), (lds_void_ptr)(base + (s - s_al)), 4, 0,
+                                       0);
+    return base + (s - s_al);
+  }
+  const int nh = (int)((a - s) >> 2), nt = (int)((e - b) >> 2);
+  if (wave == 0 && lane < nh)
+    __builtin_amdgcn_global_load_lds((const void*)(s + 4 * (uintptr_t)lane), (lds_void_ptr)(base + (s - s_al)), 4, 0, 0);
+  if (wave == nwave - 1 && lane < nt)
+    __builtin_amdgcn_global_load_lds((const void*)(b + 4 * (uintptr_t)lane), (lds_void_ptr)(base + (b - s_al)), 4, 0, 0);
+  const int64_t n16 = (int64_t)((b - a) >> 4);
+  unsigned char* mid = base + (a - s_al);
+  for (int64_t q = wave; q * 64 < n16; q += nwave) {
+    const int64_t idx = q * 64 + lane;
+    if (idx < n16)
+      __builtin_amdgcn_global_load_lds((const void*)(a + 16 * (uintptr_t)idx), (lds_void_ptr)(mid + q * 1024), 16, 0, 0);
+  }
+  return base + (s - s_al);
 }
 
 // Staged variant: the workgroup copies the problem's level-block table, the
@@ -130,63 +178,71 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
   const int64_t seg = I.offset + (int64_t)ch.species * I.ndof;
   double vpre[PRE_I][PRE_Q];
   if constexpr (!std::is_void_v<TV>) pre_basis<TV>(da, (int)rhs, ch, vpre);
+  // LDS layout (regions of 256-byte multiples with 16 bytes of slack, as the
+  // direct copies keep each array's offset within its 16-byte line):
+  // block-start table | per distinct 1D operator: row pointers, source cells |
+  // x segment | (STAGE_VALS) per distinct operator: block values.  The tables and x are moved by direct global -> LDS copies,
+  // all in flight together; only the block-start table goes through VGPRs.
   int ntab = 1;
   for (int m = 0; m < D; ++m) ntab *= (I.N + 1);
+  const int64_t ndof = I.ndof;
+  const int wave = tid >> 6, wl64 = tid & 63, nwave = nthr >> 6;
+  // every table descriptor is read before the first direct copy is issued
+  // (loads complete in order, so a later wait would also wait for the copies)
+  BCsr bcs[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) bcs[i] = T.bcsr[I.bcsr_off[i]];
   int32_t* bst = (int32_t*)smem;
-  for (int i = tid; i < ntab; i += nthr) {
-    const int b = T.blkid[I.blkid_off + i];
-    bst[i] = b >= 0 ? (int32_t)T.lstart[b] : -1;
-  }
-  // row pointers and source cells of each distinct 1D operator of the instance
-  // (directions sharing an operator share its LDS copy; every array index
-  // below is a compile-time constant after unrolling, so the pointer tables
-  // stay in registers)
+  const int bid = tid < ntab ? T.blkid[I.blkid_off + tid] : -1;
+  unsigned char* cur = smem + lds_al256((int64_t)ntab * 4);
   RowsLds rows;
   ValsLds<P> vl;
   unsigned dup = 0;  // bit i: direction i reuses an earlier direction's operator
-  int32_t* rp = bst + ntab;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    const BCsr bc = T.bcsr[I.bcsr_off[i]];
+    const BCsr bc = bcs[i];
 #pragma unroll
     for (int i2 = 0; i2 < i; ++i2)
-      if (!((dup >> i) & 1u) && T.bcsr[I.bcsr_off[i2]].cptr_off == bc.cptr_off) {
+      if (!((dup >> i) & 1u) && bcs[i2].cptr_off == bc.cptr_off) {
         rows.cptr[i] = rows.cptr[i2];
         rows.src[i] = rows.src[i2];
         dup |= 1u << i;
       }
     if ((dup >> i) & 1u) continue;
-    rows.cptr[i] = rp;
-    for (int t = tid; t <= bc.ncell; t += nthr) rp[t] = T.cptr[bc.cptr_off + t];
-    rp += bc.ncell + 1;
-    rows.src[i] = rp;
-    for (int t = tid; t < bc.nnzb; t += nthr) rp[t] = T.src[bc.src_off + t];
-    rp += bc.nnzb;
+    rows.cptr[i] = (int32_t*)dma_copy(cur, T.cptr + bc.cptr_off, ((int64_t)bc.ncell + 1) * 4, wave, nwave, wl64);
+    cur += lds_al256(((int64_t)bc.ncell + 1) * 4 + 16);
+    rows.src[i] = (int32_t*)dma_copy(cur, T.src + bc.src_off, (int64_t)bc.nnzb * 4, wave, nwave, wl64);
+    cur += lds_al256((int64_t)bc.nnzb * 4 + 16);
   }
-  unsigned char* cur = smem + ((((unsigned char*)rp - smem) + 15) & ~15);
   typename P::X* xl = (typename P::X*)cur;
   const typename P::X* __restrict__ xg = x + rhs * xstride + seg;
-  for (int64_t i = tid; i < I.ndof; i += nthr) xl[i] = xg[i];
-  cur += (I.ndof * (int64_t)sizeof(typename P::X) + 15) & ~15;
+  if constexpr (sizeof(typename P::X) >= 4)
+    xl = (typename P::X*)dma_copy(cur, xg, ndof * (int64_t)sizeof(typename P::X), wave, nwave, wl64);
+  else
+    for (int64_t i = tid; i < ndof; i += nthr) xl[i] = xg[i];
+  cur += lds_al256(ndof * (int64_t)sizeof(typename P::X) + 16);
   if constexpr (STAGE_VALS) {
     const V* __restrict__ vals = P::vals(T);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      const BCsr bc = T.bcsr[I.bcsr_off[i]];
+      const BCsr bc = bcs[i];
 #pragma unroll
       for (int i2 = 0; i2 < i; ++i2)
-        if (T.bcsr[I.bcsr_off[i2]].cptr_off == bc.cptr_off) vl.v[i] = vl.v[i2];
+        if (bcs[i2].cptr_off == bc.cptr_off) vl.v[i] = vl.v[i2];
       if ((dup >> i) & 1u) continue;
-      V* dst = (V*)cur;
       const int64_t nv = (int64_t)bc.nnzb * (K + 1) * (K + 1);
-      for (int64_t t = tid; t < nv; t += nthr) dst[t] = vals[bc.val_off + t];
-      vl.v[i] = dst;
-      cur += (nv * (int64_t)sizeof(V) + 15) & ~15;
+      vl.v[i] = (V*)dma_copy(cur, vals + bc.val_off, nv * (int64_t)sizeof(V), wave, nwave, wl64);
+      cur += lds_al256(nv * (int64_t)sizeof(V) + 16);
     }
   }
+  if (tid < ntab) bst[tid] = bid >= 0 ? (int32_t)T.lstart[bid] : -1;
+  __builtin_amdgcn_s_waitcnt(0);  // the direct copies have landed
   __syncthreads();
-  const int e = tid / APPLY_G;
-  const int lane = tid % APPLY_G;
+  // ch.g lanes per output: APPLY_G for most chunks, more for the chunks of
+  // coarse levels, whose rows reach every finer cell under their support
+  const int G = ch.g;
+  const int e = tid / G;
+  const int lane = tid - e * G;
   const bool active = e < ch.count;
   typename P::A acc = 0;
   if (active) {
@@ -194,19 +250,21 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
     const GBlock& B = T.gblk[find_block(T, ch, g)];
     SrcLds<P> xs{xl, bst};
     if constexpr (STAGE_VALS)
-      acc = apply_one<D, K, APPLY_G, P>(T, B, I, g, lane, xs, rows, vl);
+      acc = apply_one<D, K, P>(T, B, I, g, lane, G, xs, rows, vl);
     else
-      acc = apply_one<D, K, APPLY_G, P>(T, B, I, g, lane, xs, rows, ValsGlobal<P>{P::vals(T)});
+      acc = apply_one<D, K, P>(T, B, I, g, lane, G, xs, rows, ValsGlobal<P>{P::vals(T)});
   }
-  // fixed-order combination of the lane partials: (l0 + l1) + (l2 + l3)
-#pragma unroll
-  for (int o = 1; o < APPLY_G; o <<= 1) acc += __shfl_xor(acc, o, APPLY_G);
+  // fixed-order combination of the lane partials (butterfly within each
+  // aligned group of G lanes)
+  for (int o = 1; o < G; o <<= 1) acc += __shfl_xor(acc, o, 64);
   const typename P::Y out = (typename P::Y)acc;
   if (active && lane == 0) y[rhs * ystride + ch.start + e] = out;
   if constexpr (!std::is_void_v<TV>) {
     __syncthreads();  // the staged tables are dead; reuse the LDS for the chunk output
     double* wl = (double*)smem;
-    if (lane == 0) wl[e] = active ? (double)out : 0.0;
+    if (tid < CHUNK) wl[tid] = 0.0;
+    __syncthreads();
+    if (active && lane == 0) wl[e] = (double)out;
     __syncthreads();
     chunk_dots_pre(da, cid, (int)rhs, ch, vpre, wl);
   }

@@ -210,7 +210,8 @@ __global__ __launch_bounds__(PA_THREADS) void k_arnoldi(DevTables T, const int32
       cur += (nv * (int64_t)sizeof(V) + 15) & ~15;
     }
   }
-  const int e = tid / APPLY_G, lane = tid % APPLY_G;
+  const int G = ch.g;  // lanes per output (more for the heavy rows of coarse levels)
+  const int e = tid / G, lane = tid - e * G;
   const bool active = e < ch.count;
   const int64_t g = ch.start + e;
   const GBlock* Bp = active ? &T.gblk[find_block(T, ch, g)] : nullptr;
@@ -239,14 +240,15 @@ __global__ __launch_bounds__(PA_THREADS) void k_arnoldi(DevTables T, const int32
       if (active) {
         SrcLds<P> xs{xl, bst};
         if constexpr (SV)
-          acc = apply_one<D, K, APPLY_G, P>(T, *Bp, I, g, lane, xs, rows, vl);
+          acc = apply_one<D, K, P>(T, *Bp, I, g, lane, G, xs, rows, vl);
         else
-          acc = apply_one<D, K, APPLY_G, P>(T, *Bp, I, g, lane, xs, rows, ValsGlobal<P>{P::vals(T)});
+          acc = apply_one<D, K, P>(T, *Bp, I, g, lane, G, xs, rows, ValsGlobal<P>{P::vals(T)});
       }
-#pragma unroll
-      for (int o = 1; o < APPLY_G; o <<= 1) acc += __shfl_xor(acc, o, APPLY_G);
+      for (int o = 1; o < G; o <<= 1) acc += __shfl_xor(acc, o, 64);
       __syncthreads();  // x is dead: the overlay takes its place
-      if (lane == 0) wl[e] = active ? (double)(typename P::Y)acc : 0.0;
+      if (tid < CHUNK) wl[tid] = 0.0;
+      __syncthreads();
+      if (active && lane == 0) wl[e] = (double)(typename P::Y)acc;
       __syncthreads();
       pa_dots<TV>(ws, j + 1, false, nrhs, rhs, total, ch, wl, part1);
     }

@@ -55,6 +55,48 @@ std::vector<std::vector<int>> level_blocks(int d, int N) {
   return out;
 }
 
+// Lanes per output element for every block of an instance.  The work of an
+// output is the number of row entries the sweep walks for it, summed over
+// directions: in direction m, the entries of the 1D row of its target cell
+// whose source cell lies within the level budget N - |l|_1 + l_m (maximum
+// over the block's cells).  A coarse level's rows reach every finer cell
+// under its support, so its work is up to ~2^(N - |l|_1) times that of the
+// finest level; such blocks get lanes in proportion (powers of two, from
+// APPLY_G up to APPLY_GMAX) so that no output needs more than about twice
+// the iterations of a finest-level output.
+std::vector<int> block_lanes(const sgdg_plan* p, const HostInstance& hi) {
+  const int d = hi.desc.d, N = hi.desc.n;
+  std::vector<int64_t> work(hi.blocks.size(), 0);
+  int64_t wfine = 1;
+  for (size_t b = 0; b < hi.blocks.size(); ++b) {
+    const std::vector<int>& lev = hi.blocks[b];
+    const int lsum = std::accumulate(lev.begin(), lev.end(), 0);
+    int64_t w = 0;
+    for (int m = 0; m < d; ++m) {
+      const Op1D& op = p->ops[hi.dir_tab[m]];
+      const int32_t lim = 1 << (N - lsum + lev[m]);
+      const int l = lev[m];
+      const int c_lo = l == 0 ? 0 : 1 << (l - 1), c_hi = l == 0 ? 1 : 1 << l;
+      int64_t mx = 0;
+      for (int c = c_lo; c < c_hi; ++c) {
+        const int32_t* r0 = op.src.data() + op.cptr[c];
+        const int32_t* r1 = op.src.data() + op.cptr[c + 1];
+        mx = std::max<int64_t>(mx, std::lower_bound(r0, r1, lim) - r0);
+      }
+      w += mx;
+    }
+    work[b] = w;
+    if (lsum == N) wfine = std::max(wfine, w);
+  }
+  std::vector<int> lanes(hi.blocks.size(), APPLY_G);
+  for (size_t b = 0; b < hi.blocks.size(); ++b) {
+    int g = APPLY_G;
+    while (g < APPLY_GMAX && work[b] * APPLY_G > 2 * wfine * g) g *= 2;
+    lanes[b] = g;
+  }
+  return lanes;
+}
+
 template <class T>
 sgdg_status upload(sgdg_plan* p, const std::vector<T>& v, T** out) {
   size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
@@ -298,13 +340,27 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
         }
         p->gblk.push_back(g);
       }
-      // chunks of this species segment
+      // chunks of this species segment: runs of consecutive elements whose
+      // blocks share a lane count, at most CHUNK * APPLY_G / lanes elements
       int64_t segstart = hi.offset + (int64_t)s * hi.ndof;
-      int32_t b = seg_first;
-      for (int64_t c0 = 0; c0 < hi.ndof; c0 += CHUNK) {
+      const std::vector<int> lanes = block_lanes(p, hi);
+      int64_t c0 = 0;
+      size_t bi = 0;
+      while (c0 < hi.ndof) {
+        while (hi.bstart[bi] + hi.bsize[bi] <= c0) ++bi;
+        const int g = lanes[bi];
+        const int64_t cap = CHUNK * APPLY_G / g;
+        int64_t end = c0;
+        size_t bj = bi;
+        while (end < hi.ndof && end - c0 < cap) {
+          while (hi.bstart[bj] + hi.bsize[bj] <= end) ++bj;
+          if (lanes[bj] != g) break;
+          end = std::min<int64_t>(hi.bstart[bj] + hi.bsize[bj], c0 + cap);
+        }
         Chunk ch{};
         ch.start = segstart + c0;
-        ch.count = (int32_t)std::min<int64_t>(CHUNK, hi.ndof - c0);
+        ch.count = (int32_t)(end - c0);
+        int32_t b = seg_first;
         while (p->gblk[b].start + p->gblk[b].size <= ch.start) ++b;
         ch.b0 = b;
         int32_t b1 = b;
@@ -313,7 +369,9 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
         ch.inst = i;
         ch.species = s;
         ch.problem = i * 2 + s;
+        ch.g = g;
         p->chunks.push_back(ch);
+        c0 = end;
       }
     }
     p->instdev.push_back(id);
@@ -328,12 +386,16 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
   p->list_lds.assign(SWEEP_TIERS * (SGDG_MAX_K + 1), 0);
   p->list_fixed.assign(SWEEP_TIERS * (SGDG_MAX_K + 1), 0);
   auto al16 = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+  auto al256 = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
   for (int32_t c = 0; c < p->nchunks; ++c) {
     const HostInstance& hi = p->inst[p->chunks[c].inst];
     int64_t ntab = 1;
     for (int m = 0; m < d; ++m) ntab *= (hi.desc.n + 1);
     // block table, row pointers and source cells of each distinct 1D operator
-    int64_t rows = 0, vals = 0;
+    // (the staged sweep gives every region 16 bytes of slack, rounded to 256
+    // bytes, for its direct global -> LDS copies; the persistent Arnoldi
+    // kernel packs them)
+    int64_t rows = 0, vals = 0, rows256 = 0, vals256 = 0;
     for (int m = 0; m < d; ++m) {
       bool seen = false;
       for (int m2 = 0; m2 < m; ++m2) seen = seen || hi.dir_tab[m2] == hi.dir_tab[m];
@@ -341,9 +403,11 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
       const Op1D& op = p->ops[hi.dir_tab[m]];
       rows += (int64_t)op.cptr.size() + (int64_t)op.src.size();
       vals += al16((int64_t)op.val.size() * vbytes);
+      rows256 += al256((int64_t)op.cptr.size() * 4 + 16) + al256((int64_t)op.src.size() * 4 + 16);
+      vals256 += al256((int64_t)op.val.size() * vbytes + 16);
     }
-    const int64_t lds1 = al16((ntab + rows) * 4) + al16(hi.ndof * xbytes);
-    const int64_t lds2 = lds1 + vals;
+    const int64_t lds1 = al256(ntab * 4) + rows256 + al256(hi.ndof * xbytes + 16);
+    const int64_t lds2 = lds1 + vals256;
     const int tier = lds2 <= APPLY_LDS_BYTES_HOST ? 2 : (lds1 <= APPLY_LDS_BYTES_HOST ? 1 : 0);
     const int kind = hi.desc.k * SWEEP_TIERS + tier;
     p->chunk_lists[kind].push_back(c);

@@ -30,11 +30,12 @@ struct GBlock {
 // element of a chunk belongs to blocks b0..b1 of that segment.
 struct Chunk {
   int64_t start;
-  int32_t count;
+  int32_t count;    // <= CHUNK * APPLY_G / g
   int32_t b0, b1;
   int32_t inst;
   int32_t species;
   int32_t problem;  // inst * 2 + species
+  int32_t g;        // lanes per output in the staged sweep (APPLY_G..64); g / APPLY_G in the global one
 };
 
 // Per-instance constants seen by the kernels.
@@ -133,7 +134,8 @@ namespace sgdg {
 constexpr int CHUNK = 256;
 constexpr int APPLY_LDS_BYTES_HOST = 160 * 1024;  // same budget as the staged sweep kernels
 constexpr int SWEEP_TIERS = 3;
-constexpr int APPLY_G = 4;  // lanes per output element in the staged sweeps
+constexpr int APPLY_G = 4;  // lanes per output element in the staged sweeps (the least; rows with more work get more)
+constexpr int APPLY_GMAX = 64;
 
 // error reporting
 sgdg_status fail(sgdg_status st, const std::string& msg);

@@ -108,9 +108,9 @@ struct ValsLds {
 // share one output; the caller sums the G partials).  Already scaled by
 // -D_s.  Rows of B_i are walked in ascending source cell order, so the block
 // base of a source level is looked up once per level, not per entry.
-template <int D, int K, int G, class P, class Src, class Rows, class Vals>
+template <int D, int K, class P, class Src, class Rows, class Vals>
 __device__ __forceinline__ typename P::A apply_one(const DevTables& T, const GBlock& B, const InstDev& I, int64_t g,
-                                                   int lane, const Src& xs, const Rows& rows, const Vals& vs) {
+                                                   int lane, int G, const Src& xs, const Rows& rows, const Vals& vs) {
   using A = typename P::A;
   using V = typename P::V;
   constexpr int K1 = K + 1;
