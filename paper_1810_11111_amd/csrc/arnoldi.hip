@@ -151,7 +151,7 @@ __global__ __launch_bounds__(PA_THREADS) void k_arnoldi(DevTables T, const int32
   const Chunk ch = T.chunks[cid];
   const InstDev& I = T.inst[ch.inst];
   const int p = (rhs * ninst + ch.inst) * 2 + ch.species;
-  const int c0 = T.pchunk0[ch.problem], nc = T.pnchunk[ch.problem];
+  const int c0 = ch.pc0, nc = ch.pnc;
   const int64_t seg = I.offset + (int64_t)ch.species * I.ndof;
   const int Mp = (int)min((int64_t)M, I.ndof);
   const double brk = KRYLOV_BREAKDOWN_REL * I.anorm[ch.species];

@@ -378,6 +378,16 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
   }
   p->nchunks = (int32_t)p->chunks.size();
   p->nblocks = (int32_t)p->gblk.size();
+  std::vector<int32_t> pc0(2 * ninst, 0), pnc(2 * ninst, 0);
+  for (int32_t c = p->nchunks - 1; c >= 0; --c) {
+    const Chunk& ch = p->chunks[c];
+    pc0[ch.problem] = c;
+    pnc[ch.problem]++;
+  }
+  for (Chunk& ch : p->chunks) {
+    ch.pc0 = pc0[ch.problem];
+    ch.pnc = pnc[ch.problem];
+  }
   // sweep kinds: k and how much of the problem fits the LDS budget of the
   // staged sweeps (block table + row tables + x segment, then block values)
   const int xbytes = prec == SGDG_FP64 ? 8 : (prec == SGDG_FP32_SWEEP ? 4 : 2);
@@ -428,12 +438,6 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
       (st = upload(p, val_all, &p->dev.val)) != SGDG_OK || (st = upload(p, valf, &p->dev.valf)) != SGDG_OK) {
     sg_dg_destroy(p);
     return st;
-  }
-  std::vector<int32_t> pc0(2 * ninst, 0), pnc(2 * ninst, 0);
-  for (int32_t c = p->nchunks - 1; c >= 0; --c) {
-    const Chunk& ch = p->chunks[c];
-    pc0[ch.problem] = c;
-    pnc[ch.problem]++;
   }
   if ((st = upload(p, pc0, &p->dev.pchunk0)) != SGDG_OK || (st = upload(p, pnc, &p->dev.pnchunk)) != SGDG_OK) {
     sg_dg_destroy(p);

@@ -36,6 +36,7 @@ struct Chunk {
   int32_t species;
   int32_t problem;  // inst * 2 + species
   int32_t g;        // lanes per output in the staged sweep (APPLY_G..64); g / APPLY_G in the global one
+  int32_t pc0, pnc; // first chunk and number of chunks of this chunk's problem (species segment)
 };
 
 // Per-instance constants seen by the kernels.

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(CHUNK) void k_init(DevTables T, int nchunks, int ni
       ws.bar[0] = 0u;
       ws.bar[2] = 0u;
     }
-    if (c == T.pchunk0[ch.problem]) {
+    if (c == ch.pc0) {
       const int p = prob_of(rhs, ninst, ch);
       ws.done[p] = 0;
       ws.m[p] = 0;
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(CHUNK) void k_norm(DevTables T, int nchunks, int ni
                                                 const double* __restrict__ v, KrylovWs ws) {
   const int c = blockIdx.x, rhs = blockIdx.y, tid = threadIdx.x, nrhs = gridDim.y;
   const Chunk ch = T.chunks[c];
-  const int c0 = T.pchunk0[ch.problem], nc = T.pnchunk[ch.problem];
+  const int c0 = ch.pc0, nc = ch.pnc;
   __shared__ double sb;
   if (tid == 0) {
     double t = 0.0;
@@ -155,49 +155,6 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
   __syncthreads();
 }
 
-// Chunk partials against x = ul (LDS): out[i] = <v_i, x> for i < J (basis
-// from memory), out[J] = <vl, x> (vl in LDS), out[J + 1] = |x|^2, J < JB.
-// Thread (i, s) of a (JB + 2) x S arrangement sums the elements s, s + S, ...
-// of column i in that order; the trip count is a compile-time constant, so
-// all of a thread's loads are in flight together (indices clamped, excess
-// masked).
-template <class TV, int JB>
-__device__ __forceinline__ void chunk_dots_next(const KrylovWs& ws, int J, int nrhs, int rhs, int64_t total,
-                                                int64_t g0, int count, const double* vl, const double* ul,
-                                                double* red, double* out) {
-  constexpr int CJ = JB + 2, S = CHUNK / CJ, NE = (CHUNK + S - 1) / S;
-  const int tid = threadIdx.x;
-  const int i = tid / S, s = tid - i * S;
-  if (i < J + 2) {
-    double raw[NE];
-    if (i < J) {
-      const TV* v = vec<TV>(ws, i, nrhs, rhs, total) + g0;
-#pragma unroll
-      for (int q = 0; q < NE; ++q) raw[q] = (double)v[min(s + q * S, count - 1)];
-    } else {
-      const double* a = i == J ? vl : ul;
-#pragma unroll
-      for (int q = 0; q < NE; ++q) raw[q] = a[min(s + q * S, CHUNK - 1)];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    double acc = 0.0;
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int e = s + q * S;
-      if (e < count) acc += raw[q] * ul[e];
-    }
-    red[tid] = acc;
-  }
-  __syncthreads();
-  if (tid < J + 2) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < S; ++q) t += red[tid * S + q];
-    out[tid] = t;
-  }
-  __syncthreads();
-}
-
 // Arnoldi step j after the sweep (see the header).  With s'_i the reduced
 // sweep partials and c_i, n the partials left by step j-1 (none for j = 0,
 // where x_0 = v_0):
@@ -215,10 +172,9 @@ __global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int nin
   const int c = blockIdx.x, rhs = blockIdx.y, tid = threadIdx.x, nrhs = gridDim.y;
   const Chunk ch = T.chunks[c];
   const int p = prob_of(rhs, ninst, ch);
-  const int dn = ws.done[p];
-  if (dn && j >= dn - 1) return;
-  const int c0 = T.pchunk0[ch.problem], nc = T.pnchunk[ch.problem];
-  __shared__ double sv[SGDG_MAX_M + 1], cv[SGDG_MAX_M + 1], red[CHUNK], vl[CHUNK], ul[CHUNK], out[SGDG_MAX_M + 2];
+  const int c0 = ch.pc0, nc = ch.pnc;
+  // products v_i x_{j+1} of the chunk, column i at tp[i][.] (see the end)
+  __shared__ double sv[SGDG_MAX_M + 1], cv[SGDG_MAX_M + 1], red[CHUNK], tp[(JB + 2) * CHUNK];
   __shared__ double alpha_s;
   __shared__ int stop_s;
   const double* pin = (j & 1) ? ws.part3 : ws.part2;
@@ -247,7 +203,9 @@ __global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int nin
   double vv[JB];
 #pragma unroll
   for (int i = 0; i < JB; ++i) vv[i] = (double)vec<TV>(ws, max(min(i, j - 1), 0), nrhs, rhs, total)[g];
+  const int dn = ws.done[p];
   __builtin_amdgcn_sched_barrier(0);  // keep the sums below every load
+  if (dn && j >= dn - 1) return;  // (the loads above are in range either way)
   {
     // the same summation order on both paths (the padded terms are zeros)
     double acc = 0.0;
@@ -324,11 +282,36 @@ __global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int nin
       if (ws.Vb) ws.Vb[rhs * total + g] = f_to_bf16((float)ut);
     }
   }
-  vl[tid] = vr;
-  ul[tid] = ur;
+  // chunk partials <v_i, x_{j+1}> (i < j), <v_j, x_{j+1}>, |x_{j+1}|^2 from
+  // the basis entries already in registers: the products go to LDS by
+  // column, then thread (i, s) of a (JB + 2) x S arrangement sums elements
+  // s, s + S, ... of column i in that order, and the S slices in order
+#pragma unroll
+  for (int i = 0; i < JB; ++i)
+    if (i < j) tp[i * CHUNK + tid] = vv[i] * ur;
+  tp[j * CHUNK + tid] = vr * ur;
+  tp[(j + 1) * CHUNK + tid] = ur * ur;
   __syncthreads();
-  chunk_dots_next<TV, JB>(ws, j, nrhs, rhs, total, ch.start, ch.count, vl, ul, red, out);
-  if (tid <= j + 1) pout[((int64_t)rhs * nchunks + c) * (M + 2) + tid] = out[tid];
+  {
+    constexpr int CJ = JB + 2, S2 = CHUNK / CJ, NE = (CHUNK + S2 - 1) / S2;
+    const int i = tid / S2, s2 = tid - i * S2;
+    if (i < j + 2) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int e = s2 + q * S2;
+        if (e < CHUNK) acc += tp[i * CHUNK + e];
+      }
+      red[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < j + 2) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < S2; ++q) t += red[tid * S2 + q];
+      pout[((int64_t)rhs * nchunks + c) * (M + 2) + tid] = t;
+    }
+  }
 }
 
 // ---- exp(h H_m) e_1: Pade approximation with scaling and squaring ---------
