@@ -52,6 +52,7 @@ struct RHost {
   std::vector<int64_t> cum_line, cum_fin;
   int64_t rws = 0;  // doubles of reaction workspace per right-hand side
   int max_n1 = 0, max_np1 = 0;
+  int ncu = 0;  // compute units of the plan's device
   bool supported = true;
 };
 

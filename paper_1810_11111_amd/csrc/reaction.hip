@@ -75,8 +75,28 @@ constexpr int RX_TAIL = 64 + 16;  // two-scale matrices + per-wave partial sums
 static size_t fibre_lds_bytes(const RHost* rh) {
   return (3 * (size_t)rh->max_n1 + (size_t)rh->max_np1 + RX_TAIL) * sizeof(double);
 }
-static size_t line_lds_bytes(const RHost* rh) {
-  return (3 * (size_t)rh->max_n1 + 4 * (size_t)rh->max_np1 + RX_TAIL) * sizeof(double);
+static size_t line_lds_bytes(const RHost* rh, int ngrp) {
+  return (3 * (size_t)ngrp * rh->max_n1 + 4 * (size_t)rh->max_np1 + RX_TAIL) * sizeof(double);
+}
+// Concurrent transform groups of the line kernel (4, 2 or 1).  More groups
+// shorten each line's chain of barriers but take more LDS per workgroup; the
+// most that fit the LDS and still let every line of the launch be resident at
+// once (when a launch is larger than one wave of workgroups, throughput
+// matters more than the length of a line's chain).
+static int line_groups(const RHost* rh, int64_t nlines) {
+  int g = 4;
+  while (g > 1) {
+    const size_t b = line_lds_bytes(rh, g);
+    const int64_t per_cu = b <= (size_t)APPLY_LDS_BYTES_HOST ? (int64_t)APPLY_LDS_BYTES_HOST / (int64_t)b : 0;
+    if (per_cu > 0 && nlines <= per_cu * std::max(rh->ncu, 1)) break;
+    g >>= 1;
+  }
+  return g;
+}
+static int line_groups_max(const RHost* rh) {
+  int g = 4;
+  while (g > 1 && line_lds_bytes(rh, g) > (size_t)APPLY_LDS_BYTES_HOST) g >>= 1;
+  return g;
 }
 static sgdg_status set_lds_attrs(const RHost* rh);
 
@@ -204,6 +224,10 @@ sgdg_status reaction_build(sgdg_plan* plan) {
     if ((st = up(plan, rh->cum_x[m], &rh->dev.cum_x[m])) != SGDG_OK) return st;
     if ((st = up(plan, rh->cum_y[m], &rh->dev.cum_y[m])) != SGDG_OK) return st;
   }
+  if (hipDeviceGetAttribute(&rh->ncu, hipDeviceAttributeMultiprocessorCount, plan->device) != hipSuccess) {
+    rh->ncu = 0;
+    (void)hipGetLastError();
+  }
   return set_lds_attrs(rh);
 }
 
@@ -265,9 +289,13 @@ __device__ __forceinline__ void load_mats(const RTables& R, const RInst& I, doub
 
 // inverse fast multiwavelet transform: hierarchical levels 0..L in h -> level-L
 // cell-Legendre coefficients (returned pointer, one of b0 / b1)
+// The transforms below are run by a group of nt threads with local index tid
+// (by default the whole workgroup); every thread of the workgroup passes the
+// same barriers, and a thread with tid >= any loop bound takes part in the
+// barriers only.
 template <int K1>
-__device__ __forceinline__ double* ifwt(const double* h, double* b0, double* b1, int L, const double* M) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+__device__ __forceinline__ double* ifwt(const double* h, double* b0, double* b1, int L, const double* M,
+                                        int tid = threadIdx.x, int nt = blockDim.x) {
   for (int e = tid; e < K1; e += nt) b0[e] = h[e];
   __syncthreads();
   double* cur = b0;
@@ -298,8 +326,8 @@ __device__ __forceinline__ double* ifwt(const double* h, double* b0, double* b1,
 // tmp are overwritten); emit(level, j, p, value) receives every hierarchical
 // coefficient (wavelets of levels N..1, then level 0).
 template <int K1, class Emit>
-__device__ __forceinline__ void ffwt(double* s, double* tmp, int N, const double* M, Emit emit) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+__device__ __forceinline__ void ffwt(double* s, double* tmp, int N, const double* M, Emit emit, int tid = threadIdx.x,
+                                     int nt = blockDim.x) {
   double* cur = s;
   double* nxt = tmp;
   for (int n = N; n >= 1; --n) {
@@ -345,10 +373,10 @@ __device__ __forceinline__ double eval_pt(const double* s, const double* __restr
 // weighted point values g (weights already applied) -> level-N cell coefficients in out
 template <int K1>
 __device__ __forceinline__ void project_cells(const double* g, const double* __restrict__ EL, int N, int np1,
-                                              double* out) {
+                                              double* out, int tid = threadIdx.x, int nt = blockDim.x) {
   const int ncell = 1 << N;
   const double* e = EL + (int64_t)N * np1 * K1;
-  for (int t = threadIdx.x; t < ncell * K1; t += blockDim.x) {
+  for (int t = tid; t < ncell * K1; t += nt) {
     const int c = t / K1, p = t - c * K1;
     double acc = 0.0;
 #pragma unroll
@@ -497,17 +525,20 @@ __global__ __launch_bounds__(RX_THREADS_FIB) void k_rx_expand(RTables R, int nin
 // plan vectors are read and finished directly
 template <int K1>
 __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total, const RxArgs& a, int64_t rws,
-                             int max_n1, int max_np1, int64_t nfin, double* lds) {
+                             int max_n1, int max_np1, int64_t nfin, int ngrp, double* lds) {
   const int rhs = blockIdx.y;
   const int64_t gl = blockIdx.x;
   const RInst& I = R.inst[inst];
   const int d = I.d, N = I.N, S = I.S, np1 = I.np1, n1 = I.n1;
   const int64_t pre = gl - R.cum_line[inst];
   const int nin = mode == RX_CORR ? 2 : 1;
-  double* h = lds;
-  double* b0 = lds + max_n1;
-  double* b1 = lds + 2 * max_n1;
-  double* pts = lds + 3 * max_n1;  // [z*2+s][max_np1]
+  // ngrp groups of threads transform different (input, species) lines at the
+  // same time, each in its own three buffers
+  const int gs = blockDim.x / ngrp, gi = threadIdx.x / gs, gt = threadIdx.x - gi * gs;
+  double* h = lds + (int64_t)gi * 3 * max_n1;
+  double* b0 = h + max_n1;
+  double* b1 = b0 + max_n1;
+  double* pts = lds + (int64_t)ngrp * 3 * max_n1;  // [z*2+s][max_np1]
   double* M = pts + 4 * max_np1;
   double* wsum = M + 64;
   double* xr = a.rws + (int64_t)rhs * rws;
@@ -515,19 +546,21 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
   const double* __restrict__ w1 = R.w1 + I.w_off;
   const double dt2 = a.dt2;
   load_mats(R, I, M);
-#pragma unroll
-  for (int z = 0; z < 2; ++z)
-    for (int s = 0; s < S; ++s) {
-      if (z >= nin) break;
-      const double* in = d == 1 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof
-                                : xr + I.X_off[d - 1] + (((int64_t)z * S + s) * I.npre[d - 1] + pre) * n1;
-      for (int i = threadIdx.x; i < n1; i += blockDim.x) h[i] = in[i];
-      __syncthreads();
-      const double* sc = ifwt<K1>(h, b0, b1, N, M);
-      double* pz = pts + (z * 2 + s) * max_np1;
-      for (int q = threadIdx.x; q < np1; q += blockDim.x) pz[q] = eval_pt<K1>(sc, EL, N, N, np1, q);
-      __syncthreads();
-    }
+  const int npair = nin * S;
+  for (int r0 = 0; r0 < npair; r0 += ngrp) {
+    const int pi = r0 + gi;
+    const bool act = pi < npair;
+    const int z = act ? pi / S : 0, s = act ? pi - z * S : 0;
+    const int lt = act ? gt : (1 << 30);  // an idle group passes the barriers only
+    const double* in = d == 1 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof
+                              : xr + I.X_off[d - 1] + (((int64_t)z * S + s) * I.npre[d - 1] + pre) * n1;
+    for (int i = lt; i < n1; i += gs) h[i] = in[i];
+    __syncthreads();
+    const double* sc = ifwt<K1>(h, b0, b1, N, M, lt, gs);
+    double* pz = pts + (z * 2 + s) * max_np1;
+    for (int q = lt; q < np1; q += gs) pz[q] = eval_pt<K1>(sc, EL, N, N, np1, q);
+    __syncthreads();
+  }
   for (int q = threadIdx.x; q < np1; q += blockDim.x) {
     double u[2] = {pts[q], S > 1 ? pts[max_np1 + q] : 0.0};
     double out[2];
@@ -576,16 +609,25 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
   }
   __syncthreads();
   double g2 = 0.0;
-  for (int s = 0; s < S; ++s) {
-    project_cells<K1>(pts + s * max_np1, EL, N, np1, b0);
+  // contraction: the species at the same time when there are groups enough
+  const int cg = min(ngrp, S);
+  const int cgs = blockDim.x / cg, cgi = threadIdx.x / cgs, cgt = threadIdx.x - cgi * cgs;
+  double* c0 = lds + (int64_t)cgi * 3 * max_n1;
+  double* c1 = c0 + max_n1;
+  for (int r0 = 0; r0 < S; r0 += cg) {
+    const int s = r0 + cgi;
+    const bool act = s < S;
+    const int lt = act ? cgt : (1 << 30);
+    const int sp = act ? s : 0;
+    project_cells<K1>(pts + sp * max_np1, EL, N, np1, c0, lt, cgs);
     if (d == 1) {
-      const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)s * I.ndof;
-      ffwt<K1>(b0, b1, N, M, [&](int n, int j, int p, double v) {
+      const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)sp * I.ndof;
+      ffwt<K1>(c0, c1, N, M, [&](int n, int j, int p, double v) {
         g2 += finish(a, mode, base + off1(n, K1) + j * K1 + p, v);
-      });
+      }, lt, cgs);
     } else {
-      double* out = xr + I.Y_off[d - 1] + ((int64_t)s * I.npre[d - 1] + pre) * n1;
-      ffwt<K1>(b0, b1, N, M, [&](int n, int j, int p, double v) { out[off1(n, K1) + j * K1 + p] = v; });
+      double* out = xr + I.Y_off[d - 1] + ((int64_t)sp * I.npre[d - 1] + pre) * n1;
+      ffwt<K1>(c0, c1, N, M, [&](int n, int j, int p, double v) { out[off1(n, K1) + j * K1 + p] = v; }, lt, cgs);
     }
   }
   if (d == 1 && mode == RX_RESID) {
@@ -595,14 +637,15 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
 }
 
 __global__ __launch_bounds__(RX_THREADS_LINE) void k_rx_line(RTables R, int ninst, int mode, int64_t total, RxArgs a,
-                                                             int64_t rws, int max_n1, int max_np1, int64_t nfin) {
+                                                             int64_t rws, int max_n1, int max_np1, int64_t nfin,
+                                                             int ngrp) {
   extern __shared__ double lds[];
   const int inst = find_inst(R.cum_line, ninst, blockIdx.x);
   if (a.conv && a.conv[blockIdx.y * ninst + inst]) return;
   switch (R.inst[inst].K1) {
-    case 2: rx_line_body<2>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, lds); break;
-    case 3: rx_line_body<3>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, lds); break;
-    default: rx_line_body<4>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, lds); break;
+    case 2: rx_line_body<2>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, ngrp, lds); break;
+    case 3: rx_line_body<3>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, ngrp, lds); break;
+    default: rx_line_body<4>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, ngrp, lds); break;
   }
 }
 
@@ -678,7 +721,7 @@ __global__ __launch_bounds__(RX_THREADS_FIB) void k_rx_contract(RTables R, int n
 
 static sgdg_status set_lds_attrs(const RHost* rh) {
   hipError_t e = hipFuncSetAttribute((const void*)k_rx_line, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)line_lds_bytes(rh));
+                                     (int)line_lds_bytes(rh, line_groups_max(rh)));
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_rx_expand, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fibre_lds_bytes(rh));
@@ -693,13 +736,14 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
   const RHost* rh = (const RHost*)plan->rdata;
   const int d = plan->d, ninst = plan->ninst;
   const int nin = mode == RX_CORR ? 2 : 1;
-  const size_t fl = fibre_lds_bytes(rh), ll = line_lds_bytes(rh);
+  const int ngrp = std::min(line_groups(rh, rh->cum_line.back() * nrhs), line_groups_max(rh));
+  const size_t fl = fibre_lds_bytes(rh), ll = line_lds_bytes(rh, ngrp);
   const int64_t nfin = rh->cum_fin.back();
   for (int m = 0; m + 1 <= d - 1; ++m)
     hipLaunchKernelGGL(k_rx_expand, dim3((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin),
                        dim3(RX_THREADS_FIB), fl, s, rh->dev, ninst, m, plan->total, a, rh->rws, rh->max_n1);
   hipLaunchKernelGGL(k_rx_line, dim3((unsigned)rh->cum_line.back(), (unsigned)nrhs), dim3(RX_THREADS_LINE), ll, s, rh->dev,
-                     ninst, (int)mode, plan->total, a, rh->rws, rh->max_n1, rh->max_np1, nfin);
+                     ninst, (int)mode, plan->total, a, rh->rws, rh->max_n1, rh->max_np1, nfin, ngrp);
   for (int m = d - 2; m >= 0; --m) {
     const int64_t nf = m == 0 ? nfin : rh->cum_y[m].back();
     hipLaunchKernelGGL(k_rx_contract, dim3((unsigned)nf, (unsigned)nrhs), dim3(RX_THREADS_FIB), fl, s, rh->dev, ninst, m,
