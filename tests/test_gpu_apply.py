@@ -157,3 +157,37 @@ def test_apply_full_size_workloads(name):
     for s, Ds in enumerate(inst.D):
         seg = slice(s * nd, (s + 1) * nd)
         _check(yd.cpu().numpy()[seg], Ds * (A1 @ X[seg]), Ds * A1, X[seg], 1e-13, f"{name} species {s}")
+
+
+def test_apply_out_of_cache_properties():
+    """The out-of-cache sweep the benchmark times (d=3 N=16 k=1, 24,641,536 DOF,
+    the global-gather kernel, coarse chunks with up to 16 lanes per output),
+    where the explicit operator is out of reach: properties that hold at any
+    size.  A is symmetric (x.Ay = y.Ax), negative semi-definite (x.Ax <= 0)
+    and annihilates the constant function (the first coefficient: level 0,
+    cell 0, degree 0 in every direction).  Bounds: rounding of the sweep and
+    the dot products is far below 1e-12 ||x|| ||Ay|| (about n u |x| |A||y|, a
+    relative 1e-14 here), while any indexing mistake breaks symmetry at O(1)."""
+    sg = lib()
+    import torch
+
+    inst = I.Instance(3, 16, 1, [1.0], I.rx_zeros(1))
+    say("apply out-of-cache properties d=3 N=16 k=1")
+    plan = sg.Plan([inst], "fp64")
+    n = plan.total
+    assert n == 24641536
+    X = to_dev(I.smooth_random(n, 5, 2))
+    Y = torch.empty_like(X)
+    plan.apply(X, Y, nrhs=2)
+    e = torch.zeros(n, dtype=torch.float64, device="cuda")
+    e[0] = 1.0
+    Ae = torch.empty_like(e)
+    plan.apply(e, Ae)
+    torch.cuda.synchronize()
+    x, y, Ax, Ay = (t.cpu().numpy() for t in (X[0], X[1], Y[0], Y[1]))
+    nx, ny, nAx, nAy = (np.linalg.norm(t) for t in (x, y, Ax, Ay))
+    assert abs(x @ Ay - y @ Ax) <= 1e-12 * nx * nAy
+    assert x @ Ax <= 1e-12 * nx * nAx and y @ Ay <= 1e-12 * ny * nAy
+    assert x @ Ax < 0 and y @ Ay < 0
+    assert np.abs(Ae.cpu().numpy()).max() <= 1e-13 * plan.norm_inf(0, 0)
+    plan.close()
