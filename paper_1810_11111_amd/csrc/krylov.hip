@@ -111,10 +111,12 @@ __global__ __launch_bounds__(CHUNK) void k_norm(DevTables T, int nchunks, int ni
   const Chunk ch = T.chunks[c];
   const int c0 = ch.pc0, nc = ch.pnc;
   __shared__ double sb;
-  if (tid == 0) {
+  if (tid < 64) {
+    // fixed-order sum of the nc chunk partials by one wave (lane-strided, then butterfly)
     double t = 0.0;
-    for (int q = 0; q < nc; ++q) t += ws.part1[((int64_t)rhs * nchunks + c0 + q) * (M + 2)];
-    sb = sqrt(t);
+    for (int q = tid; q < nc; q += 64) t += ws.part1[((int64_t)rhs * nchunks + c0 + q) * (M + 2)];
+    t = wave_sum(t);
+    if (tid == 0) sb = sqrt(t);
   }
   __syncthreads();
   const double beta = sb;

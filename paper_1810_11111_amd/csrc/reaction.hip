@@ -245,28 +245,33 @@ int64_t reaction_final_fibres(const sgdg_plan* plan) {
 
 // ---------------------------------------------------------------- device helpers
 
+// the instance of work item e from the ascending first items cum[0..ninst)
+// (one round of loads per 64 instances, as in find_rblk)
 __device__ __forceinline__ int find_inst(const int64_t* __restrict__ cum, int ninst, int64_t e) {
-  int lo = 0, hi = ninst - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (cum[mid] <= e)
-      lo = mid;
-    else
-      hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int best = 0;
+  for (int t0 = 0; t0 < ninst; t0 += 64) {
+    const int t = min(t0 + lane, ninst - 1);
+    const bool ok = t0 + lane < ninst && cum[t] <= e;
+    const unsigned long long mk = __ballot(ok);
+    if (mk) best = t0 + 63 - __clzll(mk);
   }
-  return lo;
+  return best;
 }
 
+// the block of b[0..n) (ascending starts) holding element e: every lane of
+// the wave tests one block per round of 64, so the search costs one round of
+// loads (the starts at or below e are a prefix; the last of them wins)
 __device__ __forceinline__ int find_rblk(const RBlk* __restrict__ b, int n, int64_t e) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (b[mid].start <= e)
-      lo = mid;
-    else
-      hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int best = 0;
+  for (int t0 = 0; t0 < n; t0 += 64) {
+    const int t = min(t0 + lane, n - 1);
+    const bool ok = t0 + lane < n && b[t].start <= e;
+    const unsigned long long mk = __ballot(ok);
+    if (mk) best = t0 + 63 - __clzll(mk);
   }
-  return lo;
+  return best;
 }
 
 // a[m] for a small kernel-argument array without a dynamic index (which would
