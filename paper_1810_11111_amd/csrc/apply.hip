@@ -180,8 +180,8 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
   if constexpr (!std::is_void_v<TV>) pre_basis<TV>(da, (int)rhs, ch, vpre);
   // LDS layout (regions of 256-byte multiples with 16 bytes of slack, as the
   // direct copies keep each array's offset within its 16-byte line):
-  // block-start table | per distinct 1D operator: row pointers, source cells |
-  // x segment | (STAGE_VALS) per distinct operator: block values.  The tables and x are moved by direct global -> LDS copies,
+  // block-start table | per direction: the chunk's row pointers, source cells
+  // | x segment | (STAGE_VALS) per direction: the chunk's block values.  The tables and x are moved by direct global -> LDS copies,
   // all in flight together; only the block-start table goes through VGPRs.
   int ntab = 1;
   for (int m = 0; m < D; ++m) ntab *= (I.N + 1);
@@ -192,27 +192,39 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
   BCsr bcs[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) bcs[i] = T.bcsr[I.bcsr_off[i]];
+  const StageRange* __restrict__ sr = T.srange + (int64_t)cid * SGDG_MAX_D;
+  StageRange rg[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) rg[i] = sr[i];
   int32_t* bst = (int32_t*)smem;
   const int bid = tid < ntab ? T.blkid[I.blkid_off + tid] : -1;
   unsigned char* cur = smem + lds_al256((int64_t)ntab * 4);
+  // per direction, only the rows this chunk's outputs use (their row
+  // pointers, source cells and, with STAGE_VALS, block values)
+  // (directions sharing an operator share its copy: the plan gives them the
+  // same range; every index below is a compile-time constant after
+  // unrolling, so the pointer tables stay in registers)
   RowsLds rows;
   ValsLds<P> vl;
-  unsigned dup = 0;  // bit i: direction i reuses an earlier direction's operator
+  unsigned dup = 0;  // bit i: direction i reuses an earlier direction's copy
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     const BCsr bc = bcs[i];
+    rows.tlo[i] = rg[i].tlo;
+    rows.elo[i] = rg[i].elo;
 #pragma unroll
     for (int i2 = 0; i2 < i; ++i2)
-      if (!((dup >> i) & 1u) && bcs[i2].cptr_off == bc.cptr_off) {
+      if (!((dup >> i) & 1u) && bcs[i2].cptr_off == bc.cptr_off && rg[i2].tlo == rg[i].tlo) {
         rows.cptr[i] = rows.cptr[i2];
         rows.src[i] = rows.src[i2];
         dup |= 1u << i;
       }
     if ((dup >> i) & 1u) continue;
-    rows.cptr[i] = (int32_t*)dma_copy(cur, T.cptr + bc.cptr_off, ((int64_t)bc.ncell + 1) * 4, wave, nwave, wl64);
-    cur += lds_al256(((int64_t)bc.ncell + 1) * 4 + 16);
-    rows.src[i] = (int32_t*)dma_copy(cur, T.src + bc.src_off, (int64_t)bc.nnzb * 4, wave, nwave, wl64);
-    cur += lds_al256((int64_t)bc.nnzb * 4 + 16);
+    rows.cptr[i] = (int32_t*)dma_copy(cur, T.cptr + bc.cptr_off + rg[i].tlo, ((int64_t)rg[i].nrow + 1) * 4, wave,
+                                      nwave, wl64);
+    cur += lds_al256(((int64_t)rg[i].nrow + 1) * 4 + 16);
+    rows.src[i] = (int32_t*)dma_copy(cur, T.src + bc.src_off + rg[i].elo, (int64_t)rg[i].nent * 4, wave, nwave, wl64);
+    cur += lds_al256((int64_t)rg[i].nent * 4 + 16);
   }
   typename P::X* xl = (typename P::X*)cur;
   const typename P::X* __restrict__ xg = x + rhs * xstride + seg;
@@ -221,18 +233,22 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
   else
     for (int64_t i = tid; i < ndof; i += nthr) xl[i] = xg[i];
   cur += lds_al256(ndof * (int64_t)sizeof(typename P::X) + 16);
-  if constexpr (STAGE_VALS) {
+  {
     const V* __restrict__ vals = P::vals(T);
+    constexpr int64_t KK = (int64_t)(K + 1) * (K + 1);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      const BCsr bc = bcs[i];
+      const V* vsrc = vals + bcs[i].val_off + (int64_t)rg[i].elo * KK;
 #pragma unroll
       for (int i2 = 0; i2 < i; ++i2)
-        if (bcs[i2].cptr_off == bc.cptr_off) vl.v[i] = vl.v[i2];
+        if (bcs[i2].cptr_off == bcs[i].cptr_off && rg[i2].tlo == rg[i].tlo) vl.v[i] = vl.v[i2];
       if ((dup >> i) & 1u) continue;
-      const int64_t nv = (int64_t)bc.nnzb * (K + 1) * (K + 1);
-      vl.v[i] = (V*)dma_copy(cur, vals + bc.val_off, nv * (int64_t)sizeof(V), wave, nwave, wl64);
-      cur += lds_al256(nv * (int64_t)sizeof(V) + 16);
+      if constexpr (STAGE_VALS) {
+        vl.v[i] = (V*)dma_copy(cur, vsrc, (int64_t)rg[i].nent * KK * (int64_t)sizeof(V), wave, nwave, wl64);
+        cur += lds_al256((int64_t)rg[i].nent * KK * (int64_t)sizeof(V) + 16);
+      } else {
+        vl.v[i] = vsrc;  // the block values stay in global memory
+      }
     }
   }
   if (tid < ntab) bst[tid] = bid >= 0 ? (int32_t)T.lstart[bid] : -1;
@@ -249,10 +265,7 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
     const int64_t g = ch.start + e;
     const GBlock& B = T.gblk[find_block(T, ch, g)];
     SrcLds<P> xs{xl, bst};
-    if constexpr (STAGE_VALS)
-      acc = apply_one<D, K, P>(T, B, I, g, lane, G, xs, rows, vl);
-    else
-      acc = apply_one<D, K, P>(T, B, I, g, lane, G, xs, rows, ValsGlobal<P>{P::vals(T)});
+    acc = apply_one<D, K, P>(T, B, I, g, lane, G, xs, rows, vl);
   }
   // fixed-order combination of the lane partials (butterfly within each
   // aligned group of G lanes)

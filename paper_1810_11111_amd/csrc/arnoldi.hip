@@ -176,9 +176,13 @@ __global__ __launch_bounds__(PA_THREADS) void k_arnoldi(DevTables T, const int32
       if (!((dup >> i) & 1u) && T.bcsr[I.bcsr_off[i2]].cptr_off == bc.cptr_off) {
         rows.cptr[i] = rows.cptr[i2];
         rows.src[i] = rows.src[i2];
+        rows.tlo[i] = 0;
+        rows.elo[i] = 0;
         dup |= 1u << i;
       }
     if ((dup >> i) & 1u) continue;
+    rows.tlo[i] = 0;  // whole tables
+    rows.elo[i] = 0;
     rows.cptr[i] = rp;
     for (int t = tid; t <= bc.ncell; t += PA_THREADS) rp[t] = T.cptr[bc.cptr_off + t];
     rp += bc.ncell + 1;

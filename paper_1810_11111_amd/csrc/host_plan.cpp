@@ -397,24 +397,71 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
   p->list_fixed.assign(SWEEP_TIERS * (SGDG_MAX_K + 1), 0);
   auto al16 = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
   auto al256 = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+  // rows of each direction's 1D operator that a chunk's outputs use: the
+  // range of their target cells (the staged sweep copies only these)
+  std::vector<StageRange> srange((size_t)p->nchunks * SGDG_MAX_D, StageRange{0, 0, 0, 0});
+  for (int32_t c = 0; c < p->nchunks; ++c) {
+    const Chunk& ch = p->chunks[c];
+    const HostInstance& hi = p->inst[ch.inst];
+    const int K1 = hi.desc.k + 1;
+    int tlo[SGDG_MAX_D], thi[SGDG_MAX_D];
+    for (int m = 0; m < d; ++m) {
+      tlo[m] = INT32_MAX;
+      thi[m] = -1;
+    }
+    for (int32_t b = ch.b0; b <= ch.b1; ++b) {
+      const GBlock& gb = p->gblk[b];
+      const int64_t e0 = std::max(ch.start, gb.start), e1 = std::min(ch.start + ch.count, gb.start + gb.size);
+      for (int64_t g = e0; g < e1; ++g) {
+        int64_t rem = g - gb.start;  // the sweep's decoding of a block-local index
+        for (int m = d - 1; m >= 0; --m) {
+          const int l = gb.lev[m];
+          const int64_t ext = (int64_t)K1 << (l > 0 ? l - 1 : 0);
+          const int64_t t = rem % ext;
+          rem /= ext;
+          const int tc = l == 0 ? 0 : (1 << (l - 1)) + (int)(t / K1);
+          tlo[m] = std::min(tlo[m], tc);
+          thi[m] = std::max(thi[m], tc);
+        }
+      }
+    }
+    // directions that share a 1D operator share one staged copy: the union
+    // of their ranges (so a chunk never stages more than the whole tables)
+    for (int m = 0; m < d; ++m) {
+      int lo = tlo[m], hi_ = thi[m];
+      for (int m2 = 0; m2 < d; ++m2)
+        if (hi.dir_tab[m2] == hi.dir_tab[m]) {
+          lo = std::min(lo, tlo[m2]);
+          hi_ = std::max(hi_, thi[m2]);
+        }
+      const Op1D& op = p->ops[hi.dir_tab[m]];
+      StageRange& r = srange[(size_t)c * SGDG_MAX_D + m];
+      r.tlo = lo;
+      r.nrow = hi_ - lo + 1;
+      r.elo = op.cptr[lo];
+      r.nent = op.cptr[hi_ + 1] - r.elo;
+    }
+  }
   for (int32_t c = 0; c < p->nchunks; ++c) {
     const HostInstance& hi = p->inst[p->chunks[c].inst];
     int64_t ntab = 1;
     for (int m = 0; m < d; ++m) ntab *= (hi.desc.n + 1);
-    // block table, row pointers and source cells of each distinct 1D operator
-    // (the staged sweep gives every region 16 bytes of slack, rounded to 256
-    // bytes, for its direct global -> LDS copies; the persistent Arnoldi
-    // kernel packs them)
+    const int64_t kk = (int64_t)(hi.desc.k + 1) * (hi.desc.k + 1);
+    // staged sweep: block table, then per direction the chunk's row pointers,
+    // source cells (and block values), each region with 16 bytes of slack
+    // rounded to 256 bytes for the direct global -> LDS copies.  The
+    // persistent Arnoldi kernel stages whole tables, packed (list_fixed).
     int64_t rows = 0, vals = 0, rows256 = 0, vals256 = 0;
     for (int m = 0; m < d; ++m) {
       bool seen = false;
       for (int m2 = 0; m2 < m; ++m2) seen = seen || hi.dir_tab[m2] == hi.dir_tab[m];
       if (seen) continue;
+      const StageRange& r = srange[(size_t)c * SGDG_MAX_D + m];
+      rows256 += al256(((int64_t)r.nrow + 1) * 4 + 16) + al256((int64_t)r.nent * 4 + 16);
+      vals256 += al256((int64_t)r.nent * kk * vbytes + 16);
       const Op1D& op = p->ops[hi.dir_tab[m]];
       rows += (int64_t)op.cptr.size() + (int64_t)op.src.size();
       vals += al16((int64_t)op.val.size() * vbytes);
-      rows256 += al256((int64_t)op.cptr.size() * 4 + 16) + al256((int64_t)op.src.size() * 4 + 16);
-      vals256 += al256((int64_t)op.val.size() * vbytes + 16);
     }
     const int64_t lds1 = al256(ntab * 4) + rows256 + al256(hi.ndof * xbytes + 16);
     const int64_t lds2 = lds1 + vals256;
@@ -430,7 +477,7 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
 
   sgdg_status st = SGDG_OK;
   std::vector<float> valf(val_all.begin(), val_all.end());
-  if ((st = upload(p, p->gblk, &p->dev.gblk)) != SGDG_OK ||
+  if ((st = upload(p, p->gblk, &p->dev.gblk)) != SGDG_OK || (st = upload(p, srange, &p->dev.srange)) != SGDG_OK ||
       (st = upload(p, p->chunks, &p->dev.chunks)) != SGDG_OK ||
       (st = upload(p, p->instdev, &p->dev.inst)) != SGDG_OK || (st = upload(p, blkid, &p->dev.blkid)) != SGDG_OK ||
       (st = upload(p, lstart, &p->dev.lstart)) != SGDG_OK || (st = upload(p, bcsr, &p->dev.bcsr)) != SGDG_OK ||

@@ -68,8 +68,16 @@ struct BCsr {
   int32_t pad;
 };
 
+// Rows of one direction's 1D operator that a chunk's outputs use: target
+// cells tlo .. tlo + nrow - 1, i.e. CSR entries elo .. elo + nent - 1 (the
+// staged sweep copies only these rows, their source cells and block values).
+struct StageRange {
+  int32_t tlo, nrow, elo, nent;
+};
+
 struct DevTables {
   GBlock* gblk = nullptr;
+  StageRange* srange = nullptr;  // [chunk][SGDG_MAX_D]
   Chunk* chunks = nullptr;
   InstDev* inst = nullptr;
   int32_t* blkid = nullptr;

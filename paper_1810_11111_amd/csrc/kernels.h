@@ -84,9 +84,11 @@ struct RowsGlobal {
   __device__ __forceinline__ int sc(const BCsr& bc, int i, int e) const { return src[bc.src_off + e]; }
 };
 struct RowsLds {
-  const int32_t* cptr[SGDG_MAX_D];  // LDS, per direction
-  const int32_t* src[SGDG_MAX_D];
-  __device__ __forceinline__ int rp(const BCsr& bc, int i, int t) const { return cptr[i][t]; }
+  const int32_t* cptr[SGDG_MAX_D];  // LDS, per direction: row pointers of target cells tlo.. (entry numbers of the CSR)
+  const int32_t* src[SGDG_MAX_D];   // LDS: source cells of entries elo..
+  int32_t tlo[SGDG_MAX_D], elo[SGDG_MAX_D];
+  // entry numbers relative to elo (so that src[e] and the block values of entry e are at e)
+  __device__ __forceinline__ int rp(const BCsr& bc, int i, int t) const { return cptr[i][t - tlo[i]] - elo[i]; }
   __device__ __forceinline__ int sc(const BCsr& bc, int i, int e) const { return src[i][e]; }
 };
 
