@@ -163,68 +163,62 @@ __device__ __forceinline__ void* dma_copy(void* dst, const void* src, int64_t nb
 // block values into LDS, then APPLY_G lanes share each output element and
 // split its row entries; their partial sums are combined in a fixed order.
 template <int D, int K, class P, bool STAGE_VALS, class TV>
-__global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, const int32_t* __restrict__ list,
+__global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, const SweepTask* __restrict__ tasks,
                                                                    const typename P::X* __restrict__ x,
                                                                    typename P::Y* __restrict__ y, int64_t xstride,
                                                                    int64_t ystride, DotArgs da) {
   using V = typename P::V;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int cid = list[blockIdx.x];
-  const Chunk ch = T.chunks[cid];
+  // one record holds everything needed before the first copy
+  const SweepTask& tk = tasks[blockIdx.x];
+  const int cid = tk.cid;
+  Chunk ch{};
+  ch.start = tk.start;
+  ch.count = tk.count;
+  ch.b0 = tk.b0;
+  ch.b1 = tk.b1;
+  ch.inst = tk.inst;
+  ch.species = tk.species;
+  ch.g = tk.g;
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const int64_t rhs = blockIdx.y;
-  const InstDev& I = T.inst[ch.inst];
-  const int64_t seg = I.offset + (int64_t)ch.species * I.ndof;
+  const int64_t seg = tk.seg, ndof = tk.ndof;
+  const int ntab = tk.ntab;
   double vpre[PRE_I][PRE_Q];
   if constexpr (!std::is_void_v<TV>) pre_basis<TV>(da, (int)rhs, ch, vpre);
   // LDS layout (regions of 256-byte multiples with 16 bytes of slack, as the
   // direct copies keep each array's offset within its 16-byte line):
   // block-start table | per direction: the chunk's row pointers, source cells
-  // | x segment | (STAGE_VALS) per direction: the chunk's block values.  The tables and x are moved by direct global -> LDS copies,
-  // all in flight together; only the block-start table goes through VGPRs.
-  int ntab = 1;
-  for (int m = 0; m < D; ++m) ntab *= (I.N + 1);
-  const int64_t ndof = I.ndof;
+  // | x segment | (STAGE_VALS) per direction: the chunk's block values.  The
+  // tables and x are moved by direct global -> LDS copies, all in flight
+  // together; only the block-start table goes through VGPRs.
   const int wave = tid >> 6, wl64 = tid & 63, nwave = nthr >> 6;
-  // every table descriptor is read before the first direct copy is issued
-  // (loads complete in order, so a later wait would also wait for the copies)
-  BCsr bcs[D];
-#pragma unroll
-  for (int i = 0; i < D; ++i) bcs[i] = T.bcsr[I.bcsr_off[i]];
-  const StageRange* __restrict__ sr = T.srange + (int64_t)cid * SGDG_MAX_D;
-  StageRange rg[D];
-#pragma unroll
-  for (int i = 0; i < D; ++i) rg[i] = sr[i];
   int32_t* bst = (int32_t*)smem;
-  const int bid = tid < ntab ? T.blkid[I.blkid_off + tid] : -1;
+  const int bid = tid < ntab ? T.blkid[tk.blkid_off + tid] : -1;
   unsigned char* cur = smem + lds_al256((int64_t)ntab * 4);
-  // per direction, only the rows this chunk's outputs use (their row
-  // pointers, source cells and, with STAGE_VALS, block values)
-  // (directions sharing an operator share its copy: the plan gives them the
-  // same range; every index below is a compile-time constant after
-  // unrolling, so the pointer tables stay in registers)
+  // per direction, only the rows this chunk's outputs use (row pointers,
+  // source cells and, with STAGE_VALS, block values); directions sharing an
+  // operator share its copy (every index below is a compile-time constant
+  // after unrolling, so the pointer tables stay in registers)
   RowsLds rows;
   ValsLds<P> vl;
-  unsigned dup = 0;  // bit i: direction i reuses an earlier direction's copy
+  const unsigned dup = tk.dup;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    const BCsr bc = bcs[i];
-    rows.tlo[i] = rg[i].tlo;
-    rows.elo[i] = rg[i].elo;
+    rows.tlo[i] = tk.tlo[i];
+    rows.elo[i] = tk.elo[i];
 #pragma unroll
     for (int i2 = 0; i2 < i; ++i2)
-      if (!((dup >> i) & 1u) && bcs[i2].cptr_off == bc.cptr_off && rg[i2].tlo == rg[i].tlo) {
+      if (((dup >> i) & 1u) && tk.cp[i2] == tk.cp[i]) {
         rows.cptr[i] = rows.cptr[i2];
         rows.src[i] = rows.src[i2];
-        dup |= 1u << i;
       }
     if ((dup >> i) & 1u) continue;
-    rows.cptr[i] = (int32_t*)dma_copy(cur, T.cptr + bc.cptr_off + rg[i].tlo, ((int64_t)rg[i].nrow + 1) * 4, wave,
-                                      nwave, wl64);
-    cur += lds_al256(((int64_t)rg[i].nrow + 1) * 4 + 16);
-    rows.src[i] = (int32_t*)dma_copy(cur, T.src + bc.src_off + rg[i].elo, (int64_t)rg[i].nent * 4, wave, nwave, wl64);
-    cur += lds_al256((int64_t)rg[i].nent * 4 + 16);
+    rows.cptr[i] = (int32_t*)dma_copy(cur, T.cptr + tk.cp[i], ((int64_t)tk.nrow[i] + 1) * 4, wave, nwave, wl64);
+    cur += lds_al256(((int64_t)tk.nrow[i] + 1) * 4 + 16);
+    rows.src[i] = (int32_t*)dma_copy(cur, T.src + tk.sp[i], (int64_t)tk.nent[i] * 4, wave, nwave, wl64);
+    cur += lds_al256((int64_t)tk.nent[i] * 4 + 16);
   }
   typename P::X* xl = (typename P::X*)cur;
   const typename P::X* __restrict__ xg = x + rhs * xstride + seg;
@@ -238,16 +232,15 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
     constexpr int64_t KK = (int64_t)(K + 1) * (K + 1);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      const V* vsrc = vals + bcs[i].val_off + (int64_t)rg[i].elo * KK;
 #pragma unroll
       for (int i2 = 0; i2 < i; ++i2)
-        if (bcs[i2].cptr_off == bcs[i].cptr_off && rg[i2].tlo == rg[i].tlo) vl.v[i] = vl.v[i2];
+        if (((dup >> i) & 1u) && tk.cp[i2] == tk.cp[i]) vl.v[i] = vl.v[i2];
       if ((dup >> i) & 1u) continue;
       if constexpr (STAGE_VALS) {
-        vl.v[i] = (V*)dma_copy(cur, vsrc, (int64_t)rg[i].nent * KK * (int64_t)sizeof(V), wave, nwave, wl64);
-        cur += lds_al256((int64_t)rg[i].nent * KK * (int64_t)sizeof(V) + 16);
+        vl.v[i] = (V*)dma_copy(cur, vals + tk.vp[i], (int64_t)tk.nent[i] * KK * (int64_t)sizeof(V), wave, nwave, wl64);
+        cur += lds_al256((int64_t)tk.nent[i] * KK * (int64_t)sizeof(V) + 16);
       } else {
-        vl.v[i] = vsrc;  // the block values stay in global memory
+        vl.v[i] = vals + tk.vp[i];  // the block values stay in global memory
       }
     }
   }
@@ -262,6 +255,7 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
   const bool active = e < ch.count;
   typename P::A acc = 0;
   if (active) {
+    const InstDev& I = T.inst[ch.inst];
     const int64_t g = ch.start + e;
     const GBlock& B = T.gblk[find_block(T, ch, g)];
     SrcLds<P> xs{xl, bst};
@@ -296,7 +290,7 @@ static void launch_staged(const sgdg_plan* plan, int kind, int nrhs, const void*
   }
   hipLaunchKernelGGL((apply_kernel_lds<D, K, P, SV, TV>),
                      dim3((unsigned)plan->chunk_lists[kind].size(), (unsigned)nrhs), dim3(CHUNK * APPLY_G), lds, s,
-                     plan->dev, plan->dev_chunk_lists[kind], (const typename P::X*)x, (typename P::Y*)y, xs, ys, da);
+                     plan->dev, plan->dev_tasks[kind], (const typename P::X*)x, (typename P::Y*)y, xs, ys, da);
 }
 
 template <int D, int K, class P, class TV>

@@ -493,9 +493,51 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
   p->pchunk0 = pc0;
   p->pnchunk = pnc;
   p->dev_chunk_lists.assign(p->chunk_lists.size(), nullptr);
+  p->dev_tasks.assign(p->chunk_lists.size(), nullptr);
   for (size_t kind = 0; kind < p->chunk_lists.size(); ++kind) {
     if (p->chunk_lists[kind].empty()) continue;
     if ((st = upload(p, p->chunk_lists[kind], &p->dev_chunk_lists[kind])) != SGDG_OK) {
+      sg_dg_destroy(p);
+      return st;
+    }
+    if (kind % SWEEP_TIERS == 0) continue;
+    std::vector<SweepTask> tasks(p->chunk_lists[kind].size());
+    for (size_t e = 0; e < tasks.size(); ++e) {
+      const int32_t c = p->chunk_lists[kind][e];
+      const Chunk& ch = p->chunks[c];
+      const HostInstance& hi = p->inst[ch.inst];
+      const InstDev& id = p->instdev[ch.inst];
+      const int64_t kk = (int64_t)(hi.desc.k + 1) * (hi.desc.k + 1);
+      SweepTask& t = tasks[e];
+      t = SweepTask{};
+      t.start = ch.start;
+      t.seg = hi.offset + (int64_t)ch.species * hi.ndof;
+      t.ndof = hi.ndof;
+      t.cid = c;
+      t.count = ch.count;
+      t.g = ch.g;
+      t.inst = ch.inst;
+      t.species = ch.species;
+      t.b0 = ch.b0;
+      t.b1 = ch.b1;
+      t.ntab = 1;
+      for (int m = 0; m < d; ++m) t.ntab *= (hi.desc.n + 1);
+      t.blkid_off = id.blkid_off;
+      for (int m = 0; m < d; ++m) {
+        const BCsr& bc = bcsr[id.bcsr_off[m]];
+        const StageRange& r = srange[(size_t)c * SGDG_MAX_D + m];
+        t.cp[m] = bc.cptr_off + r.tlo;
+        t.sp[m] = bc.src_off + r.elo;
+        t.vp[m] = bc.val_off + (int64_t)r.elo * kk;
+        t.nrow[m] = r.nrow;
+        t.nent[m] = r.nent;
+        t.tlo[m] = r.tlo;
+        t.elo[m] = r.elo;
+        for (int m2 = 0; m2 < m; ++m2)
+          if (!((t.dup >> m) & 1u) && hi.dir_tab[m2] == hi.dir_tab[m]) t.dup |= 1u << m;
+      }
+    }
+    if ((st = upload(p, tasks, &p->dev_tasks[kind])) != SGDG_OK) {
       sg_dg_destroy(p);
       return st;
     }

@@ -75,6 +75,19 @@ struct StageRange {
   int32_t tlo, nrow, elo, nent;
 };
 
+// Everything the staged sweep reads before its first copy, one record per
+// entry of a staged chunk list (one scalar load round instead of a chain of
+// chunk -> instance -> operator lookups).
+struct SweepTask {
+  int64_t start, seg, ndof;      // chunk start, species segment start, segment length
+  int32_t cid, count, g, inst, species, b0, b1, ntab, blkid_off;
+  uint32_t dup;                  // bit i: direction i shares an earlier direction's staged copy
+  int64_t cp[SGDG_MAX_D];        // staged rows of direction i: T.cptr + cp, T.src + sp, block values + vp
+  int64_t sp[SGDG_MAX_D];
+  int64_t vp[SGDG_MAX_D];
+  int32_t nrow[SGDG_MAX_D], nent[SGDG_MAX_D], tlo[SGDG_MAX_D], elo[SGDG_MAX_D];
+};
+
 struct DevTables {
   GBlock* gblk = nullptr;
   StageRange* srange = nullptr;  // [chunk][SGDG_MAX_D]
@@ -128,6 +141,7 @@ struct sgdg_plan {
   // 2 = block values staged as well
   std::vector<std::vector<int32_t>> chunk_lists;
   std::vector<int32_t*> dev_chunk_lists;
+  std::vector<sgdg::SweepTask*> dev_tasks;  // staged lists: per entry, its SweepTask
   std::vector<int> list_lds;    // dynamic LDS bytes of the staged lists
   std::vector<int> list_fixed;  // of which tables and block values (all but the x segment), maximum over the list
   std::vector<sgdg::InstDev> instdev;
