@@ -70,7 +70,7 @@ static std::vector<std::vector<int>> grid_blocks(int r, int N) {
 constexpr int RX_THREADS_FIB = 128;   // expansion / contraction fibres
 constexpr int RX_THREADS_LINE = 256;  // lines of the last axis
 constexpr int RX_MAX_N1 = 2048;
-constexpr int RX_TAIL = 64 + 16;  // two-scale matrices + per-wave partial sums
+constexpr int RX_TAIL = 64 + 16 + 16;  // two-scale matrices + per-wave partial sums + level starts of a fibre
 
 static size_t fibre_lds_bytes(const RHost* rh) {
   return (3 * (size_t)rh->max_n1 + (size_t)rh->max_np1 + RX_TAIL) * sizeof(double);
@@ -502,11 +502,15 @@ __device__ void rx_expand_body(const RTables& R, int inst, int m, int64_t total,
              : xr + I.X_off[m] + (((int64_t)z * S + s) * I.npre[m] + pre0) * gd_in;
   double* out = xr + I.X_off[m + 1] + (((int64_t)z * S + s) * I.npre[m + 1] + pre0 * np1) * gd_out + eo;
   const double* __restrict__ EL = R.EL + I.EL_off;
+  // start of the fibre's level-l block (l <= L), one thread per level, then
+  // every entry of every level is loaded in one round
+  int64_t* lb = (int64_t*)(M + 80);
+  if ((int)threadIdx.x <= L) lb[threadIdx.x] = ib[id[threadIdx.x * pw + lin]].start + rest;
   load_mats(R, I, M);
-  for (int l = 0; l <= L; ++l) {
-    const int64_t base = ib[id[l * pw + lin]].start + rest;
-    const int cnt = level_count(l) * K1;
-    for (int t = threadIdx.x; t < cnt; t += blockDim.x) h[off1(l, K1) + t] = in[base + (int64_t)t * Sb];
+  __syncthreads();
+  for (int e = threadIdx.x; e < (K1 << L); e += blockDim.x) {
+    const int l = e < K1 ? 0 : 32 - __clz(e / K1);  // entry e of levels 0..L in hierarchical order
+    h[e] = in[lb[l] + (int64_t)(e - off1(l, K1)) * Sb];
   }
   __syncthreads();
   const double* sc = ifwt<K1>(h, b0, b1, L, M);
@@ -687,23 +691,27 @@ __device__ void rx_contract_body(const RTables& R, int inst, int m, int mode, in
   double* xr = a.rws + (int64_t)rhs * rws;
   const double* __restrict__ EL = R.EL + I.EL_off;
   const double* __restrict__ w1 = R.w1 + I.w_off;
+  // start of the output's level-n block (n <= L), one thread per level,
+  // before the transform needs them
+  const int32_t* __restrict__ id = R.rid + I.id_off[r];
+  const RBlk* ib = R.rblk + I.blk_off[r];
+  int64_t* lb = (int64_t*)(M + 80);
+  if ((int)threadIdx.x <= L) lb[threadIdx.x] = ib[id[threadIdx.x * pw + lin]].start;
   load_mats(R, I, M);
   const double* __restrict__ in = xr + I.Y_off[m + 1] + ((int64_t)s * I.npre[m + 1] + pre0 * np1) * gd_in + eo;
   for (int q = threadIdx.x; q < np1; q += blockDim.x) g[q] = w1[q] * in[(int64_t)q * gd_in];
   __syncthreads();
   project_cells<K1>(g, EL, N, np1, b0);
-  const int32_t* __restrict__ id = R.rid + I.id_off[r];
-  const RBlk* ib = R.rblk + I.blk_off[r];
   if (m > 0) {
     double* out = xr + I.Y_off[m] + ((int64_t)s * I.npre[m] + pre0) * gd_out + rest;
     ffwt<K1>(b0, b1, N, M, [&](int n, int j, int p, double v) {
-      if (n <= L) out[ib[id[n * pw + lin]].start + (int64_t)(j * K1 + p) * Sb] = v;
+      if (n <= L) out[lb[n] + (int64_t)(j * K1 + p) * Sb] = v;
     });
   } else {
     const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)s * I.ndof + rest;
     double g2 = 0.0;
     ffwt<K1>(b0, b1, N, M, [&](int n, int j, int p, double v) {
-      if (n <= L) g2 += finish(a, mode, base + ib[id[n * pw + lin]].start + (int64_t)(j * K1 + p) * Sb, v);
+      if (n <= L) g2 += finish(a, mode, base + lb[n] + (int64_t)(j * K1 + p) * Sb, v);
     });
     if (mode == RX_RESID) {
       g2 = block_sum(g2, wsum);
