@@ -541,9 +541,12 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
   const int d = I.d, N = I.N, S = I.S, np1 = I.np1, n1 = I.n1;
   const int64_t pre = gl - R.cum_line[inst];
   const int nin = mode == RX_CORR ? 2 : 1;
-  // ngrp groups of threads transform different (input, species) lines at the
-  // same time, each in its own three buffers
-  const int gs = blockDim.x / ngrp, gi = threadIdx.x / gs, gt = threadIdx.x - gi * gs;
+  // up to ngrp groups of threads transform different (input, species) lines
+  // at the same time, each in its own three buffers (no more groups than
+  // lines, so that each group is as large as possible)
+  const int npair = nin * S;
+  const int ng = min(ngrp, npair);
+  const int gs = blockDim.x / ng, gi = threadIdx.x / gs, gt = threadIdx.x - gi * gs;
   double* h = lds + (int64_t)gi * 3 * max_n1;
   double* b0 = h + max_n1;
   double* b1 = b0 + max_n1;
@@ -555,8 +558,7 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
   const double* __restrict__ w1 = R.w1 + I.w_off;
   const double dt2 = a.dt2;
   load_mats(R, I, M);
-  const int npair = nin * S;
-  for (int r0 = 0; r0 < npair; r0 += ngrp) {
+  for (int r0 = 0; r0 < npair; r0 += ng) {
     const int pi = r0 + gi;
     const bool act = pi < npair;
     const int z = act ? pi / S : 0, s = act ? pi - z * S : 0;
@@ -619,7 +621,7 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
   __syncthreads();
   double g2 = 0.0;
   // contraction: the species at the same time when there are groups enough
-  const int cg = min(ngrp, S);
+  const int cg = min(ng, S);
   const int cgs = blockDim.x / cg, cgi = threadIdx.x / cgs, cgt = threadIdx.x - cgi * cgs;
   double* c0 = lds + (int64_t)cgi * 3 * max_n1;
   double* c1 = c0 + max_n1;
