@@ -176,7 +176,10 @@ __global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int nin
   const int p = prob_of(rhs, ninst, ch);
   const int c0 = ch.pc0, nc = ch.pnc;
   // products v_i x_{j+1} of the chunk, column i at tp[i][.] (see the end)
-  __shared__ double sv[SGDG_MAX_M + 1], cv[SGDG_MAX_M + 1], red[CHUNK], tp[(JB + 2) * CHUNK];
+  // (column stride CHUNK + 1: the slice sums read columns in the same rows,
+  // and an odd stride puts them in different LDS banks)
+  constexpr int TPS = CHUNK + 1;
+  __shared__ double sv[SGDG_MAX_M + 1], cv[SGDG_MAX_M + 1], red[CHUNK], tp[(JB + 2) * TPS];
   __shared__ double alpha_s;
   __shared__ int stop_s;
   const double* pin = (j & 1) ? ws.part3 : ws.part2;
@@ -290,9 +293,9 @@ __global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int nin
   // s, s + S, ... of column i in that order, and the S slices in order
 #pragma unroll
   for (int i = 0; i < JB; ++i)
-    if (i < j) tp[i * CHUNK + tid] = vv[i] * ur;
-  tp[j * CHUNK + tid] = vr * ur;
-  tp[(j + 1) * CHUNK + tid] = ur * ur;
+    if (i < j) tp[i * TPS + tid] = vv[i] * ur;
+  tp[j * TPS + tid] = vr * ur;
+  tp[(j + 1) * TPS + tid] = ur * ur;
   __syncthreads();
   {
     constexpr int CJ = JB + 2, S2 = CHUNK / CJ, NE = (CHUNK + S2 - 1) / S2;
@@ -302,7 +305,7 @@ __global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int nin
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
         const int e = s2 + q * S2;
-        if (e < CHUNK) acc += tp[i * CHUNK + e];
+        if (e < CHUNK) acc += tp[i * TPS + e];
       }
       red[tid] = acc;
     }
