@@ -495,6 +495,8 @@ __device__ __forceinline__ double hess_from_log(const DevTables& T, const Krylov
       Rm[j * LDM + j] = j ? x : 1.0;
     }
   }
+  // the diagonal of R was scattered by other waves' threads
+  __syncthreads();
   if (tid < mp) rinv[tid] = tid < m ? 1.0 / (tid ? Rm[tid * LDM + tid] : 1.0) : 1.0;
   __syncthreads();
   if (tid < m) {

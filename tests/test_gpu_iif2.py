@@ -213,6 +213,45 @@ def test_iif2_gray_scott_batch_uneven():
             assert st[i * 2 + s]["status"] == 0
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_iif2_batch_long_run_stays_finite(prec):
+    """150 back-to-back IIF2 steps of the 64-instance Gray-Scott batch: every
+    problem converges in every step and the state stays finite.  Regression
+    for a wave-ordering race in the Hessenberg assembly (a wave read R's
+    diagonal before another wave had written it), which turned the Krylov
+    coefficients of some problem into NaN in about one step in a hundred."""
+    import torch
+
+    sg = lib()
+    wl = I.gray_scott_batch()
+    say(f"iif2 gray-scott batch 64, 150 steps, {prec}")
+    plan = sg.Plan(wl.instances, prec)
+    x = np.zeros(plan.total)
+    for i in range(len(wl.instances)):
+        nd, off, _ = plan.info(i)
+        for s, (terms, mults, _) in enumerate(wl.initial_condition(i, nd)):
+            for (amp, fac), mult in zip(terms, mults):
+                pr = plan.project(i, amp, fac)
+                x[off + s * nd : off + (s + 1) * nd] += pr * (1.0 + mult) if mult is not None else pr
+    U = to_dev(x)
+    F = torch.zeros_like(U)
+    ws = _ws(plan, wl.M)
+    st = _stats(plan)
+    plan.reaction(U, F, ws)
+    worst = 0
+    # (a tolerance a little above the rounding floor of the largest instances'
+    # residual, so that only non-finite values or divergence can fail)
+    for n in range(150):
+        plan.iif2_step(wl.dt, wl.M, U, F, ws, newton_tol=1e-13, newton_max=5, stats=st)
+        if n % 10 == 9:
+            s = sg.stats_array(st)
+            worst = max(worst, int(s["status"].max()))
+            assert worst == 0, (n, np.nonzero(s["status"])[0][:8])
+    Uh = U.cpu().numpy()
+    assert np.isfinite(Uh).all()
+    plan.close()
+
+
 def test_iif2_quadratic_batch_of_rhs():
     sg = lib()
     wl = I.quadratic_d4(N=3, nrhs=4, steps=2)
