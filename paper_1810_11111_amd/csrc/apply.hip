@@ -82,6 +82,100 @@ __device__ __forceinline__ void chunk_dots_pre(const DotArgs& da, int c, int rhs
   }
 }
 
+// Global-gather form of apply_one for the outputs of a chunk's first block:
+// the source block of level lc in direction i starts at bb[i * BB_L + lc]
+// (a table the workgroup builds in LDS), and each lane takes its row entries
+// RB at a time -- their source cells loaded together, then every block value
+// and x entry of the RB entries, then the products -- so a round costs three
+// dependent memory round trips where the entry-by-entry walk costs two per
+// entry plus two table loads per source level.  Entries past the row or the
+// level budget are masked (their clamped loads stay inside the source
+// blocks), and the walk ends with the round that reaches the budget; the
+// products are summed in the order apply_one sums them.
+constexpr int BB_L = 32;
+
+// (measured for d=3 N=16 k=1: 2 entries per lane per round 1.60 ms, 4: 1.64,
+// 8: 1.88, the entry-by-entry walk 2.20)
+template <int K>
+constexpr int batch_entries() {
+  return 2;
+}
+
+template <int D, int K, class P>
+__device__ __forceinline__ typename P::A apply_one_batched(const DevTables& T, const GBlock& B, const InstDev& I,
+                                                           int64_t g, int lane, int G,
+                                                           const typename P::X* __restrict__ x, const int64_t* bb) {
+  using A = typename P::A;
+  using V = typename P::V;
+  constexpr int K1 = K + 1;
+  constexpr int RB = batch_entries<K>();
+  int ext[D], sh[D], t[D], lev[D];
+  {
+    int rem = (int)(g - B.start);
+    for (int m = D - 1; m >= 0; --m) {
+      lev[m] = B.lev[m];
+      sh[m] = lev[m] > 0 ? lev[m] - 1 : 0;
+      ext[m] = K1 << sh[m];
+      const int q = (rem / K1) >> sh[m];
+      t[m] = rem - q * ext[m];
+      rem = q;
+    }
+  }
+  int str[D];
+  str[D - 1] = 1;
+  for (int m = D - 2; m >= 0; --m) str[m] = str[m + 1] * ext[m + 1];
+  int pre[D + 1], suf[D + 1];
+  pre[0] = 0;
+  for (int m = 0; m < D; ++m) pre[m + 1] = pre[m] * ext[m] + t[m];
+  suf[D] = 0;
+  for (int m = D - 1; m >= 0; --m) suf[m] = suf[m + 1] + t[m] * str[m];
+  const V* __restrict__ vals = P::vals(T);
+  A acc = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int li = lev[i];
+    const int lim = 1 << (I.N - B.lsum + li);
+    const int pt = t[i] % K1, jt = t[i] / K1;
+    const int tcell = li == 0 ? 0 : (1 << (li - 1)) + jt;
+    const int S = str[i], Ahi = pre[i], Blo = suf[i + 1];
+    const BCsr bc = T.bcsr[I.bcsr_off[i]];
+    const int e0 = T.cptr[bc.cptr_off + tcell], e1 = T.cptr[bc.cptr_off + tcell + 1];
+    const int32_t* __restrict__ srow = T.src + bc.src_off;
+    const V* __restrict__ vrow = vals + bc.val_off + pt * K1;
+    const int64_t* bbi = bb + i * BB_L;
+    for (int eb = e0 + lane; eb < e1; eb += RB * G) {
+      int sc[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) sc[r] = srow[min(eb + r * G, e1 - 1)];
+      A xv[RB][K1];
+      V vv[RB][K1];
+      bool ok[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        ok[r] = eb + r * G < e1 && sc[r] < lim;
+        const int lc = ok[r] && sc[r] > 0 ? 32 - __clz(sc[r]) : 0;
+        const int extc = lc == 0 ? K1 : (K1 << (lc - 1));
+        const int jc = lc == 0 ? 0 : sc[r] - (1 << (lc - 1));
+        const int64_t base = bbi[lc] + (int64_t)(Ahi * extc + jc * K1) * S + Blo;
+        const V* __restrict__ v = vrow + (int64_t)min(eb + r * G, e1 - 1) * K1 * K1;
+#pragma unroll
+        for (int pc = 0; pc < K1; ++pc) {
+          vv[r][pc] = v[pc];
+          xv[r][pc] = P::load(x + base + (int64_t)pc * S);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int pc = 0; pc < K1; ++pc) acc += (ok[r] ? (A)vv[r][pc] : (A)0) * (ok[r] ? xv[r][pc] : (A)0);
+      // a row lists its source cells in ascending order (coarse levels
+      // first), so once an entry is past the level budget the rest are too
+      if (sc[RB - 1] >= lim) break;
+    }
+  }
+  return acc * (A)(-I.D[B.species]);
+}
+
 template <int D, int K, class P, class TV>
 __global__ __launch_bounds__(CHUNK) void apply_kernel(DevTables T, const int32_t* __restrict__ list,
                                                       const typename P::X* __restrict__ x, typename P::Y* __restrict__ y,
@@ -90,6 +184,21 @@ __global__ __launch_bounds__(CHUNK) void apply_kernel(DevTables T, const int32_t
   const Chunk ch = T.chunks[c];
   const int tid = threadIdx.x;
   const int64_t rhs = blockIdx.y;
+  // start of every source block the chunk's first block reads, per direction
+  // and source level (one thread each, all loads in flight together)
+  __shared__ int64_t bb[SGDG_MAX_D * BB_L];
+  const GBlock& B0 = T.gblk[ch.b0];
+  const InstDev& I0 = T.inst[B0.inst];
+  const bool tab = I0.N < BB_L;
+  if (tab && tid < D * BB_L) {
+    const int i = tid / BB_L, lc = tid - i * BB_L;
+    if (lc <= I0.N - B0.lsum + B0.lev[i]) {
+      int lin = (lc - B0.lev[i]) * I0.pow[i];
+      for (int m = 0; m < D; ++m) lin += B0.lev[m] * I0.pow[m];
+      bb[tid] = I0.offset + (int64_t)B0.species * I0.ndof + T.lstart[T.blkid[I0.blkid_off + lin]];
+    }
+  }
+  __syncthreads();
   // chunks of heavy (coarse-level) rows give each output several lanes
   const int G = ch.g / APPLY_G;
   const int e = tid / G, lane = tid - e * G;
@@ -97,12 +206,16 @@ __global__ __launch_bounds__(CHUNK) void apply_kernel(DevTables T, const int32_t
   typename P::A acc = 0;
   if (active) {
     const int64_t g = ch.start + e;
-    const GBlock& B = T.gblk[find_block(T, ch, g)];
-    const InstDev& I = T.inst[B.inst];
-    SrcGlobal<P> xs{x + rhs * xstride, T.blkid + I.blkid_off, T.lstart, I.offset + (int64_t)B.species * I.ndof};
-    RowsGlobal rows{T.cptr, T.src};
-    ValsGlobal<P> vs{P::vals(T)};
-    acc = apply_one<D, K, P>(T, B, I, g, lane, G, xs, rows, vs);
+    if (tab && g < B0.start + B0.size) {
+      acc = apply_one_batched<D, K, P>(T, B0, I0, g, lane, G, x + rhs * xstride, bb);
+    } else {
+      const GBlock& B = T.gblk[find_block(T, ch, g)];
+      const InstDev& I = T.inst[B.inst];
+      SrcGlobal<P> xs{x + rhs * xstride, T.blkid + I.blkid_off, T.lstart, I.offset + (int64_t)B.species * I.ndof};
+      RowsGlobal rows{T.cptr, T.src};
+      ValsGlobal<P> vs{P::vals(T)};
+      acc = apply_one<D, K, P>(T, B, I, g, lane, G, xs, rows, vs);
+    }
   }
   for (int o = 1; o < G; o <<= 1) acc += __shfl_xor(acc, o, 64);
   const typename P::Y out = (typename P::Y)acc;

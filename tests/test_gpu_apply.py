@@ -25,6 +25,16 @@ CASES = [
     (3, 4, 2, [1.0], (1.0, 0.5, 1.0)),
     (4, 3, 1, [2.0], None),
     (5, 2, 1, [1.0], None),
+    # segments too large for the LDS: the global-gather kernel (k = 1, 2, 3).
+    # The library's and the oracle's 1D operator entries differ by rounding
+    # that grows with the number of levels and the degree (two-scale
+    # transforms of large penalty terms): measured 1.6e-13 (d=2 N=10 k=1),
+    # 7.2e-14 (d=3 N=7 k=2) and 6.2e-13 (d=3 N=6 k=3) of max(|A||x|), the same
+    # for every summation order of the sweep; these cases use 1e-12 / 2e-12,
+    # still 1e11 below an indexing mistake.
+    (2, 10, 1, [0.5, 2.0], None, 1e-12),
+    (3, 7, 2, [1.0], None, 1e-12),
+    (3, 6, 3, [1.0], (1.0, 0.5, 1.0), 2e-12),
 ]
 
 
@@ -48,7 +58,8 @@ def test_apply_fp64_matches_explicit_operator(case):
     sg = lib()
     import torch
 
-    d, N, k, D, kdiag = case
+    d, N, k, D, kdiag = case[:5]
+    tol = case[5] if len(case) > 5 else 1e-13
     inst = I.Instance(d, N, k, D, I.rx_zeros(len(D)), kdiag=kdiag)
     say("apply fp64", case)
     plan = sg.Plan([inst], "fp64")
@@ -69,7 +80,7 @@ def test_apply_fp64_matches_explicit_operator(case):
     for r in range(nrhs):
         for s, Ds in enumerate(D):
             seg = slice(off + s * nd, off + (s + 1) * nd)
-            _check(Y[r, seg], Ds * (A1 @ X[r, seg]), Ds * A1, X[r, seg], 1e-13, f"rhs {r} species {s}")
+            _check(Y[r, seg], Ds * (A1 @ X[r, seg]), Ds * A1, X[r, seg], tol, f"rhs {r} species {s}")
     # ||A_s||_inf agrees with the explicit matrix
     for s, Ds in enumerate(D):
         assert plan.norm_inf(0, s) == pytest.approx(Ds * operator.inf_norm(A1), rel=1e-12)
@@ -117,11 +128,12 @@ def test_apply_multi_instance_uneven_levels():
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 1e-2)])
-def test_apply_reduced_precision(prec, tol):
+@pytest.mark.parametrize("dnk", [(3, 4, 1), (3, 7, 2)], ids=["staged", "global"])
+def test_apply_reduced_precision(prec, tol, dnk):
     sg = lib()
     import torch
 
-    d, N, k = 3, 4, 1
+    d, N, k = dnk
     say("apply", prec, d, N, k)
     plan = sg.Plan([I.Instance(d, N, k, [1.0], I.rx_zeros(1))], prec)
     X = I.smooth_random(plan.total, 5, 1)[0]
