@@ -94,8 +94,9 @@ __device__ __forceinline__ void chunk_dots_pre(const DotArgs& da, int c, int rhs
 // products are summed in the order apply_one sums them.
 constexpr int BB_L = 32;
 
-// (measured for d=3 N=16 k=1: 2 entries per lane per round 1.60 ms, 4: 1.64,
-// 8: 1.88, the entry-by-entry walk 2.20)
+// (measured for d=3 N=16 k=1 before the wave-uniform walk below: 2 entries
+// per lane per round 1.60 ms, 4: 1.64, 8: 1.88, the entry-by-entry walk 2.20;
+// with it, 2 entries per round there as well: 1.49 ms, 4: 1.52, 8: 1.59)
 template <int K>
 constexpr int batch_entries() {
   return 2;
@@ -139,10 +140,50 @@ __device__ __forceinline__ typename P::A apply_one_batched(const DevTables& T, c
     const int tcell = li == 0 ? 0 : (1 << (li - 1)) + jt;
     const int S = str[i], Ahi = pre[i], Blo = suf[i + 1];
     const BCsr bc = T.bcsr[I.bcsr_off[i]];
-    const int e0 = T.cptr[bc.cptr_off + tcell], e1 = T.cptr[bc.cptr_off + tcell + 1];
     const int32_t* __restrict__ srow = T.src + bc.src_off;
-    const V* __restrict__ vrow = vals + bc.val_off + pt * K1;
     const int64_t* bbi = bb + i * BB_L;
+    // when every lane of the wave reads the same row (one lane per output,
+    // and the wave's outputs differ only in the axes after i), the row is
+    // walked once with wave-uniform loads of its source cells and block
+    // values; only x differs between the lanes, at consecutive addresses
+    const int tc0 = __builtin_amdgcn_readfirstlane(tcell);
+    const int pt0 = __builtin_amdgcn_readfirstlane(pt);
+    const int ah0 = __builtin_amdgcn_readfirstlane(Ahi);
+    if (G == 1 && __builtin_amdgcn_ballot_w64(tcell != tc0 || pt != pt0 || Ahi != ah0) == 0) {
+      constexpr int RU = 2;
+      const int u0 = T.cptr[bc.cptr_off + tc0], u1 = T.cptr[bc.cptr_off + tc0 + 1];
+      const V* __restrict__ vrow0 = vals + bc.val_off + pt0 * K1;
+      for (int eb = u0; eb < u1; eb += RU) {
+        int sc[RU];
+#pragma unroll
+        for (int r = 0; r < RU; ++r) sc[r] = srow[min(eb + r, u1 - 1)];
+        A xv[RU][K1];
+        V vv[RU][K1];
+        bool ok[RU];
+#pragma unroll
+        for (int r = 0; r < RU; ++r) {
+          ok[r] = eb + r < u1 && sc[r] < lim;
+          const int lc = ok[r] && sc[r] > 0 ? 32 - __clz(sc[r]) : 0;
+          const int extc = lc == 0 ? K1 : (K1 << (lc - 1));
+          const int jc = lc == 0 ? 0 : sc[r] - (1 << (lc - 1));
+          const int64_t base = bbi[lc] + (int64_t)(ah0 * extc + jc * K1) * S + Blo;
+          const V* __restrict__ v = vrow0 + (int64_t)min(eb + r, u1 - 1) * K1 * K1;
+#pragma unroll
+          for (int pc = 0; pc < K1; ++pc) {
+            vv[r][pc] = v[pc];
+            xv[r][pc] = P::load(x + base + (int64_t)pc * S);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < RU; ++r)
+#pragma unroll
+          for (int pc = 0; pc < K1; ++pc) acc += (ok[r] ? (A)vv[r][pc] : (A)0) * (ok[r] ? xv[r][pc] : (A)0);
+        if (sc[RU - 1] >= lim) break;
+      }
+      continue;
+    }
+    const int e0 = T.cptr[bc.cptr_off + tcell], e1 = T.cptr[bc.cptr_off + tcell + 1];
+    const V* __restrict__ vrow = vals + bc.val_off + pt * K1;
     for (int eb = e0 + lane; eb < e1; eb += RB * G) {
       int sc[RB];
 #pragma unroll
