@@ -72,30 +72,38 @@ constexpr int RX_THREADS_LINE = 256;  // lines of the last axis
 constexpr int RX_MAX_N1 = 2048;
 constexpr int RX_TAIL = 64 + 16 + 16;  // two-scale matrices + per-wave partial sums + level starts of a fibre
 
-static size_t fibre_lds_bytes(const RHost* rh) {
-  return (3 * (size_t)rh->max_n1 + (size_t)rh->max_np1 + RX_TAIL) * sizeof(double);
+// LDS per workgroup (doubles: buffers of the largest fibre, then the tail).
+// The expansion keeps the hierarchical input and two transform buffers; the
+// contraction's point values are dead once projected, so its second
+// transform buffer takes their place; the line kernel has three buffers per
+// transform group and one point buffer per (input, species) pair.
+static size_t expand_lds_bytes(const RHost* rh) {
+  return (3 * (size_t)rh->max_n1 + RX_TAIL) * sizeof(double);
 }
-static size_t line_lds_bytes(const RHost* rh, int ngrp) {
-  return (3 * (size_t)ngrp * rh->max_n1 + 4 * (size_t)rh->max_np1 + RX_TAIL) * sizeof(double);
+static size_t contract_lds_bytes(const RHost* rh) {
+  return (2 * (size_t)rh->max_n1 + RX_TAIL) * sizeof(double);
+}
+static size_t line_lds_bytes(const RHost* rh, int ngrp, int nin) {
+  return (3 * (size_t)ngrp * rh->max_n1 + 2 * (size_t)nin * rh->max_np1 + RX_TAIL) * sizeof(double);
 }
 // Concurrent transform groups of the line kernel (4, 2 or 1).  More groups
 // shorten each line's chain of barriers but take more LDS per workgroup; the
 // most that fit the LDS and still let every line of the launch be resident at
 // once (when a launch is larger than one wave of workgroups, throughput
 // matters more than the length of a line's chain).
-static int line_groups(const RHost* rh, int64_t nlines) {
+static int line_groups(const RHost* rh, int64_t nlines, int nin) {
   int g = 4;
   while (g > 1) {
-    const size_t b = line_lds_bytes(rh, g);
+    const size_t b = line_lds_bytes(rh, g, nin);
     const int64_t per_cu = b <= (size_t)APPLY_LDS_BYTES_HOST ? (int64_t)APPLY_LDS_BYTES_HOST / (int64_t)b : 0;
     if (per_cu > 0 && nlines <= per_cu * std::max(rh->ncu, 1)) break;
     g >>= 1;
   }
   return g;
 }
-static int line_groups_max(const RHost* rh) {
+static int line_groups_max(const RHost* rh, int nin) {
   int g = 4;
-  while (g > 1 && line_lds_bytes(rh, g) > (size_t)APPLY_LDS_BYTES_HOST) g >>= 1;
+  while (g > 1 && line_lds_bytes(rh, g, nin) > (size_t)APPLY_LDS_BYTES_HOST) g >>= 1;
   return g;
 }
 static sgdg_status set_lds_attrs(const RHost* rh);
@@ -550,8 +558,8 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
   double* h = lds + (int64_t)gi * 3 * max_n1;
   double* b0 = h + max_n1;
   double* b1 = b0 + max_n1;
-  double* pts = lds + (int64_t)ngrp * 3 * max_n1;  // [z*2+s][max_np1]
-  double* M = pts + 4 * max_np1;
+  double* pts = lds + (int64_t)ngrp * 3 * max_n1;  // [z*2+s][max_np1], z < nin
+  double* M = pts + 2 * nin * max_np1;
   double* wsum = M + 64;
   double* xr = a.rws + (int64_t)rhs * rws;
   const double* __restrict__ EL = R.EL + I.EL_off;
@@ -687,8 +695,8 @@ __device__ void rx_contract_body(const RTables& R, int inst, int m, int mode, in
   }
   double* g = lds;
   double* b0 = lds + max_n1;
-  double* b1 = lds + 2 * max_n1;
-  double* M = lds + 3 * max_n1;
+  double* b1 = lds;  // the point values are dead once projected into b0
+  double* M = lds + 2 * max_n1;
   double* wsum = M + 64;
   double* xr = a.rws + (int64_t)rhs * rws;
   const double* __restrict__ EL = R.EL + I.EL_off;
@@ -735,14 +743,15 @@ __global__ __launch_bounds__(RX_THREADS_FIB) void k_rx_contract(RTables R, int n
 }
 
 static sgdg_status set_lds_attrs(const RHost* rh) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_rx_line, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)line_lds_bytes(rh, line_groups_max(rh)));
+  size_t lmax = 0;
+  for (int nin = 1; nin <= 2; ++nin) lmax = std::max(lmax, line_lds_bytes(rh, line_groups_max(rh, nin), nin));
+  hipError_t e = hipFuncSetAttribute((const void*)k_rx_line, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lmax);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_rx_expand, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)fibre_lds_bytes(rh));
+                            (int)expand_lds_bytes(rh));
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_rx_contract, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)fibre_lds_bytes(rh));
+                            (int)contract_lds_bytes(rh));
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(reaction kernels LDS)");
   return SGDG_OK;
 }
@@ -751,17 +760,17 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
   const RHost* rh = (const RHost*)plan->rdata;
   const int d = plan->d, ninst = plan->ninst;
   const int nin = mode == RX_CORR ? 2 : 1;
-  const int ngrp = std::min(line_groups(rh, rh->cum_line.back() * nrhs), line_groups_max(rh));
-  const size_t fl = fibre_lds_bytes(rh), ll = line_lds_bytes(rh, ngrp);
+  const int ngrp = std::min(line_groups(rh, rh->cum_line.back() * nrhs, nin), line_groups_max(rh, nin));
+  const size_t el = expand_lds_bytes(rh), cl = contract_lds_bytes(rh), ll = line_lds_bytes(rh, ngrp, nin);
   const int64_t nfin = rh->cum_fin.back();
   for (int m = 0; m + 1 <= d - 1; ++m)
     hipLaunchKernelGGL(k_rx_expand, dim3((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin),
-                       dim3(RX_THREADS_FIB), fl, s, rh->dev, ninst, m, plan->total, a, rh->rws, rh->max_n1);
+                       dim3(RX_THREADS_FIB), el, s, rh->dev, ninst, m, plan->total, a, rh->rws, rh->max_n1);
   hipLaunchKernelGGL(k_rx_line, dim3((unsigned)rh->cum_line.back(), (unsigned)nrhs), dim3(RX_THREADS_LINE), ll, s, rh->dev,
                      ninst, (int)mode, plan->total, a, rh->rws, rh->max_n1, rh->max_np1, nfin, ngrp);
   for (int m = d - 2; m >= 0; --m) {
     const int64_t nf = m == 0 ? nfin : rh->cum_y[m].back();
-    hipLaunchKernelGGL(k_rx_contract, dim3((unsigned)nf, (unsigned)nrhs), dim3(RX_THREADS_FIB), fl, s, rh->dev, ninst, m,
+    hipLaunchKernelGGL(k_rx_contract, dim3((unsigned)nf, (unsigned)nrhs), dim3(RX_THREADS_FIB), cl, s, rh->dev, ninst, m,
                        (int)mode, plan->total, a, rh->rws, rh->max_n1, nfin);
   }
 }
