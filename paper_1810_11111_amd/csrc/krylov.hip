@@ -790,18 +790,29 @@ static void run_typed(const sgdg_plan* plan, int nrhs, double h, int M, const do
       // sweep w = A x_j fused with the chunk partials <v_i, w>, i < j, and <x_j, w>
       const DotArgs da{ws.V, ws.part1, j, M + 2, plan->nchunks, nrhs, plan->total};
       launch_apply_dots<P, TV>(plan, nrhs, xin, ws.wy, da, s);
+      // the smallest bucket JB > j: the kernel loads and multiplies JB basis
+      // entries per element (measured per launch: 6.0 / 6.5 / 8.6 us at
+      // JB = 8 / 16 / 32 for the 2 x 5184-DOF plan)
+#define SGDG_UPD(JB)                                                                                               \
+  hipLaunchKernelGGL((k_upd<TV, TY, JB>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, j, \
+                     ws)
       if (j < 8)
-        hipLaunchKernelGGL((k_upd<TV, TY, 8>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M,
-                           j, ws);
+        SGDG_UPD(8);
       else if (j < 16)
-        hipLaunchKernelGGL((k_upd<TV, TY, 16>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M,
-                           j, ws);
+        SGDG_UPD(16);
+      else if (j < 20)
+        SGDG_UPD(20);
+      else if (j < 24)
+        SGDG_UPD(24);
+      else if (j < 28)
+        SGDG_UPD(28);
       else if (j < 32)
-        hipLaunchKernelGGL((k_upd<TV, TY, 32>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M,
-                           j, ws);
+        SGDG_UPD(32);
+      else if (j < 40)
+        SGDG_UPD(40);
       else
-        hipLaunchKernelGGL((k_upd<TV, TY, SGDG_MAX_M>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst,
-                           plan->total, M, j, ws);
+        SGDG_UPD(SGDG_MAX_M);
+#undef SGDG_UPD
     }
   }
   hipLaunchKernelGGL(k_expm, dim3((unsigned)(nrhs * plan->ninst * 2)), dim3(256), 0, s, plan->dev, plan->ninst,
