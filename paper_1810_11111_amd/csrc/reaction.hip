@@ -256,6 +256,7 @@ int64_t reaction_final_fibres(const sgdg_plan* plan) {
 // the instance of work item e from the ascending first items cum[0..ninst)
 // (one round of loads per 64 instances, as in find_rblk)
 __device__ __forceinline__ int find_inst(const int64_t* __restrict__ cum, int ninst, int64_t e) {
+  if (ninst == 1) return 0;  // no table load for single-instance plans
   const int lane = threadIdx.x & 63;
   int best = 0;
   for (int t0 = 0; t0 < ninst; t0 += 64) {
