@@ -53,11 +53,11 @@ constexpr int PRE_I = (SGDG_MAX_M + PRE_W - 1) / PRE_W;
 constexpr int PRE_Q = CHUNK / 64;
 static_assert(PRE_W == 16, "the staged kernel has 16 waves");
 
-template <class TV>
-__device__ __forceinline__ void pre_basis(const DotArgs& da, int rhs, const Chunk& ch, double (&vp)[PRE_I][PRE_Q]) {
+template <class TV, int PI>
+__device__ __forceinline__ void pre_basis(const DotArgs& da, int rhs, const Chunk& ch, double (&vp)[PI][PRE_Q]) {
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
 #pragma unroll
-  for (int a = 0; a < PRE_I; ++a) {
+  for (int a = 0; a < PI; ++a) {
     const int i = wv + a * PRE_W;
 #pragma unroll
     for (int b = 0; b < PRE_Q; ++b)  // clamped indices: no load sits under a branch; the excess is masked later
@@ -66,11 +66,12 @@ __device__ __forceinline__ void pre_basis(const DotArgs& da, int rhs, const Chun
   }
 }
 
+template <int PI>
 __device__ __forceinline__ void chunk_dots_pre(const DotArgs& da, int c, int rhs, const Chunk& ch,
-                                               const double (&vp)[PRE_I][PRE_Q], const double* wl) {
+                                               const double (&vp)[PI][PRE_Q], const double* wl) {
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
 #pragma unroll
-  for (int a = 0; a < PRE_I; ++a) {
+  for (int a = 0; a < PI; ++a) {
     const int i = wv + a * PRE_W;
     if (i > da.j) break;
     double s = 0.0;
@@ -316,7 +317,8 @@ __device__ __forceinline__ void* dma_copy(void* dst, const void* src, int64_t nb
 // row tables of its distinct 1D operators, its x segment and (STAGE_VALS) the
 // block values into LDS, then APPLY_G lanes share each output element and
 // split its row entries; their partial sums are combined in a fixed order.
-template <int D, int K, class P, bool STAGE_VALS, class TV>
+// PI: rounds of 16 basis vectors the fused inner products need (j < 16 PI)
+template <int D, int K, class P, bool STAGE_VALS, class TV, int PI>
 __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, const SweepTask* __restrict__ tasks,
                                                                    const typename P::X* __restrict__ x,
                                                                    typename P::Y* __restrict__ y, int64_t xstride,
@@ -339,8 +341,8 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
   const int64_t rhs = blockIdx.y;
   const int64_t seg = tk.seg, ndof = tk.ndof;
   const int ntab = tk.ntab;
-  double vpre[PRE_I][PRE_Q];
-  if constexpr (!std::is_void_v<TV>) pre_basis<TV>(da, (int)rhs, ch, vpre);
+  double vpre[PI][PRE_Q];
+  if constexpr (!std::is_void_v<TV>) pre_basis<TV, PI>(da, (int)rhs, ch, vpre);
   // LDS layout (regions of 256-byte multiples with 16 bytes of slack, as the
   // direct copies keep each array's offset within its 16-byte line):
   // block-start table | per direction: the chunk's row pointers, source cells
@@ -427,7 +429,7 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
     __syncthreads();
     if (active && lane == 0) wl[e] = (double)out;
     __syncthreads();
-    chunk_dots_pre(da, cid, (int)rhs, ch, vpre, wl);
+    chunk_dots_pre<PI>(da, cid, (int)rhs, ch, vpre, wl);
   }
 }
 
@@ -438,13 +440,29 @@ static void launch_staged(const sgdg_plan* plan, int kind, int nrhs, const void*
   const int lds = std::max(plan->list_lds[kind], std::is_void_v<TV> ? 0 : (int)(CHUNK * sizeof(double)));
   static std::atomic<int> attr_set{0};
   if (attr_set.load() < lds) {
-    hipFuncSetAttribute((const void*)apply_kernel_lds<D, K, P, SV, TV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute((const void*)apply_kernel_lds<D, K, P, SV, TV, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         APPLY_LDS_BYTES);
+    if constexpr (!std::is_void_v<TV>) {
+      hipFuncSetAttribute((const void*)apply_kernel_lds<D, K, P, SV, TV, 2>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, APPLY_LDS_BYTES);
+      hipFuncSetAttribute((const void*)apply_kernel_lds<D, K, P, SV, TV, PRE_I>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, APPLY_LDS_BYTES);
+    }
     attr_set.store(APPLY_LDS_BYTES);
   }
-  hipLaunchKernelGGL((apply_kernel_lds<D, K, P, SV, TV>),
-                     dim3((unsigned)plan->chunk_lists[kind].size(), (unsigned)nrhs), dim3(CHUNK * APPLY_G), lds, s,
-                     plan->dev, plan->dev_tasks[kind], (const typename P::X*)x, (typename P::Y*)y, xs, ys, da);
+  const dim3 grid((unsigned)plan->chunk_lists[kind].size(), (unsigned)nrhs), blk(CHUNK * APPLY_G);
+  const SweepTask* tk = plan->dev_tasks[kind];
+  const auto* xp = (const typename P::X*)x;
+  auto* yp = (typename P::Y*)y;
+  // the basis vectors loaded for the fused inner products: only as many
+  // rounds of 16 as step j needs
+  if (std::is_void_v<TV> || da.j < PRE_W)
+    hipLaunchKernelGGL((apply_kernel_lds<D, K, P, SV, TV, 1>), grid, blk, lds, s, plan->dev, tk, xp, yp, xs, ys, da);
+  else if (da.j < 2 * PRE_W)
+    hipLaunchKernelGGL((apply_kernel_lds<D, K, P, SV, TV, 2>), grid, blk, lds, s, plan->dev, tk, xp, yp, xs, ys, da);
+  else
+    hipLaunchKernelGGL((apply_kernel_lds<D, K, P, SV, TV, PRE_I>), grid, blk, lds, s, plan->dev, tk, xp, yp, xs, ys,
+                       da);
 }
 
 template <int D, int K, class P, class TV>
