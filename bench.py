@@ -325,7 +325,7 @@ def main():
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
                        "traffic": traffic_record("apply_kernel_lds", wl.name),
-                       "kernel": "apply_kernel_lds<2,2,PrecF64,true,void> (operator sweep, y = A x)",
+                       "kernel": "apply_kernel_lds<2,2,PrecF64,true,void,1> (operator sweep, y = A x)",
                        "avg_us": avg * 1e6, "bytes_per_launch": nbytes,
                        "launches_per_step": wl.M * 1,
                        "note": "algorithmic bytes = read x + write y, 8 B each per DOF; the working set "
