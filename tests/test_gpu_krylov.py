@@ -234,3 +234,53 @@ def test_expv_reduced_precision_stated_error(prec, tol):
     V = I.smooth_random(plan.total, 21, 1)
     W, st = _run(plan, wl.dt, wl.M, V)
     _compare(plan, [inst], wl.dt, wl.M, V, W, st, lambda h, an: tol)
+
+
+def test_expv_and_step_bit_reproducible():
+    """Partial sums are reduced in a fixed order, so repeating a call on the same
+    input gives bit-identical results, whatever ran on the device before.  The
+    64-instance Gray-Scott plan: krylov_expv and iif2_step, each repeated with
+    other kernels (sweeps, reaction passes on other data) in between."""
+    import torch
+
+    sg = lib()
+    wl = I.gray_scott_batch()
+    say("bit reproducibility, gray-scott batch 64")
+    plan = sg.Plan(wl.instances, "fp64")
+    kb, ib = plan.workspace_size(wl.M, 1)
+    ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
+    st = torch.zeros(len(wl.instances) * 2 * sg.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    # the batch's initial data (library projection), a state the Newton stage
+    # converges from
+    x = np.zeros(plan.total)
+    for i in range(len(wl.instances)):
+        nd, off, _ = plan.info(i)
+        for s, (terms, mults, _) in enumerate(wl.initial_condition(i, nd)):
+            for (amp, fac), mult in zip(terms, mults):
+                pr = plan.project(i, amp, fac)
+                x[off + s * nd : off + (s + 1) * nd] += pr * (1.0 + mult) if mult is not None else pr
+    v = to_dev(x)
+    other = to_dev(0.3 + 0.2 * I.smooth_random(plan.total, 18, 1)[0])
+    scratch = torch.empty_like(v)
+    F0 = torch.empty_like(v)
+    plan.reaction(v, F0, ws)
+    outs, steps = [], []
+    for rep in range(4):
+        w = torch.empty_like(v)
+        plan.krylov_expv(wl.dt, wl.M, v, w, ws, stats=st)
+        outs.append(w)
+        U = v.clone()
+        F = F0.clone()
+        plan.iif2_step(wl.dt, wl.M, U, F, ws, newton_tol=1e-13, newton_max=5, stats=st)
+        steps.append(U)
+        for _ in range(rep + 1):  # unrelated work between the repeats
+            plan.apply(other, scratch)
+            plan.reaction(other, scratch, ws)
+    torch.cuda.synchronize()
+    w0, u0 = outs[0].cpu().numpy(), steps[0].cpu().numpy()
+    assert np.isfinite(w0).all() and np.isfinite(u0).all()
+    for w, u in zip(outs[1:], steps[1:]):
+        assert np.array_equal(w.cpu().numpy(), w0)
+        assert np.array_equal(u.cpu().numpy(), u0)
+    assert (sg.stats_array(st)["status"] == 0).all()
+    plan.close()
