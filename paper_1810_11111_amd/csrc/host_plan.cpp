@@ -475,6 +475,53 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
     }
   }
 
+  // Staged lists: workgroups go to the XCDs round-robin (workgroup t to XCD
+  // t mod 8), and each XCD's L2 fetches what its workgroups stage.  Ordering
+  // the list so that a problem's chunks land on their own subset of XCDs (a
+  // share of the eight by problem count, or one XCD each when there are more
+  // problems than XCDs) keeps every L2 to the segments and row tables of its
+  // own problems.
+  constexpr int NXCD = 8;
+  for (size_t kind = 0; kind < p->chunk_lists.size(); ++kind) {
+    std::vector<int32_t>& L = p->chunk_lists[kind];
+    if (kind % SWEEP_TIERS == 0 || L.size() <= (size_t)NXCD) continue;
+    std::vector<int32_t> probs;
+    for (int32_t c : L)
+      if (probs.empty() || probs.back() != p->chunks[c].problem) probs.push_back(p->chunks[c].problem);
+    std::sort(probs.begin(), probs.end());
+    probs.erase(std::unique(probs.begin(), probs.end()), probs.end());
+    const int np = (int)probs.size();
+    std::vector<std::vector<int32_t>> q(NXCD);
+    std::vector<int> rr(np, 0);
+    for (int32_t c : L) {
+      const int pi = (int)(std::lower_bound(probs.begin(), probs.end(), p->chunks[c].problem) - probs.begin());
+      int x;
+      if (np <= NXCD) {
+        const int x0 = pi * NXCD / np, x1 = (pi + 1) * NXCD / np;
+        x = x0 + rr[pi]++ % std::max(1, x1 - x0);
+      } else {
+        x = pi % NXCD;
+      }
+      q[x].push_back(c);
+    }
+    std::vector<size_t> head(NXCD, 0);
+    std::vector<int32_t> out;
+    out.reserve(L.size());
+    for (size_t t = 0; out.size() < L.size(); ++t) {
+      int x = (int)(t % NXCD);
+      if (head[x] == q[x].size()) {  // this XCD's queue is empty: take from the longest
+        size_t best = 0;
+        for (int y = 0; y < NXCD; ++y)
+          if (q[y].size() - head[y] > best) {
+            best = q[y].size() - head[y];
+            x = y;
+          }
+      }
+      out.push_back(q[x][head[x]++]);
+    }
+    L.swap(out);
+  }
+
   sgdg_status st = SGDG_OK;
   std::vector<float> valf(val_all.begin(), val_all.end());
   if ((st = upload(p, p->gblk, &p->dev.gblk)) != SGDG_OK || (st = upload(p, srange, &p->dev.srange)) != SGDG_OK ||
