@@ -152,9 +152,10 @@ def run_steps_iif3(sg, torch, wl, U0, steps, warmup):
 
 
 def kernel_source_hash():
-    """Hash of the sweep kernel sources (traffic counters are only valid for this code)."""
+    """Hash of the sweep kernel sources and of the plan builder that lays out its
+    chunks and task lists (traffic counters are only valid for this code)."""
     h = hashlib.sha256()
-    for f in ("apply.hip", "kernels.h", "internal.h"):
+    for f in ("apply.hip", "kernels.h", "internal.h", "host_plan.cpp"):
         with open(os.path.join(ROOT, "paper_1810_11111_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
