@@ -266,7 +266,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
+        print(f"bench.py: the library runs on one GPU (--gpus {args.gpus} requested); "
               "independent instances would shard one per GPU with no communication", file=sys.stderr)
         sys.exit(2)
 

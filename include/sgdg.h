@@ -60,7 +60,7 @@ typedef enum {
   SGDG_ERR_ARG = 1,         /* invalid argument (nothing was done)                  */
   SGDG_ERR_ALLOC = 2,       /* device or host allocation failed                     */
   SGDG_ERR_HIP = 3,         /* a HIP runtime call failed                            */
-  SGDG_ERR_UNSUPPORTED = 4, /* valid request outside what this build implements     */
+  SGDG_ERR_UNSUPPORTED = 4, /* valid request outside what the library implements   */
   SGDG_ERR_NOCONV = 5,      /* implicit stage did not reach its tolerance (stats)   */
   SGDG_ERR_NONFINITE = 6    /* a NaN/Inf was produced or consumed (stats)           */
 } sgdg_status;
