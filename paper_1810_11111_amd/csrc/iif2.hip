@@ -80,13 +80,6 @@ __global__ __launch_bounds__(256) void k_axpy(double* __restrict__ out, const do
   if (i < n) out[i] = x[i] + a * y[i];
 }
 
-// out = a y
-__global__ __launch_bounds__(256) void k_scale(double* __restrict__ out, double a, const double* __restrict__ y,
-                                               int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = a * y[i];
-}
-
 // out = a x + b y + c z
 __global__ __launch_bounds__(256) void k_lin3(double* __restrict__ out, double a, const double* __restrict__ x, double b,
                                               const double* __restrict__ y, double c, const double* __restrict__ z,
@@ -263,8 +256,8 @@ extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt,
     a.F = F;
     reaction_pass(plan, nrhs, RX_F, a, s);
   }
-  hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.v, U, dt2, F, n);
-  sgdg_status st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s);
+  const KrylovIn vin{w.v, U, F, dt2};  // v = U + dt/2 F, formed by the first Krylov kernel
+  sgdg_status st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s, &vin);
   if (st != SGDG_OK) return st;
   implicit_stage(plan, nrhs, dt2, U, F, S_next, w, newton_tol, newton_max, stats, s);
   return check_launch("iif2_step launch");
@@ -288,13 +281,13 @@ extern "C" sgdg_status iif3_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   const int64_t n = plan->total * (int64_t)nrhs;
   const dim3 vg((unsigned)((n + 255) / 256)), vb(256);
   // exp(2 A dt)(-1/12 dt F^{n-1}); F^{n-1} is then replaced by F^n
-  hipLaunchKernelGGL(k_scale, vg, vb, 0, s, w.v, -dt / 12.0, Fprev, n);
-  sgdg_status st = krylov_run(plan, nrhs, 2.0 * dt, M, w.v, w.W2, w.kws, stats, s);
+  const KrylovIn vin1{w.v, nullptr, Fprev, -dt / 12.0};
+  sgdg_status st = krylov_run(plan, nrhs, 2.0 * dt, M, w.v, w.W2, w.kws, stats, s, &vin1);
   if (st != SGDG_OK) return st;
   hipLaunchKernelGGL(k_copy, vg, vb, 0, s, Fprev, Fcur, n);
   // exp(A dt)(U^n + 2/3 dt F^n), plus the first term
-  hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.v, U, 2.0 * dt / 3.0, Fcur, n);
-  st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s);
+  const KrylovIn vin2{w.v, U, Fcur, 2.0 * dt / 3.0};
+  st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s, &vin2);
   if (st != SGDG_OK) return st;
   hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.W, w.W, 1.0, w.W2, n);
   implicit_stage(plan, nrhs, 5.0 * dt / 12.0, U, Fcur, S_next, w, newton_tol, newton_max, stats, s);
@@ -361,8 +354,8 @@ extern "C" sgdg_status iif2_step_local(const sgdg_plan* plan, int32_t nrhs, doub
   const double c = 0.5 * dt;
   const int64_t n = plan->total * (int64_t)nrhs;
   const dim3 vg((unsigned)((n + 255) / 256)), vb(256);
-  hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.v, U, c, Fcache, n);
-  sgdg_status st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s);
+  const KrylovIn vin{w.v, U, Fcache, c};
+  sgdg_status st = krylov_run(plan, nrhs, dt, M, w.v, w.W, w.kws, stats, s, &vin);
   if (st != SGDG_OK) return st;
   if (S_next) hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, w.W, w.W, c, S_next, n);
   // U = P u, u - c f(u) = R W at every Gauss point

@@ -35,8 +35,17 @@ KrylovWs krylov_carve(const sgdg_plan* plan, int M, int nrhs, void* base);
 // nothing) otherwise.
 bool arnoldi_persistent(const sgdg_plan* plan, int nrhs, int M, const KrylovWs& ws, hipStream_t s);
 
+// Optional input combination: the first kernel forms v = x + a y (x may be
+// null: v = a y) and stores it in vbuf, which then serves as v.
+struct KrylovIn {
+  double* vbuf;
+  const double* x;
+  const double* y;
+  double a;
+};
+
 // w = exp(h A) v for nrhs plan vectors (v, w FP64, may alias).
 sgdg_status krylov_run(const sgdg_plan* plan, int nrhs, double h, int M, const double* v, double* w,
-                       const KrylovWs& ws, sgdg_stats* stats, hipStream_t s);
+                       const KrylovWs& ws, sgdg_stats* stats, hipStream_t s, const KrylovIn* in = nullptr);
 
 }  // namespace sgdg

@@ -73,14 +73,24 @@ __device__ __forceinline__ const TV* vec(const KrylovWs& ws, int i, int nrhs, in
   return (const TV*)ws.V + ((int64_t)i * nrhs + rhs) * total;
 }
 
-// ||v||^2 partial per chunk; resets the per-problem state.
+// ||v||^2 partial per chunk; resets the per-problem state.  With vbuf, v is
+// first formed as vx + va vy (vx may be null) and stored there.
 __global__ __launch_bounds__(CHUNK) void k_init(DevTables T, int nchunks, int ninst, int64_t total, int M,
-                                                const double* __restrict__ v, KrylovWs ws) {
+                                                const double* __restrict__ v, KrylovWs ws, double* __restrict__ vbuf,
+                                                const double* __restrict__ vx, const double* __restrict__ vy,
+                                                double va) {
   const int c = blockIdx.x, rhs = blockIdx.y, tid = threadIdx.x;
   const Chunk ch = T.chunks[c];
   double x = 0.0;
   if (tid < ch.count) {
-    double a = v[rhs * total + ch.start + tid];
+    const int64_t i = rhs * total + ch.start + tid;
+    double a;
+    if (vbuf) {
+      a = vx ? vx[i] + va * vy[i] : va * vy[i];
+      vbuf[i] = a;
+    } else {
+      a = v[i];
+    }
     x = a * a;
   }
   x = wave_sum(x);
@@ -779,9 +789,11 @@ KrylovWs krylov_carve(const sgdg_plan* plan, int M, int nrhs, void* base) {
 
 template <class P, class TV, class TY>
 static void run_typed(const sgdg_plan* plan, int nrhs, double h, int M, const double* v, double* w,
-                      const KrylovWs& ws, sgdg_stats* stats, hipStream_t s) {
+                      const KrylovWs& ws, sgdg_stats* stats, hipStream_t s, const KrylovIn* in) {
   const dim3 grid((unsigned)plan->nchunks, (unsigned)nrhs), blk(CHUNK);
-  hipLaunchKernelGGL(k_init, grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, v, ws);
+  if (in) v = in->vbuf;
+  hipLaunchKernelGGL(k_init, grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, v, ws,
+                     in ? in->vbuf : nullptr, in ? in->x : nullptr, in ? in->y : nullptr, in ? in->a : 0.0);
   hipLaunchKernelGGL((k_norm<TV>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, v, ws);
   const bool persistent = arnoldi_persistent(plan, nrhs, M, ws, s);
   if (!persistent) {
@@ -821,11 +833,11 @@ static void run_typed(const sgdg_plan* plan, int nrhs, double h, int M, const do
 }
 
 sgdg_status krylov_run(const sgdg_plan* plan, int nrhs, double h, int M, const double* v, double* w,
-                       const KrylovWs& ws, sgdg_stats* stats, hipStream_t s) {
+                       const KrylovWs& ws, sgdg_stats* stats, hipStream_t s, const KrylovIn* in) {
   switch (plan->prec) {
-    case SGDG_FP64: run_typed<PrecF64, double, double>(plan, nrhs, h, M, v, w, ws, stats, s); break;
-    case SGDG_FP32_SWEEP: run_typed<PrecF32, float, float>(plan, nrhs, h, M, v, w, ws, stats, s); break;
-    default: run_typed<PrecBF16, float, float>(plan, nrhs, h, M, v, w, ws, stats, s); break;
+    case SGDG_FP64: run_typed<PrecF64, double, double>(plan, nrhs, h, M, v, w, ws, stats, s, in); break;
+    case SGDG_FP32_SWEEP: run_typed<PrecF32, float, float>(plan, nrhs, h, M, v, w, ws, stats, s, in); break;
+    default: run_typed<PrecBF16, float, float>(plan, nrhs, h, M, v, w, ws, stats, s, in); break;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "krylov_expv launch");
