@@ -314,7 +314,43 @@ __device__ __forceinline__ double* ifwt(const double* h, double* b0, double* b1,
   __syncthreads();
   double* cur = b0;
   double* nxt = b1;
-  for (int n = 1; n <= L; ++n) {
+  int n = 1;
+  // coarse levels two per barrier while level n+1 has at most one item per
+  // thread: the thread forms the K1 level-n values of its item's parent cell
+  // (the sums of the one-level pass, in the same order), then its item
+  for (; n + 1 <= L && (K1 << (n + 1)) <= nt; n += 2) {
+    const double* dw1 = h + (K1 << (n - 1));
+    const double* dw2 = h + (K1 << n);
+    const int e = tid;
+    if (e < (K1 << (n + 1))) {
+      const int c = e / K1, q = e - c * K1, c1 = c >> 1, j = c1 >> 1;
+      const double* M1 = (c1 & 1) ? M + 16 : M;
+      const double* W1 = (c1 & 1) ? M + 48 : M + 32;
+      double pv[K1];
+#pragma unroll
+      for (int q1 = 0; q1 < K1; ++q1) {
+        double a = 0.0;
+#pragma unroll
+        for (int i = 0; i < K1; ++i) a += M1[q1 * K1 + i] * cur[j * K1 + i];
+#pragma unroll
+        for (int p = 0; p < K1; ++p) a += W1[p * K1 + q1] * dw1[j * K1 + p];
+        pv[q1] = a;
+      }
+      const double* M2 = (c & 1) ? M + 16 : M;
+      const double* W2 = (c & 1) ? M + 48 : M + 32;
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < K1; ++i) acc += M2[q * K1 + i] * pv[i];
+#pragma unroll
+      for (int p = 0; p < K1; ++p) acc += W2[p * K1 + q] * dw2[c1 * K1 + p];
+      nxt[e] = acc;
+    }
+    __syncthreads();
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  for (; n <= L; ++n) {
     const double* dw = h + (K1 << (n - 1));
     const int items = (K1 << n);
     for (int e = tid; e < items; e += nt) {
