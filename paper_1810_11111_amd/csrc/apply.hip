@@ -10,13 +10,15 @@
 // no read-modify-write of y); rows of B_i are stored as cell blocks so a
 // group of K+1 consecutive source entries shares one index decode.
 //
-// Three tiers, chosen per species segment when the plan is built: when the
-// segment, its level-block table and the row tables fit in LDS, every
-// workgroup first stages them there and gathers from LDS (small problems are
-// latency bound: a gather then costs LDS latency, not L2 latency), and when the
-// block values fit as well they are staged too; otherwise the gathers read
-// global memory.  The staged kernels give each output APPLY_G lanes, which
-// quadruples the waves per compute unit for latency hiding.
+// Three tiers, chosen per chunk when the plan is built: when the species
+// segment, its level-block table and the chunk's rows of the 1D operators fit
+// in LDS, every workgroup first stages them there and gathers from LDS (small
+// problems are latency bound: a gather then costs LDS latency, not L2
+// latency), and when the block values fit as well they are staged too;
+// otherwise the gathers read global memory, with the source-block starts the
+// chunk needs in an LDS table and the row entries loaded a few at a time.
+// Each output gets 4..64 lanes (APPLY_G and up, by the length of its rows), so
+// the heavy rows of coarse levels do not hold back a chunk.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
