@@ -82,6 +82,10 @@ def _compare(plan, insts, h, M, V, W, stats, tol_fn, nrhs=1):
         (3, 4, 1, [1.0], 0.01, 15, 3),
         (1, 7, 2, [0.3], 0.02, 40, 4),
         (4, 3, 1, [1.0], 0.005, 40, 5),
+        # segments too large for the LDS: the global-gather form of the sweep
+        # with its fused inner products
+        (4, 6, 1, [1.0], 0.005, 40, 6),
+        (2, 9, 2, [1.0, 0.2], 0.001, 30, 7),
     ],
 )
 def test_expv_fp64_random(d, N, k, D, h, M, seed):
