@@ -403,6 +403,11 @@ __global__ __launch_bounds__(CHUNK* APPLY_G) void apply_kernel_lds(DevTables T, 
     }
   }
   if (tid < ntab) bst[tid] = bid >= 0 ? (int32_t)T.lstart[bid] : -1;
+  // tables larger than the workgroup ((N+1)^d > 1024, e.g. d = 4, N >= 5)
+  for (int t2 = tid + nthr; t2 < ntab; t2 += nthr) {
+    const int b2 = T.blkid[tk.blkid_off + t2];
+    bst[t2] = b2 >= 0 ? (int32_t)T.lstart[b2] : -1;
+  }
   __builtin_amdgcn_s_waitcnt(0);  // the direct copies have landed
   __syncthreads();
   // ch.g lanes per output: APPLY_G for most chunks, more for the chunks of

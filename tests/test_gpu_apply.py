@@ -128,7 +128,7 @@ def test_apply_multi_instance_uneven_levels():
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 1e-2)])
-@pytest.mark.parametrize("dnk", [(3, 4, 1), (3, 7, 2)], ids=["staged", "global"])
+@pytest.mark.parametrize("dnk", [(3, 4, 1), (3, 7, 2), (4, 6, 1)], ids=["staged", "global", "table2401"])
 def test_apply_reduced_precision(prec, tol, dnk):
     sg = lib()
     import torch

@@ -240,6 +240,21 @@ def test_expv_reduced_precision_stated_error(prec, tol):
     _compare(plan, [inst], wl.dt, wl.M, V, W, st, lambda h, an: tol)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 3e-2)])
+def test_expv_reduced_precision_large_block_table(prec, tol):
+    """The same stated errors at d=4 N=6 k=1: in FP32/BF16 the segment fits
+    the LDS (FP64 takes the global-gather sweep), and the staged sweep's
+    level-block table has 7^4 = 2401 entries, more than the workgroup's
+    threads (regression: entries past the thread count were left unset)."""
+    sg = lib()
+    inst = I.Instance(4, 6, 1, [1.0], I.rx_zeros(1))
+    say("expv large block table", prec)
+    plan = sg.Plan([inst], prec)
+    V = I.smooth_random(plan.total, 22, 1)
+    W, st = _run(plan, 0.005, 40, V)
+    _compare(plan, [inst], 0.005, 40, V, W, st, lambda h, an: tol)
+
+
 def test_expv_and_step_bit_reproducible():
     """Partial sums are reduced in a fixed order, so repeating a call on the same
     input gives bit-identical results, whatever ran on the device before.  The
