@@ -150,6 +150,37 @@ def test_apply_reduced_precision(prec, tol, dnk):
     _check(yd.cpu().numpy().astype(np.float64), A @ xin, A, xin, tol, prec)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 1e-2)])
+def test_apply_reduced_precision_multi_instance_two_rhs(prec, tol):
+    """Uneven (N, k) instances with two species and two right-hand sides in FP32/BF16 storage."""
+    sg = lib()
+    import torch
+
+    spec = [(2, 5, 1, [1.0, 2.0]), (2, 9, 2, [0.7]), (2, 7, 3, [1.0])]
+    insts = [I.Instance(d, N, k, D, I.rx_zeros(len(D))) for d, N, k, D in spec]
+    say("apply multi-instance", prec, len(insts))
+    plan = sg.Plan(insts, prec)
+    nrhs = 2
+    X = I.smooth_random(plan.total, 41, nrhs)
+    if prec == "fp32":
+        xd = to_dev(X.astype(np.float32))
+        xin = X.astype(np.float32).astype(np.float64)
+    else:
+        bits, xin = bf16_bits(X)
+        xd = to_dev(bits.view(np.int16))
+    yd = torch.zeros((nrhs, plan.total), dtype=torch.float32, device="cuda")
+    plan.apply(xd, yd, nrhs=nrhs)
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy().astype(np.float64)
+    for i, (d, N, k, D) in enumerate(spec):
+        nd, off, _ = plan.info(i)
+        A1 = _oracle_A(d, N, k, None)
+        for r in range(nrhs):
+            for s, Ds in enumerate(D):
+                seg = slice(off + s * nd, off + (s + 1) * nd)
+                _check(Y[r, seg], Ds * (A1 @ xin[r, seg]), Ds * A1, xin[r, seg], tol, f"{prec} inst {i} rhs {r} species {s}")
+
+
 @pytest.mark.parametrize("name", ["heat_linear_d2", "schnakenberg_d2", "allen_cahn_d3", "quadratic_d4"])
 def test_apply_full_size_workloads(name):
     """Workload-size operators (the configurations the benchmark runs)."""
