@@ -10,8 +10,8 @@ a system of the size of the unknowns (Sec. 5: the sparse basis is global, so
 the "local implicit property" is lost and Newton iterations are needed).
 
 Readings:
-* The spec form of the stage is a pointwise quasi-Newton iteration with
-  the same root as Newton on G:
+* The stage is solved by a pointwise quasi-Newton iteration with the same
+  root as Newton on G:
       U <- U - P[(I_s - dt/2 J_f(u_q))^{-1} (R G)_q],
   with a species-by-species Jacobian inverse at every quadrature point q.
   `implicit_stage_newton_dense` is the exact-Jacobian Newton on tiny grids
