@@ -86,6 +86,10 @@ def _compare(plan, insts, h, M, V, W, stats, tol_fn, nrhs=1):
         # with its fused inner products
         (4, 6, 1, [1.0], 0.005, 40, 6),
         (2, 9, 2, [1.0, 0.2], 0.001, 30, 7),
+        # the largest Krylov dimension: Arnoldi steps 40..47 take the last
+        # basis-update bucket and H is padded to 48 x 48
+        (2, 6, 2, [1.0, 0.3], 0.002, 48, 8),
+        (3, 5, 1, [1.0], 0.005, 48, 9),
     ],
 )
 def test_expv_fp64_random(d, N, k, D, h, M, seed):
@@ -253,6 +257,18 @@ def test_expv_reduced_precision_large_block_table(prec, tol):
     V = I.smooth_random(plan.total, 22, 1)
     W, st = _run(plan, 0.005, 40, V)
     _compare(plan, [inst], 0.005, 40, V, W, st, lambda h, an: tol)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 3e-2)])
+def test_expv_reduced_precision_largest_krylov_dimension(prec, tol):
+    """M = 48 (the largest accepted) with reduced-precision basis vectors and sweeps."""
+    sg = lib()
+    inst = I.Instance(2, 6, 2, [1.0, 0.3], I.rx_zeros(2))
+    say("expv M=48", prec)
+    plan = sg.Plan([inst], prec)
+    V = I.smooth_random(plan.total, 23, 1)
+    W, st = _run(plan, 0.002, 48, V)
+    _compare(plan, [inst], 0.002, 48, V, W, st, lambda h, an: tol)
 
 
 def test_expv_and_step_bit_reproducible():
