@@ -25,6 +25,11 @@ CASES = [
     (3, 4, 2, [1.0], (1.0, 0.5, 1.0)),
     (4, 3, 1, [2.0], None),
     (5, 2, 1, [1.0], None),
+    # the largest dimension: 4^6 = 4096 level blocks at N = 3
+    (5, 4, 1, [1.0], None),
+    (6, 2, 1, [1.0], None),
+    (6, 3, 1, [1.0, 0.5], None),
+    (6, 2, 2, [1.0], None),
     # segments too large for the LDS: the global-gather kernel (k = 1, 2, 3).
     # The library's and the oracle's 1D operator entries differ by rounding
     # that grows with the number of levels and the degree (two-scale

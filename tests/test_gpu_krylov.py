@@ -90,6 +90,7 @@ def _compare(plan, insts, h, M, V, W, stats, tol_fn, nrhs=1):
         # basis-update bucket and H is padded to 48 x 48
         (2, 6, 2, [1.0, 0.3], 0.002, 48, 8),
         (3, 5, 1, [1.0], 0.005, 48, 9),
+        (6, 3, 1, [1.0], 0.002, 30, 10),
     ],
 )
 def test_expv_fp64_random(d, N, k, D, h, M, seed):
