@@ -126,6 +126,34 @@ def test_reaction_F_d1_and_multi_instance():
         assert np.abs(F[off : off + 2 * nd] - Fref).max() <= 1e-12 * max(1.0, np.abs(Fref).max()), i
 
 
+@pytest.mark.parametrize("d,N,k,rx", [
+    (2, 5, 3, "schnakenberg"),
+    (3, 3, 3, "quadratic"),
+    (5, 2, 1, "quadratic"),
+    (6, 2, 1, "gray_scott"),
+])
+def test_reaction_F_cubic_degree_and_high_dimension(d, N, k, rx):
+    """k = 3 (four Gauss points per axis) and d = 5, 6 (the deepest chains of
+    per-axis expansion and contraction stages), one and two species."""
+    sg = lib()
+    import torch
+
+    r = {"schnakenberg": I.rx_schnakenberg(0.1, 0.9), "quadratic": I.rx_quadratic(-1.0),
+         "gray_scott": I.rx_gray_scott(0.04, 0.06)}[rx]
+    S = 1 if rx == "quadratic" else 2
+    inst = I.Instance(d, N, k, [1.0] * S, r)
+    say("reaction F", d, N, k, rx)
+    plan = sg.Plan([inst], "fp64")
+    nd = plan.info(0)[0]
+    U0 = 0.5 + 0.2 * I.smooth_random(S * nd, 17 + d, 1)[0]
+    Fd = torch.zeros(plan.total, dtype=torch.float64, device="cuda")
+    plan.reaction(to_dev(U0), Fd, _ws(plan, 1))
+    torch.cuda.synchronize()
+    Fref = reaction.F(reaction.Quadrature(d, N, k), inst.rx, U0.reshape(S, nd)).ravel()
+    err = np.abs(Fd.cpu().numpy() - Fref).max()
+    assert err <= 1e-12 * max(1.0, np.abs(Fref).max()), err
+
+
 # ----------------------------------------------------------------------------- projection
 
 def test_projection_matches_oracle():
