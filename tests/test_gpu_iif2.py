@@ -222,6 +222,37 @@ def test_iif2_matches_oracle(name, kw, steps):
     assert abs(int(st[0]["newton_iters"]) - infos[-1]["iters"]) <= 1
 
 
+@pytest.mark.parametrize("d,N,k,rx,D,dt,M", [
+    (2, 4, 3, "schnakenberg", [0.01, 1.0], 0.01, 30),
+    (5, 2, 1, "quadratic", [1.0], 0.005, 20),
+    (6, 2, 1, "quadratic", [1.0], 0.005, 20),
+])
+def test_iif2_cubic_degree_and_high_dimension(d, N, k, rx, D, dt, M):
+    """Two IIF2 steps at k = 3 and at d = 5, 6 against the oracle, from a small random state."""
+    from types import SimpleNamespace
+
+    sg = lib()
+    r = I.rx_schnakenberg(0.1, 0.9) if rx == "schnakenberg" else I.rx_quadratic(-1.0)
+    inst = I.Instance(d, N, k, D, r)
+    say("iif2", d, N, k, rx)
+    plan = sg.Plan([inst], "fp64")
+    nd = plan.info(0)[0]
+    S = len(D)
+    U0 = 0.02 * I.smooth_random(S * nd, 31 + d, 1)[0].reshape(S, nd)
+    steps = 2
+    Ug, st = _run_gpu(plan, SimpleNamespace(dt=dt, M=M), U0.ravel(), steps)
+    prob = _oracle_problem(inst, dt, M)
+    Ur, _, infos = iif.iif2_run(prob, U0, steps, tol=1e-14)
+    Ug = Ug.reshape(S, nd)
+    for s in range(S):
+        vnorm = np.linalg.norm(U0[s]) + np.linalg.norm(Ur[s])
+        tol = _step_tol(inst, dt, vnorm, s, steps, prob.anorm[s])
+        err = np.linalg.norm(Ug[s] - Ur[s])
+        assert err <= tol, f"species {s}: err {err:.3e} > {tol:.3e}"
+        assert st[s]["status"] == 0 and st[s]["krylov_m"] == infos[-1]["krylov"][s]["m"]
+    assert abs(int(st[0]["newton_iters"]) - infos[-1]["iters"]) <= 1
+
+
 def test_iif2_gray_scott_batch_uneven():
     sg = lib()
     wl = I.gray_scott_batch(ninst=8, steps=2)
