@@ -327,6 +327,37 @@ def test_iif2_quadratic_batch_of_rhs():
         assert np.linalg.norm(Ug[r] - Ur[0]) <= tol, r
 
 
+def test_iif2_two_species_instances_and_rhs():
+    """Two right-hand sides over three two-species instances with uneven (N, k):
+    every (rhs, instance) pair against its own oracle run, and the statistics
+    slot (rhs * ninst + instance) * 2 + species."""
+    from types import SimpleNamespace
+
+    sg = lib()
+    r = I.rx_gray_scott(0.04, 0.06)
+    insts = [I.Instance(2, 4, 1, [1.0, 0.5], r), I.Instance(2, 5, 2, [0.3, 1.0], r), I.Instance(2, 3, 1, [1.0, 1.0], r)]
+    say("iif2 two species, 3 instances, nrhs=2")
+    plan = sg.Plan(insts, "fp64")
+    nrhs, dt, M, steps = 2, 0.01, 20, 2
+    U0 = 0.02 * I.smooth_random(plan.total, 51, nrhs)
+    Ug, st = _run_gpu(plan, SimpleNamespace(dt=dt, M=M), U0, steps, nrhs=nrhs)
+    Ug = Ug.reshape(nrhs, plan.total)
+    for rh in range(nrhs):
+        for i, inst in enumerate(insts):
+            nd, off, _ = plan.info(i)
+            Ui = U0[rh, off : off + 2 * nd].reshape(2, nd)
+            prob = _oracle_problem(inst, dt, M)
+            Ur, _, infos = iif.iif2_run(prob, Ui, steps, tol=1e-14)
+            Gi = Ug[rh, off : off + 2 * nd].reshape(2, nd)
+            for s in range(2):
+                vnorm = np.linalg.norm(Ui[s]) + np.linalg.norm(Ur[s])
+                tol = _step_tol(inst, dt, vnorm, s, steps, prob.anorm[s])
+                err = np.linalg.norm(Gi[s] - Ur[s])
+                assert err <= tol, f"rhs {rh} inst {i} species {s}: err {err:.3e} > {tol:.3e}"
+                e = st[(rh * len(insts) + i) * 2 + s]
+                assert e["status"] == 0 and e["krylov_m"] == infos[-1]["krylov"][s]["m"], (rh, i, s)
+
+
 def test_iif2_closed_form_constant_state():
     """f = -u, constant initial state: U^n = c ((1 - dt/2) / (1 + dt/2))^n exactly (Sec. 3, eq. 3.5)."""
     sg = lib()
