@@ -464,6 +464,48 @@ def test_iif3_matches_oracle(name, kw, steps):
         assert np.linalg.norm(Fg[s] - Fr[s]) <= ftol and np.linalg.norm(Fpg[s] - Fpr[s]) <= ftol
 
 
+def test_iif3_two_species_instances_and_rhs():
+    """IIF3 (one IIF2 start-up step, then eq. 3.6) on two right-hand sides over
+    two two-species instances with uneven (N, k), each pair against the oracle."""
+    import torch
+
+    sg = lib()
+    r = I.rx_gray_scott(0.04, 0.06)
+    insts = [I.Instance(2, 4, 1, [1.0, 0.5], r), I.Instance(2, 5, 2, [0.3, 1.0], r)]
+    say("iif3 two species, 2 instances, nrhs=2")
+    plan = sg.Plan(insts, "fp64")
+    nrhs, dt, M, steps = 2, 0.01, 20, 3
+    U0 = 0.02 * I.smooth_random(plan.total, 52, nrhs)
+    Ud = to_dev(U0.copy())
+    ws = _ws(plan, M, nrhs)
+    st = _stats(plan, nrhs)
+    Fc = torch.zeros_like(Ud)
+    plan.reaction(Ud, Fc, ws, nrhs=nrhs)
+    Fp = Fc.clone()
+    for n in range(steps):
+        if n == 0:
+            plan.iif2_step(dt, M, Ud, Fc, ws, newton_tol=1e-14, newton_max=12, stats=st, nrhs=nrhs)
+        else:
+            plan.iif3_step(dt, M, Ud, Fc, Fp, ws, newton_tol=1e-14, newton_max=12, stats=st, nrhs=nrhs)
+    torch.cuda.synchronize()
+    Ug = Ud.cpu().numpy()
+    stats = lib().stats_array(st)
+    for rh in range(nrhs):
+        for i, inst in enumerate(insts):
+            nd, off, _ = plan.info(i)
+            Ui = U0[rh, off : off + 2 * nd].reshape(2, nd)
+            prob = _oracle_problem(inst, dt, M)
+            Ur, _, _, infos = iif.iif3_run(prob, Ui, steps, tol=1e-14)
+            Gi = Ug[rh, off : off + 2 * nd].reshape(2, nd)
+            for s in range(2):
+                vnorm = np.linalg.norm(Ui[s]) + np.linalg.norm(Ur[s])
+                tol = _step_tol(inst, 2 * dt, vnorm, s, steps, prob.anorm[s])
+                err = np.linalg.norm(Gi[s] - Ur[s])
+                assert err <= tol, f"rhs {rh} inst {i} species {s}: err {err:.3e} > {tol:.3e}"
+                e = stats[(rh * len(insts) + i) * 2 + s]
+                assert e["status"] == 0 and e["krylov_m"] == infos[-1]["krylov"][s]["m"], (rh, i, s)
+
+
 def test_iif3_third_order_on_constant_state():
     """Spatially constant state, f = -u^2 (A keeps constants): the library's
     IIF3 converges at third order to u0 / (1 + u0 t) -- a closed form, not the
