@@ -727,6 +727,42 @@ def test_local_stage_matches_oracle(name, kw, steps):
         assert st[s]["status"] == 0
 
 
+def test_local_stage_two_species_instances_and_rhs():
+    """iif2_step_local on two right-hand sides over two two-species instances
+    with uneven (N, k), each pair against the oracle."""
+    import torch
+
+    sg = lib()
+    r = I.rx_gray_scott(0.04, 0.06)
+    insts = [I.Instance(2, 4, 1, [1.0, 0.5], r), I.Instance(2, 5, 2, [0.3, 1.0], r)]
+    say("iif2 local two species, 2 instances, nrhs=2")
+    plan = sg.Plan(insts, "fp64")
+    nrhs, dt, M, steps = 2, 0.01, 20, 3
+    U0 = 0.02 * I.smooth_random(plan.total, 53, nrhs)
+    Ud = to_dev(U0.copy())
+    ws = _ws(plan, M, nrhs)
+    st = _stats(plan, nrhs)
+    F = torch.zeros_like(Ud)
+    plan.reaction(Ud, F, ws, nrhs=nrhs)
+    for _ in range(steps):
+        plan.iif2_step_local(dt, M, Ud, F, ws, stats=st, nrhs=nrhs)
+    torch.cuda.synchronize()
+    Ug = Ud.cpu().numpy()
+    stats = lib().stats_array(st)
+    for rh in range(nrhs):
+        for i, inst in enumerate(insts):
+            nd, off, _ = plan.info(i)
+            Ui = U0[rh, off : off + 2 * nd].reshape(2, nd)
+            prob = _oracle_problem(inst, dt, M)
+            Ur, _, _ = iif.iif2_run_local(prob, Ui, steps)
+            Gi = Ug[rh, off : off + 2 * nd].reshape(2, nd)
+            for s in range(2):
+                tol = _step_tol(inst, dt, np.linalg.norm(Ui[s]) + np.linalg.norm(Ur[s]), s, steps, prob.anorm[s])
+                err = np.linalg.norm(Gi[s] - Ur[s])
+                assert err <= tol, f"rhs {rh} inst {i} species {s}: err {err:.3e} > {tol:.3e}"
+                assert stats[(rh * len(insts) + i) * 2 + s]["status"] == 0, (rh, i, s)
+
+
 def test_local_stage_example3_on_gpu():
     """Example 3 (zero Dirichlet, forcing) with the local stage: parity with the
     oracle over the full time range at N = 4, and second order N = 3..5."""
