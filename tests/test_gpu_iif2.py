@@ -253,6 +253,27 @@ def test_iif2_cubic_degree_and_high_dimension(d, N, k, rx, D, dt, M):
     assert abs(int(st[0]["newton_iters"]) - infos[-1]["iters"]) <= 1
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 3e-2)])
+def test_iif2_reduced_precision_stated_error(prec, tol):
+    """FP32/BF16 sweeps and basis vectors (state, inner products, the
+    Hessenberg exponential and the stage residual in FP64): five Schnakenberg
+    steps against the FP64 oracle within the stated relative error."""
+    sg = lib()
+    wl = I.schnakenberg_d2(N=5, k=2, steps=5)
+    inst = wl.instances[0]
+    say("iif2", prec)
+    plan = sg.Plan([inst], prec)
+    nd = plan.info(0)[0]
+    U0 = _ic_oracle(wl, 0, inst, nd)
+    Ug, st = _run_gpu(plan, wl, U0.ravel(), 5)
+    Ur, _, _ = iif.iif2_run(_oracle_problem(inst, wl.dt, wl.M), U0, 5, tol=1e-14)
+    Ug = Ug.reshape(inst.species, nd)
+    for s in range(inst.species):
+        err = np.linalg.norm(Ug[s] - Ur[s]) / np.linalg.norm(Ur[s])
+        assert err <= tol, f"{prec} species {s}: rel L2 err {err:.3e} > {tol:.1e}"
+        assert st[s]["status"] == 0
+
+
 def test_iif2_gray_scott_batch_uneven():
     sg = lib()
     wl = I.gray_scott_batch(ninst=8, steps=2)
