@@ -272,6 +272,19 @@ def test_expv_reduced_precision_largest_krylov_dimension(prec, tol):
     _compare(plan, [inst], 0.002, 48, V, W, st, lambda h, an: tol)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 3e-2)])
+def test_expv_reduced_precision_instances_and_rhs(prec, tol):
+    """Two right-hand sides over three instances with uneven (N, k) and one or two species."""
+    sg = lib()
+    insts = [I.Instance(2, 4, 1, [1.0, 0.5], I.rx_zeros(2)), I.Instance(2, 6, 2, [0.3], I.rx_zeros(1)),
+             I.Instance(2, 5, 3, [1.0, 2.0], I.rx_zeros(2))]
+    say("expv instances and rhs", prec)
+    plan = sg.Plan(insts, prec)
+    V = I.smooth_random(plan.total, 24, 2)
+    W, st = _run(plan, 0.002, 30, V, nrhs=2)
+    _compare(plan, insts, 0.002, 30, V, W, st, lambda h, an: tol, nrhs=2)
+
+
 def test_expv_and_step_bit_reproducible():
     """Partial sums are reduced in a fixed order, so repeating a call on the same
     input gives bit-identical results, whatever ran on the device before.  The
