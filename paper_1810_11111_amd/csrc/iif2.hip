@@ -215,7 +215,7 @@ extern "C" sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const 
   if (!U || !F || !workspace) return fail(SGDG_ERR_ARG, "sgdg_reaction: null device pointer");
   if ((const void*)U == (const void*)F || (const void*)S == (const void*)F)
     return fail(SGDG_ERR_ARG, "sgdg_reaction: F must not alias U or S");
-  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "sgdg_reaction: (k+1) 2^N above 2048 per axis");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "sgdg_reaction: (k+1) 2^N above 2048 per axis (1024 with two species)");
   if (workspace_bytes < iif2_ws_bytes(plan, 1, nrhs)) return fail(SGDG_ERR_ARG, "sgdg_reaction: workspace too small");
   IifWs w = carve(plan, 1, nrhs, workspace);
   RxArgs a{};
@@ -241,7 +241,7 @@ extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   if (newton_max < 0 || newton_max > 1000) return fail(SGDG_ERR_ARG, "iif2_step: newton_max must be in 0..1000");
   if (!U || !workspace) return fail(SGDG_ERR_ARG, "iif2_step: null device pointer");
   if (S_next && !Fcache) return fail(SGDG_ERR_ARG, "iif2_step: a source needs the F cache (F of the old level)");
-  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "iif2_step: (k+1) 2^N above 2048 per axis");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "iif2_step: (k+1) 2^N above 2048 per axis (1024 with two species)");
   if (workspace_bytes < iif2_ws_bytes(plan, M, nrhs)) return fail(SGDG_ERR_ARG, "iif2_step: workspace too small");
   hipStream_t s = (hipStream_t)stream;
   IifWs w = carve(plan, M, nrhs, workspace);
@@ -274,7 +274,7 @@ extern "C" sgdg_status iif3_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   if (newton_max < 0 || newton_max > 1000) return fail(SGDG_ERR_ARG, "iif3_step: newton_max must be in 0..1000");
   if (!U || !Fcur || !Fprev || !workspace) return fail(SGDG_ERR_ARG, "iif3_step: null device pointer");
   if (U == Fcur || U == Fprev || Fcur == Fprev) return fail(SGDG_ERR_ARG, "iif3_step: U, Fcur and Fprev must not alias");
-  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "iif3_step: (k+1) 2^N above 2048 per axis");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "iif3_step: (k+1) 2^N above 2048 per axis (1024 with two species)");
   if (workspace_bytes < iif2_ws_bytes(plan, M, nrhs)) return fail(SGDG_ERR_ARG, "iif3_step: workspace too small");
   hipStream_t s = (hipStream_t)stream;
   IifWs w = carve(plan, M, nrhs, workspace);
@@ -315,7 +315,7 @@ extern "C" sgdg_status rk_step(const sgdg_plan* plan, int32_t nrhs, double dt, i
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SGDG_ERR_ARG, "rk_step: dt must be positive");
   if (!U || !workspace) return fail(SGDG_ERR_ARG, "rk_step: null device pointer");
   if (plan->prec != SGDG_FP64) return fail(SGDG_ERR_UNSUPPORTED, "rk_step: FP64 plans only");
-  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "rk_step: (k+1) 2^N above 2048 per axis");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "rk_step: (k+1) 2^N above 2048 per axis (1024 with two species)");
   if (workspace_bytes < iif2_ws_bytes(plan, 1, nrhs)) return fail(SGDG_ERR_ARG, "rk_step: workspace too small");
   hipStream_t s = (hipStream_t)stream;
   IifWs w = carve(plan, 1, nrhs, workspace);
@@ -346,7 +346,7 @@ extern "C" sgdg_status iif2_step_local(const sgdg_plan* plan, int32_t nrhs, doub
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SGDG_ERR_ARG, "iif2_step_local: dt must be positive");
   if (!U || !Fcache || !workspace) return fail(SGDG_ERR_ARG, "iif2_step_local: null device pointer");
   if (U == Fcache) return fail(SGDG_ERR_ARG, "iif2_step_local: U and Fcache must not alias");
-  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "iif2_step_local: (k+1) 2^N above 2048 per axis");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "iif2_step_local: (k+1) 2^N above 2048 per axis (1024 with two species)");
   if (workspace_bytes < iif2_ws_bytes(plan, M, nrhs))
     return fail(SGDG_ERR_ARG, "iif2_step_local: workspace too small");
   hipStream_t s = (hipStream_t)stream;

@@ -20,11 +20,15 @@ struct RInst {
   int64_t seg;    // offset of the instance in a plan vector
   int64_t ndof;
   int64_t EL_off;    // into EL: [(L * np1 + q) * K1 + p] = level-L cell basis p at finest 1D Gauss point q
+  int64_t EH_off;    // into EH: [(q * (N + 1) + l) * K1 + p] = hierarchical function (l, cell of q at level l, p) at point q
   int64_t w_off;     // into w1: Gauss weight times h_N of 1D point q
   int64_t mats_off;  // into mats: ML, MR, cL, cR (each 16 doubles, row length K1)
   int32_t blk_off[SGDG_MAX_D + 1];  // into rblk, r-dim grid
   int32_t nblk[SGDG_MAX_D + 1];
   int32_t id_off[SGDG_MAX_D + 1];   // into rid: (N+1)^r entries, -1 if |l|_1 > N
+  int32_t ntile[SGDG_MAX_D];        // fibre tiles of stage m per (species, prefix)
+  int64_t be_off[SGDG_MAX_D + 1];   // into rbe: block (index in the r-dim grid) of every element
+  int32_t nl[3];                    // lines per tile of the last-axis kernel, by number of inputs (1, 2)
   int32_t pad2;
   int64_t gdof[SGDG_MAX_D + 1];     // DOFs of the r-dim grid
   int64_t npre[SGDG_MAX_D + 1];     // np1^m
@@ -37,21 +41,25 @@ struct RTables {
   RInst* inst = nullptr;
   RBlk* rblk = nullptr;
   int32_t* rid = nullptr;
+  int32_t* rbe = nullptr;
   double* EL = nullptr;
+  double* EH = nullptr;
   double* w1 = nullptr;
   double* mats = nullptr;
-  int64_t* cum_x[SGDG_MAX_D] = {};  // expansion stage m: fibres per instance (prefix sums, ninst+1)
-  int64_t* cum_y[SGDG_MAX_D] = {};  // contraction stage m >= 1
-  int64_t* cum_line = nullptr;      // lines of the last axis
-  int64_t* cum_fin = nullptr;       // fibres of the final stage (partial residual sums)
+  int64_t* cum_x[SGDG_MAX_D] = {};  // fibre tiles of stage m per instance (prefix sums, ninst+1)
+  int64_t* cum_line[3] = {};        // line tiles of the last axis, by number of inputs
+  int64_t* cum_fin = nullptr;       // workgroups of the final stage (partial residual sums)
 };
 
 struct RHost {
   RTables dev;
-  std::vector<std::vector<int64_t>> cum_x, cum_y;
-  std::vector<int64_t> cum_line, cum_fin;
-  int64_t rws = 0;  // doubles of reaction workspace per right-hand side
+  std::vector<std::vector<int64_t>> cum_x;
+  std::vector<int64_t> cum_line[3], cum_fin;
+  int lam[SGDG_MAX_D] = {};  // stage m splits each fibre's points into 2^lam chunks (lam <= 2)
+  int64_t rws = 0;           // doubles of reaction workspace per right-hand side
+  size_t line_lds[3] = {};   // LDS bytes of the last-axis kernel, by number of inputs
   int max_n1 = 0, max_np1 = 0;
+  int k1mask = 0;  // bit K1 set when an instance has degree K1 - 1
   int ncu = 0;  // compute units of the plan's device
   bool supported = true;
 };
@@ -67,7 +75,7 @@ constexpr int RX_LOCAL_MAX_ITER = 30;
 
 // One reaction pass over nrhs right-hand sides.
 //   RX_F    : F = P f(R U)
-//   RX_RESID: F = P f(R U), G = U - dt2 F - W, per-final-fibre |G|^2 into part
+//   RX_RESID: F = P f(R U), G = U - dt2 F - W, per-final-workgroup |G|^2 into part
 //   RX_CORR : U <- U - P[(I - dt2 J_f(R U))^{-1} R G]
 //   RX_LOCAL: Gout = P u, u solving u - dt2 f(u) = R U at every point (U holds W)
 // Instances with conv[rhs * ninst + inst] != 0 are skipped (conv may be null).
@@ -77,7 +85,7 @@ struct RxArgs {
   double* F;
   double* Gout;
   const double* W;
-  double* part;  // [rhs][final fibre]
+  double* part;  // [rhs][final workgroup]
   const int32_t* conv;
   double dt2;
   double* rws;  // reaction workspace base

@@ -10,20 +10,34 @@
 // R and P = R^T diag(W) are applied axis by axis ("unidirectional"), each
 // axis as a batch of independent 1D fibres.  A fibre along axis m with level
 // budget L = N - (levels of the other, not yet transformed axes) holds a 1D
-// hierarchical vector of levels 0..L:
-//   expand  : inverse fast multiwavelet transform to the 2^L level-L cells
-//             (two-scale relations), then (k+1)-term evaluation at each of the
-//             np1 = (k+1) 2^N Gauss points of the axis;
-//   contract: weights, projection of the np1 point values onto the 2^N finest
-//             cells, forward fast multiwavelet transform, levels <= L kept.
-// Both are O((k+1)^2 n) per fibre and uniform across lanes (a coefficient's
-// support is never summed point by point).  Stages: expand axes 0..d-2,
-// line kernel on the last axis (expand, pointwise f or per-point species
-// Jacobian solve, contract), contract axes d-2..0; the last contraction
-// writes plan vectors with the residual / correction post-processing fused.
-// One workgroup per fibre (128 lanes; 256 for the lines of the last axis),
-// all intermediate work in LDS, the polynomial degree a template constant; every stage
-// covers all instances, species and right-hand sides in one launch.
+// hierarchical vector of levels 0..L.  Stages: expand axes 0..d-2, a line
+// kernel on the last axis (expand, pointwise f or per-point species Jacobian
+// solve, contract), contract axes d-2..0; the last contraction writes plan
+// vectors with the residual / correction post-processing fused.  Every stage
+// covers all instances, species and right-hand sides in one launch, and the
+// polynomial degree is a template constant.
+//
+// Expansion and contraction stages (one thread per fibre, no LDS, no
+// barriers).  A point q of the axis lies in exactly one cell of every level,
+// so a fibre's value there is sum over levels l <= L and p of
+// v_{l,j(q,l),p}(x_q) c_{l,j,p}: each thread walks the points of its fibre
+// in order, holding the coefficients of the current cell of every level in
+// registers (reloaded when a cell boundary is crossed) and reading the basis
+// values from a per-instance table.  The contraction is the transpose: it
+// accumulates w_q v(x_q) g_q into one running sum per level and emits a
+// cell's coefficients when the walk leaves the cell.  Consecutive threads
+// take consecutive fibres, which sit at consecutive addresses of both the
+// hierarchical and the point-valued arrays, so every load and store is
+// coalesced.  Small stages split each fibre's points into 2^lam chunks
+// (threads of one fibre in one wave); the contraction then combines the
+// partial sums of the coarse levels across the chunks with a fixed-order
+// butterfly.
+//
+// Last axis (one workgroup per tile of whole lines, all inputs and species
+// staged in LDS): inverse fast multiwavelet transform of every line in place
+// (two-scale relations, all lines of the tile in the same barrier step), the
+// pointwise map cell by cell (point values from the finest-level cell
+// coefficients, map, projection back), and the forward transform in place.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +45,7 @@
 #include <cstring>
 #include <functional>
 #include <numeric>
+#include <type_traits>
 
 #include "internal.h"
 #include "kernels.h"
@@ -67,67 +82,72 @@ static std::vector<std::vector<int>> grid_blocks(int r, int N) {
   return out;
 }
 
-constexpr int RX_THREADS_FIB = 128;   // expansion / contraction fibres
-constexpr int RX_THREADS_LINE = 256;  // lines of the last axis
-constexpr int RX_MAX_N1 = 2048;
-constexpr int RX_TAIL = 64 + 16 + 16;  // two-scale matrices + per-wave partial sums + level starts of a fibre
+constexpr int RX_THREADS = 256;        // every reaction kernel
+constexpr int RX_MAX_N1 = 2048;        // (k+1) 2^N per axis
+constexpr int RX_LMAX = 11;            // levels 0..10 (k >= 1, (k+1) 2^N <= 2048)
+// levels of a fibre for degree K1 - 1: N <= log2(2048 / K1)
+template <int K1>
+constexpr int rx_levels() {
+  return K1 == 2 ? 11 : 10;
+}
+constexpr int RX_LINE_LDS = 32 * 1024; // LDS budget of a line tile (several tiles per compute unit)
+constexpr int RX_TAIL = 64 + 16;       // two-scale matrices + per-wave partial sums
+constexpr int64_t RX_THREADS_WANTED = 1 << 17;
 
-// LDS per workgroup (doubles: buffers of the largest fibre, then the tail).
-// The expansion keeps the hierarchical input and two transform buffers; the
-// contraction's point values are dead once projected, so its second
-// transform buffer takes their place; the line kernel has three buffers per
-// transform group and one point buffer per (input, species) pair.
-static size_t expand_lds_bytes(const RHost* rh) {
-  return (3 * (size_t)rh->max_n1 + RX_TAIL) * sizeof(double);
-}
-static size_t contract_lds_bytes(const RHost* rh) {
-  return (2 * (size_t)rh->max_n1 + RX_TAIL) * sizeof(double);
-}
-static size_t line_lds_bytes(const RHost* rh, int ngrp, int nin) {
-  return (3 * (size_t)ngrp * rh->max_n1 + 2 * (size_t)nin * rh->max_np1 + RX_TAIL) * sizeof(double);
-}
-// Concurrent transform groups of the line kernel (4, 2 or 1).  More groups
-// shorten each line's chain of barriers but take more LDS per workgroup; the
-// most that fit the LDS and still let every line of the launch be resident at
-// once (when a launch is larger than one wave of workgroups, throughput
-// matters more than the length of a line's chain).
-static int line_groups(const RHost* rh, int64_t nlines, int nin) {
-  int g = 4;
-  while (g > 1) {
-    const size_t b = line_lds_bytes(rh, g, nin);
-    const int64_t per_cu = b <= (size_t)APPLY_LDS_BYTES_HOST ? (int64_t)APPLY_LDS_BYTES_HOST / (int64_t)b : 0;
-    if (per_cu > 0 && nlines <= per_cu * std::max(rh->ncu, 1)) break;
-    g >>= 1;
-  }
-  return g;
-}
-static int line_groups_max(const RHost* rh, int nin) {
-  int g = 4;
-  while (g > 1 && line_lds_bytes(rh, g, nin) > (size_t)APPLY_LDS_BYTES_HOST) g >>= 1;
-  return g;
-}
-static sgdg_status set_lds_attrs(const RHost* rh);
+// LDS of the last-axis kernel: per line 2.5 npair n1 doubles (inputs, and the
+// two scaling buffers of the transforms), plus the tail
+static int64_t line_doubles(int npair, int n1) { return (int64_t)5 * npair * (n1 / 2); }
+static size_t line_tile_doubles(int npair, int nl, int n1) { return (size_t)line_doubles(npair, n1) * nl + RX_TAIL; }
+static sgdg_status set_line_lds(const RHost* rh);
 
 sgdg_status reaction_build(sgdg_plan* plan) {
   RHost* rh = new RHost();
   plan->rdata = rh;
   const int d = plan->d;
-  // A fibre of a whole finest-grid line stays in LDS: (k+1) 2^N <= 2048.
-  // Larger plans are still valid for the sweep and the Krylov exponential;
-  // their reaction calls report SGDG_ERR_UNSUPPORTED.
-  for (const HostInstance& hi : plan->inst)
-    if (((hi.desc.k + 1) << hi.desc.n) > RX_MAX_N1) {
+  // A whole finest-grid line stays in LDS: (k+1) 2^N <= 2048.  Larger plans
+  // are still valid for the sweep and the Krylov exponential; their reaction
+  // calls report SGDG_ERR_UNSUPPORTED.
+  // Two-species instances keep four lines of inputs and their transform
+  // buffers in LDS during the implicit-stage correction: (k+1) 2^N <= 1024.
+  for (const HostInstance& hi : plan->inst) {
+    const int n1 = (hi.desc.k + 1) << hi.desc.n;
+    const size_t need = line_tile_doubles(2 * hi.desc.nspecies, 1, n1) * sizeof(double);
+    if (n1 > RX_MAX_N1 || need > (size_t)APPLY_LDS_BYTES_HOST) {
       rh->supported = false;
       return SGDG_OK;
     }
+  }
   std::vector<RInst> ri;
   std::vector<RBlk> rblk;
-  std::vector<int32_t> rid;
-  std::vector<double> EL, w1, mats;
+  std::vector<int32_t> rid, rbe;
+  std::vector<double> EL, EH, w1, mats;
   int64_t ws = 0;
+  // chunking of every stage: enough threads to fill the device, and tiles no
+  // wider than the smallest fibre set of the plan
+  int nmin = 1 << 30;
+  for (const HostInstance& hi : plan->inst) nmin = std::min(nmin, hi.desc.n);
+  for (int m = 0; m + 1 <= d - 1; ++m) {
+    int64_t nf = 0, gmin = INT64_MAX;
+    for (const HostInstance& hi : plan->inst) {
+      const int N = hi.desc.n, K1 = hi.desc.k + 1;
+      // fibres of stage m: species x np1^m prefixes x DOFs of the (d-m-1)-dim grid
+      int64_t g = 0;
+      for (const auto& b : grid_blocks(d - m - 1, N)) {
+        int64_t sz = 1;
+        for (int v : b) sz *= (int64_t)level_count(v) * K1;
+        g += sz;
+      }
+      int64_t pre = 1;
+      for (int t = 0; t < m; ++t) pre *= (int64_t)K1 << N;
+      nf += hi.desc.nspecies * pre * g;
+      gmin = std::min(gmin, g);
+    }
+    int lam = 0;
+    while (lam < std::min(2, nmin) && ((RX_THREADS >> lam) > gmin || (nf << lam) < RX_THREADS_WANTED)) ++lam;
+    rh->lam[m] = lam;
+  }
   rh->cum_x.assign(d, std::vector<int64_t>(1, 0));
-  rh->cum_y.assign(d, std::vector<int64_t>(1, 0));
-  rh->cum_line.assign(1, 0);
+  for (int z = 1; z <= 2; ++z) rh->cum_line[z].assign(1, 0);
   rh->cum_fin.assign(1, 0);
   for (int i = 0; i < plan->ninst; ++i) {
     const HostInstance& hi = plan->inst[i];
@@ -143,6 +163,7 @@ sgdg_status reaction_build(sgdg_plan* plan) {
     r.seg = hi.offset;
     r.ndof = hi.ndof;
     std::memcpy(r.rx, hi.desc.rx, sizeof(r.rx));
+    rh->k1mask |= 1 << K1;
     rh->max_n1 = std::max(rh->max_n1, r.n1);
     rh->max_np1 = std::max(rh->max_np1, r.np1);
     std::vector<double> xg, wg;
@@ -150,6 +171,7 @@ sgdg_status reaction_build(sgdg_plan* plan) {
     const Basis1D& bs = basis1d(hi.desc.k);
     const double h = std::ldexp(1.0, -N);
     r.EL_off = (int64_t)EL.size();
+    r.EH_off = (int64_t)EH.size();
     r.w_off = (int64_t)w1.size();
     r.mats_off = (int64_t)mats.size();
     for (int q = 0; q < r.np1; ++q) w1.push_back(wg[q % r.nq] * h);
@@ -163,6 +185,16 @@ sgdg_status reaction_build(sgdg_plan* plan) {
         legendre01_all(hi.desc.k, xloc, phi, nullptr);
         for (int p = 0; p < K1; ++p) EL.push_back(std::sqrt(std::ldexp(1.0, L)) * phi[p]);
       }
+    // hierarchical basis (eq. 2.6) at the finest Gauss points, one row per
+    // point: for every level l the one cell of level l that holds the point
+    // (level 0: the Legendre basis)
+    for (int q = 0; q < r.np1; ++q)
+      for (int l = 0; l <= N; ++l) {
+        const int cellN = q / r.nq;
+        const double x = (cellN + xg[q % r.nq]) * h;
+        const int j = l == 0 ? 0 : cellN >> (N - l + 1);
+        for (int p = 0; p < K1; ++p) EH.push_back(hier_value(bs, l, j, p, x, false));
+      }
     // two-scale matrices, rows padded to 16 entries each
     const std::vector<double>* src[4] = {&bs.ML, &bs.MR, &bs.cL, &bs.cR};
     for (int t = 0; t < 4; ++t) {
@@ -170,12 +202,13 @@ sgdg_status reaction_build(sgdg_plan* plan) {
       std::copy(src[t]->begin(), src[t]->end(), pad.begin());
       mats.insert(mats.end(), pad.begin(), pad.end());
     }
-    // r-dimensional sparse grids, r = 1..d
+    // r-dimensional sparse grids, r = 1..d, and the block of every element
     for (int rr = 1; rr <= d; ++rr) {
       auto blocks = grid_blocks(rr, N);
       r.blk_off[rr] = (int32_t)rblk.size();
       r.nblk[rr] = (int32_t)blocks.size();
       r.id_off[rr] = (int32_t)rid.size();
+      r.be_off[rr] = (int64_t)rbe.size();
       int pw = 1;
       for (int m = 0; m < rr; ++m) pw *= (N + 1);
       std::vector<int32_t> tab(pw, -1);
@@ -194,6 +227,7 @@ sgdg_status reaction_build(sgdg_plan* plan) {
         B.lsum = std::accumulate(blocks[b].begin(), blocks[b].end(), 0);
         tab[lin] = (int32_t)b;
         rblk.push_back(B);
+        rbe.insert(rbe.end(), (size_t)sz, (int32_t)b);
         st += sz;
       }
       r.gdof[rr] = st;
@@ -211,32 +245,42 @@ sgdg_status reaction_build(sgdg_plan* plan) {
       r.Y_off[m] = ws;
       ws += (int64_t)S * r.npre[m] * r.gdof[d - m];
     }
-    // fibres: expansion/contraction stage m runs over (species, prefix, column of the (d-m-1)-dim grid)
-    for (int m = 0; m + 1 <= d - 1; ++m)
-      rh->cum_x[m].push_back(rh->cum_x[m].back() + (int64_t)S * r.npre[m] * r.gdof[d - m - 1]);
-    for (int m = 1; m + 1 <= d - 1; ++m)
-      rh->cum_y[m].push_back(rh->cum_y[m].back() + (int64_t)S * r.npre[m] * r.gdof[d - m - 1]);
-    rh->cum_line.push_back(rh->cum_line.back() + r.npre[d - 1]);
-    rh->cum_fin.push_back(rh->cum_fin.back() + (d >= 2 ? (int64_t)S * r.gdof[d - 1] : 1));
+    // fibre tiles of stage m: 256 >> lam fibres of one (species, prefix)
+    for (int m = 0; m + 1 <= d - 1; ++m) {
+      const int64_t tw = RX_THREADS >> rh->lam[m];
+      r.ntile[m] = (int32_t)((r.gdof[d - m - 1] + tw - 1) / tw);
+      rh->cum_x[m].push_back(rh->cum_x[m].back() + (int64_t)S * r.npre[m] * r.ntile[m]);
+    }
+    // line tiles: as many whole lines as the LDS budget and the per-thread
+    // item bound of the in-place transforms allow
+    for (int nin = 1; nin <= 2; ++nin) {
+      const int npair = nin * S;
+      int64_t nl = (int64_t)RX_LINE_LDS / (line_doubles(npair, r.n1) * 8);
+      nl = std::max<int64_t>(1, std::min<int64_t>(nl, r.npre[d - 1]));
+      r.nl[nin] = (int32_t)nl;
+      rh->cum_line[nin].push_back(rh->cum_line[nin].back() + (r.npre[d - 1] + nl - 1) / nl);
+      rh->line_lds[nin] = std::max(rh->line_lds[nin], line_tile_doubles(npair, (int)nl, r.n1) * sizeof(double));
+    }
+    rh->cum_fin.push_back(rh->cum_fin.back() + (d >= 2 ? (int64_t)S * r.ntile[0] : 1));
     ri.push_back(r);
   }
   rh->rws = ws;
   sgdg_status st;
   if ((st = up(plan, ri, &rh->dev.inst)) != SGDG_OK || (st = up(plan, rblk, &rh->dev.rblk)) != SGDG_OK ||
-      (st = up(plan, rid, &rh->dev.rid)) != SGDG_OK || (st = up(plan, EL, &rh->dev.EL)) != SGDG_OK ||
+      (st = up(plan, rid, &rh->dev.rid)) != SGDG_OK || (st = up(plan, rbe, &rh->dev.rbe)) != SGDG_OK ||
+      (st = up(plan, EL, &rh->dev.EL)) != SGDG_OK || (st = up(plan, EH, &rh->dev.EH)) != SGDG_OK ||
       (st = up(plan, w1, &rh->dev.w1)) != SGDG_OK || (st = up(plan, mats, &rh->dev.mats)) != SGDG_OK ||
-      (st = up(plan, rh->cum_line, &rh->dev.cum_line)) != SGDG_OK ||
+      (st = up(plan, rh->cum_line[1], &rh->dev.cum_line[1])) != SGDG_OK ||
+      (st = up(plan, rh->cum_line[2], &rh->dev.cum_line[2])) != SGDG_OK ||
       (st = up(plan, rh->cum_fin, &rh->dev.cum_fin)) != SGDG_OK)
     return st;
-  for (int m = 0; m < d; ++m) {
+  for (int m = 0; m + 1 <= d - 1; ++m)
     if ((st = up(plan, rh->cum_x[m], &rh->dev.cum_x[m])) != SGDG_OK) return st;
-    if ((st = up(plan, rh->cum_y[m], &rh->dev.cum_y[m])) != SGDG_OK) return st;
-  }
   if (hipDeviceGetAttribute(&rh->ncu, hipDeviceAttributeMultiprocessorCount, plan->device) != hipSuccess) {
     rh->ncu = 0;
     (void)hipGetLastError();
   }
-  return set_lds_attrs(rh);
+  return set_line_lds(rh);
 }
 
 void reaction_destroy(sgdg_plan* plan) {
@@ -254,7 +298,7 @@ int64_t reaction_final_fibres(const sgdg_plan* plan) {
 // ---------------------------------------------------------------- device helpers
 
 // the instance of work item e from the ascending first items cum[0..ninst)
-// (one round of loads per 64 instances, as in find_rblk)
+// (one round of loads per 64 instances)
 __device__ __forceinline__ int find_inst(const int64_t* __restrict__ cum, int ninst, int64_t e) {
   if (ninst == 1) return 0;  // no table load for single-instance plans
   const int lane = threadIdx.x & 63;
@@ -262,21 +306,6 @@ __device__ __forceinline__ int find_inst(const int64_t* __restrict__ cum, int ni
   for (int t0 = 0; t0 < ninst; t0 += 64) {
     const int t = min(t0 + lane, ninst - 1);
     const bool ok = t0 + lane < ninst && cum[t] <= e;
-    const unsigned long long mk = __ballot(ok);
-    if (mk) best = t0 + 63 - __clzll(mk);
-  }
-  return best;
-}
-
-// the block of b[0..n) (ascending starts) holding element e: every lane of
-// the wave tests one block per round of 64, so the search costs one round of
-// loads (the starts at or below e are a prefix; the last of them wins)
-__device__ __forceinline__ int find_rblk(const RBlk* __restrict__ b, int n, int64_t e) {
-  const int lane = threadIdx.x & 63;
-  int best = 0;
-  for (int t0 = 0; t0 < n; t0 += 64) {
-    const int t = min(t0 + lane, n - 1);
-    const bool ok = t0 + lane < n && b[t].start <= e;
     const unsigned long long mk = __ballot(ok);
     if (mk) best = t0 + 63 - __clzll(mk);
   }
@@ -291,149 +320,6 @@ __device__ __forceinline__ const int64_t* pick(const int64_t* const (&a)[SGDG_MA
   for (int i = 1; i < SGDG_MAX_D; ++i)
     if (m == i) r = a[i];
   return r;
-}
-
-__device__ __forceinline__ int off1(int l, int K1) { return l == 0 ? 0 : (K1 << (l - 1)); }
-
-// two-scale matrices in LDS: M[0..15] ML[q][i] (child q from parent i), M[16..] MR,
-// M[32..] cL[p][q] (wavelet p on left child basis q), M[48..] cR; row length K1
-__device__ __forceinline__ void load_mats(const RTables& R, const RInst& I, double* M) {
-  for (int e = threadIdx.x; e < 64; e += blockDim.x) M[e] = R.mats[I.mats_off + e];
-}
-
-// inverse fast multiwavelet transform: hierarchical levels 0..L in h -> level-L
-// cell-Legendre coefficients (returned pointer, one of b0 / b1)
-// The transforms below are run by a group of nt threads with local index tid
-// (by default the whole workgroup); every thread of the workgroup passes the
-// same barriers, and a thread with tid >= any loop bound takes part in the
-// barriers only.
-template <int K1>
-__device__ __forceinline__ double* ifwt(const double* h, double* b0, double* b1, int L, const double* M,
-                                        int tid = threadIdx.x, int nt = blockDim.x) {
-  for (int e = tid; e < K1; e += nt) b0[e] = h[e];
-  __syncthreads();
-  double* cur = b0;
-  double* nxt = b1;
-  int n = 1;
-  // coarse levels two per barrier while level n+1 has at most one item per
-  // thread: the thread forms the K1 level-n values of its item's parent cell
-  // (the sums of the one-level pass, in the same order), then its item
-  for (; n + 1 <= L && (K1 << (n + 1)) <= nt; n += 2) {
-    const double* dw1 = h + (K1 << (n - 1));
-    const double* dw2 = h + (K1 << n);
-    const int e = tid;
-    if (e < (K1 << (n + 1))) {
-      const int c = e / K1, q = e - c * K1, c1 = c >> 1, j = c1 >> 1;
-      const double* M1 = (c1 & 1) ? M + 16 : M;
-      const double* W1 = (c1 & 1) ? M + 48 : M + 32;
-      double pv[K1];
-#pragma unroll
-      for (int q1 = 0; q1 < K1; ++q1) {
-        double a = 0.0;
-#pragma unroll
-        for (int i = 0; i < K1; ++i) a += M1[q1 * K1 + i] * cur[j * K1 + i];
-#pragma unroll
-        for (int p = 0; p < K1; ++p) a += W1[p * K1 + q1] * dw1[j * K1 + p];
-        pv[q1] = a;
-      }
-      const double* M2 = (c & 1) ? M + 16 : M;
-      const double* W2 = (c & 1) ? M + 48 : M + 32;
-      double acc = 0.0;
-#pragma unroll
-      for (int i = 0; i < K1; ++i) acc += M2[q * K1 + i] * pv[i];
-#pragma unroll
-      for (int p = 0; p < K1; ++p) acc += W2[p * K1 + q] * dw2[c1 * K1 + p];
-      nxt[e] = acc;
-    }
-    __syncthreads();
-    double* t = cur;
-    cur = nxt;
-    nxt = t;
-  }
-  for (; n <= L; ++n) {
-    const double* dw = h + (K1 << (n - 1));
-    const int items = (K1 << n);
-    for (int e = tid; e < items; e += nt) {
-      const int c = e / K1, q = e - c * K1, j = c >> 1;
-      const double* Mq = (c & 1) ? M + 16 : M;
-      const double* Wq = (c & 1) ? M + 48 : M + 32;
-      double acc = 0.0;
-#pragma unroll
-      for (int i = 0; i < K1; ++i) acc += Mq[q * K1 + i] * cur[j * K1 + i];
-#pragma unroll
-      for (int p = 0; p < K1; ++p) acc += Wq[p * K1 + q] * dw[j * K1 + p];
-      nxt[e] = acc;
-    }
-    __syncthreads();
-    double* t = cur;
-    cur = nxt;
-    nxt = t;
-  }
-  return cur;
-}
-
-// forward fast multiwavelet transform of level-N cell coefficients in s (s and
-// tmp are overwritten); emit(level, j, p, value) receives every hierarchical
-// coefficient (wavelets of levels N..1, then level 0).
-template <int K1, class Emit>
-__device__ __forceinline__ void ffwt(double* s, double* tmp, int N, const double* M, Emit emit, int tid = threadIdx.x,
-                                     int nt = blockDim.x) {
-  double* cur = s;
-  double* nxt = tmp;
-  for (int n = N; n >= 1; --n) {
-    const int npar = 1 << (n - 1);
-    const int half = npar * K1;
-    for (int e = tid; e < 2 * half; e += nt) {
-      const int w = e >= half;
-      const int e2 = e - w * half;
-      const int j = e2 / K1, i = e2 - j * K1;
-      const double* sl = cur + (2 * j) * K1;
-      const double* sr = sl + K1;
-      double acc = 0.0;
-      if (!w) {
-#pragma unroll
-        for (int q = 0; q < K1; ++q) acc += M[q * K1 + i] * sl[q] + M[16 + q * K1 + i] * sr[q];
-        nxt[j * K1 + i] = acc;
-      } else {
-#pragma unroll
-        for (int q = 0; q < K1; ++q) acc += M[32 + i * K1 + q] * sl[q] + M[48 + i * K1 + q] * sr[q];
-        emit(n, j, i, acc);
-      }
-    }
-    __syncthreads();
-    double* t = cur;
-    cur = nxt;
-    nxt = t;
-  }
-  for (int e = tid; e < K1; e += nt) emit(0, 0, e, cur[e]);
-  __syncthreads();
-}
-
-// value at finest point q of the level-L cell expansion s (K1 Gauss points per cell)
-template <int K1>
-__device__ __forceinline__ double eval_pt(const double* s, const double* __restrict__ EL, int L, int N, int np1, int q) {
-  const int c = (q / K1) >> (N - L);
-  const double* e = EL + ((int64_t)L * np1 + q) * K1;
-  double u = 0.0;
-#pragma unroll
-  for (int p = 0; p < K1; ++p) u += s[c * K1 + p] * e[p];
-  return u;
-}
-
-// weighted point values g (weights already applied) -> level-N cell coefficients in out
-template <int K1>
-__device__ __forceinline__ void project_cells(const double* g, const double* __restrict__ EL, int N, int np1,
-                                              double* out, int tid = threadIdx.x, int nt = blockDim.x) {
-  const int ncell = 1 << N;
-  const double* e = EL + (int64_t)N * np1 * K1;
-  for (int t = tid; t < ncell * K1; t += nt) {
-    const int c = t / K1, p = t - c * K1;
-    double acc = 0.0;
-#pragma unroll
-    for (int gq = 0; gq < K1; ++gq) acc += g[c * K1 + gq] * e[(c * K1 + gq) * K1 + p];
-    out[t] = acc;
-  }
-  __syncthreads();
 }
 
 __device__ __forceinline__ const double* plan_in(const RxArgs& a, int z, int64_t rhs_total) {
@@ -476,6 +362,53 @@ __device__ __forceinline__ void rx_jac(const double (*c)[4][4], int S, const dou
   }
 }
 
+// The pointwise map of a pass at one point: u[s] = R U (mode RX_CORR also
+// g[s] = R G); returns the values to project (before the quadrature weight).
+__device__ __forceinline__ void rx_map(const RInst& I, int mode, double dt2, const double* u, const double* g,
+                                       double* out) {
+  const int S = I.S;
+  if (mode == RX_CORR) {
+    double J[2][2];
+    rx_jac(I.rx, S, u, J);
+    if (S == 1) {
+      out[0] = g[0] / (1.0 - dt2 * J[0][0]);
+      out[1] = 0.0;
+    } else {
+      const double A = 1.0 - dt2 * J[0][0], Bq = -dt2 * J[0][1];
+      const double C = -dt2 * J[1][0], D = 1.0 - dt2 * J[1][1];
+      const double det = A * D - Bq * C;
+      out[0] = (D * g[0] - Bq * g[1]) / det;
+      out[1] = (A * g[1] - C * g[0]) / det;
+    }
+  } else if (mode == RX_LOCAL) {
+    // u - dt2 f(u) = w at this point, Newton from u = w (at most RX_LOCAL_MAX_ITER corrections)
+    const double w0 = u[0], w1v = S > 1 ? u[1] : 0.0;
+    const double wmag = fmax(1.0, fmax(fabs(w0), fabs(w1v)));
+    double x[2] = {w0, w1v};
+    for (int it = 0; it <= RX_LOCAL_MAX_ITER; ++it) {
+      double f[2];
+      rx_f(I.rx, S, x, f);
+      const double g0 = x[0] - dt2 * f[0] - w0, g1 = S > 1 ? x[1] - dt2 * f[1] - w1v : 0.0;
+      if (fmax(fabs(g0), fabs(g1)) <= RX_LOCAL_TOL * wmag || it == RX_LOCAL_MAX_ITER) break;
+      double J[2][2];
+      rx_jac(I.rx, S, x, J);
+      if (S == 1) {
+        x[0] -= g0 / (1.0 - dt2 * J[0][0]);
+      } else {
+        const double A = 1.0 - dt2 * J[0][0], Bq = -dt2 * J[0][1];
+        const double C = -dt2 * J[1][0], D = 1.0 - dt2 * J[1][1];
+        const double det = A * D - Bq * C;
+        x[0] -= (D * g0 - Bq * g1) / det;
+        x[1] -= (A * g1 - C * g0) / det;
+      }
+    }
+    out[0] = x[0];
+    out[1] = x[1];
+  } else {
+    rx_f(I.rx, S, u, out);
+  }
+}
+
 // post-processing of one output coefficient of the final stage; returns G^2 (RESID) or 0
 __device__ __forceinline__ double finish(const RxArgs& a, int mode, int64_t gi, double v) {
   if (mode == RX_F) {
@@ -508,308 +441,475 @@ __device__ __forceinline__ double block_sum(double v, double* wsum) {
   return t;
 }
 
+// Geometry of one fibre of stage m (fibres along axis m): the block of the
+// (r-1)-dim grid (axes m+1..d-1, r = d - m) that holds element eo, and the
+// start of the r-dim grid block (l, that block's levels) for every level l of
+// axis m within the fibre's budget L.
+template <int LM>
+struct Fibre {
+  int32_t rest, Sb;
+  int L;
+  int32_t bl[LM];  // offsets inside one r-dim grid (< 2^31 for every supported plan)
+};
+
+template <int LM>
+__device__ __forceinline__ Fibre<LM> fibre_geometry(const RTables& R, const RInst& I, int r, int64_t eo) {
+  Fibre<LM> F;
+  const int N = I.N;
+  const RBlk& B = R.rblk[I.blk_off[r - 1] + R.rbe[I.be_off[r - 1] + eo]];
+  F.rest = (int32_t)(eo - B.start);
+  F.Sb = B.size;
+  F.L = N - B.lsum;
+  int lin = 0, pw = 1;
+  for (int t = r - 2; t >= 0; --t) {
+    lin += B.lev[t] * pw;
+    pw *= (N + 1);
+  }
+  const int32_t* __restrict__ id = R.rid + I.id_off[r];
+  const RBlk* __restrict__ ib = R.rblk + I.blk_off[r];
+  // levels past the budget keep a valid address (level 0's) and are masked by the caller
+#pragma unroll
+  for (int l = 0; l < LM; ++l) F.bl[l] = (int32_t)ib[id[(l <= F.L ? l : 0) * pw + lin]].start + F.rest;
+  return F;
+}
+
 // ---------------------------------------------------------------- kernels
 
-// expansion stage m: fibres along axis m, grid (fibres, rhs, input)
+// Tile of stage m: (species, prefix, tile of 256 >> lam fibres).  Every
+// wave holds 64 consecutive fibres and one chunk of their points (2^lam
+// chunks, lam <= 2, all in the workgroup), so the point index -- and with it
+// every basis-table and weight address -- is the same across the wave.
+struct TileIdx {
+  int s;
+  int64_t pre;
+  int64_t eo;  // this thread's fibre
+  int qc;      // its chunk of points (wave-uniform)
+  int fb;      // its wave's block of 64 fibres
+};
+
+__device__ __forceinline__ TileIdx tile_index(const RInst& I, int m, int64_t le, int lam) {
+  TileIdx t;
+  const int ntile = I.ntile[m];
+  const int64_t per_s = I.npre[m] * ntile;
+  t.s = (int)(le / per_s);
+  le -= (int64_t)t.s * per_s;
+  t.pre = le / ntile;
+  const int tt = (int)(le - t.pre * ntile);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  t.qc = w >> (2 - lam);
+  t.fb = w & ((4 >> lam) - 1);
+  t.eo = (int64_t)tt * (RX_THREADS >> lam) + t.fb * 64 + (threadIdx.x & 63);
+  return t;
+}
+
+// expansion stage m: hierarchical along axis m -> point values, grid (tiles, rhs, input)
 template <int K1>
-__device__ void rx_expand_body(const RTables& R, int inst, int m, int64_t total, const RxArgs& a, int64_t rws,
-                               int max_n1, double* lds) {
-  const int z = blockIdx.z, rhs = blockIdx.y;
-  const int64_t f = blockIdx.x;
-  const int64_t* cum = pick(R.cum_x, m);
+__device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg, int inst, int m, int64_t total,
+                               const RxArgs& a, int64_t rws, int lam) {
   const RInst& I = R.inst[inst];
+  const int z = blockIdx.z, rhs = blockIdx.y;
   const int d = I.d, r = d - m, N = I.N, S = I.S, np1 = I.np1;
-  int64_t le = f - cum[inst];
+  const TileIdx t = tile_index(I, m, (int64_t)blockIdx.x - pick(R.cum_x, m)[inst], lam);
   const int64_t gd_in = I.gdof[r], gd_out = I.gdof[r - 1];
-  const int64_t per_s = I.npre[m] * gd_out;
-  const int s = (int)(le / per_s);
-  le -= (int64_t)s * per_s;
-  const int64_t pre0 = le / gd_out;
-  const int64_t eo = le - pre0 * gd_out;
-  const RBlk* ob = R.rblk + I.blk_off[r - 1];
-  const RBlk& B = ob[find_rblk(ob, I.nblk[r - 1], eo)];
-  const int64_t rest = eo - B.start, Sb = B.size;
-  const int L = N - B.lsum;
-  int lin = 0, pw = 1;
-  for (int t = r - 2; t >= 0; --t) {
-    lin += B.lev[t] * pw;
-    pw *= (N + 1);
-  }
-  double* h = lds;
-  double* b0 = lds + max_n1;
-  double* b1 = lds + 2 * max_n1;
-  double* M = lds + 3 * max_n1;
-  const int32_t* __restrict__ id = R.rid + I.id_off[r];
-  const RBlk* ib = R.rblk + I.blk_off[r];
+  if (t.eo >= gd_out) return;
+  constexpr int LM = rx_levels<K1>();
+  const Fibre<LM> F = fibre_geometry<LM>(R, I, r, t.eo);
   double* xr = a.rws + (int64_t)rhs * rws;
   const double* __restrict__ in =
-      m == 0 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof
-             : xr + I.X_off[m] + (((int64_t)z * S + s) * I.npre[m] + pre0) * gd_in;
-  double* out = xr + I.X_off[m + 1] + (((int64_t)z * S + s) * I.npre[m + 1] + pre0 * np1) * gd_out + eo;
-  const double* __restrict__ EL = R.EL + I.EL_off;
-  // start of the fibre's level-l block (l <= L), one thread per level, then
-  // every entry of every level is loaded in one round
-  int64_t* lb = (int64_t*)(M + 80);
-  if ((int)threadIdx.x <= L) lb[threadIdx.x] = ib[id[threadIdx.x * pw + lin]].start + rest;
-  load_mats(R, I, M);
-  __syncthreads();
-  for (int e = threadIdx.x; e < (K1 << L); e += blockDim.x) {
-    const int l = e < K1 ? 0 : 32 - __clz(e / K1);  // entry e of levels 0..L in hierarchical order
-    h[e] = in[lb[l] + (int64_t)(e - off1(l, K1)) * Sb];
-  }
-  __syncthreads();
-  const double* sc = ifwt<K1>(h, b0, b1, L, M);
-  for (int q = threadIdx.x; q < np1; q += blockDim.x) out[(int64_t)q * gd_out] = eval_pt<K1>(sc, EL, L, N, np1, q);
-}
-
-__global__ __launch_bounds__(RX_THREADS_FIB) void k_rx_expand(RTables R, int ninst, int m, int64_t total, RxArgs a,
-                                                              int64_t rws, int max_n1) {
-  extern __shared__ double lds[];
-  const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
-  if (a.conv && a.conv[blockIdx.y * ninst + inst]) return;
-  switch (R.inst[inst].K1) {
-    case 2: rx_expand_body<2>(R, inst, m, total, a, rws, max_n1, lds); break;
-    case 3: rx_expand_body<3>(R, inst, m, total, a, rws, max_n1, lds); break;
-    default: rx_expand_body<4>(R, inst, m, total, a, rws, max_n1, lds); break;
-  }
-}
-
-// one workgroup per line of the last axis: expand (all species and inputs),
-// pointwise map, contract; for d = 1 the line is the whole instance and the
-// plan vectors are read and finished directly
-template <int K1>
-__device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total, const RxArgs& a, int64_t rws,
-                             int max_n1, int max_np1, int64_t nfin, int ngrp, double* lds) {
-  const int rhs = blockIdx.y;
-  const int64_t gl = blockIdx.x;
-  const RInst& I = R.inst[inst];
-  const int d = I.d, N = I.N, S = I.S, np1 = I.np1, n1 = I.n1;
-  const int64_t pre = gl - R.cum_line[inst];
-  const int nin = mode == RX_CORR ? 2 : 1;
-  // up to ngrp groups of threads transform different (input, species) lines
-  // at the same time, each in its own three buffers (no more groups than
-  // lines, so that each group is as large as possible)
-  const int npair = nin * S;
-  const int ng = min(ngrp, npair);
-  const int gs = blockDim.x / ng, gi = threadIdx.x / gs, gt = threadIdx.x - gi * gs;
-  double* h = lds + (int64_t)gi * 3 * max_n1;
-  double* b0 = h + max_n1;
-  double* b1 = b0 + max_n1;
-  double* pts = lds + (int64_t)ngrp * 3 * max_n1;  // [z*2+s][max_np1], z < nin
-  double* M = pts + 2 * nin * max_np1;
-  double* wsum = M + 64;
-  double* xr = a.rws + (int64_t)rhs * rws;
-  const double* __restrict__ EL = R.EL + I.EL_off;
-  const double* __restrict__ w1 = R.w1 + I.w_off;
-  const double dt2 = a.dt2;
-  load_mats(R, I, M);
-  for (int r0 = 0; r0 < npair; r0 += ng) {
-    const int pi = r0 + gi;
-    const bool act = pi < npair;
-    const int z = act ? pi / S : 0, s = act ? pi - z * S : 0;
-    const int lt = act ? gt : (1 << 30);  // an idle group passes the barriers only
-    const double* in = d == 1 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof
-                              : xr + I.X_off[d - 1] + (((int64_t)z * S + s) * I.npre[d - 1] + pre) * n1;
-    for (int i = lt; i < n1; i += gs) h[i] = in[i];
-    __syncthreads();
-    const double* sc = ifwt<K1>(h, b0, b1, N, M, lt, gs);
-    double* pz = pts + (z * 2 + s) * max_np1;
-    for (int q = lt; q < np1; q += gs) pz[q] = eval_pt<K1>(sc, EL, N, N, np1, q);
-    __syncthreads();
-  }
-  for (int q = threadIdx.x; q < np1; q += blockDim.x) {
-    double u[2] = {pts[q], S > 1 ? pts[max_np1 + q] : 0.0};
-    double out[2];
-    if (mode == RX_CORR) {
-      const double g0 = pts[2 * max_np1 + q], g1 = S > 1 ? pts[3 * max_np1 + q] : 0.0;
-      double J[2][2];
-      rx_jac(I.rx, S, u, J);
-      if (S == 1) {
-        out[0] = g0 / (1.0 - dt2 * J[0][0]);
-      } else {
-        const double A = 1.0 - dt2 * J[0][0], Bq = -dt2 * J[0][1];
-        const double C = -dt2 * J[1][0], D = 1.0 - dt2 * J[1][1];
-        const double det = A * D - Bq * C;
-        out[0] = (D * g0 - Bq * g1) / det;
-        out[1] = (A * g1 - C * g0) / det;
+      m == 0 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)t.s * I.ndof
+             : xr + I.X_off[m] + (((int64_t)z * S + t.s) * I.npre[m] + t.pre) * gd_in;
+  double* __restrict__ out =
+      xr + I.X_off[m + 1] + (((int64_t)z * S + t.s) * I.npre[m + 1] + t.pre * np1) * gd_out + t.eo;
+  const double* __restrict__ EH = EHg + I.EH_off;
+  const int NL1 = N + 1;
+  const int cw = (1 << N) >> lam, c0 = t.qc * cw;
+  // coefficients of the current cell of every level (zero past the fibre's
+  // budget); the level loops run to N, the same bound for the whole wave
+  double cf[LM][K1];
+#pragma unroll
+  for (int l = 0; l < LM; ++l)
+    if (l <= N) {
+      const int j = l == 0 ? 0 : c0 >> (N - l + 1);
+      const bool on = l <= F.L;
+#pragma unroll
+      for (int p = 0; p < K1; ++p) {
+        const double v = in[F.bl[l] + (int64_t)((on ? j : 0) * K1 + p) * F.Sb];
+        cf[l][p] = on ? v : 0.0;
       }
-    } else if (mode == RX_LOCAL) {
-      // u - dt2 f(u) = w at this point, Newton from u = w (at most RX_LOCAL_MAX_ITER corrections)
-      const double w0 = u[0], w1v = u[1];
-      const double wmag = fmax(1.0, fmax(fabs(w0), fabs(w1v)));
-      double x[2] = {w0, w1v};
-      for (int it = 0; it <= RX_LOCAL_MAX_ITER; ++it) {
-        double f[2];
-        rx_f(I.rx, S, x, f);
-        const double g0 = x[0] - dt2 * f[0] - w0, g1 = S > 1 ? x[1] - dt2 * f[1] - w1v : 0.0;
-        if (fmax(fabs(g0), fabs(g1)) <= RX_LOCAL_TOL * wmag || it == RX_LOCAL_MAX_ITER) break;
-        double J[2][2];
-        rx_jac(I.rx, S, x, J);
-        if (S == 1) {
-          x[0] -= g0 / (1.0 - dt2 * J[0][0]);
-        } else {
-          const double A = 1.0 - dt2 * J[0][0], Bq = -dt2 * J[0][1];
-          const double C = -dt2 * J[1][0], D = 1.0 - dt2 * J[1][1];
-          const double det = A * D - Bq * C;
-          x[0] -= (D * g0 - Bq * g1) / det;
-          x[1] -= (A * g1 - C * g0) / det;
+    }
+  for (int c = c0; c < c0 + cw; ++c) {
+    if (c != c0) {
+#pragma unroll
+      for (int l = 1; l < LM; ++l)
+        if (l <= N && (c & ((1 << (N - l + 1)) - 1)) == 0) {
+          const int j = c >> (N - l + 1);
+          const bool on = l <= F.L;
+#pragma unroll
+          for (int p = 0; p < K1; ++p) {
+            const double v = in[F.bl[l] + (int64_t)((on ? j : 0) * K1 + p) * F.Sb];
+            cf[l][p] = on ? v : 0.0;
+          }
+        }
+    }
+#pragma unroll
+    for (int gq = 0; gq < K1; ++gq) {
+      const int q = c * K1 + gq;
+      const double* __restrict__ eh = EH + (int64_t)q * NL1 * K1;  // the point's row: levels 0..N, K1 each
+      double u = 0.0;
+#pragma unroll
+      for (int l = 0; l < LM; ++l)
+        if (l <= N)
+#pragma unroll
+          for (int p = 0; p < K1; ++p) u += eh[l * K1 + p] * cf[l][p];
+      out[(int64_t)q * gd_out] = u;
+    }
+  }
+}
+
+// one kernel per degree (register use follows K1); workgroups of instances
+// of another degree return at once
+// (the basis table is its own argument: its loads are wave-uniform and go
+// through the scalar cache)
+template <int K1>
+__global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, const double* __restrict__ EHg, int ninst, int m,
+                                                          int64_t total, RxArgs a, int64_t rws, int lam) {
+  const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
+  if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
+  rx_expand_body<K1>(R, EHg, inst, m, total, a, rws, lam);
+}
+
+// contraction stage m: weighted point values along axis m -> hierarchical
+// (m >= 1 writes Y_m; m == 0 finishes plan vectors), grid (tiles, rhs)
+template <int K1>
+__device__ void rx_contract_body(const RTables& R, const double* __restrict__ EHg, const double* __restrict__ w1g,
+                                 int inst, int m, int mode, int64_t total, const RxArgs& a, int64_t rws, int lam,
+                                 int64_t nfin) {
+  // partial sums of the levels whose cells span several chunks: [wave][level <= 2][p][lane]
+  __shared__ double red[4][3][K1][64];
+  __shared__ double wsum[RX_THREADS / 64];
+  const RInst& I = R.inst[inst];
+  const int rhs = blockIdx.y, ln = threadIdx.x & 63;
+  const int d = I.d, r = d - m, N = I.N, np1 = I.np1;
+  const int64_t le = (int64_t)blockIdx.x - pick(R.cum_x, m)[inst];
+  const TileIdx t = tile_index(I, m, le, lam);
+  const int w = t.qc * (4 >> lam) + t.fb;
+  const int64_t gd_in = I.gdof[r - 1], gd_out = I.gdof[r];
+  // every thread passes the barriers; threads past the fibre set carry zeros
+  // and emit nothing
+  const bool valid = t.eo < gd_in;
+  constexpr int LM = rx_levels<K1>();
+  const Fibre<LM> F = fibre_geometry<LM>(R, I, r, valid ? t.eo : 0);
+  const int L = valid ? F.L : -1;
+  double* xr = a.rws + (int64_t)rhs * rws;
+  const double* __restrict__ in = xr + I.Y_off[m + 1] + ((int64_t)t.s * I.npre[m + 1] + t.pre * np1) * gd_in + t.eo;
+  const double* __restrict__ EH = EHg + I.EH_off;
+  const double* __restrict__ w1 = w1g + I.w_off;
+  double* outm = m > 0 ? xr + I.Y_off[m] + ((int64_t)t.s * I.npre[m] + t.pre) * gd_out : nullptr;
+  const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)t.s * I.ndof;
+  double g2 = 0.0;
+  auto emit = [&](int l, int j, int p, double v) {
+    const int64_t o = F.bl[l] + (int64_t)(j * K1 + p) * F.Sb;
+    if (m > 0)
+      outm[o] = v;
+    else
+      g2 += finish(a, mode, base + o, v);
+  };
+  const int NL1 = N + 1;
+  const int cw = (1 << N) >> lam, c0 = t.qc * cw;
+  double acc[LM][K1];
+#pragma unroll
+  for (int l = 0; l < LM; ++l)
+#pragma unroll
+    for (int p = 0; p < K1; ++p) acc[l][p] = 0.0;
+  for (int c = c0; c < c0 + cw; ++c) {
+#pragma unroll
+    for (int gq = 0; gq < K1; ++gq) {
+      const int q = c * K1 + gq;
+      const double* __restrict__ eh = EH + (int64_t)q * NL1 * K1;
+      const double g = valid ? w1[q] * in[(int64_t)q * gd_in] : 0.0;
+#pragma unroll
+      for (int l = 0; l < LM; ++l)
+        if (l <= N)
+#pragma unroll
+          for (int p = 0; p < K1; ++p) acc[l][p] += eh[l * K1 + p] * g;  // (unused past the fibre's budget)
+    }
+    // levels whose cells lie inside one chunk: a cell is complete when the walk leaves it
+#pragma unroll
+    for (int l = 1; l < LM; ++l)
+      if (l > lam && l <= L && ((c + 1) & ((1 << (N - l + 1)) - 1)) == 0) {
+#pragma unroll
+        for (int p = 0; p < K1; ++p) {
+          emit(l, c >> (N - l + 1), p, acc[l][p]);
+          acc[l][p] = 0.0;
         }
       }
-      out[0] = x[0];
-      out[1] = x[1];
-    } else {
-      rx_f(I.rx, S, u, out);
-    }
-    pts[q] = w1[q] * out[0];
-    if (S > 1) pts[max_np1 + q] = w1[q] * out[1];
   }
-  __syncthreads();
-  double g2 = 0.0;
-  // contraction: the species at the same time when there are groups enough
-  const int cg = min(ng, S);
-  const int cgs = blockDim.x / cg, cgi = threadIdx.x / cgs, cgt = threadIdx.x - cgi * cgs;
-  double* c0 = lds + (int64_t)cgi * 3 * max_n1;
-  double* c1 = c0 + max_n1;
-  for (int r0 = 0; r0 < S; r0 += cg) {
-    const int s = r0 + cgi;
-    const bool act = s < S;
-    const int lt = act ? cgt : (1 << 30);
-    const int sp = act ? s : 0;
-    project_cells<K1>(pts + sp * max_np1, EL, N, np1, c0, lt, cgs);
-    if (d == 1) {
-      const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)sp * I.ndof;
-      ffwt<K1>(c0, c1, N, M, [&](int n, int j, int p, double v) {
-        g2 += finish(a, mode, base + off1(n, K1) + j * K1 + p, v);
-      }, lt, cgs);
-    } else {
-      double* out = xr + I.Y_off[d - 1] + ((int64_t)sp * I.npre[d - 1] + pre) * n1;
-      ffwt<K1>(c0, c1, N, M, [&](int n, int j, int p, double v) { out[off1(n, K1) + j * K1 + p] = v; }, lt, cgs);
-    }
-  }
-  if (d == 1 && mode == RX_RESID) {
-    g2 = block_sum(g2, wsum);
-    if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + R.cum_fin[inst]] = g2;
-  }
-}
-
-__global__ __launch_bounds__(RX_THREADS_LINE) void k_rx_line(RTables R, int ninst, int mode, int64_t total, RxArgs a,
-                                                             int64_t rws, int max_n1, int max_np1, int64_t nfin,
-                                                             int ngrp) {
-  extern __shared__ double lds[];
-  const int inst = find_inst(R.cum_line, ninst, blockIdx.x);
-  if (a.conv && a.conv[blockIdx.y * ninst + inst]) return;
-  switch (R.inst[inst].K1) {
-    case 2: rx_line_body<2>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, ngrp, lds); break;
-    case 3: rx_line_body<3>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, ngrp, lds); break;
-    default: rx_line_body<4>(R, inst, mode, total, a, rws, max_n1, max_np1, nfin, ngrp, lds); break;
-  }
-}
-
-// contraction stage m (m >= 1 writes Y_m; m == 0 finishes plan vectors)
-template <int K1>
-__device__ void rx_contract_body(const RTables& R, int inst, int m, int mode, int64_t total, const RxArgs& a,
-                                 int64_t rws, int max_n1, int64_t nfin, double* lds) {
-  const int rhs = blockIdx.y;
-  const int64_t f = blockIdx.x;
-  const int64_t* cum = m == 0 ? R.cum_fin : pick(R.cum_y, m);
-  const RInst& I = R.inst[inst];
-  const int d = I.d, r = d - m, N = I.N, np1 = I.np1;
-  int64_t le = f - cum[inst];
-  const int64_t gd_in = I.gdof[r - 1], gd_out = I.gdof[r];
-  const int64_t per_s = I.npre[m] * gd_in;
-  const int s = (int)(le / per_s);
-  le -= (int64_t)s * per_s;
-  const int64_t pre0 = le / gd_in;
-  const int64_t eo = le - pre0 * gd_in;
-  const RBlk* ob = R.rblk + I.blk_off[r - 1];
-  const RBlk& B = ob[find_rblk(ob, I.nblk[r - 1], eo)];
-  const int64_t rest = eo - B.start, Sb = B.size;
-  const int L = N - B.lsum;
-  int lin = 0, pw = 1;
-  for (int t = r - 2; t >= 0; --t) {
-    lin += B.lev[t] * pw;
-    pw *= (N + 1);
-  }
-  double* g = lds;
-  double* b0 = lds + max_n1;
-  double* b1 = lds;  // the point values are dead once projected into b0
-  double* M = lds + 2 * max_n1;
-  double* wsum = M + 64;
-  double* xr = a.rws + (int64_t)rhs * rws;
-  const double* __restrict__ EL = R.EL + I.EL_off;
-  const double* __restrict__ w1 = R.w1 + I.w_off;
-  // start of the output's level-n block (n <= L), one thread per level,
-  // before the transform needs them
-  const int32_t* __restrict__ id = R.rid + I.id_off[r];
-  const RBlk* ib = R.rblk + I.blk_off[r];
-  int64_t* lb = (int64_t*)(M + 80);
-  if ((int)threadIdx.x <= L) lb[threadIdx.x] = ib[id[threadIdx.x * pw + lin]].start;
-  load_mats(R, I, M);
-  const double* __restrict__ in = xr + I.Y_off[m + 1] + ((int64_t)s * I.npre[m + 1] + pre0 * np1) * gd_in + eo;
-  for (int q = threadIdx.x; q < np1; q += blockDim.x) g[q] = w1[q] * in[(int64_t)q * gd_in];
-  __syncthreads();
-  project_cells<K1>(g, EL, N, np1, b0);
-  if (m > 0) {
-    double* out = xr + I.Y_off[m] + ((int64_t)s * I.npre[m] + pre0) * gd_out + rest;
-    ffwt<K1>(b0, b1, N, M, [&](int n, int j, int p, double v) {
-      if (n <= L) out[lb[n] + (int64_t)(j * K1 + p) * Sb] = v;
-    });
+  // coarser levels span 2^(lam-l+1) chunks (level 0 all of them): the wave of
+  // the first chunk of each cell adds the chunks' partial sums in order
+  if (lam > 0) {
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+      if (l <= lam)
+#pragma unroll
+        for (int p = 0; p < K1; ++p) red[w][l][p][ln] = acc[l][p];
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+      if (l <= lam) {
+        const int gb = l == 0 ? lam : lam - l + 1;  // log2 of the chunks per cell
+        if (l <= L && (t.qc & ((1 << gb) - 1)) == 0) {
+          const int j = l == 0 ? 0 : t.qc >> gb;
+#pragma unroll
+          for (int p = 0; p < K1; ++p) {
+            double v = 0.0;
+            for (int cc = 0; cc < (1 << gb); ++cc) v += red[(t.qc + cc) * (4 >> lam) + t.fb][l][p][ln];
+            emit(l, j, p, v);
+          }
+        }
+      }
   } else {
-    const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)s * I.ndof + rest;
+#pragma unroll
+    for (int p = 0; p < K1; ++p)
+      if (L >= 0) emit(0, 0, p, acc[0][p]);
+  }
+  if (m == 0 && mode == RX_RESID) {
+    g2 = block_sum(g2, wsum);
+    if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + blockIdx.x] = g2;
+  }
+}
+
+template <int K1>
+__global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, const double* __restrict__ EHg,
+                                                            const double* __restrict__ w1g, int ninst, int m, int mode,
+                                                            int64_t total, RxArgs a, int64_t rws, int lam,
+                                                            int64_t nfin) {
+  const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
+  if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
+  rx_contract_body<K1>(R, EHg, w1g, inst, m, mode, total, a, rws, lam, nfin);
+}
+
+// Last axis: a tile of nl whole lines (consecutive prefixes).  LDS per line,
+// pair = input * S + species (npair = 1, 2 or 4):
+//   H [pair][n1]     the hierarchical inputs; later the projections and one
+//                    of the two scaling buffers of the forward transform
+//   SA[pair][n1]     level-n cell coefficients of the inverse transform (n = N, N-2, ..);
+//                    later the wavelets of the forward transform
+//   SB[pair][n1/2]   level-n cell coefficients for n = N-1, N-3, ..
+// Every transform level is one barrier step over all lines of the tile
+// (ping-pong between the buffers, the wavelets read from / written to their
+// own places).  For d = 1 the line is the instance itself, read from and
+// finished into plan vectors.
+template <int K1>
+__device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total, const RxArgs& a, int64_t rws,
+                             int nin, int64_t nfin, double* lds) {
+  const RInst& I = R.inst[inst];
+  const int rhs = blockIdx.y, tid = threadIdx.x;
+  const int d = I.d, N = I.N, S = I.S, np1 = I.np1, n1 = I.n1;
+  const int NL = I.nl[nin];
+  const int64_t pre0 = ((int64_t)blockIdx.x - (nin == 1 ? R.cum_line[1] : R.cum_line[2])[inst]) * NL;
+  const int nl = (int)min((int64_t)NL, I.npre[d - 1] - pre0);
+  const int npair = nin * S;
+  const int lp = npair == 1 ? 0 : (npair == 2 ? 1 : 2);  // log2 npair
+  const int ls = S == 1 ? 0 : 1;                        // log2 S
+  const int LSL = 5 * npair * (n1 / 2);                 // doubles per line: 2.5 npair n1
+  double* M = lds + (int64_t)NL * LSL;
+  double* wsum = M + 64;
+  // row of (line, pair) in each buffer
+  auto Hr = [&](int ln, int pr) { return lds + (int64_t)ln * LSL + pr * n1; };
+  auto SAr = [&](int ln, int pr) { return lds + (int64_t)ln * LSL + (npair + pr) * n1; };
+  auto SBr = [&](int ln, int pr) { return lds + (int64_t)ln * LSL + 2 * npair * n1 + pr * (n1 / 2); };
+  double* xr = a.rws + (int64_t)rhs * rws;
+  const double* __restrict__ EL = R.EL + I.EL_off + (int64_t)N * np1 * K1;  // finest-level cell basis
+  const double* __restrict__ w1 = R.w1 + I.w_off;
+  for (int e = tid; e < 64; e += RX_THREADS) M[e] = R.mats[I.mats_off + e];
+  for (int pr = 0; pr < npair; ++pr) {
+    const int z = pr / S, s = pr - z * S;
+    const double* __restrict__ in = d == 1 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof
+                                           : xr + I.X_off[d - 1] + (((int64_t)z * S + s) * I.npre[d - 1] + pre0) * n1;
+    for (int i = tid; i < nl * n1; i += RX_THREADS) {
+      const int ln = (i / K1) >> N, e = i - ln * n1;
+      Hr(ln, pr)[e] = in[i];
+    }
+  }
+  __syncthreads();
+  // inverse transform, levels 1..N: s_n from s_{n-1} and the level-n wavelets
+  // (s_0 and the wavelets stay in H); s_n goes to SA when N - n is even
+  for (int n = 1; n <= N; ++n) {
+    const int per = K1 << n, half = K1 << (n - 1);
+    const bool toA = ((N - n) & 1) == 0;
+    for (int it = tid; it < npair * nl * per; it += RX_THREADS) {
+      const int pl = (it / K1) >> n, e = it - pl * per;
+      const int pr = pl & (npair - 1), ln = pl >> lp;
+      const double* h = Hr(ln, pr);
+      const double* cur = n == 1 ? h : (toA ? SBr(ln, pr) : SAr(ln, pr));
+      double* nxt = toA ? SAr(ln, pr) : SBr(ln, pr);
+      const int c = e / K1, q = e - c * K1, j = c >> 1;
+      const double* Mq = (c & 1) ? M + 16 : M;
+      const double* Wq = (c & 1) ? M + 48 : M + 32;
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < K1; ++i) acc += Mq[q * K1 + i] * cur[j * K1 + i];
+#pragma unroll
+      for (int p = 0; p < K1; ++p) acc += Wq[p * K1 + q] * h[half + j * K1 + p];
+      nxt[e] = acc;
+    }
+    __syncthreads();
+  }
+  // pointwise map cell by cell: values at the K1 points of finest cell c of
+  // every pair, map, weights, projection onto the cell's K1 functions, into H
+  // of (input 0, species s)
+  const double dt2 = a.dt2;
+  for (int it = tid; it < nl << N; it += RX_THREADS) {
+    const int ln = it >> N, c = it - (ln << N);
+    double pv[2][2][K1];  // [input][species][point]
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        double cc[K1];
+        if (z < nin && s < S) {
+          const double* src = (N == 0 ? Hr(ln, z * S + s) : SAr(ln, z * S + s)) + c * K1;
+#pragma unroll
+          for (int p = 0; p < K1; ++p) cc[p] = src[p];
+        } else {
+#pragma unroll
+          for (int p = 0; p < K1; ++p) cc[p] = 0.0;
+        }
+#pragma unroll
+        for (int gq = 0; gq < K1; ++gq) {
+          const double* e = EL + (int64_t)(c * K1 + gq) * K1;
+          double u = 0.0;
+#pragma unroll
+          for (int p = 0; p < K1; ++p) u += cc[p] * e[p];
+          pv[z][s][gq] = u;
+        }
+      }
+    double ow[2][K1];
+#pragma unroll
+    for (int gq = 0; gq < K1; ++gq) {
+      const double u[2] = {pv[0][0][gq], pv[0][1][gq]};
+      const double g[2] = {pv[1][0][gq], pv[1][1][gq]};
+      double o[2];
+      rx_map(I, mode, dt2, u, g, o);
+      const double wq = w1[c * K1 + gq];
+      ow[0][gq] = wq * o[0];
+      ow[1][gq] = wq * o[1];
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      if (s < S) {
+        double* h = Hr(ln, s) + c * K1;
+#pragma unroll
+        for (int p = 0; p < K1; ++p) {
+          double acc = 0.0;
+#pragma unroll
+          for (int gq = 0; gq < K1; ++gq) acc += ow[s][gq] * EL[(int64_t)(c * K1 + gq) * K1 + p];
+          h[p] = acc;
+        }
+      }
+  }
+  __syncthreads();
+  // forward transform, levels N..1: s_n -> s_{n-1} (H and SB in turn, from H
+  // at level N) and the level-n wavelets (into SA at their final places)
+  for (int n = N; n >= 1; --n) {
+    const int per = K1 << n, half = K1 << (n - 1);
+    const bool fromH = ((N - n) & 1) == 0;
+    for (int it = tid; it < S * nl * per; it += RX_THREADS) {
+      const int pl = (it / K1) >> n, e = it - pl * per;
+      const int s = pl & (S - 1), ln = pl >> ls;
+      const double* cur = fromH ? Hr(ln, s) : SBr(ln, s);
+      const int w = e >= half;
+      const int e2 = e - w * half;
+      const int j = e2 / K1, i = e2 - j * K1;
+      const double* sl = cur + (2 * j) * K1;
+      const double* sr = sl + K1;
+      double acc = 0.0;
+      if (!w) {
+#pragma unroll
+        for (int q = 0; q < K1; ++q) acc += M[q * K1 + i] * sl[q] + M[16 + q * K1 + i] * sr[q];
+        (fromH ? SBr(ln, s) : Hr(ln, s))[e] = acc;
+      } else {
+#pragma unroll
+        for (int q = 0; q < K1; ++q) acc += M[32 + i * K1 + q] * sl[q] + M[48 + i * K1 + q] * sr[q];
+        SAr(ln, s)[e] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  // s_0 is where level 1 (or, for N = 0, the projection) left it
+  const bool s0H = N == 0 || ((N - 1) & 1) == 1;
+  auto coef = [&](int ln, int s, int e) -> double {
+    return e < K1 ? (s0H ? Hr(ln, s) : SBr(ln, s))[e] : SAr(ln, s)[e];
+  };
+  if (d >= 2) {
+    for (int s = 0; s < S; ++s) {
+      double* out = xr + I.Y_off[d - 1] + ((int64_t)s * I.npre[d - 1] + pre0) * n1;
+      for (int i = tid; i < nl * n1; i += RX_THREADS) {
+        const int ln = (i / K1) >> N, e = i - ln * n1;
+        out[i] = coef(ln, s, e);
+      }
+    }
+  } else {
     double g2 = 0.0;
-    ffwt<K1>(b0, b1, N, M, [&](int n, int j, int p, double v) {
-      if (n <= L) g2 += finish(a, mode, base + lb[n] + (int64_t)(j * K1 + p) * Sb, v);
-    });
+    for (int s = 0; s < S; ++s) {
+      const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)s * I.ndof;
+      for (int i = tid; i < n1; i += RX_THREADS) g2 += finish(a, mode, base + i, coef(0, s, i));
+    }
     if (mode == RX_RESID) {
       g2 = block_sum(g2, wsum);
-      if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + f] = g2;
+      if (tid == 0) a.part[(int64_t)rhs * nfin + R.cum_fin[inst]] = g2;
     }
   }
 }
 
-__global__ __launch_bounds__(RX_THREADS_FIB) void k_rx_contract(RTables R, int ninst, int m, int mode, int64_t total,
-                                                                RxArgs a, int64_t rws, int max_n1, int64_t nfin) {
+template <int K1>
+__global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, int ninst, int mode, int64_t total, RxArgs a,
+                                                        int64_t rws, int nin, int64_t nfin) {
   extern __shared__ double lds[];
-  const int inst = find_inst(m == 0 ? R.cum_fin : pick(R.cum_y, m), ninst, blockIdx.x);
-  if (a.conv && a.conv[blockIdx.y * ninst + inst]) return;
-  switch (R.inst[inst].K1) {
-    case 2: rx_contract_body<2>(R, inst, m, mode, total, a, rws, max_n1, nfin, lds); break;
-    case 3: rx_contract_body<3>(R, inst, m, mode, total, a, rws, max_n1, nfin, lds); break;
-    default: rx_contract_body<4>(R, inst, m, mode, total, a, rws, max_n1, nfin, lds); break;
-  }
-}
-
-static sgdg_status set_lds_attrs(const RHost* rh) {
-  size_t lmax = 0;
-  for (int nin = 1; nin <= 2; ++nin) lmax = std::max(lmax, line_lds_bytes(rh, line_groups_max(rh, nin), nin));
-  hipError_t e = hipFuncSetAttribute((const void*)k_rx_line, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lmax);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_rx_expand, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)expand_lds_bytes(rh));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_rx_contract, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)contract_lds_bytes(rh));
-  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(reaction kernels LDS)");
-  return SGDG_OK;
+  const int inst = find_inst(nin == 1 ? R.cum_line[1] : R.cum_line[2], ninst, blockIdx.x);
+  if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
+  rx_line_body<K1>(R, inst, mode, total, a, rws, nin, nfin, lds);
 }
 
 void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s) {
   const RHost* rh = (const RHost*)plan->rdata;
   const int d = plan->d, ninst = plan->ninst;
   const int nin = mode == RX_CORR ? 2 : 1;
-  const int ngrp = std::min(line_groups(rh, rh->cum_line.back() * nrhs, nin), line_groups_max(rh, nin));
-  const size_t el = expand_lds_bytes(rh), cl = contract_lds_bytes(rh), ll = line_lds_bytes(rh, ngrp, nin);
   const int64_t nfin = rh->cum_fin.back();
+  const size_t ll = rh->line_lds[nin];
+  // every degree present in the plan gets its own launch of each stage
+  auto each = [&](auto launch) {
+    if (rh->k1mask & 4) launch(std::integral_constant<int, 2>());
+    if (rh->k1mask & 8) launch(std::integral_constant<int, 3>());
+    if (rh->k1mask & 16) launch(std::integral_constant<int, 4>());
+  };
   for (int m = 0; m + 1 <= d - 1; ++m)
-    hipLaunchKernelGGL(k_rx_expand, dim3((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin),
-                       dim3(RX_THREADS_FIB), el, s, rh->dev, ninst, m, plan->total, a, rh->rws, rh->max_n1);
-  hipLaunchKernelGGL(k_rx_line, dim3((unsigned)rh->cum_line.back(), (unsigned)nrhs), dim3(RX_THREADS_LINE), ll, s, rh->dev,
-                     ninst, (int)mode, plan->total, a, rh->rws, rh->max_n1, rh->max_np1, nfin, ngrp);
-  for (int m = d - 2; m >= 0; --m) {
-    const int64_t nf = m == 0 ? nfin : rh->cum_y[m].back();
-    hipLaunchKernelGGL(k_rx_contract, dim3((unsigned)nf, (unsigned)nrhs), dim3(RX_THREADS_FIB), cl, s, rh->dev, ninst, m,
-                       (int)mode, plan->total, a, rh->rws, rh->max_n1, nfin);
-  }
+    each([&](auto k1) {
+      hipLaunchKernelGGL(k_rx_expand<decltype(k1)::value>,
+                         dim3((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin), dim3(RX_THREADS), 0, s,
+                         rh->dev, (const double*)rh->dev.EH, ninst, m, plan->total, a, rh->rws, rh->lam[m]);
+    });
+  each([&](auto k1) {
+    hipLaunchKernelGGL(k_rx_line<decltype(k1)::value>, dim3((unsigned)rh->cum_line[nin].back(), (unsigned)nrhs),
+                       dim3(RX_THREADS), ll, s, rh->dev, ninst, (int)mode, plan->total, a, rh->rws, nin, nfin);
+  });
+  for (int m = d - 2; m >= 0; --m)
+    each([&](auto k1) {
+      hipLaunchKernelGGL(k_rx_contract<decltype(k1)::value>, dim3((unsigned)rh->cum_x[m].back(), (unsigned)nrhs),
+                         dim3(RX_THREADS), 0, s, rh->dev, (const double*)rh->dev.EH, (const double*)rh->dev.w1, ninst,
+                         m, (int)mode, plan->total, a, rh->rws, rh->lam[m], nfin);
+    });
+}
+
+static sgdg_status set_line_lds(const RHost* rh) {
+  const int ll = (int)std::max(rh->line_lds[1], rh->line_lds[2]);
+  hipError_t e = hipFuncSetAttribute((const void*)k_rx_line<2>, hipFuncAttributeMaxDynamicSharedMemorySize, ll);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_rx_line<3>, hipFuncAttributeMaxDynamicSharedMemorySize, ll);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_rx_line<4>, hipFuncAttributeMaxDynamicSharedMemorySize, ll);
+  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(reaction line kernel LDS)");
+  return SGDG_OK;
 }
 
 }  // namespace sgdg

@@ -40,3 +40,11 @@ def bf16_bits(a):
 
     t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16)
     return t.view(torch.int16).numpy().view(np.uint16), t.to(torch.float64).numpy()
+
+
+def note(label, err, tol, scale=None):
+    """Print a parity margin: the error, its tolerance, their ratio and (given
+    the norm of the input) the error relative to that norm, so that a run's log
+    shows how close each case runs to its bound."""
+    rel = "" if scale is None else f" rel {err / max(scale, 1e-300):.3e}"
+    print(f"[parity] {label}: err {err:.3e} tol {tol:.3e} ratio {err / max(tol, 1e-300):.4f}{rel}", flush=True)

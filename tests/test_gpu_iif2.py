@@ -15,7 +15,7 @@ import pytest
 from oracle import iif, project, reaction
 from paper_1810_11111_amd import inputs as I
 
-from _gpu_common import lib, say, to_dev
+from _gpu_common import lib, note, say, to_dev
 
 pytestmark = pytest.mark.gpu
 U_RND = 2.0 ** -53
@@ -216,6 +216,7 @@ def test_iif2_matches_oracle(name, kw, steps):
         vnorm = np.linalg.norm(U0[s]) + np.linalg.norm(Ur[s])
         tol = _step_tol(inst, wl.dt, vnorm, s, steps, prob.anorm[s])
         err = np.linalg.norm(Ug[s] - Ur[s])
+        note(f"species {s}", err, tol)
         assert err <= tol, f"species {s}: err {err:.3e} > {tol:.3e}"
         assert st[s]["status"] == 0 and st[s]["krylov_m"] == infos[-1]["krylov"][s]["m"]
     # the same number of corrections as the oracle (up to one near the threshold)
@@ -248,6 +249,7 @@ def test_iif2_cubic_degree_and_high_dimension(d, N, k, rx, D, dt, M):
         vnorm = np.linalg.norm(U0[s]) + np.linalg.norm(Ur[s])
         tol = _step_tol(inst, dt, vnorm, s, steps, prob.anorm[s])
         err = np.linalg.norm(Ug[s] - Ur[s])
+        note(f"species {s}", err, tol)
         assert err <= tol, f"species {s}: err {err:.3e} > {tol:.3e}"
         assert st[s]["status"] == 0 and st[s]["krylov_m"] == infos[-1]["krylov"][s]["m"]
     assert abs(int(st[0]["newton_iters"]) - infos[-1]["iters"]) <= 1
@@ -270,6 +272,7 @@ def test_iif2_reduced_precision_stated_error(prec, tol):
     Ug = Ug.reshape(inst.species, nd)
     for s in range(inst.species):
         err = np.linalg.norm(Ug[s] - Ur[s]) / np.linalg.norm(Ur[s])
+        note(f"{prec} species {s}", err, tol)
         assert err <= tol, f"{prec} species {s}: rel L2 err {err:.3e} > {tol:.1e}"
         assert st[s]["status"] == 0
 
@@ -374,6 +377,7 @@ def test_iif2_two_species_instances_and_rhs():
                 vnorm = np.linalg.norm(Ui[s]) + np.linalg.norm(Ur[s])
                 tol = _step_tol(inst, dt, vnorm, s, steps, prob.anorm[s])
                 err = np.linalg.norm(Gi[s] - Ur[s])
+                note(f"rhs {rh} inst {i} species {s}", err, tol)
                 assert err <= tol, f"rhs {rh} inst {i} species {s}: err {err:.3e} > {tol:.3e}"
                 e = st[(rh * len(insts) + i) * 2 + s]
                 assert e["status"] == 0 and e["krylov_m"] == infos[-1]["krylov"][s]["m"], (rh, i, s)
@@ -479,6 +483,7 @@ def test_iif3_matches_oracle(name, kw, steps):
         vnorm = np.linalg.norm(U0[s]) + np.linalg.norm(Ur[s])
         tol = _step_tol(inst, 2 * wl.dt, vnorm, s, steps, prob.anorm[s])
         err = np.linalg.norm(Ug[s] - Ur[s])
+        note(f"species {s}", err, tol)
         assert err <= tol, f"species {s}: err {err:.3e} > {tol:.3e}"
         assert st[s]["status"] == 0 and st[s]["krylov_m"] == infos[-1]["krylov"][s]["m"]
         ftol = tol * max(1.0, np.abs(Fr[s]).max() / max(np.abs(Ur[s]).max(), 1e-300)) * 10
@@ -522,6 +527,7 @@ def test_iif3_two_species_instances_and_rhs():
                 vnorm = np.linalg.norm(Ui[s]) + np.linalg.norm(Ur[s])
                 tol = _step_tol(inst, 2 * dt, vnorm, s, steps, prob.anorm[s])
                 err = np.linalg.norm(Gi[s] - Ur[s])
+                note(f"rhs {rh} inst {i} species {s}", err, tol)
                 assert err <= tol, f"rhs {rh} inst {i} species {s}: err {err:.3e} > {tol:.3e}"
                 e = stats[(rh * len(insts) + i) * 2 + s]
                 assert e["status"] == 0 and e["krylov_m"] == infos[-1]["krylov"][s]["m"], (rh, i, s)
@@ -780,6 +786,7 @@ def test_local_stage_two_species_instances_and_rhs():
             for s in range(2):
                 tol = _step_tol(inst, dt, np.linalg.norm(Ui[s]) + np.linalg.norm(Ur[s]), s, steps, prob.anorm[s])
                 err = np.linalg.norm(Gi[s] - Ur[s])
+                note(f"rhs {rh} inst {i} species {s}", err, tol)
                 assert err <= tol, f"rhs {rh} inst {i} species {s}: err {err:.3e} > {tol:.3e}"
                 assert stats[(rh * len(insts) + i) * 2 + s]["status"] == 0, (rh, i, s)
 

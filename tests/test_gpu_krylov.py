@@ -19,7 +19,7 @@ import pytest
 from oracle import krylov, operator, project
 from paper_1810_11111_amd import inputs as I
 
-from _gpu_common import lib, say, to_dev
+from _gpu_common import lib, note, say, to_dev
 
 pytestmark = pytest.mark.gpu
 U = 2.0 ** -53
@@ -67,6 +67,7 @@ def _compare(plan, insts, h, M, V, W, stats, tol_fn, nrhs=1):
                 err = np.linalg.norm(W[r, seg] - ref) / max(np.linalg.norm(V[r, seg]), 1e-300)
                 tol = tol_fn(h, an)
                 worst = max(worst, err / tol)
+                note(f"expv rhs {r} inst {i} species {s}", err, tol)
                 assert err <= tol, f"rhs {r} inst {i} species {s}: rel err {err:.3e} > {tol:.3e}"
                 st = stats[(r * len(insts) + i) * 2 + s]
                 assert st["krylov_m"] == info["m"], (st["krylov_m"], info["m"])
