@@ -28,8 +28,6 @@ struct RInst {
   int32_t id_off[SGDG_MAX_D + 1];   // into rid: (N+1)^r entries, -1 if |l|_1 > N
   int32_t ntile[SGDG_MAX_D];        // fibre tiles of stage m per (species, prefix)
   int64_t be_off[SGDG_MAX_D + 1];   // into rbe: block (index in the r-dim grid) of every element
-  int32_t nl[3];                    // lines per tile of the last-axis kernel, by number of inputs (1, 2)
-  int32_t pad2;
   int64_t gdof[SGDG_MAX_D + 1];     // DOFs of the r-dim grid
   int64_t npre[SGDG_MAX_D + 1];     // np1^m
   int64_t X_off[SGDG_MAX_D];        // per-rhs workspace offsets (doubles) of expansion outputs, m = 1..d-1
@@ -47,17 +45,33 @@ struct RTables {
   double* w1 = nullptr;
   double* mats = nullptr;
   int64_t* cum_x[SGDG_MAX_D] = {};  // fibre tiles of stage m per instance (prefix sums, ninst+1)
-  int64_t* cum_line[3] = {};        // line tiles of the last axis, by number of inputs
   int64_t* cum_fin = nullptr;       // workgroups of the final stage (partial residual sums)
+};
+
+// A tile of the last-axis kernel: nl consecutive lines from prefix pre0 of one instance.
+struct LineTask {
+  int32_t inst, nl;
+  int64_t pre0;
+};
+
+// Instances of the same degree, level and species count share one LDS layout
+// of the last-axis kernel and one launch (by number of inputs 1, 2).
+struct LineClass {
+  int K1 = 0, N = 0, S = 0;
+  std::vector<LineTask> tasks[3];
+  LineTask* dev[3] = {};
+  size_t lds[3] = {};  // dynamic LDS bytes
+  int threads[3] = {}; // workgroup size
 };
 
 struct RHost {
   RTables dev;
   std::vector<std::vector<int64_t>> cum_x;
-  std::vector<int64_t> cum_line[3], cum_fin;
-  int lam[SGDG_MAX_D] = {};  // stage m splits each fibre's points into 2^lam chunks (lam <= 2)
+  std::vector<int64_t> cum_fin;
+  std::vector<LineClass> lclass;
+  int lam[SGDG_MAX_D] = {};    // stage m splits each fibre's points into 2^lam chunks (lam <= 8)
+  int llane[SGDG_MAX_D] = {};  // of which the low llane chunk bits are lane bits (lam - llane <= 2)
   int64_t rws = 0;           // doubles of reaction workspace per right-hand side
-  size_t line_lds[3] = {};   // LDS bytes of the last-axis kernel, by number of inputs
   int max_n1 = 0, max_np1 = 0;
   int k1mask = 0;  // bit K1 set when an instance has degree K1 - 1
   int ncu = 0;  // compute units of the plan's device

@@ -91,13 +91,17 @@ constexpr int rx_levels() {
   return K1 == 2 ? 11 : 10;
 }
 constexpr int RX_LINE_LDS = 32 * 1024; // LDS budget of a line tile (several tiles per compute unit)
-constexpr int RX_TAIL = 64 + 16;       // two-scale matrices + per-wave partial sums
+constexpr int RX_ITEMS = 2;            // transform items per thread of a line tile at the finest level
+constexpr int RX_TAIL = 64 + 32 + 8;   // two-scale matrices, reaction coefficients, per-wave partial sums
 constexpr int64_t RX_THREADS_WANTED = 1 << 17;
+constexpr int RX_WALK = 64;  // most points one thread of an expansion / contraction walks
 
 // LDS of the last-axis kernel: per line 2.5 npair n1 doubles (inputs, and the
 // two scaling buffers of the transforms), plus the tail
 static int64_t line_doubles(int npair, int n1) { return (int64_t)5 * npair * (n1 / 2); }
-static size_t line_tile_doubles(int npair, int nl, int n1) { return (size_t)line_doubles(npair, n1) * nl + RX_TAIL; }
+static size_t line_tile_doubles(int npair, int nl, int n1, int K1) {
+  return (size_t)line_doubles(npair, n1) * nl + RX_TAIL + (size_t)n1 * (K1 + 1);
+}
 static sgdg_status set_line_lds(const RHost* rh);
 
 sgdg_status reaction_build(sgdg_plan* plan) {
@@ -111,7 +115,7 @@ sgdg_status reaction_build(sgdg_plan* plan) {
   // buffers in LDS during the implicit-stage correction: (k+1) 2^N <= 1024.
   for (const HostInstance& hi : plan->inst) {
     const int n1 = (hi.desc.k + 1) << hi.desc.n;
-    const size_t need = line_tile_doubles(2 * hi.desc.nspecies, 1, n1) * sizeof(double);
+    const size_t need = line_tile_doubles(2 * hi.desc.nspecies, 1, n1, hi.desc.k + 1) * sizeof(double);
     if (n1 > RX_MAX_N1 || need > (size_t)APPLY_LDS_BYTES_HOST) {
       rh->supported = false;
       return SGDG_OK;
@@ -126,6 +130,8 @@ sgdg_status reaction_build(sgdg_plan* plan) {
   // wider than the smallest fibre set of the plan
   int nmin = 1 << 30;
   for (const HostInstance& hi : plan->inst) nmin = std::min(nmin, hi.desc.n);
+  int maxnp1 = 0;
+  for (const HostInstance& hi : plan->inst) maxnp1 = std::max(maxnp1, (hi.desc.k + 1) << hi.desc.n);
   for (int m = 0; m + 1 <= d - 1; ++m) {
     int64_t nf = 0, gmin = INT64_MAX;
     for (const HostInstance& hi : plan->inst) {
@@ -142,12 +148,19 @@ sgdg_status reaction_build(sgdg_plan* plan) {
       nf += hi.desc.nspecies * pre * g;
       gmin = std::min(gmin, g);
     }
+    // 2^lam chunks per fibre: enough threads to fill the device, at most
+    // RX_WALK points per thread, tiles no wider than the smallest fibre set;
+    // the first two chunk bits go to waves (wave-uniform point index), the
+    // rest to lanes
     int lam = 0;
-    while (lam < std::min(2, nmin) && ((RX_THREADS >> lam) > gmin || (nf << lam) < RX_THREADS_WANTED)) ++lam;
+    const int lmax = std::min(8, nmin);
+    while (lam < lmax && ((nf << lam) < RX_THREADS_WANTED || (maxnp1 >> lam) > RX_WALK ||
+                          (RX_THREADS >> lam) > gmin))
+      ++lam;
     rh->lam[m] = lam;
+    rh->llane[m] = std::max(0, lam - 2);
   }
   rh->cum_x.assign(d, std::vector<int64_t>(1, 0));
-  for (int z = 1; z <= 2; ++z) rh->cum_line[z].assign(1, 0);
   rh->cum_fin.assign(1, 0);
   for (int i = 0; i < plan->ninst; ++i) {
     const HostInstance& hi = plan->inst[i];
@@ -251,15 +264,32 @@ sgdg_status reaction_build(sgdg_plan* plan) {
       r.ntile[m] = (int32_t)((r.gdof[d - m - 1] + tw - 1) / tw);
       rh->cum_x[m].push_back(rh->cum_x[m].back() + (int64_t)S * r.npre[m] * r.ntile[m]);
     }
-    // line tiles: as many whole lines as the LDS budget and the per-thread
-    // item bound of the in-place transforms allow
-    for (int nin = 1; nin <= 2; ++nin) {
-      const int npair = nin * S;
-      int64_t nl = (int64_t)RX_LINE_LDS / (line_doubles(npair, r.n1) * 8);
-      nl = std::max<int64_t>(1, std::min<int64_t>(nl, r.npre[d - 1]));
-      r.nl[nin] = (int32_t)nl;
-      rh->cum_line[nin].push_back(rh->cum_line[nin].back() + (r.npre[d - 1] + nl - 1) / nl);
-      rh->line_lds[nin] = std::max(rh->line_lds[nin], line_tile_doubles(npair, (int)nl, r.n1) * sizeof(double));
+    // line tiles: instances of the same (degree, level, species) form one
+    // class, one LDS layout and one launch
+    {
+      LineClass* lc = nullptr;
+      for (LineClass& c : rh->lclass)
+        if (c.K1 == K1 && c.N == N && c.S == S) lc = &c;
+      if (!lc) {
+        rh->lclass.emplace_back();
+        lc = &rh->lclass.back();
+        lc->K1 = K1;
+        lc->N = N;
+        lc->S = S;
+      }
+      for (int nin = 1; nin <= 2; ++nin) {
+        // lines per tile: the LDS budget of one workgroup; threads: about
+        // RX_ITEMS transform items each at the finest level, 64..256
+        const int npair = nin * S;
+        int64_t nl = ((int64_t)RX_LINE_LDS / 8 - RX_TAIL - (int64_t)r.n1 * (K1 + 1)) / line_doubles(npair, r.n1);
+        nl = std::max<int64_t>(1, std::min<int64_t>(nl, r.npre[d - 1]));
+        int th = 64;
+        while (th < RX_THREADS && (int64_t)npair * nl * r.n1 > (int64_t)th * RX_ITEMS) th *= 2;
+        for (int64_t p0 = 0; p0 < r.npre[d - 1]; p0 += nl)
+          lc->tasks[nin].push_back(LineTask{i, (int32_t)std::min<int64_t>(nl, r.npre[d - 1] - p0), p0});
+        lc->lds[nin] = std::max(lc->lds[nin], line_tile_doubles(npair, (int)nl, r.n1, K1) * sizeof(double));
+        lc->threads[nin] = std::max(lc->threads[nin], th);
+      }
     }
     rh->cum_fin.push_back(rh->cum_fin.back() + (d >= 2 ? (int64_t)S * r.ntile[0] : 1));
     ri.push_back(r);
@@ -270,12 +300,14 @@ sgdg_status reaction_build(sgdg_plan* plan) {
       (st = up(plan, rid, &rh->dev.rid)) != SGDG_OK || (st = up(plan, rbe, &rh->dev.rbe)) != SGDG_OK ||
       (st = up(plan, EL, &rh->dev.EL)) != SGDG_OK || (st = up(plan, EH, &rh->dev.EH)) != SGDG_OK ||
       (st = up(plan, w1, &rh->dev.w1)) != SGDG_OK || (st = up(plan, mats, &rh->dev.mats)) != SGDG_OK ||
-      (st = up(plan, rh->cum_line[1], &rh->dev.cum_line[1])) != SGDG_OK ||
-      (st = up(plan, rh->cum_line[2], &rh->dev.cum_line[2])) != SGDG_OK ||
       (st = up(plan, rh->cum_fin, &rh->dev.cum_fin)) != SGDG_OK)
     return st;
   for (int m = 0; m + 1 <= d - 1; ++m)
     if ((st = up(plan, rh->cum_x[m], &rh->dev.cum_x[m])) != SGDG_OK) return st;
+  for (LineClass& lc : rh->lclass)
+    for (int nin = 1; nin <= 2; ++nin) {
+      if ((st = up(plan, lc.tasks[nin], &lc.dev[nin])) != SGDG_OK) return st;
+    }
   if (hipDeviceGetAttribute(&rh->ncu, hipDeviceAttributeMultiprocessorCount, plan->device) != hipSuccess) {
     rh->ncu = 0;
     (void)hipGetLastError();
@@ -364,12 +396,11 @@ __device__ __forceinline__ void rx_jac(const double (*c)[4][4], int S, const dou
 
 // The pointwise map of a pass at one point: u[s] = R U (mode RX_CORR also
 // g[s] = R G); returns the values to project (before the quadrature weight).
-__device__ __forceinline__ void rx_map(const RInst& I, int mode, double dt2, const double* u, const double* g,
-                                       double* out) {
-  const int S = I.S;
+__device__ __forceinline__ void rx_map(const double (*rx)[4][4], int S, int mode, double dt2, const double* u,
+                                       const double* g, double* out) {
   if (mode == RX_CORR) {
     double J[2][2];
-    rx_jac(I.rx, S, u, J);
+    rx_jac(rx, S, u, J);
     if (S == 1) {
       out[0] = g[0] / (1.0 - dt2 * J[0][0]);
       out[1] = 0.0;
@@ -387,11 +418,11 @@ __device__ __forceinline__ void rx_map(const RInst& I, int mode, double dt2, con
     double x[2] = {w0, w1v};
     for (int it = 0; it <= RX_LOCAL_MAX_ITER; ++it) {
       double f[2];
-      rx_f(I.rx, S, x, f);
+      rx_f(rx, S, x, f);
       const double g0 = x[0] - dt2 * f[0] - w0, g1 = S > 1 ? x[1] - dt2 * f[1] - w1v : 0.0;
       if (fmax(fabs(g0), fabs(g1)) <= RX_LOCAL_TOL * wmag || it == RX_LOCAL_MAX_ITER) break;
       double J[2][2];
-      rx_jac(I.rx, S, x, J);
+      rx_jac(rx, S, x, J);
       if (S == 1) {
         x[0] -= g0 / (1.0 - dt2 * J[0][0]);
       } else {
@@ -405,7 +436,7 @@ __device__ __forceinline__ void rx_map(const RInst& I, int mode, double dt2, con
     out[0] = x[0];
     out[1] = x[1];
   } else {
-    rx_f(I.rx, S, u, out);
+    rx_f(rx, S, u, out);
   }
 }
 
@@ -475,19 +506,24 @@ __device__ __forceinline__ Fibre<LM> fibre_geometry(const RTables& R, const RIns
 
 // ---------------------------------------------------------------- kernels
 
-// Tile of stage m: (species, prefix, tile of 256 >> lam fibres).  Every
-// wave holds 64 consecutive fibres and one chunk of their points (2^lam
-// chunks, lam <= 2, all in the workgroup), so the point index -- and with it
-// every basis-table and weight address -- is the same across the wave.
+// Tile of stage m: (species, prefix, tile of 256 >> lam fibres), each fibre's
+// points cut into 2^lam chunks.  The low ll chunk bits are lane bits (a wave
+// holds 64 >> ll fibres times 2^ll chunks), the others wave bits (waves of
+// the workgroup).  Without lane bits every wave holds 64 consecutive fibres
+// and one chunk, so the point index -- and with it every basis-table and
+// weight address -- is the same across the wave (LANES = false).
 struct TileIdx {
   int s;
   int64_t pre;
   int64_t eo;  // this thread's fibre
-  int qc;      // its chunk of points (wave-uniform)
-  int fb;      // its wave's block of 64 fibres
+  int qc;      // its chunk of points: (wave chunk << ll) | lane chunk
+  int wc, lc;  // wave and lane chunk
+  int fb;      // its wave's block of fibres
+  int fpw;     // fibres per wave
 };
 
-__device__ __forceinline__ TileIdx tile_index(const RInst& I, int m, int64_t le, int lam) {
+template <bool LANES>
+__device__ __forceinline__ TileIdx tile_index(const RInst& I, int m, int64_t le, int lam, int ll) {
   TileIdx t;
   const int ntile = I.ntile[m];
   const int64_t per_s = I.npre[m] * ntile;
@@ -495,21 +531,32 @@ __device__ __forceinline__ TileIdx tile_index(const RInst& I, int m, int64_t le,
   le -= (int64_t)t.s * per_s;
   t.pre = le / ntile;
   const int tt = (int)(le - t.pre * ntile);
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  t.qc = w >> (2 - lam);
-  t.fb = w & ((4 >> lam) - 1);
-  t.eo = (int64_t)tt * (RX_THREADS >> lam) + t.fb * 64 + (threadIdx.x & 63);
+  const int lw = LANES ? lam - ll : lam;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
+  t.wc = w >> (2 - lw);
+  t.fb = w & ((4 >> lw) - 1);
+  if (LANES) {
+    t.fpw = 64 >> ll;
+    t.lc = ln >> (6 - ll);
+    t.qc = (t.wc << ll) | t.lc;
+    t.eo = (int64_t)tt * (RX_THREADS >> lam) + t.fb * t.fpw + (ln & (t.fpw - 1));
+  } else {
+    t.fpw = 64;
+    t.lc = 0;
+    t.qc = t.wc;
+    t.eo = (int64_t)tt * (RX_THREADS >> lam) + t.fb * 64 + ln;
+  }
   return t;
 }
 
 // expansion stage m: hierarchical along axis m -> point values, grid (tiles, rhs, input)
-template <int K1>
+template <int K1, bool LANES>
 __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg, int inst, int m, int64_t total,
-                               const RxArgs& a, int64_t rws, int lam) {
+                               const RxArgs& a, int64_t rws, int lam, int ll) {
   const RInst& I = R.inst[inst];
   const int z = blockIdx.z, rhs = blockIdx.y;
   const int d = I.d, r = d - m, N = I.N, S = I.S, np1 = I.np1;
-  const TileIdx t = tile_index(I, m, (int64_t)blockIdx.x - pick(R.cum_x, m)[inst], lam);
+  const TileIdx t = tile_index<LANES>(I, m, (int64_t)blockIdx.x - pick(R.cum_x, m)[inst], lam, ll);
   const int64_t gd_in = I.gdof[r], gd_out = I.gdof[r - 1];
   if (t.eo >= gd_out) return;
   constexpr int LM = rx_levels<K1>();
@@ -570,20 +617,20 @@ __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg,
 // of another degree return at once
 // (the basis table is its own argument: its loads are wave-uniform and go
 // through the scalar cache)
-template <int K1>
+template <int K1, bool LANES>
 __global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, const double* __restrict__ EHg, int ninst, int m,
-                                                          int64_t total, RxArgs a, int64_t rws, int lam) {
+                                                          int64_t total, RxArgs a, int64_t rws, int lam, int ll) {
   const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
   if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
-  rx_expand_body<K1>(R, EHg, inst, m, total, a, rws, lam);
+  rx_expand_body<K1, LANES>(R, EHg, inst, m, total, a, rws, lam, ll);
 }
 
 // contraction stage m: weighted point values along axis m -> hierarchical
 // (m >= 1 writes Y_m; m == 0 finishes plan vectors), grid (tiles, rhs)
-template <int K1>
+template <int K1, bool LANES>
 __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EHg, const double* __restrict__ w1g,
                                  int inst, int m, int mode, int64_t total, const RxArgs& a, int64_t rws, int lam,
-                                 int64_t nfin) {
+                                 int ll, int64_t nfin) {
   // partial sums of the levels whose cells span several chunks: [wave][level <= 2][p][lane]
   __shared__ double red[4][3][K1][64];
   __shared__ double wsum[RX_THREADS / 64];
@@ -591,8 +638,9 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
   const int rhs = blockIdx.y, ln = threadIdx.x & 63;
   const int d = I.d, r = d - m, N = I.N, np1 = I.np1;
   const int64_t le = (int64_t)blockIdx.x - pick(R.cum_x, m)[inst];
-  const TileIdx t = tile_index(I, m, le, lam);
-  const int w = t.qc * (4 >> lam) + t.fb;
+  const TileIdx t = tile_index<LANES>(I, m, le, lam, ll);
+  const int lw = LANES ? lam - ll : lam;
+  const int w = t.wc * (4 >> lw) + t.fb;
   const int64_t gd_in = I.gdof[r - 1], gd_out = I.gdof[r];
   // every thread passes the barriers; threads past the fibre set carry zeros
   // and emit nothing
@@ -621,145 +669,194 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
   for (int l = 0; l < LM; ++l)
 #pragma unroll
     for (int p = 0; p < K1; ++p) acc[l][p] = 0.0;
-  for (int c = c0; c < c0 + cw; ++c) {
+  // the point values of CB cells are loaded together ahead of their use
+  constexpr int CB = LANES ? 1 : (K1 == 2 ? 4 : 2);
+  for (int cb = c0; cb < c0 + cw; cb += CB) {
+    double gv[CB][K1];
 #pragma unroll
-    for (int gq = 0; gq < K1; ++gq) {
-      const int q = c * K1 + gq;
-      const double* __restrict__ eh = EH + (int64_t)q * NL1 * K1;
-      const double g = valid ? w1[q] * in[(int64_t)q * gd_in] : 0.0;
+    for (int b = 0; b < CB; ++b)
 #pragma unroll
-      for (int l = 0; l < LM; ++l)
-        if (l <= N)
+      for (int gq = 0; gq < K1; ++gq) {
+        const int q = (cb + b) * K1 + gq;
+        gv[b][gq] = valid && cb + b < c0 + cw ? in[(int64_t)q * gd_in] : 0.0;
+      }
 #pragma unroll
-          for (int p = 0; p < K1; ++p) acc[l][p] += eh[l * K1 + p] * g;  // (unused past the fibre's budget)
+    for (int b = 0; b < CB; ++b) {
+      const int c = cb + b;
+      if (c >= c0 + cw) continue;
+#pragma unroll
+      for (int gq = 0; gq < K1; ++gq) {
+        const int q = c * K1 + gq;
+        const double* __restrict__ eh = EH + (int64_t)q * NL1 * K1;
+        const double g = w1[q] * gv[b][gq];
+#pragma unroll
+        for (int l = 0; l < LM; ++l)
+          if (l <= N)
+#pragma unroll
+            for (int p = 0; p < K1; ++p) acc[l][p] += eh[l * K1 + p] * g;  // (unused past the fibre's budget)
+      }
+      // levels whose cells lie inside one chunk: a cell is complete when the walk leaves it
+#pragma unroll
+      for (int l = 1; l < LM; ++l)
+        if (l > lam && l <= L && ((c + 1) & ((1 << (N - l + 1)) - 1)) == 0) {
+#pragma unroll
+          for (int p = 0; p < K1; ++p) {
+            emit(l, c >> (N - l + 1), p, acc[l][p]);
+            acc[l][p] = 0.0;
+          }
+        }
     }
-    // levels whose cells lie inside one chunk: a cell is complete when the walk leaves it
+  }
+  // coarser levels span 2^g chunks, g = lam - l + 1 (level 0: g = lam):
+  // fixed-order butterfly over the lane bits of the chunk, then the wave of
+  // the first chunk adds the waves' sums in order
+  const int llv = LANES ? ll : 0;
+  if (LANES) {
 #pragma unroll
-    for (int l = 1; l < LM; ++l)
-      if (l > lam && l <= L && ((c + 1) & ((1 << (N - l + 1)) - 1)) == 0) {
+    for (int l = 0; l < LM; ++l)
+      if (l <= lam) {
+        const int gl = min(l == 0 ? lam : lam - l + 1, llv);
 #pragma unroll
         for (int p = 0; p < K1; ++p) {
-          emit(l, c >> (N - l + 1), p, acc[l][p]);
-          acc[l][p] = 0.0;
+          double v = acc[l][p];
+          for (int b = 0; b < gl; ++b) v += __shfl_xor(v, t.fpw << b, 64);
+          acc[l][p] = v;
         }
       }
   }
-  // coarser levels span 2^(lam-l+1) chunks (level 0 all of them): the wave of
-  // the first chunk of each cell adds the chunks' partial sums in order
-  if (lam > 0) {
+  if (lw > 0) {
 #pragma unroll
     for (int l = 0; l < 3; ++l)
-      if (l <= lam)
+      if (l <= lw)
 #pragma unroll
         for (int p = 0; p < K1; ++p) red[w][l][p][ln] = acc[l][p];
     __syncthreads();
+  }
+  constexpr int LR = LANES ? LM : 3;  // levels that can span chunks (lam <= 2 without lane bits)
 #pragma unroll
-    for (int l = 0; l < 3; ++l)
-      if (l <= lam) {
-        const int gb = l == 0 ? lam : lam - l + 1;  // log2 of the chunks per cell
-        if (l <= L && (t.qc & ((1 << gb) - 1)) == 0) {
-          const int j = l == 0 ? 0 : t.qc >> gb;
+  for (int l = 0; l < LR; ++l)
+    if (l <= lam) {
+      const int g = l == 0 ? lam : lam - l + 1;  // log2 of the chunks per cell
+      const int gl = min(g, llv), gw = g - gl;
+      if (l <= L && (t.lc & ((1 << gl) - 1)) == 0 && (t.wc & ((1 << gw) - 1)) == 0) {
+        const int j = l == 0 ? 0 : t.qc >> g;
 #pragma unroll
-          for (int p = 0; p < K1; ++p) {
-            double v = 0.0;
-            for (int cc = 0; cc < (1 << gb); ++cc) v += red[(t.qc + cc) * (4 >> lam) + t.fb][l][p][ln];
-            emit(l, j, p, v);
+        for (int p = 0; p < K1; ++p) {
+          double v = acc[l][p];
+          if (gw > 0 && l < 3) {
+            v = 0.0;
+            for (int cc = 0; cc < (1 << gw); ++cc) v += red[(t.wc + cc) * (4 >> lw) + t.fb][l][p][ln];
           }
+          emit(l, j, p, v);
         }
       }
-  } else {
-#pragma unroll
-    for (int p = 0; p < K1; ++p)
-      if (L >= 0) emit(0, 0, p, acc[0][p]);
-  }
+    }
   if (m == 0 && mode == RX_RESID) {
     g2 = block_sum(g2, wsum);
     if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + blockIdx.x] = g2;
   }
 }
 
-template <int K1>
+template <int K1, bool LANES>
 __global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, const double* __restrict__ EHg,
                                                             const double* __restrict__ w1g, int ninst, int m, int mode,
-                                                            int64_t total, RxArgs a, int64_t rws, int lam,
+                                                            int64_t total, RxArgs a, int64_t rws, int lam, int ll,
                                                             int64_t nfin) {
   const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
   if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
-  rx_contract_body<K1>(R, EHg, w1g, inst, m, mode, total, a, rws, lam, nfin);
+  rx_contract_body<K1, LANES>(R, EHg, w1g, inst, m, mode, total, a, rws, lam, ll, nfin);
 }
 
-// Last axis: a tile of nl whole lines (consecutive prefixes).  LDS per line,
-// pair = input * S + species (npair = 1, 2 or 4):
+// Last axis: a tile of nl whole lines (consecutive prefixes).  LDS: the
+// two-scale matrices, the reaction coefficients, the finest-cell basis at the
+// Gauss points and the weights, then per line (pair = input * S + species,
+// npair = 1, 2 or 4):
 //   H [pair][n1]     the hierarchical inputs; later the projections and one
 //                    of the two scaling buffers of the forward transform
-//   SA[pair][n1]     level-n cell coefficients of the inverse transform (n = N, N-2, ..);
-//                    later the wavelets of the forward transform
-//   SB[pair][n1/2]   level-n cell coefficients for n = N-1, N-3, ..
-// Every transform level is one barrier step over all lines of the tile
-// (ping-pong between the buffers, the wavelets read from / written to their
-// own places).  For d = 1 the line is the instance itself, read from and
-// finished into plan vectors.
+//   SA[pair][n1]     cell coefficients of the inverse transform (the last step
+//                    writes the finest level here); later the wavelets of
+//                    the forward transform at their final places
+//   SB[pair][n1/2]   the other scaling buffer of both transforms
+// The transforms take two levels per barrier step (an item is a cell two
+// levels above the finer one: its two children are formed in registers and
+// their four children written out, or the reverse).  For d = 1 the line is
+// the instance itself, read from and finished into plan vectors.
 template <int K1>
-__device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total, const RxArgs& a, int64_t rws,
-                             int nin, int64_t nfin, double* lds) {
-  const RInst& I = R.inst[inst];
-  const int rhs = blockIdx.y, tid = threadIdx.x;
-  const int d = I.d, N = I.N, S = I.S, np1 = I.np1, n1 = I.n1;
-  const int NL = I.nl[nin];
-  const int64_t pre0 = ((int64_t)blockIdx.x - (nin == 1 ? R.cum_line[1] : R.cum_line[2])[inst]) * NL;
-  const int nl = (int)min((int64_t)NL, I.npre[d - 1] - pre0);
+__device__ void rx_line_tile(const RInst& I, int mode, int64_t total, const RxArgs& a, int64_t rws, int nin,
+                             int64_t nfin, int64_t fin_index, int rhs, int64_t pre0, int nl, double* lds) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int d = I.d, N = I.N, S = I.S, n1 = I.n1, np1 = I.np1;
   const int npair = nin * S;
   const int lp = npair == 1 ? 0 : (npair == 2 ? 1 : 2);  // log2 npair
   const int ls = S == 1 ? 0 : 1;                        // log2 S
   const int LSL = 5 * npair * (n1 / 2);                 // doubles per line: 2.5 npair n1
-  double* M = lds + (int64_t)NL * LSL;
-  double* wsum = M + 64;
-  // row of (line, pair) in each buffer
-  auto Hr = [&](int ln, int pr) { return lds + (int64_t)ln * LSL + pr * n1; };
-  auto SAr = [&](int ln, int pr) { return lds + (int64_t)ln * LSL + (npair + pr) * n1; };
-  auto SBr = [&](int ln, int pr) { return lds + (int64_t)ln * LSL + 2 * npair * n1 + pr * (n1 / 2); };
+  double* M = lds;                                      // 64
+  double (*rx)[4][4] = (double (*)[4][4])(lds + 64);    // 32
+  double* wsum = lds + 96;                              // 8
+  double* EL = lds + RX_TAIL;                           // [q][p] finest-level cell basis, np1 K1
+  double* w1 = EL + np1 * K1;                           // np1
+  double* L0 = w1 + np1;                                // line buffers
+  auto Hr = [&](int ln, int pr) { return L0 + (int64_t)ln * LSL + pr * n1; };
+  auto SAr = [&](int ln, int pr) { return L0 + (int64_t)ln * LSL + (npair + pr) * n1; };
+  auto SBr = [&](int ln, int pr) { return L0 + (int64_t)ln * LSL + 2 * npair * n1 + pr * (n1 / 2); };
   double* xr = a.rws + (int64_t)rhs * rws;
-  const double* __restrict__ EL = R.EL + I.EL_off + (int64_t)N * np1 * K1;  // finest-level cell basis
-  const double* __restrict__ w1 = R.w1 + I.w_off;
-  for (int e = tid; e < 64; e += RX_THREADS) M[e] = R.mats[I.mats_off + e];
-  for (int pr = 0; pr < npair; ++pr) {
-    const int z = pr / S, s = pr - z * S;
-    const double* __restrict__ in = d == 1 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)s * I.ndof
-                                           : xr + I.X_off[d - 1] + (((int64_t)z * S + s) * I.npre[d - 1] + pre0) * n1;
-    for (int i = tid; i < nl * n1; i += RX_THREADS) {
-      const int ln = (i / K1) >> N, e = i - ln * n1;
-      Hr(ln, pr)[e] = in[i];
-    }
-  }
-  __syncthreads();
-  // inverse transform, levels 1..N: s_n from s_{n-1} and the level-n wavelets
-  // (s_0 and the wavelets stay in H); s_n goes to SA when N - n is even
-  for (int n = 1; n <= N; ++n) {
-    const int per = K1 << n, half = K1 << (n - 1);
-    const bool toA = ((N - n) & 1) == 0;
-    for (int it = tid; it < npair * nl * per; it += RX_THREADS) {
-      const int pl = (it / K1) >> n, e = it - pl * per;
-      const int pr = pl & (npair - 1), ln = pl >> lp;
-      const double* h = Hr(ln, pr);
-      const double* cur = n == 1 ? h : (toA ? SBr(ln, pr) : SAr(ln, pr));
-      double* nxt = toA ? SAr(ln, pr) : SBr(ln, pr);
-      const int c = e / K1, q = e - c * K1, j = c >> 1;
-      const double* Mq = (c & 1) ? M + 16 : M;
-      const double* Wq = (c & 1) ? M + 48 : M + 32;
-      double acc = 0.0;
+  // one level of the inverse transform: the two children of level-n cell c
+  // (K1 values each) from s_n[c] and the level-(n+1) wavelets w[c]
+  auto up = [&](const double* sc, const double* wc, double (&ch)[2][K1]) {
 #pragma unroll
-      for (int i = 0; i < K1; ++i) acc += Mq[q * K1 + i] * cur[j * K1 + i];
+    for (int side = 0; side < 2; ++side)
 #pragma unroll
-      for (int p = 0; p < K1; ++p) acc += Wq[p * K1 + q] * h[half + j * K1 + p];
-      nxt[e] = acc;
+      for (int q = 0; q < K1; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < K1; ++i) acc += M[side * 16 + q * K1 + i] * sc[i];
+#pragma unroll
+        for (int p = 0; p < K1; ++p) acc += M[32 + side * 16 + p * K1 + q] * wc[p];
+        ch[side][q] = acc;
+      }
+  };
+  // inverse transform, levels 1..N, two per step; the finest cells land in SA
+  {
+    const int ns = (N + 1) / 2;
+    int n = 1;  // next level to form
+    for (int st = 0; st < ns; ++st) {
+      const bool toA = ((ns - 1 - st) & 1) == 0;
+      const bool two = n + 1 <= N;
+      const int nb = n - 1;  // items: cells of level n - 1
+      for (int it = tid; it < (npair * nl) << nb; it += nt) {
+        const int j = it & ((1 << nb) - 1), pl = it >> nb;
+        const int pr = pl & (npair - 1), ln = pl >> lp;
+        const double* h = Hr(ln, pr);
+        const double* cur = n == 1 ? h : (toA ? SBr(ln, pr) : SAr(ln, pr));
+        double* nxt = toA ? SAr(ln, pr) : SBr(ln, pr);
+        double c1[2][K1];
+        up(cur + j * K1, h + (K1 << (n - 1)) + j * K1, c1);
+        if (!two) {
+#pragma unroll
+          for (int side = 0; side < 2; ++side)
+#pragma unroll
+            for (int q = 0; q < K1; ++q) nxt[(2 * j + side) * K1 + q] = c1[side][q];
+        } else {
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            double c2[2][K1];
+            up(c1[side], h + (K1 << n) + (2 * j + side) * K1, c2);
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+              for (int q = 0; q < K1; ++q) nxt[(4 * j + 2 * side + s2) * K1 + q] = c2[s2][q];
+          }
+        }
+      }
+      __syncthreads();
+      n += two ? 2 : 1;
     }
-    __syncthreads();
   }
   // pointwise map cell by cell: values at the K1 points of finest cell c of
   // every pair, map, weights, projection onto the cell's K1 functions, into H
   // of (input 0, species s)
   const double dt2 = a.dt2;
-  for (int it = tid; it < nl << N; it += RX_THREADS) {
+  for (int it = tid; it < nl << N; it += nt) {
     const int ln = it >> N, c = it - (ln << N);
     double pv[2][2][K1];  // [input][species][point]
 #pragma unroll
@@ -777,7 +874,7 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
         }
 #pragma unroll
         for (int gq = 0; gq < K1; ++gq) {
-          const double* e = EL + (int64_t)(c * K1 + gq) * K1;
+          const double* e = EL + (c * K1 + gq) * K1;
           double u = 0.0;
 #pragma unroll
           for (int p = 0; p < K1; ++p) u += cc[p] * e[p];
@@ -790,7 +887,7 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
       const double u[2] = {pv[0][0][gq], pv[0][1][gq]};
       const double g[2] = {pv[1][0][gq], pv[1][1][gq]};
       double o[2];
-      rx_map(I, mode, dt2, u, g, o);
+      rx_map(rx, S, mode, dt2, u, g, o);
       const double wq = w1[c * K1 + gq];
       ow[0][gq] = wq * o[0];
       ow[1][gq] = wq * o[1];
@@ -803,48 +900,78 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
         for (int p = 0; p < K1; ++p) {
           double acc = 0.0;
 #pragma unroll
-          for (int gq = 0; gq < K1; ++gq) acc += ow[s][gq] * EL[(int64_t)(c * K1 + gq) * K1 + p];
+          for (int gq = 0; gq < K1; ++gq) acc += ow[s][gq] * EL[(c * K1 + gq) * K1 + p];
           h[p] = acc;
         }
       }
   }
   __syncthreads();
-  // forward transform, levels N..1: s_n -> s_{n-1} (H and SB in turn, from H
-  // at level N) and the level-n wavelets (into SA at their final places)
-  for (int n = N; n >= 1; --n) {
-    const int per = K1 << n, half = K1 << (n - 1);
-    const bool fromH = ((N - n) & 1) == 0;
-    for (int it = tid; it < S * nl * per; it += RX_THREADS) {
-      const int pl = (it / K1) >> n, e = it - pl * per;
+  // one level of the forward transform: parent cell coefficients (sc) and
+  // wavelets (wc) from the two children sl, sr
+  auto down = [&](const double* sl, const double* sr, double* sc, double* wc) {
+#pragma unroll
+    for (int i = 0; i < K1; ++i) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < K1; ++q) {
+        a0 += M[q * K1 + i] * sl[q] + M[16 + q * K1 + i] * sr[q];
+        a1 += M[32 + i * K1 + q] * sl[q] + M[48 + i * K1 + q] * sr[q];
+      }
+      sc[i] = a0;
+      wc[i] = a1;
+    }
+  };
+  // forward transform, levels N..1, two per step (from the projections in H;
+  // cell coefficients alternate SB / H, wavelets to SA at their final places)
+  int st = 0;
+  for (int n = N; n >= 1; ++st) {
+    const bool two = n >= 2;
+    const bool fromH = (st & 1) == 0;
+    const int nb = two ? n - 2 : n - 1;  // items: cells of the coarser output level
+    for (int it = tid; it < (S * nl) << nb; it += nt) {
+      const int j = it & ((1 << nb) - 1), pl = it >> nb;
       const int s = pl & (S - 1), ln = pl >> ls;
       const double* cur = fromH ? Hr(ln, s) : SBr(ln, s);
-      const int w = e >= half;
-      const int e2 = e - w * half;
-      const int j = e2 / K1, i = e2 - j * K1;
-      const double* sl = cur + (2 * j) * K1;
-      const double* sr = sl + K1;
-      double acc = 0.0;
-      if (!w) {
+      double* nxt = fromH ? SBr(ln, s) : Hr(ln, s);
+      double* fw = SAr(ln, s);
+      if (!two) {
+        double sc[K1], wc[K1];
+        down(cur + (2 * j) * K1, cur + (2 * j + 1) * K1, sc, wc);
 #pragma unroll
-        for (int q = 0; q < K1; ++q) acc += M[q * K1 + i] * sl[q] + M[16 + q * K1 + i] * sr[q];
-        (fromH ? SBr(ln, s) : Hr(ln, s))[e] = acc;
+        for (int i = 0; i < K1; ++i) {
+          nxt[j * K1 + i] = sc[i];
+          fw[(K1 << (n - 1)) + j * K1 + i] = wc[i];
+        }
       } else {
+        double s1[2][K1];
 #pragma unroll
-        for (int q = 0; q < K1; ++q) acc += M[32 + i * K1 + q] * sl[q] + M[48 + i * K1 + q] * sr[q];
-        SAr(ln, s)[e] = acc;
+        for (int side = 0; side < 2; ++side) {
+          double wc[K1];
+          down(cur + (4 * j + 2 * side) * K1, cur + (4 * j + 2 * side + 1) * K1, s1[side], wc);
+#pragma unroll
+          for (int i = 0; i < K1; ++i) fw[(K1 << (n - 1)) + (2 * j + side) * K1 + i] = wc[i];
+        }
+        double sc[K1], wc[K1];
+        down(s1[0], s1[1], sc, wc);
+#pragma unroll
+        for (int i = 0; i < K1; ++i) {
+          nxt[j * K1 + i] = sc[i];
+          fw[(K1 << (n - 2)) + j * K1 + i] = wc[i];
+        }
       }
     }
     __syncthreads();
+    n -= two ? 2 : 1;
   }
-  // s_0 is where level 1 (or, for N = 0, the projection) left it
-  const bool s0H = N == 0 || ((N - 1) & 1) == 1;
+  // s_0 is where the last step (for N = 0: the projection) left it
+  const bool s0H = st == 0 || ((st - 1) & 1) == 1;
   auto coef = [&](int ln, int s, int e) -> double {
     return e < K1 ? (s0H ? Hr(ln, s) : SBr(ln, s))[e] : SAr(ln, s)[e];
   };
   if (d >= 2) {
     for (int s = 0; s < S; ++s) {
       double* out = xr + I.Y_off[d - 1] + ((int64_t)s * I.npre[d - 1] + pre0) * n1;
-      for (int i = tid; i < nl * n1; i += RX_THREADS) {
+      for (int i = tid; i < nl * n1; i += nt) {
         const int ln = (i / K1) >> N, e = i - ln * n1;
         out[i] = coef(ln, s, e);
       }
@@ -853,22 +980,54 @@ __device__ void rx_line_body(const RTables& R, int inst, int mode, int64_t total
     double g2 = 0.0;
     for (int s = 0; s < S; ++s) {
       const int64_t base = (int64_t)rhs * total + I.seg + (int64_t)s * I.ndof;
-      for (int i = tid; i < n1; i += RX_THREADS) g2 += finish(a, mode, base + i, coef(0, s, i));
+      for (int i = tid; i < n1; i += nt) g2 += finish(a, mode, base + i, coef(0, s, i));
     }
     if (mode == RX_RESID) {
       g2 = block_sum(g2, wsum);
-      if (tid == 0) a.part[(int64_t)rhs * nfin + R.cum_fin[inst]] = g2;
+      if (tid == 0) a.part[(int64_t)rhs * nfin + fin_index] = g2;
     }
   }
 }
 
+// One workgroup per (tile, right-hand side) of one class of instances (same
+// degree, level and species count, so one LDS layout); the class sets the
+// workgroup size (64..256 threads, a few transform items per thread), so the
+// tiles of short lines run as single waves whose barriers cost almost nothing.
 template <int K1>
-__global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, int ninst, int mode, int64_t total, RxArgs a,
-                                                        int64_t rws, int nin, int64_t nfin) {
+__global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, const LineTask* __restrict__ tasks, int ninst,
+                                                        int mode, int64_t total, RxArgs a, int64_t rws, int nin,
+                                                        int64_t nfin) {
   extern __shared__ double lds[];
-  const int inst = find_inst(nin == 1 ? R.cum_line[1] : R.cum_line[2], ninst, blockIdx.x);
-  if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
-  rx_line_body<K1>(R, inst, mode, total, a, rws, nin, nfin, lds);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const LineTask t = tasks[blockIdx.x];
+  const int rhs = blockIdx.y;
+  if (a.conv && a.conv[rhs * ninst + t.inst]) return;
+  const RInst& I = R.inst[t.inst];
+  const int d = I.d, N = I.N, S = I.S, np1 = I.np1, n1 = I.n1;
+  const int npair = nin * S;
+  const int LSL = 5 * npair * (n1 / 2);
+  {
+    const double* __restrict__ ELg = R.EL + I.EL_off + (int64_t)N * np1 * K1;
+    const double* __restrict__ wg = R.w1 + I.w_off;
+    double* EL = lds + RX_TAIL;
+    for (int e = tid; e < 64; e += nt) lds[e] = R.mats[I.mats_off + e];
+    for (int e = tid; e < 32; e += nt) lds[64 + e] = (&I.rx[0][0][0])[e];
+    for (int e = tid; e < np1 * K1; e += nt) EL[e] = ELg[e];
+    for (int e = tid; e < np1; e += nt) EL[np1 * K1 + e] = wg[e];
+  }
+  double* L0 = lds + RX_TAIL + np1 * (K1 + 1);
+  const double* xr = a.rws + (int64_t)rhs * rws;
+  for (int pr = 0; pr < npair; ++pr) {
+    const int z = pr / S, sp = pr - z * S;
+    const double* __restrict__ in = d == 1 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)sp * I.ndof
+                                           : xr + I.X_off[d - 1] + (((int64_t)z * S + sp) * I.npre[d - 1] + t.pre0) * n1;
+    for (int i = tid; i < t.nl * n1; i += nt) {
+      const int ln = (i / K1) >> N, e = i - ln * n1;
+      L0[(int64_t)ln * LSL + pr * n1 + e] = in[i];
+    }
+  }
+  __syncthreads();
+  rx_line_tile<K1>(I, mode, total, a, rws, nin, nfin, R.cum_fin[t.inst], rhs, t.pre0, t.nl, lds);
 }
 
 void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s) {
@@ -876,7 +1035,6 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
   const int d = plan->d, ninst = plan->ninst;
   const int nin = mode == RX_CORR ? 2 : 1;
   const int64_t nfin = rh->cum_fin.back();
-  const size_t ll = rh->line_lds[nin];
   // every degree present in the plan gets its own launch of each stage
   auto each = [&](auto launch) {
     if (rh->k1mask & 4) launch(std::integral_constant<int, 2>());
@@ -885,24 +1043,48 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
   };
   for (int m = 0; m + 1 <= d - 1; ++m)
     each([&](auto k1) {
-      hipLaunchKernelGGL(k_rx_expand<decltype(k1)::value>,
-                         dim3((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin), dim3(RX_THREADS), 0, s,
-                         rh->dev, (const double*)rh->dev.EH, ninst, m, plan->total, a, rh->rws, rh->lam[m]);
+      const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin);
+      if (rh->llane[m] > 0)
+        hipLaunchKernelGGL((k_rx_expand<decltype(k1)::value, true>), grid, dim3(RX_THREADS), 0, s, rh->dev,
+                           (const double*)rh->dev.EH, ninst, m, plan->total, a, rh->rws, rh->lam[m], rh->llane[m]);
+      else
+        hipLaunchKernelGGL((k_rx_expand<decltype(k1)::value, false>), grid, dim3(RX_THREADS), 0, s, rh->dev,
+                           (const double*)rh->dev.EH, ninst, m, plan->total, a, rh->rws, rh->lam[m], 0);
     });
-  each([&](auto k1) {
-    hipLaunchKernelGGL(k_rx_line<decltype(k1)::value>, dim3((unsigned)rh->cum_line[nin].back(), (unsigned)nrhs),
-                       dim3(RX_THREADS), ll, s, rh->dev, ninst, (int)mode, plan->total, a, rh->rws, nin, nfin);
-  });
+  for (const LineClass& lc : rh->lclass) {
+    const dim3 grid((unsigned)lc.tasks[nin].size(), (unsigned)nrhs), blk((unsigned)lc.threads[nin]);
+    switch (lc.K1) {
+      case 2:
+        hipLaunchKernelGGL(k_rx_line<2>, grid, blk, lc.lds[nin], s, rh->dev, lc.dev[nin], ninst, (int)mode, plan->total,
+                           a, rh->rws, nin, nfin);
+        break;
+      case 3:
+        hipLaunchKernelGGL(k_rx_line<3>, grid, blk, lc.lds[nin], s, rh->dev, lc.dev[nin], ninst, (int)mode, plan->total,
+                           a, rh->rws, nin, nfin);
+        break;
+      default:
+        hipLaunchKernelGGL(k_rx_line<4>, grid, blk, lc.lds[nin], s, rh->dev, lc.dev[nin], ninst, (int)mode, plan->total,
+                           a, rh->rws, nin, nfin);
+        break;
+    }
+  }
   for (int m = d - 2; m >= 0; --m)
     each([&](auto k1) {
-      hipLaunchKernelGGL(k_rx_contract<decltype(k1)::value>, dim3((unsigned)rh->cum_x[m].back(), (unsigned)nrhs),
-                         dim3(RX_THREADS), 0, s, rh->dev, (const double*)rh->dev.EH, (const double*)rh->dev.w1, ninst,
-                         m, (int)mode, plan->total, a, rh->rws, rh->lam[m], nfin);
+      const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs);
+      if (rh->llane[m] > 0)
+        hipLaunchKernelGGL((k_rx_contract<decltype(k1)::value, true>), grid, dim3(RX_THREADS), 0, s, rh->dev,
+                           (const double*)rh->dev.EH, (const double*)rh->dev.w1, ninst, m, (int)mode, plan->total, a,
+                           rh->rws, rh->lam[m], rh->llane[m], nfin);
+      else
+        hipLaunchKernelGGL((k_rx_contract<decltype(k1)::value, false>), grid, dim3(RX_THREADS), 0, s, rh->dev,
+                           (const double*)rh->dev.EH, (const double*)rh->dev.w1, ninst, m, (int)mode, plan->total, a,
+                           rh->rws, rh->lam[m], 0, nfin);
     });
 }
 
 static sgdg_status set_line_lds(const RHost* rh) {
-  const int ll = (int)std::max(rh->line_lds[1], rh->line_lds[2]);
+  int ll = 0;
+  for (const LineClass& lc : rh->lclass) ll = std::max(ll, (int)std::max(lc.lds[1], lc.lds[2]));
   hipError_t e = hipFuncSetAttribute((const void*)k_rx_line<2>, hipFuncAttributeMaxDynamicSharedMemorySize, ll);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_rx_line<3>, hipFuncAttributeMaxDynamicSharedMemorySize, ll);
