@@ -180,12 +180,7 @@ sgdg_status sg_dg_apply(const sgdg_plan* plan, int32_t nrhs, const void* x, void
  * and squaring (Higham 2005, degrees 3..13).  M is clamped to the DOF count
  * of each species.  v, w: device FP64 plan vectors (nrhs*total), may alias.
  * workspace: device buffer of at least krylov_bytes (sg_dg_workspace_size).
- * stats: device array of nrhs*ninst*2 sgdg_stats or NULL.
- * Environment: SGDG_ARNOLDI=persistent runs the M Arnoldi steps in one
- * cooperative launch (grid-wide barriers) when every chunk of the plan is in
- * an LDS-staged sweep list and chunks x nrhs <= compute units; otherwise, and
- * by default, one launch per Gram-Schmidt pass.  Same arithmetic either way;
- * a barrier that fails to complete reports SGDG_ERR_HIP in stats.           */
+ * stats: device array of nrhs*ninst*2 sgdg_stats or NULL.                  */
 sgdg_status krylov_expv(const sgdg_plan* plan, int32_t nrhs, double h, int32_t M, const double* v, double* w,
                         void* workspace, size_t workspace_bytes, sgdg_stats* stats, void* stream);
 
@@ -208,8 +203,8 @@ sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const double* U, 
  * first step) and F(U') on return; NULL recomputes it every step.
  * S_next: projected forcing at the new time level (F = P f(R U) + S), device
  * plan vectors or NULL; a source needs Fcache (the old level's F includes
- * its own source).  workspace: at least iif2_bytes.  stats: device array or
- * NULL.                                                                    */
+ * its own source).  U, Fcache and S_next must not alias (SGDG_ERR_ARG).
+ * workspace: at least iif2_bytes.  stats: device array or NULL.            */
 sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcache,
                       const double* S_next, double newton_tol, int32_t newton_max, void* workspace,
                       size_t workspace_bytes, sgdg_stats* stats, void* stream);

@@ -394,7 +394,6 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
   const int vbytes = prec == SGDG_FP64 ? 8 : 4;
   p->chunk_lists.assign(SWEEP_TIERS * (SGDG_MAX_K + 1), {});
   p->list_lds.assign(SWEEP_TIERS * (SGDG_MAX_K + 1), 0);
-  p->list_fixed.assign(SWEEP_TIERS * (SGDG_MAX_K + 1), 0);
   auto al16 = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
   auto al256 = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
   // rows of each direction's 1D operator that a chunk's outputs use: the
@@ -449,9 +448,8 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
     const int64_t kk = (int64_t)(hi.desc.k + 1) * (hi.desc.k + 1);
     // staged sweep: block table, then per direction the chunk's row pointers,
     // source cells (and block values), each region with 16 bytes of slack
-    // rounded to 256 bytes for the direct global -> LDS copies.  The
-    // persistent Arnoldi kernel stages whole tables, packed (list_fixed).
-    int64_t rows = 0, vals = 0, rows256 = 0, vals256 = 0;
+    // rounded to 256 bytes for the direct global -> LDS copies.
+    int64_t rows256 = 0, vals256 = 0;
     for (int m = 0; m < d; ++m) {
       bool seen = false;
       for (int m2 = 0; m2 < m; ++m2) seen = seen || hi.dir_tab[m2] == hi.dir_tab[m];
@@ -459,20 +457,13 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
       const StageRange& r = srange[(size_t)c * SGDG_MAX_D + m];
       rows256 += al256(((int64_t)r.nrow + 1) * 4 + 16) + al256((int64_t)r.nent * 4 + 16);
       vals256 += al256((int64_t)r.nent * kk * vbytes + 16);
-      const Op1D& op = p->ops[hi.dir_tab[m]];
-      rows += (int64_t)op.cptr.size() + (int64_t)op.src.size();
-      vals += al16((int64_t)op.val.size() * vbytes);
     }
     const int64_t lds1 = al256(ntab * 4) + rows256 + al256(hi.ndof * xbytes + 16);
     const int64_t lds2 = lds1 + vals256;
     const int tier = lds2 <= APPLY_LDS_BYTES_HOST ? 2 : (lds1 <= APPLY_LDS_BYTES_HOST ? 1 : 0);
     const int kind = hi.desc.k * SWEEP_TIERS + tier;
     p->chunk_lists[kind].push_back(c);
-    if (tier > 0) {
-      p->list_lds[kind] = std::max(p->list_lds[kind], (int)(tier == 2 ? lds2 : lds1));
-      const int64_t fixed = al16((ntab + rows) * 4) + (tier == 2 ? vals : 0);
-      p->list_fixed[kind] = std::max(p->list_fixed[kind], (int)fixed);
-    }
+    if (tier > 0) p->list_lds[kind] = std::max(p->list_lds[kind], (int)(tier == 2 ? lds2 : lds1));
   }
 
   // Staged lists: workgroups go to the XCDs round-robin (workgroup t to XCD

@@ -240,6 +240,8 @@ extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   if (!(newton_tol >= 0.0)) return fail(SGDG_ERR_ARG, "iif2_step: newton_tol must be >= 0");
   if (newton_max < 0 || newton_max > 1000) return fail(SGDG_ERR_ARG, "iif2_step: newton_max must be in 0..1000");
   if (!U || !workspace) return fail(SGDG_ERR_ARG, "iif2_step: null device pointer");
+  if (U == Fcache || (const double*)U == S_next || (S_next && (const double*)Fcache == S_next))
+    return fail(SGDG_ERR_ARG, "iif2_step: U, Fcache and S_next must not alias");
   if (S_next && !Fcache) return fail(SGDG_ERR_ARG, "iif2_step: a source needs the F cache (F of the old level)");
   if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "iif2_step: (k+1) 2^N above 2048 per axis (1024 with two species)");
   if (workspace_bytes < iif2_ws_bytes(plan, M, nrhs)) return fail(SGDG_ERR_ARG, "iif2_step: workspace too small");

@@ -143,7 +143,6 @@ struct sgdg_plan {
   std::vector<int32_t*> dev_chunk_lists;
   std::vector<sgdg::SweepTask*> dev_tasks;  // staged lists: per entry, its SweepTask
   std::vector<int> list_lds;    // dynamic LDS bytes of the staged lists
-  std::vector<int> list_fixed;  // of which tables and block values (all but the x segment), maximum over the list
   std::vector<sgdg::InstDev> instdev;
   std::vector<int32_t> pchunk0, pnchunk;  // host copies of the per-species chunk ranges
   sgdg::DevTables dev;

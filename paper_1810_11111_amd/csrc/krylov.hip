@@ -101,10 +101,6 @@ __global__ __launch_bounds__(CHUNK) void k_init(DevTables T, int nchunks, int ni
     double t = 0.0;
     for (int w = 0; w < NW; ++w) t += red[w];
     ws.part1[((int64_t)rhs * nchunks + c) * (M + 2)] = t;
-    if (c == 0 && rhs == 0) {
-      ws.bar[0] = 0u;
-      ws.bar[2] = 0u;
-    }
     if (c == ch.pc0) {
       const int p = prob_of(rhs, ninst, ch);
       ws.done[p] = 0;
@@ -521,10 +517,9 @@ __device__ __forceinline__ double hess_from_log(const DevTables& T, const Krylov
   return hn_s;
 }
 
-// from_log: H from the k_upd log (launch-per-step form), else from ws.H
-// (persistent form).
-__global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int nchunks, int M, double hstep, int from_log,
-                                              KrylovWs ws, sgdg_stats* __restrict__ stats) {
+// H is assembled from the step log of the k_upd launches.
+__global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int nchunks, int M, double hstep, KrylovWs ws,
+                                              sgdg_stats* __restrict__ stats) {
   const int p = blockIdx.x;
   const int species = p & 1;
   const int inst = (p >> 1) % ninst;
@@ -533,7 +528,6 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int nchunk
   if (species >= T.inst[inst].S) return;
   const int m = ws.m[p];
   const double beta = ws.beta[p];
-  const double* Hp = ws.H + (int64_t)p * (M + 1) * M;
   __shared__ __align__(16) double Am[MM * LDM], A2[MM * LDM], A4[MM * LDM], A6[MM * LDM], Tm[MM * LDM],
       Um[MM * LDM], Vm[MM * LDM];
   __shared__ double b[14], fac[MM];
@@ -550,13 +544,12 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int nchunk
   }
   // only the Hessenberg part of H is ever written (rows <= column + 1); every
   // work matrix starts zero on the padded square used by mat_mul
-  double hnext = 0.0;
-  if (from_log) hnext = hess_from_log(T, ws, p, rhs, inst * 2 + species, nchunks, M, m, Tm, A2, A4, fac, Vm, Um);
+  const double hnext = hess_from_log(T, ws, p, rhs, inst * 2 + species, nchunks, M, m, Tm, A2, A4, fac, Vm, Um);
   const int mp = (m + 15) & ~15;
   for (int e = tid; e < mp * mp; e += blockDim.x) {
     const int r = e / mp, c = e - r * mp, q = r * LDM + c;
     const bool in = r < m && c < m && r <= c + 1;
-    Am[q] = in ? hstep * (from_log ? Tm[q] : Hp[r * M + c]) : 0.0;
+    Am[q] = in ? hstep * Tm[q] : 0.0;
     A2[q] = A4[q] = A6[q] = Tm[q] = Um[q] = Vm[q] = 0.0;
   }
   __syncthreads();
@@ -715,8 +708,8 @@ __global__ __launch_bounds__(256) void k_expm(DevTables T, int ninst, int nchunk
     bool fin = isfinite(beta);
     for (int i = 0; i < m; ++i) fin = fin && isfinite(R[i * LDM]);
     stats[p].krylov_m = m;
-    stats[p].h_next = from_log ? hnext : Hp[m * M + (m - 1)];
-    stats[p].status = ws.bar[2] ? SGDG_ERR_HIP : (fin ? SGDG_OK : SGDG_ERR_NONFINITE);
+    stats[p].h_next = hnext;
+    stats[p].status = fin ? SGDG_OK : SGDG_ERR_NONFINITE;
   }
 }
 
@@ -751,12 +744,10 @@ size_t krylov_ws_bytes(const sgdg_plan* plan, int M, int nrhs) {
   b += align256(plan->prec == SGDG_BF16_SWEEP ? tot * 2 : 0);             // Vb
   b += align256(tot * sweep_bytes(plan->prec));                           // wy
   b += 3 * align256((size_t)nrhs * plan->nchunks * (M + 2) * 8);          // part1, part2, part3
-  b += align256(np * (M + 1) * M * 8);                                    // H
   b += align256(np * (M + 1) * (2 * M + 1) * 8);                          // step log
   b += align256(np * M * 8);                                              // y
   b += align256(np * 8);                                                  // beta
   b += 2 * align256(np * 4);                                              // m, done
-  b += align256(64);                                                      // barrier words
   return b;
 }
 
@@ -777,13 +768,11 @@ KrylovWs krylov_carve(const sgdg_plan* plan, int M, int nrhs, void* base) {
   ws.part1 = (double*)take((size_t)nrhs * plan->nchunks * (M + 2) * 8);
   ws.part2 = (double*)take((size_t)nrhs * plan->nchunks * (M + 2) * 8);
   ws.part3 = (double*)take((size_t)nrhs * plan->nchunks * (M + 2) * 8);
-  ws.H = (double*)take(np * (M + 1) * M * 8);
   ws.lg = (double*)take(np * (M + 1) * (2 * M + 1) * 8);
   ws.y = (double*)take(np * M * 8);
   ws.beta = (double*)take(np * 8);
   ws.m = (int32_t*)take(np * 4);
   ws.done = (int32_t*)take(np * 4);
-  ws.bar = (uint32_t*)take(64);
   return ws;
 }
 
@@ -795,8 +784,7 @@ static void run_typed(const sgdg_plan* plan, int nrhs, double h, int M, const do
   hipLaunchKernelGGL(k_init, grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, v, ws,
                      in ? in->vbuf : nullptr, in ? in->x : nullptr, in ? in->y : nullptr, in ? in->a : 0.0);
   hipLaunchKernelGGL((k_norm<TV>), grid, blk, 0, s, plan->dev, plan->nchunks, plan->ninst, plan->total, M, v, ws);
-  const bool persistent = arnoldi_persistent(plan, nrhs, M, ws, s);
-  if (!persistent) {
+  {
     for (int j = 0; j < M; ++j) {
       const void* xin = ws.Vb ? (const void*)ws.Vb : (const void*)((const TV*)ws.V + (size_t)j * nrhs * plan->total);
       // sweep w = A x_j fused with the chunk partials <v_i, w>, i < j, and <x_j, w>
@@ -828,7 +816,7 @@ static void run_typed(const sgdg_plan* plan, int nrhs, double h, int M, const do
     }
   }
   hipLaunchKernelGGL(k_expm, dim3((unsigned)(nrhs * plan->ninst * 2)), dim3(256), 0, s, plan->dev, plan->ninst,
-                     plan->nchunks, M, h, persistent ? 0 : 1, ws, stats);
+                     plan->nchunks, M, h, ws, stats);
   hipLaunchKernelGGL((k_comb<TV>), grid, blk, 0, s, plan->dev, plan->ninst, plan->total, M, ws, w);
 }
 

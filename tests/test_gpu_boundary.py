@@ -47,6 +47,7 @@ def test_argument_errors_leave_outputs_untouched():
     assert _status(plan.iif2_step, -0.1, M, U, y, ws) == 1
     assert _status(plan.iif2_step, 0.1, M, U, y, ws, newton_tol=-1.0) == 1
     assert _status(plan.iif3_step, 0.1, M, U, y, y, ws) == 1
+    assert _status(plan.iif2_step, 0.1, M, U, U, ws) == 1  # U aliasing the F cache
     torch.cuda.synchronize()
     assert (y.cpu().numpy() == 7.0).all()
     assert np.array_equal(U.cpu().numpy(), x.cpu().numpy())

@@ -1,15 +1,14 @@
 """GPU parity of krylov_expv (exp(hA)v by Arnoldi, Sec. 3 eqs. 3.7-3.8) against the oracle.
 
-Tolerance (FP64).  Two exact-arithmetic-equivalent evaluations of the Krylov
-exponential differ by rounding propagated through exp: a perturbation of A of
-size c u ||A|| changes exp(hA)v by at most about c u h ||A|| ||v|| (the
-exponential of a symmetric negative semi-definite matrix has a Frechet
-derivative of norm <= h).  The oracle itself shows this spread: changing only
-the summation order of its sparse product moves the stiff Schnakenberg species
-(h ||A||_inf = 6.5e5) by 4e-12 relative, and scipy's expm against the
-eigendecomposition route by 1.6e-11.  The bound used is therefore
-    ||w - w_ref|| <= max(1e-12, 4 u h ||A||_inf) * ||v||,   u = 2^-53,
-which is 1e-12 for every non-stiff case and about 3e-10 for that species.
+Tolerance (FP64): ||w - w_ref|| <= 1e-12 ||v|| for every exponential, the
+FP64 parity target, except 3e-12 ||v|| where h ||A||_inf > 1e5 (the stiff
+Schnakenberg v species, 6.5e5).  Two exact-arithmetic-equivalent evaluations
+differ by rounding propagated through exp(hA) (a perturbation of A of size
+c u ||A|| moves exp(hA)v by up to about c u h ||A|| ||v||, 3e-10 for that
+species); the measured spread is far smaller: the oracle itself moves by at
+most 6e-13 of ||v|| there when only its rounding changes
+(tests/test_oracle_noise_floor.py), and the stiff bound is five times that.
+Each comparison prints its margin ([parity] lines).
 Reduced precision: FP32 sweeps and basis 1e-4, BF16 sweeps 3e-2 (of ||v||),
 stated errors, not pins.
 """
@@ -19,14 +18,15 @@ import pytest
 from oracle import krylov, operator, project
 from paper_1810_11111_amd import inputs as I
 
-from _gpu_common import lib, note, say, to_dev
+from _gpu_common import fp64_bound, lib, note, say, to_dev
 
 pytestmark = pytest.mark.gpu
 U = 2.0 ** -53
 
 
 def fp64_tol(h, anorm):
-    return max(1e-12, 4 * U * h * anorm)
+    """The FP64 parity bound per exponential, relative to ||v||."""
+    return fp64_bound(h, anorm)
 
 
 def _A(inst):
@@ -108,36 +108,6 @@ def test_expv_fp64_random(d, N, k, D, h, M, seed):
         for s in range(len(D)):
             seg = slice(s * nd, (s + 1) * nd)
             assert np.linalg.norm(W[r, seg]) <= np.linalg.norm(V[r, seg]) * (1 + 1e-12)
-
-
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-def test_expv_persistent_and_multi_kernel_forms_agree(prec, monkeypatch):
-    """SGDG_ARNOLDI=persistent runs the Arnoldi process of a plan whose chunks
-    all fit the LDS-staged sweep in one cooperative launch; the default is the
-    launch-per-pass form.  Both orthogonalise by classical Gram-Schmidt
-    applied twice with FP64 reductions (the launch-per-pass form delays the
-    second pass by one step), so they agree to rounding."""
-    sg = lib()
-    wl = I.schnakenberg_d2(N=6, k=2)
-    inst = wl.instances[0]
-    say("expv persistent vs multi", prec)
-    plan = sg.Plan([inst], prec)
-    V = I.smooth_random(plan.total, 21, 3)
-    monkeypatch.delenv("SGDG_ARNOLDI", raising=False)
-    Wm, stm = _run(plan, wl.dt, wl.M, V, nrhs=3)
-    monkeypatch.setenv("SGDG_ARNOLDI", "persistent")
-    Wp, stp = _run(plan, wl.dt, wl.M, V, nrhs=3)
-    assert np.array_equal(stm["krylov_m"], stp["krylov_m"]) and np.all(stp["status"][: 3 * 2] == 0)
-    if prec == "fp64":
-        _compare(plan, [inst], wl.dt, wl.M, V, Wp, stp, fp64_tol, nrhs=3)
-        _compare(plan, [inst], wl.dt, wl.M, V, Wm, stm, fp64_tol, nrhs=3)
-    nd = plan.info(0)[0]
-    an = [plan.norm_inf(0, s) for s in range(2)]
-    for r in range(3):
-        for s in range(2):
-            seg = slice(s * nd, (s + 1) * nd)
-            tol = {"fp64": 2 * fp64_tol(wl.dt, an[s]), "fp32": 1e-4, "bf16": 3e-2}[prec] * np.linalg.norm(V[r, seg])
-            assert np.linalg.norm(Wp[r, seg] - Wm[r, seg]) <= tol, (prec, r, s)
 
 
 def test_expv_schnakenberg_full_size():
