@@ -1,25 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark: IIF2 steps of sparse-grid Krylov IIF DG on one MI355X.
 
-Workload (default): the 2-species Schnakenberg system on the periodic unit
-square, d=2, sparse level N=7, P2 (k=2), 5184 DOFs per species, IIF2 with
-dt=0.05 and Krylov dimension M=30, initial data (a+b, b/(a+b)^2) plus seeded
-uniform +-0.01 noise on every coefficient.  One step = one iif2_step call
-(two Krylov exponentials, the implicit reaction stage) replayed from a
-captured HIP graph; inputs are resident in HBM before timing starts.
+Headline workload: the d=4 problem u_t = Lap u - u^2 on the periodic unit
+cube, sparse level N=6, P1 (k=1), 24,320 DOF, IIF2 with dt=0.005 and Krylov
+dimension M=40, run as one plan with 16 right-hand sides (initial data
+a_r prod sin(2 pi x_i), a_r seeded U[0.1, 1]): 268M Gauss points per field
+and right-hand side, the largest configuration that runs on one GPU.  One
+step = one iif2_step call over the 16 right-hand sides, replayed from a
+captured HIP graph; inputs resident in HBM before timing starts.
 
-Prints ONE JSON line with the IIF2 throughput in DOF-steps/s (FP64 path),
-the FP32- and BF16-sweep variants with their L2 difference to the FP64
-result, the roofline of the dominant kernel, the out-of-cache sweep, a
-64-instance batched run (FP64 and FP32 sweeps), and the CPU oracle baseline
-with the L2 error of each precision against the oracle after the same steps.
+Prints ONE JSON line: the FP64 throughput in DOF-steps/s, the FP32-sweep leg
+with its relative L2 difference, the roofline of the step's dominant kernel
+(the last-axis reaction kernel, timed live with HIP events around each launch
+of a reaction pass), a >= 2 GB triad for the achievable bandwidth, the
+out-of-cache operator sweep, the other workloads (d=2 Schnakenberg, d=3
+Allen-Cahn, the 64-instance Gray-Scott batch, the single-RHS d=4 problem),
+the L2 error of FP64 and FP32 against the oracle's full-size states, and the
+CPU oracle timed on a bounded sample, on all host threads and on one.
+
+--counters NAME runs only a few launches of one kernel workload and a 256 MiB
+copy (the copy calibrates FETCH_SIZE / WRITE_SIZE); it is the program the
+hardware-counter summaries under profiles/ were taken on.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -32,104 +39,67 @@ sys.path.insert(0, ROOT)
 METRIC = "IIF2 DOF-steps/sec and operator-apply GB/s; mixed/batched vs FP64 at stated L2 err"
 HBM_PEAK_GBS = 8000.0
 NEWTON_TOL = 1e-14
-NEWTON_MAX = 5
+NEWTON_MAX = 6
+NRHS = 16
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_ic(plan, wl):
-    """Initial plan vector from the workload description (library projection)."""
-    x = np.zeros(plan.total)
-    for i in range(len(wl.instances)):
-        nd, off, _ = plan.info(i)
-        for s, (terms, mults, add) in enumerate(wl.initial_condition(i, nd)):
-            v = np.zeros(nd)
-            for (amp, fac), mult in zip(terms, mults):
-                pr = plan.project(i, amp, fac)
-                v += pr * (1.0 + mult) if mult is not None else pr
-            if add is not None:
-                v += add
-            x[off + s * nd: off + (s + 1) * nd] = v
+# ----------------------------------------------------------------------------- inputs
+
+def build_ic(plan, wl, inst_of=None, nrhs=1):
+    """Initial plan vectors from the workload description (library projection).
+    inst_of(r, i): the workload instance whose initial data right-hand side r
+    of plan instance i takes (default: instance i)."""
+    x = np.zeros((nrhs, plan.total))
+    for r in range(nrhs):
+        for i in range(len(plan.instances)):
+            nd, off, _ = plan.info(i)
+            src = inst_of(r, i) if inst_of else i
+            for s, (terms, mults, add) in enumerate(wl.initial_condition(src, nd)):
+                v = np.zeros(nd)
+                for (amp, fac), mult in zip(terms, mults):
+                    pr = plan.project(i, amp, fac)
+                    v += pr * (1.0 + mult) if mult is not None else pr
+                if add is not None:
+                    v += add
+                x[r, off + s * nd: off + (s + 1) * nd] = v
     return x
 
 
-def dof_per_step(plan, wl):
-    return sum(plan.info(i)[0] * inst.species for i, inst in enumerate(wl.instances))
+# ----------------------------------------------------------------------------- timed steps
 
-
-def run_steps(sg, torch, wl, prec, U0, steps, warmup, graph=True, local=False):
-    """Returns (seconds for `steps` steps, final U (numpy), stats).  local: the
-    stage solved pointwise (iif2_step_local) instead of the Galerkin stage."""
-    plan = sg.Plan(wl.instances, prec)
-    Ud = torch.from_numpy(U0.copy()).cuda()
+def run_steps(sg, torch, insts, prec, wl, U0, steps, warmup, nrhs=1, local=False, iif3=False):
+    """`steps` graph-replayed steps after `warmup` untimed ones.  Returns
+    (seconds, final U, stats)."""
+    plan = sg.Plan(insts, prec)
+    Ud = torch.from_numpy(np.ascontiguousarray(U0.reshape(nrhs, -1))).cuda()
     F = torch.zeros_like(Ud)
-    _, ib = plan.workspace_size(wl.M, 1)
+    _, ib = plan.workspace_size(wl.M, nrhs)
     ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
-    st = torch.zeros(len(wl.instances) * 2 * sg.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
-    plan.reaction(Ud, F, ws)
+    st = torch.zeros(nrhs * len(insts) * 2 * sg.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    plan.reaction(Ud, F, ws, nrhs=nrhs)
+    Fp = None
+    if iif3:  # IIF3 needs F at two levels: one IIF2 start-up step
+        Fp = F.clone()
+        plan.iif2_step(wl.dt, wl.M, Ud, F, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX, stats=st, nrhs=nrhs)
 
     def step():
         if local:
-            plan.iif2_step_local(wl.dt, wl.M, Ud, F, ws, stats=st)
+            plan.iif2_step_local(wl.dt, wl.M, Ud, F, ws, stats=st, nrhs=nrhs)
+        elif iif3:
+            plan.iif3_step(wl.dt, wl.M, Ud, F, Fp, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX, stats=st,
+                           nrhs=nrhs)
         else:
-            plan.iif2_step(wl.dt, wl.M, Ud, F, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX, stats=st)
+            plan.iif2_step(wl.dt, wl.M, Ud, F, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX, stats=st, nrhs=nrhs)
 
     torch.cuda.synchronize()
-    g = None
-    if graph:
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            step()  # first step eager (warm caches / code objects)
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            step()
-        done = 2  # one eager step and the captured step
-    else:
-        step()
-        done = 1
-    run = g.replay if graph else step
-    for _ in range(max(0, warmup - done)):
-        run()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        run()
-    e1.record()
-    torch.cuda.synchronize()
-    secs = e0.elapsed_time(e1) / 1e3
-    stats = sg.stats_array(st)
-    U = Ud.cpu().numpy()
-    del g
-    plan.close()
-    return secs, U, stats, done + max(0, warmup - done)
-
-
-def run_steps_iif3(sg, torch, wl, U0, steps, warmup):
-    """IIF3 (Sec. 3, eq. 3.6) on the workload: one IIF2 start-up step, then
-    IIF3 steps replayed from a captured graph.  Returns (seconds, stats)."""
-    plan = sg.Plan(wl.instances, "fp64")
-    Ud = torch.from_numpy(U0.copy()).cuda()
-    Fc = torch.zeros_like(Ud)
-    _, ib = plan.workspace_size(wl.M, 1)
-    ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
-    st = torch.zeros(len(wl.instances) * 2 * sg.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
-    plan.reaction(Ud, Fc, ws)
-    Fp = Fc.clone()
-    plan.iif2_step(wl.dt, wl.M, Ud, Fc, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX, stats=st)
-
-    def step():
-        plan.iif3_step(wl.dt, wl.M, Ud, Fc, Fp, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX, stats=st)
-
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        step()
+        step()  # first step eager (code objects, caches)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -146,24 +116,66 @@ def run_steps_iif3(sg, torch, wl, U0, steps, warmup):
     torch.cuda.synchronize()
     secs = e0.elapsed_time(e1) / 1e3
     stats = sg.stats_array(st)
-    del g
+    U = Ud.cpu().numpy()
+    del g, ws
     plan.close()
-    return secs, stats
+    torch.cuda.empty_cache()
+    return secs, U, stats
 
 
-def kernel_source_hash():
-    """Hash of the sweep kernel sources and of the plan builder that lays out its
-    chunks and task lists (traffic counters are only valid for this code)."""
+def status_ok(stats, n):
+    return bool(np.all(stats["status"][:n] == 0))
+
+
+# ----------------------------------------------------------------------------- roofline pieces
+
+def kernel_source_hash(files):
     h = hashlib.sha256()
-    for f in ("apply.hip", "kernels.h", "internal.h", "host_plan.cpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1810_11111_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
+REACTION_SOURCES = ("reaction.hip", "reaction.h", "iif2.hip", "internal.h")
+SWEEP_SOURCES = ("apply.hip", "kernels.h", "internal.h", "host_plan.cpp")
+
+
+def traffic_record(name, sources):
+    """Measured HBM bytes per launch from a committed counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash(sources):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def reaction_stage_times(sg, torch, insts, nrhs, U0, reps):
+    """Per-launch times (ms) of reaction passes F = P f(R U), HIP events around
+    every launch on the launch stream; averaged over `reps` passes."""
+    plan = sg.Plan(insts, "fp64")
+    U = torch.from_numpy(np.ascontiguousarray(U0.reshape(nrhs, -1))).cuda()
+    F = torch.zeros_like(U)
+    _, ib = plan.workspace_size(1, nrhs)
+    ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
+    plan.reaction(U, F, ws, nrhs=nrhs)  # warm
+    torch.cuda.synchronize()
+    runs = [plan.reaction_timed(U, F, ws, nrhs=nrhs) for _ in range(reps)]
+    kinds = [k for k, _ in runs[0]]
+    avg = [float(np.mean([r[i][1] for r in runs])) for i in range(len(kinds))]
+    del ws
+    plan.close()
+    torch.cuda.empty_cache()
+    return kinds, avg
+
+
 def time_sweep(sg, torch, insts, prec, reps, seed=7):
-    """Average duration of one sweep launch (sg_dg_apply, nrhs=1), measured with HIP
-    events around a captured graph of `reps` back-to-back launches on the same stream."""
+    """Average duration of one sweep launch (sg_dg_apply, nrhs=1), HIP events
+    around a captured graph of `reps` back-to-back launches on one stream."""
     from paper_1810_11111_amd import inputs as I
 
     plan = sg.Plan(insts, prec)
@@ -191,191 +203,315 @@ def time_sweep(sg, torch, insts, prec, reps, seed=7):
     return avg, 2 * total * elem, total
 
 
-def traffic_record(kernel, workload):
-    """Measured HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        rec = json.load(fh)
-    if rec.get("source_hash") != kernel_source_hash():
-        return None
-    return rec.get("bytes_per_launch")
-
-
-def cpu_baseline(wl, budget_s=20.0):
-    """The oracle (numpy/scipy FP64) on the same workload: as many steps as fit in
-    the budget, from the oracle's own projection of the initial data.  Returns
-    the record, that initial state and the oracle state after the steps run."""
-    from oracle import iif, project
-    from threadpoolctl import threadpool_info
-
-    inst = wl.instances[0]
-    prob = iif.Problem(inst.d, inst.N, inst.k, inst.D, inst.rx, wl.dt, wl.M)
-    U0 = []
-    for terms, mults, add in wl.initial_condition(0, prob.ndof):
-        v = np.zeros(prob.ndof)
-        for (amp, fac), mult in zip(terms, mults):
-            pr = project.project_separable(inst.d, inst.N, inst.k, amp, fac)
-            v += pr * (1.0 + mult) if mult is not None else pr
-        U0.append(v + add if add is not None else v)
-    U0 = np.array(U0)
-    U = U0.copy()
-    Fn = prob.F(U)
-    t0 = time.perf_counter()
-    n = 0
-    while n < wl.steps and time.perf_counter() - t0 < budget_s:
-        U, Fn, _ = iif.iif2_step(prob, U, Fn, tol=NEWTON_TOL)
-        n += 1
-    secs = time.perf_counter() - t0
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    rec = {"value": prob.ndof * inst.species * n / secs, "unit": "DOF-steps/s", "cores": int(threads),
-           "kind": "oracle", "sample": f"first {n} of {wl.steps} IIF2 steps of the same workload ({secs:.1f} s)"}
-    return rec, U0.ravel(), n, U.ravel()
-
-
-def gpu_trajectory(sg, torch, wl, prec, U0, steps):
-    """`steps` eager IIF2 steps of the library from U0 (untimed)."""
-    plan = sg.Plan(wl.instances, prec)
-    Ud = torch.from_numpy(U0.copy()).cuda()
-    F = torch.zeros_like(Ud)
-    _, ib = plan.workspace_size(wl.M, 1)
-    ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
-    plan.reaction(Ud, F, ws)
-    for _ in range(steps):
-        plan.iif2_step(wl.dt, wl.M, Ud, F, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX)
+def triad(torch, gib=1.0, reps=10):
+    """Achievable HBM bandwidth: c = a + s b over three FP64 arrays of `gib` GiB
+    each (two reads and one write per element), HIP events over `reps` runs."""
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    torch.add(a, b, alpha=0.5, out=c)
     torch.cuda.synchronize()
-    U = Ud.cpu().numpy()
-    plan.close()
-    return U
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(a, b, alpha=0.5, out=c)
+    e1.record()
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3 / reps
+    nbytes = 3 * n * 8
+    del a, b, c
+    torch.cuda.empty_cache()
+    return nbytes / secs / 1e9, nbytes
 
+
+# ----------------------------------------------------------------------------- CPU oracle
+
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline_d4(corrections_per_step, threads=None, samples=8):
+    """The oracle (NumPy/SciPy FP64) on one right-hand side of the headline
+    workload, timed on a bounded sample: one Krylov exponential (M=40) in full,
+    and the reconstruction R and projection P on `samples` of the 210 level
+    blocks (spread over the block list; their sum over blocks is the
+    definition of R and P), scaled to all blocks.  A step costs one exponential
+    and 2c+1 passes of R and of P for c stage corrections (c from the GPU run).
+    Returns the record (DOF-steps/s per right-hand side; the 16-RHS batch is 16
+    independent such runs)."""
+    import contextlib
+
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import iif, krylov, project
+    from paper_1810_11111_amd import inputs as I
+
+    wl = I.quadratic_d4()
+    inst = wl.instances[0]
+    with threadpool_limits(limits=threads) if threads else contextlib.nullcontext():
+        prob = iif.Problem(inst.d, inst.N, inst.k, inst.D, inst.rx, wl.dt, wl.M)
+        (terms, _, _), = wl.initial_condition(0, prob.ndof)
+        U = np.array([sum(project.project_separable(4, inst.N, inst.k, a, f) for a, f in terms)])
+        t0 = time.perf_counter()
+        krylov.expv(prob.A[0], wl.dt, U[0], wl.M, prob.anorm[0])
+        t_exp = time.perf_counter() - t0
+        q = prob.quad
+        nblk = len(q.blocks)
+        pick = np.linspace(0, nblk - 1, samples).round().astype(int)
+        full = (q.blocks, q.starts, q.sizes)
+        q.blocks = [full[0][i] for i in pick]
+        q.starts = np.asarray(full[1])[pick]
+        q.sizes = np.asarray(full[2])[pick]
+        t0 = time.perf_counter()
+        uq = q.R(U[0])
+        t_r = (time.perf_counter() - t0) * nblk / samples
+        q.starts = np.concatenate([[0], np.cumsum(q.sizes)[:-1]]).astype(np.int64)  # P fills a vector of the sample
+        t0 = time.perf_counter()
+        q.P(uq)
+        t_p = (time.perf_counter() - t0) * nblk / samples
+        q.blocks, q.starts, q.sizes = full
+        used = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    passes = 2 * corrections_per_step + 1
+    t_step = t_exp + passes * (t_r + t_p)
+    return {"value": prob.ndof / t_step, "unit": "DOF-steps/s", "cores": int(threads or used), "kind": "oracle",
+            "sample": f"one RHS of the same workload: Krylov exponential (M=40) timed in full ({t_exp:.2f} s); "
+                      f"R and P timed on {samples} of {nblk} level blocks and scaled ({t_r:.1f} s, {t_p:.1f} s "
+                      f"per pass); step = exponential + {passes} R/P passes ({corrections_per_step:.2f} corrections "
+                      f"per step); extrapolated {t_step:.1f} s per step and RHS"}
+
+
+# ----------------------------------------------------------------------------- counter runs
+
+def counters(name, reps):
+    """A few launches of one kernel workload, then a 256 MiB device copy."""
+    import torch
+    from paper_1810_11111_amd import inputs as I
+    from paper_1810_11111_amd import sgdg as sg
+
+    if name == "sweep_d3_n16_k1":
+        plan = sg.Plan([I.Instance(3, 16, 1, [1.0], I.rx_zeros(1))], "fp64")
+        x = torch.from_numpy(I.smooth_random(plan.total, 7, 1)[0]).cuda()
+        y = torch.empty_like(x)
+        for _ in range(reps):
+            plan.apply(x, y)
+        what = f"{reps} sweeps of {plan.total} DOF ({16 * plan.total} algorithmic bytes each)"
+    elif name in ("reaction_quadratic_d4", "reaction_quadratic_d4_rhs16"):
+        wl = I.quadratic_d4(nrhs=NRHS if name.endswith("rhs16") else 1)
+        nrhs = NRHS if name.endswith("rhs16") else 1
+        plan = sg.Plan(wl.instances[:1], "fp64")
+        U = torch.from_numpy(build_ic(plan, wl, inst_of=lambda r, i: r, nrhs=nrhs)).cuda()
+        F = torch.zeros_like(U)
+        _, ib = plan.workspace_size(1, nrhs)
+        ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
+        for _ in range(reps):
+            plan.reaction(U, F, ws, nrhs=nrhs)
+        what = f"{reps} reaction passes, nrhs={nrhs}"
+    else:
+        raise SystemExit(f"unknown counter workload {name}")
+    torch.cuda.synchronize()
+    n = (256 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[counters] {name}: {what}; copy of {n * 8} bytes", flush=True)
+
+
+# ----------------------------------------------------------------------------- main
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 legs")
-    ap.add_argument("--eager", action="store_true", help="launch steps eagerly instead of replaying a graph")
-    ap.add_argument("--no-big", action="store_true", help="skip the out-of-cache sweep measurement")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance Gray-Scott batch")
-    ap.add_argument("--no-iif3", action="store_true", help="skip the IIF3 leg")
-    ap.add_argument("--no-local", action="store_true", help="skip the local-stage variant")
-    ap.add_argument("--batched-steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    ap.add_argument("--no-extras", action="store_true", help="headline, FP32 leg and roofline only")
+    ap.add_argument("--counters", default=None, help="counter-run workload (see module docstring)")
+    ap.add_argument("--reps", type=int, default=3, help="launches of a counter run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU (--gpus {args.gpus} requested); "
-              "independent instances would shard one per GPU with no communication", file=sys.stderr)
+              "independent instances and right-hand sides would shard one share per GPU with no communication",
+              file=sys.stderr)
         sys.exit(2)
+    if args.counters:
+        counters(args.counters, args.reps)
+        return
 
     import torch
     from paper_1810_11111_amd import inputs as I
     from paper_1810_11111_amd import sgdg as sg
 
-    wl = I.schnakenberg_d2()
-    plan0 = sg.Plan(wl.instances, "fp64")
-    U0 = build_ic(plan0, wl)
-    ndps = dof_per_step(plan0, wl)
+    # ------------------------------------------------------------------ headline
+    wl = I.quadratic_d4(nrhs=NRHS)
+    insts = wl.instances[:1]
+    plan0 = sg.Plan(insts, "fp64")
+    U0 = build_ic(plan0, wl, inst_of=lambda r, i: r, nrhs=NRHS)
+    ndof = plan0.total
+    npts = plan0.info(0)[2]
     plan0.close()
-
-    log(f"[bench] fp64: {args.steps} steps, warmup {args.warmup}")
-    secs, U64, st64, _ = run_steps(sg, torch, wl, "fp64", U0, args.steps, args.warmup, graph=not args.eager)
-    if np.any(st64["status"][: 2 * len(wl.instances)] != 0):
-        log("[bench] warning: step status", st64)
-    value = ndps * args.steps / secs
+    dofs = ndof * NRHS
+    log(f"[bench] d=4 N=6 k=1, {NRHS} right-hand sides, fp64: {args.steps} steps, warmup {args.warmup}")
+    secs, U64, st64 = run_steps(sg, torch, insts, "fp64", wl, U0, args.steps, args.warmup, nrhs=NRHS)
+    ok64 = status_ok(st64, 2 * NRHS)
+    if not ok64:
+        log("[bench] error: a step did not converge or produced non-finite values", st64["status"][: 2 * NRHS])
+    iters = float(np.mean(st64["newton_iters"][0::2]))
     out = {
-        "metric": METRIC, "value": value, "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * secs / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": wl.name, "d": 2, "N": 7, "k": 2, "species": 2, "dof_per_species": ndps // 2,
-                   "dt": wl.dt, "M": wl.M, "newton_tol": NEWTON_TOL, "newton_max": NEWTON_MAX,
-                   "graph": not args.eager},
-        "newton_iters_last_step": int(st64["newton_iters"][0]),
+        "metric": METRIC, "value": dofs * args.steps / secs if ok64 else None, "unit": "DOF-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * secs / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "quadratic_d4_batch16", "d": 4, "N": 6, "k": 1, "rhs": NRHS, "species": 1,
+                   "dof_per_rhs": ndof, "gauss_points_per_rhs": npts, "dt": wl.dt, "M": wl.M,
+                   "newton_tol": NEWTON_TOL, "newton_max": NEWTON_MAX, "graph": True},
+        "status_ok": ok64,
+        "newton_corrections_last_step": iters,
     }
-    if not args.no_mixed:
-        mixed = {}
-        for prec in ("fp32", "bf16"):
-            log(f"[bench] {prec}")
-            s2, Up, stp, _ = run_steps(sg, torch, wl, prec, U0, args.steps, args.warmup, graph=not args.eager)
-            rel = float(np.linalg.norm(Up - U64) / np.linalg.norm(U64))
-            mixed[prec] = {"value": ndps * args.steps / s2, "ms_per_step": 1e3 * s2 / args.steps,
-                           "rel_l2_vs_fp64": rel, "status_ok": bool(np.all(stp["status"][:2] == 0))}
-        out["mixed"] = mixed
-    if not args.no_local:
-        log("[bench] local stage")
-        sl, Ul, stl, _ = run_steps(sg, torch, wl, "fp64", U0, args.steps, args.warmup, graph=not args.eager,
-                                   local=True)
-        out["iif2_local_stage"] = {
-            "value": ndps * args.steps / sl, "ms_per_step": 1e3 * sl / args.steps,
-            "status_ok": bool(np.all(stl["status"][: 2 * len(wl.instances)] == 0)),
-            "rel_l2_vs_galerkin_stage": float(np.linalg.norm(Ul - U64) / np.linalg.norm(U64)),
-            "note": "variant: implicit stage solved pointwise at the Gauss points (local implicit property)"}
-    if not args.no_iif3:
-        log("[bench] iif3")
-        s3, st3 = run_steps_iif3(sg, torch, wl, U0, args.steps, args.warmup)
-        out["iif3"] = {"value": ndps * args.steps / s3, "ms_per_step": 1e3 * s3 / args.steps,
-                       "status_ok": bool(np.all(st3["status"][: 2 * len(wl.instances)] == 0)),
-                       "note": "same workload with IIF3 (eq. 3.6): two Krylov exponentials per step"}
-    # roofline of the dominant kernel: the operator sweep (the same kernel the
-    # step launches for every Krylov vector), timed live on the workload plan
-    log("[bench] sweep timing")
-    avg, nbytes, _ = time_sweep(sg, torch, wl.instances, "fp64", reps=100)
-    achieved = nbytes / avg / 1e9
-    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": traffic_record("apply_kernel_lds", wl.name),
-                       "kernel": "apply_kernel_lds<2,2,PrecF64,true,void,1> (operator sweep, y = A x)",
-                       "avg_us": avg * 1e6, "bytes_per_launch": nbytes,
-                       "launches_per_step": wl.M * 1,
-                       "note": "algorithmic bytes = read x + write y, 8 B each per DOF; the working set "
-                               "(166 KB) is cache resident, so this launch is latency bound; traffic = "
-                               "FETCH_SIZE + WRITE_SIZE per launch scaled by a 256 MiB copy (each XCD's L2 "
-                               "fetches the staged operator tables once)"}
-    if not args.no_big:
+    log("[bench] fp32 sweeps")
+    s32, U32, st32 = run_steps(sg, torch, insts, "fp32", wl, U0, args.steps, args.warmup, nrhs=NRHS)
+    out["mixed"] = {"fp32": {"value": dofs * args.steps / s32, "ms_per_step": 1e3 * s32 / args.steps,
+                             "rel_l2_vs_fp64": float(np.linalg.norm(U32 - U64) / np.linalg.norm(U64)),
+                             "status_ok": status_ok(st32, 2 * NRHS)}}
+
+    # ------------------------------------------------------------------ roofline of the dominant kernel
+    log("[bench] reaction pass stage timing")
+    kinds, ms = reaction_stage_times(sg, torch, insts, NRHS, U0, reps=3)
+    line_ms = float(sum(m for k, m in zip(kinds, ms) if k == 1))
+    pass_ms = float(sum(ms))
+    # algorithmic bytes of the last-axis kernel in an F pass: the materialised
+    # field of the last axis read once and its projection written once, FP64
+    line_bytes = 2 * 8 * npts * NRHS
+    achieved = line_bytes / (line_ms / 1e3) / 1e9
+    log("[bench] triad")
+    triad_gbs, triad_bytes = triad(torch)
+    out["roofline"] = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic_record("k_rx_line_quadratic_d4_rhs16", REACTION_SOURCES),
+        "kernel": "k_rx_line<2> (last-axis reaction kernel: inverse transform, f, forward transform)",
+        "avg_us": line_ms * 1e3, "bytes_per_launch": line_bytes, "frac_of_triad": achieved / triad_gbs,
+        "reaction_pass": {"stage_kinds": kinds, "stage_ms": ms, "pass_ms": pass_ms,
+                          "note": "kinds: 0 expansion (axes 0..2), 1 last axis, 2 contraction; F pass, 16 RHS"},
+        "note": "algorithmic bytes = 16 B per Gauss point and right-hand side (the last-axis point field of "
+                "268M points per RHS read once, its projection written once); duration from HIP events "
+                "around the launch on its stream",
+    }
+    out["triad"] = {"achieved_gbs": triad_gbs, "bytes": triad_bytes, "frac_of_peak": triad_gbs / HBM_PEAK_GBS,
+                    "note": "c = a + 0.5 b over three 1 GiB FP64 arrays"}
+
+    if not args.no_extras:
+        extras = {}
+        # single right-hand side of the same problem
+        w1 = I.quadratic_d4()
+        p1 = sg.Plan(w1.instances, "fp64")
+        u1 = build_ic(p1, w1)
+        p1.close()
+        ent = {}
+        for prec in ("fp64", "fp32"):
+            log(f"[bench] d4 single rhs {prec}")
+            s, _, stx = run_steps(sg, torch, w1.instances, prec, w1, u1, args.steps, args.warmup)
+            ent[prec] = {"value": ndof * args.steps / s, "ms_per_step": 1e3 * s / args.steps, "status_ok": status_ok(stx, 2)}
+        extras["quadratic_d4"] = ent
+        # d=3 Allen-Cahn, variable k_ii
+        w3 = I.allen_cahn_d3()
+        p3 = sg.Plan(w3.instances, "fp64")
+        u3 = build_ic(p3, w3)
+        n3 = p3.total
+        p3.close()
+        ent = {}
+        for prec in ("fp64", "bf16"):
+            log(f"[bench] allen_cahn_d3 {prec}")
+            s, u, stx = run_steps(sg, torch, w3.instances, prec, w3, u3, 20, args.warmup)
+            ent[prec] = {"value": n3 * 20 / s, "ms_per_step": 1e3 * s / 20, "status_ok": status_ok(stx, 2)}
+            if prec == "fp64":
+                ref3 = u
+            else:
+                ent[prec]["rel_l2_vs_fp64"] = float(np.linalg.norm(u - ref3) / np.linalg.norm(ref3))
+        extras["allen_cahn_d3"] = ent
+        # d=2 Schnakenberg (two species), IIF2 / IIF3 / local stage
+        w2 = I.schnakenberg_d2()
+        p2 = sg.Plan(w2.instances, "fp64")
+        u2 = build_ic(p2, w2)
+        n2 = p2.total
+        p2.close()
+        ent = {}
+        for prec in ("fp64", "fp32", "bf16"):
+            log(f"[bench] schnakenberg_d2 {prec}")
+            s, u, stx = run_steps(sg, torch, w2.instances, prec, w2, u2, 50, 5)
+            ent[prec] = {"value": n2 * 50 / s, "ms_per_step": 1e3 * s / 50, "status_ok": status_ok(stx, 2)}
+            if prec == "fp64":
+                ref2 = u
+            else:
+                ent[prec]["rel_l2_vs_fp64"] = float(np.linalg.norm(u - ref2) / np.linalg.norm(ref2))
+        s, _, stx = run_steps(sg, torch, w2.instances, "fp64", w2, u2, 50, 5, iif3=True)
+        ent["iif3_fp64"] = {"value": n2 * 50 / s, "ms_per_step": 1e3 * s / 50, "status_ok": status_ok(stx, 2)}
+        s, u, stx = run_steps(sg, torch, w2.instances, "fp64", w2, u2, 50, 5, local=True)
+        ent["local_stage_fp64"] = {"value": n2 * 50 / s, "ms_per_step": 1e3 * s / 50, "status_ok": status_ok(stx, 2),
+                                   "rel_l2_vs_galerkin_stage": float(np.linalg.norm(u - ref2) / np.linalg.norm(ref2))}
+        extras["schnakenberg_d2"] = ent
+        # 64 Gray-Scott instances in one plan
+        wb = I.gray_scott_batch()
+        pb = sg.Plan(wb.instances, "fp64")
+        ub = build_ic(pb, wb)
+        nb = pb.total
+        pb.close()
+        ent = {"dof_per_step": nb}
+        for prec in ("fp64", "fp32"):
+            log(f"[bench] gray_scott_batch {prec}")
+            s, u, stx = run_steps(sg, torch, wb.instances, prec, wb, ub, 50, 3)
+            ent[prec] = {"value": nb * 50 / s, "ms_per_step": 1e3 * s / 50,
+                         "status_ok": status_ok(stx, 2 * len(wb.instances))}
+            if prec == "fp64":
+                refb = u
+            else:
+                ent[prec]["rel_l2_vs_fp64"] = float(np.linalg.norm(u - refb) / np.linalg.norm(refb))
+        extras["gray_scott_batch"] = ent
+        out["workloads"] = extras
+        # operator sweep out of cache
         log("[bench] out-of-cache sweep d=3 N=16 k=1")
         big = [I.Instance(3, 16, 1, [1.0], I.rx_zeros(1))]
         avg_b, nbytes_b, tot_b = time_sweep(sg, torch, big, "fp64", reps=10)
+        gbs = nbytes_b / avg_b / 1e9
         out["apply_out_of_cache"] = {"workload": "sweep d=3 N=16 k=1 (24.6M DOF, 197 MB per FP64 vector)",
-                                     "kernel": "apply_kernel<3,1,PrecF64,void> (global gathers)",
-                                     "dof": tot_b, "avg_ms": avg_b * 1e3, "achieved_gbs": nbytes_b / avg_b / 1e9,
-                                     "frac_of_peak": nbytes_b / avg_b / 1e9 / HBM_PEAK_GBS,
+                                     "dof": tot_b, "avg_ms": avg_b * 1e3, "achieved_gbs": gbs,
+                                     "frac_of_peak": gbs / HBM_PEAK_GBS, "frac_of_triad": gbs / triad_gbs,
                                      "bytes_per_launch": nbytes_b,
-                                     "traffic": traffic_record("apply_kernel", "sweep_d3_n16_k1")}
-    if not args.no_batched:
-        # 64 independent Gray-Scott instances (levels 5-8, k 1-2) in one plan: every
-        # launch of the step covers all of them; FP64 and FP32 sweeps
-        bw = I.gray_scott_batch()
-        bplan = sg.Plan(bw.instances, "fp64")
-        bU0 = build_ic(bplan, bw)
-        bdofs = dof_per_step(bplan, bw)
-        bplan.close()
-        batched = {"workload": f"{bw.name} ({len(bw.instances)} instances, d=2, N 5-8, k 1-2, M={bw.M}, "
-                               f"dt={bw.dt})", "dof_per_step": bdofs, "steps": args.batched_steps}
-        ref = None
-        for prec in ("fp64", "fp32"):
-            log(f"[bench] batched {prec}")
-            s2, Ub, stb, _ = run_steps(sg, torch, bw, prec, bU0, args.batched_steps, 3, graph=not args.eager)
-            ent = {"value": bdofs * args.batched_steps / s2, "ms_per_step": 1e3 * s2 / args.batched_steps,
-                   "status_ok": bool(np.all(stb["status"][: 2 * len(bw.instances)] == 0))}
-            if ref is None:
-                ref = Ub
-            else:
-                ent["rel_l2_vs_fp64"] = float(np.linalg.norm(Ub - ref) / np.linalg.norm(ref))
-            batched[prec] = ent
-        out["batched"] = batched
+                                     "traffic": traffic_record("sweep_d3_n16_k1", SWEEP_SOURCES)}
+        # FP64 / FP32 against the oracle's full-size states (two steps, two of the 16 RHS)
+        errs = {}
+        for r in (0, 15):
+            g = np.load(os.path.join(ROOT, "tests", "golden", f"fullsize_c5_rhs{r}.npz"), allow_pickle=False)
+            for prec in ("fp64", "fp32"):
+                plan = sg.Plan(insts, prec)
+                Ud = torch.from_numpy(g["U0"].copy()).cuda()
+                F = torch.zeros_like(Ud)
+                _, ib = plan.workspace_size(wl.M, 1)
+                ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
+                plan.reaction(Ud, F, ws)
+                for _ in range(2):
+                    plan.iif2_step(wl.dt, wl.M, Ud, F, ws, newton_tol=NEWTON_TOL, newton_max=NEWTON_MAX)
+                torch.cuda.synchronize()
+                d_ = Ud.cpu().numpy()[0] - g["U2"][0]
+                errs[f"rhs{r}_{prec}"] = float(np.linalg.norm(d_) / np.linalg.norm(g["U2"][0]))
+                del ws
+                plan.close()
+        out["rel_l2_vs_oracle"] = dict(errs, note="two IIF2 steps from the oracle's projection of the initial data, "
+                                                  "against the oracle's full-size states")
     if not args.no_cpu:
-        log("[bench] cpu oracle")
-        rec, U0o, n, Uo = cpu_baseline(wl)
-        out["cpu_baseline"] = rec
-        # the same steps on the GPU from the oracle's initial state: L2 error of
-        # each precision against the FP64 oracle
-        err = {"steps": n, "ic_rel_diff_library_vs_oracle": float(np.linalg.norm(U0 - U0o) / np.linalg.norm(U0o))}
-        for prec in ("fp64", "fp32", "bf16"):
-            Ug = gpu_trajectory(sg, torch, wl, prec, U0o, n)
-            err[prec] = float(np.linalg.norm(Ug - Uo) / np.linalg.norm(Uo))
-        out["rel_l2_vs_oracle"] = err
+        log("[bench] cpu oracle (all threads)")
+        out["cpu_baseline"] = cpu_baseline_d4(iters)
+        log("[bench] cpu oracle (one thread)")
+        out["cpu_baseline_1core"] = cpu_baseline_d4(iters, threads=1)
+        out["host"] = host_info()
     print(json.dumps(out), flush=True)
 
 

@@ -192,6 +192,18 @@ sgdg_status krylov_expv(const sgdg_plan* plan, int32_t nrhs, double h, int32_t M
 sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const double* U, double* F, const double* S,
                           void* workspace, size_t workspace_bytes, void* stream);
 
+/* Measurement helper: the reaction pass of sgdg_reaction (F = P f(R U), no
+ * source) with a HIP event recorded on `stream` before every kernel launch
+ * and after the last; synchronises the stream and returns the elapsed time of
+ * each launch.  stage_ms, stage_kind: host arrays of *nstage entries (in:
+ * capacity, out: launches timed); stage_kind[i] is 0 for an expansion stage
+ * (axes 0..d-2), 1 for the last-axis kernel (transform, pointwise f,
+ * transform), 2 for a contraction stage, in launch order.  Arguments as for
+ * sgdg_reaction.  Errors: SGDG_ERR_ARG, _UNSUPPORTED, _HIP.                 */
+sgdg_status sgdg_reaction_timed(const sgdg_plan* plan, int32_t nrhs, const double* U, double* F, void* workspace,
+                                size_t workspace_bytes, float* stage_ms, int32_t* stage_kind, int32_t* nstage,
+                                void* stream);
+
 /* One IIF2 step (Sec. 3, eq. 3.5):
  *   W = exp(A dt) (U + dt/2 F(U));  solve U' - dt/2 F(U') = W;  U <- U'.
  * The implicit stage iterates U <- U - P[(I - dt/2 J_f(u_q))^{-1} (R G)_q],

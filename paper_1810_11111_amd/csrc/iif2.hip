@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <functional>
+#include <vector>
 
 #include "internal.h"
 #include "kernels.h"
@@ -228,6 +230,57 @@ extern "C" sgdg_status sgdg_reaction(const sgdg_plan* plan, int32_t nrhs, const 
     hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, F, F, 1.0, S, n);
   }
   return check_launch("sgdg_reaction launch");
+}
+
+extern "C" sgdg_status sgdg_reaction_timed(const sgdg_plan* plan, int32_t nrhs, const double* U, double* F,
+                                           void* workspace, size_t workspace_bytes, float* stage_ms, int32_t* stage_kind,
+                                           int32_t* nstage, void* stream) {
+  if (!plan) return fail(SGDG_ERR_ARG, "sgdg_reaction_timed: null plan");
+  if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "sgdg_reaction_timed: nrhs must be in 1..65535");
+  if (!U || !F || !workspace || !stage_ms || !stage_kind || !nstage)
+    return fail(SGDG_ERR_ARG, "sgdg_reaction_timed: null pointer");
+  if ((const void*)U == (const void*)F) return fail(SGDG_ERR_ARG, "sgdg_reaction_timed: F must not alias U");
+  if (!reaction_supported(plan))
+    return fail(SGDG_ERR_UNSUPPORTED, "sgdg_reaction_timed: (k+1) 2^N above 2048 per axis (1024 with two species)");
+  if (workspace_bytes < iif2_ws_bytes(plan, 1, nrhs))
+    return fail(SGDG_ERR_ARG, "sgdg_reaction_timed: workspace too small");
+  const int cap = *nstage;
+  if (cap < 1) return fail(SGDG_ERR_ARG, "sgdg_reaction_timed: *nstage must be positive");
+  hipStream_t s = (hipStream_t)stream;
+  IifWs w = carve(plan, 1, nrhs, workspace);
+  RxArgs a{};
+  a.U = const_cast<double*>(U);
+  a.F = F;
+  a.rws = w.rws;
+  // one event before every launch and one after the last
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;
+  sgdg_status st = SGDG_OK;
+  const std::function<void(int)> mark = [&](int k) {
+    hipEvent_t e;
+    if (st != SGDG_OK) return;
+    if (hipEventCreate(&e) != hipSuccess || hipEventRecord(e, s) != hipSuccess) {
+      st = SGDG_ERR_HIP;
+      return;
+    }
+    ev.push_back(e);
+    kind.push_back(k);
+  };
+  reaction_pass(plan, nrhs, RX_F, a, s, &mark);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && st == SGDG_OK) e = hipStreamSynchronize(s);
+  int n = 0;
+  for (size_t i = 0; e == hipSuccess && st == SGDG_OK && i + 1 < ev.size() && n < cap; ++i, ++n) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+    stage_ms[n] = ms;
+    stage_kind[n] = kind[i];
+  }
+  for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+  if (st != SGDG_OK) return hip_fail(hipErrorUnknown, "sgdg_reaction_timed events");
+  if (e != hipSuccess) return hip_fail(e, "sgdg_reaction_timed");
+  *nstage = n;
+  return SGDG_OK;
 }
 
 extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcache,

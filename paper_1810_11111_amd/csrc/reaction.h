@@ -1,6 +1,8 @@
 // Reaction transforms: plan-level tables and launchers (reaction.hip), used by iif2.hip.
 #pragma once
 
+#include <functional>
+
 #include "internal.h"
 
 namespace sgdg {
@@ -104,7 +106,10 @@ struct RxArgs {
   double dt2;
   double* rws;  // reaction workspace base
 };
-void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s);
+// mark (optional) is called before every kernel launch with its stage (0
+// expansion, 1 last axis, 2 contraction) and once after the last with -1.
+void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s,
+                   const std::function<void(int)>* mark = nullptr);
 int64_t reaction_ws_doubles(const sgdg_plan* plan);
 
 }  // namespace sgdg

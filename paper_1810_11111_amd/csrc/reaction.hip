@@ -1030,7 +1030,8 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, const LineTas
   rx_line_tile<K1>(I, mode, total, a, rws, nin, nfin, R.cum_fin[t.inst], rhs, t.pre0, t.nl, lds);
 }
 
-void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s) {
+void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s,
+                   const std::function<void(int)>* mark) {
   const RHost* rh = (const RHost*)plan->rdata;
   const int d = plan->d, ninst = plan->ninst;
   const int nin = mode == RX_CORR ? 2 : 1;
@@ -1043,6 +1044,7 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
   };
   for (int m = 0; m + 1 <= d - 1; ++m)
     each([&](auto k1) {
+      if (mark) (*mark)(0);
       const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin);
       if (rh->llane[m] > 0)
         hipLaunchKernelGGL((k_rx_expand<decltype(k1)::value, true>), grid, dim3(RX_THREADS), 0, s, rh->dev,
@@ -1052,6 +1054,7 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
                            (const double*)rh->dev.EH, ninst, m, plan->total, a, rh->rws, rh->lam[m], 0);
     });
   for (const LineClass& lc : rh->lclass) {
+    if (mark) (*mark)(1);
     const dim3 grid((unsigned)lc.tasks[nin].size(), (unsigned)nrhs), blk((unsigned)lc.threads[nin]);
     switch (lc.K1) {
       case 2:
@@ -1070,6 +1073,7 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
   }
   for (int m = d - 2; m >= 0; --m)
     each([&](auto k1) {
+      if (mark) (*mark)(2);
       const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs);
       if (rh->llane[m] > 0)
         hipLaunchKernelGGL((k_rx_contract<decltype(k1)::value, true>), grid, dim3(RX_THREADS), 0, s, rh->dev,
@@ -1080,6 +1084,7 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
                            (const double*)rh->dev.EH, (const double*)rh->dev.w1, ninst, m, (int)mode, plan->total, a,
                            rh->rws, rh->lam[m], 0, nfin);
     });
+  if (mark) (*mark)(-1);
 }
 
 static sgdg_status set_line_lds(const RHost* rh) {

@@ -66,6 +66,7 @@ _sigs = {
     "sg_dg_apply": ([_vp, _i32, _vp, _vp, _vp], C.c_int),
     "krylov_expv": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _sz, _vp, _vp], C.c_int),
     "sgdg_reaction": ([_vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
+    "sgdg_reaction_timed": ([_vp, _i32, _vp, _vp, _vp, _sz, _vp, _vp, C.POINTER(_i32), _vp], C.c_int),
     "iif2_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
     "iif3_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
     "rk_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _sz, _vp], C.c_int),
@@ -205,6 +206,16 @@ class Plan:
     def reaction(self, U, F, workspace, nrhs=1, stream=None, source=None):
         _check(_lib.sgdg_reaction(self._h, nrhs, _ptr(U), _ptr(F), _ptr(source), _ptr(workspace),
                                   workspace.numel() * workspace.element_size(), _stream(stream)), "sgdg_reaction")
+
+    def reaction_timed(self, U, F, workspace, nrhs=1, stream=None, cap=64):
+        """One reaction pass with per-launch HIP-event timing; returns [(kind, ms), ...]."""
+        ms = (C.c_float * cap)()
+        kind = (C.c_int32 * cap)()
+        n = _i32(cap)
+        _check(_lib.sgdg_reaction_timed(self._h, nrhs, _ptr(U), _ptr(F), _ptr(workspace),
+                                        workspace.numel() * workspace.element_size(), ms, kind, C.byref(n),
+                                        _stream(stream)), "sgdg_reaction_timed")
+        return [(int(kind[i]), float(ms[i])) for i in range(n.value)]
 
     def iif2_step(self, dt, M, U, Fcache, workspace, newton_tol=1e-14, newton_max=50, stats=None, nrhs=1,
                   stream=None, source=None):
