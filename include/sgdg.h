@@ -221,6 +221,19 @@ sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M,
                       const double* S_next, double newton_tol, int32_t newton_max, void* workspace,
                       size_t workspace_bytes, sgdg_stats* stats, void* stream);
 
+/* iif2_step without a caller workspace and without any device allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  The workspace is a fixed 64 MiB
+ * device array inside the library (one per GPU, held from library load until
+ * the process ends); plans, M and nrhs whose iif2_step workspace
+ * (sg_dg_workspace_size) exceeds 64 MiB return SGDG_ERR_UNSUPPORTED before any
+ * device work.  Every call on a GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Arguments and results as iif2_step.            */
+sgdg_status iif2_step_noalloc(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcache,
+                              const double* S_next, double newton_tol, int32_t newton_max, sgdg_stats* stats,
+                              void* stream);
+
 /* One IIF3 step (Sec. 3, eq. 3.6; coefficients 5/12, 2/3, -1/12 of eq. 3.4):
  *   W = exp(A dt)(U + 2/3 dt F(U)) + exp(2 A dt)(-1/12 dt F(U^{n-1}))
  * (each exponential by its own Krylov process of dimension M), then the

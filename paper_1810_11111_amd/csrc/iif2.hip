@@ -20,6 +20,8 @@
 
 #include <cmath>
 #include <functional>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -316,6 +318,58 @@ extern "C" sgdg_status iif2_step(const sgdg_plan* plan, int32_t nrhs, double dt,
   if (st != SGDG_OK) return st;
   implicit_stage(plan, nrhs, dt2, U, F, S_next, w, newton_tol, newton_max, stats, s);
   return check_launch("iif2_step launch");
+}
+
+// ---------------------------------------------------------------- fixed scratch
+// iif2_step_noalloc runs iif2_step on a file-scope device array instead of a
+// caller workspace.  The array exists once per device for the life of the
+// process; in host code its name is not a device address, so the address
+// comes from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t SGDG_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[SGDG_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+static sgdg_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return fail(SGDG_ERR_ARG, "iif2_step_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "iif2_step_noalloc: hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return SGDG_OK;
+}
+
+extern "C" sgdg_status iif2_step_noalloc(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U,
+                                         double* Fcache, const double* S_next, double newton_tol, int32_t newton_max,
+                                         sgdg_stats* stats, void* stream) {
+  if (!plan) return fail(SGDG_ERR_ARG, "iif2_step_noalloc: null plan");
+  if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "iif2_step_noalloc: nrhs must be in 1..65535");
+  if (M < 1 || M > SGDG_MAX_M) return fail(SGDG_ERR_ARG, "iif2_step_noalloc: M must be in 1..48");
+  const size_t need = iif2_ws_bytes(plan, M, nrhs);
+  if (need > SGDG_SCRATCH_BYTES)
+    return fail(SGDG_ERR_UNSUPPORTED, "iif2_step_noalloc: this plan, M and nrhs need " + std::to_string(need) +
+                                          " bytes of workspace; the fixed device scratch holds " +
+                                          std::to_string(SGDG_SCRATCH_BYTES) + " (call iif2_step with a workspace)");
+  void* ws = nullptr;
+  const sgdg_status st = scratch_address(plan->device, &ws);
+  if (st != SGDG_OK) return st;
+  // every kernel of the step writes its part of the workspace before reading
+  // it (as with a caller workspace from an uninitialised allocation), so
+  // nothing needs clearing between calls
+  return iif2_step(plan, nrhs, dt, M, U, Fcache, S_next, newton_tol, newton_max, ws, SGDG_SCRATCH_BYTES, stats,
+                   stream);
 }
 
 extern "C" sgdg_status iif3_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t M, double* U, double* Fcur,

@@ -68,6 +68,7 @@ _sigs = {
     "sgdg_reaction": ([_vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
     "sgdg_reaction_timed": ([_vp, _i32, _vp, _vp, _vp, _sz, _vp, _vp, C.POINTER(_i32), _vp], C.c_int),
     "iif2_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
+    "iif2_step_noalloc": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _f64, _i32, _vp, _vp], C.c_int),
     "iif3_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
     "rk_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _sz, _vp], C.c_int),
     "iif2_step_local": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _vp, _sz, _vp, _vp], C.c_int),
@@ -222,6 +223,11 @@ class Plan:
         _check(_lib.iif2_step(self._h, nrhs, float(dt), M, _ptr(U), _ptr(Fcache), _ptr(source), float(newton_tol),
                               newton_max, _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(stats),
                               _stream(stream)), "iif2_step")
+
+    def iif2_step_noalloc(self, dt, M, U, Fcache, newton_tol=1e-14, newton_max=50, stats=None, nrhs=1, stream=None,
+                          source=None):
+        _check(_lib.iif2_step_noalloc(self._h, nrhs, float(dt), M, _ptr(U), _ptr(Fcache), _ptr(source),
+                                      float(newton_tol), newton_max, _ptr(stats), _stream(stream)), "iif2_step_noalloc")
 
     def iif3_step(self, dt, M, U, Fcur, Fprev, workspace, newton_tol=1e-14, newton_max=50, stats=None, nrhs=1,
                   stream=None, source=None):
