@@ -95,6 +95,8 @@ constexpr int RX_ITEMS = 2;            // transform items per thread of a line t
 constexpr int RX_TAIL = 64 + 32 + 8;   // two-scale matrices, reaction coefficients, per-wave partial sums
 constexpr int64_t RX_THREADS_WANTED = 1 << 17;
 constexpr int RX_WALK = 64;  // most points one thread of an expansion / contraction walks
+constexpr int RX_WLINE_MAXN = 7;   // last-axis wave form: at most two finest cells per lane
+constexpr int RX_WLINE_ROUNDS = 16; // its tiles: at most 16 rounds of one line per wave (more lines for N < 6)
 
 // LDS of the last-axis kernel: per line 2.5 npair n1 doubles (inputs, and the
 // two scaling buffers of the transforms), plus the tail
@@ -279,14 +281,24 @@ sgdg_status reaction_build(sgdg_plan* plan) {
       }
       for (int nin = 1; nin <= 2; ++nin) {
         // lines per tile: the LDS budget of one workgroup; threads: about
-        // RX_ITEMS transform items each at the finest level, 64..256
+        // RX_ITEMS transform items each at the finest level, 64..256 (the wave
+        // form: 16 lines per wave, a lane per finest cell or two)
         const int npair = nin * S;
         int64_t nl = ((int64_t)RX_LINE_LDS / 8 - RX_TAIL - (int64_t)r.n1 * (K1 + 1)) / line_doubles(npair, r.n1);
+        if (d >= 2 && N <= RX_WLINE_MAXN) {
+          // wave form: a whole number of wave rounds (4 waves, LPW lines each),
+          // up to 16 rounds, and about 2048 tiles per instance where it has
+          // fewer lines (small problems keep many workgroups)
+          const int64_t round = (int64_t)(RX_THREADS / 64) << std::max(0, 6 - N);
+          const int64_t want = std::max<int64_t>(1, r.npre[d - 1] / 2048 / round);
+          nl = round * std::min<int64_t>(want, RX_WLINE_ROUNDS);
+        }
         nl = std::max<int64_t>(1, std::min<int64_t>(nl, r.npre[d - 1]));
         int th = 64;
         while (th < RX_THREADS && (int64_t)npair * nl * r.n1 > (int64_t)th * RX_ITEMS) th *= 2;
         for (int64_t p0 = 0; p0 < r.npre[d - 1]; p0 += nl)
           lc->tasks[nin].push_back(LineTask{i, (int32_t)std::min<int64_t>(nl, r.npre[d - 1] - p0), p0});
+        if (d >= 2 && N <= RX_WLINE_MAXN) continue;  // (the wave form takes no dynamic LDS)
         lc->lds[nin] = std::max(lc->lds[nin], line_tile_doubles(npair, (int)nl, r.n1, K1) * sizeof(double));
         lc->threads[nin] = std::max(lc->threads[nin], th);
       }
@@ -1030,6 +1042,329 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, const LineTas
   rx_line_tile<K1>(I, mode, total, a, rws, nin, nfin, R.cum_fin[t.inst], rhs, t.pre0, t.nl, lds);
 }
 
+// Last axis, wave form (d >= 2, N <= RX_WLINE_MAXN): a group of lanes takes a
+// whole line, one finest cell per lane (two when N = 7).  A wave copies its
+// lines (a contiguous run) into its own LDS buffer with coalesced loads,
+// works on them there, and writes the projections back as one run.  Each lane follows
+// the cells that contain its own down the tree (inverse fast multiwavelet
+// transform by the two-scale relations; every lane reads the wavelets on its
+// path, so no data moves between lanes), evaluates the K1 Gauss points of its
+// cells, applies the map and the weighted projection, and the forward
+// transform goes back up with the sibling cell fetched from the neighbouring
+// lane group by a shuffle; the first lane of a parent's group writes its
+// wavelets.  No LDS buffers and no barriers: the waves of a workgroup run
+// their lines independently, and a workgroup walks its tiles in a grid-stride
+// loop (a pass whose problems have converged costs one flag test per tile).
+// The arithmetic of every value is the line kernel's (the same two-scale,
+// point and projection sums in the same order).
+// f and (for the correction and local modes) its Jacobian at one point,
+// summing only the nonzero coefficients of the reaction polynomial: mask has
+// bit s*16 + 4a + b set where c[s][a][b] != 0 (a wave-uniform value, so the
+// loop and the coefficient loads are scalar).  The terms are taken in the
+// order of rx_f / rx_jac and the skipped ones are zeros, so the values agree
+// with those to the last bit.
+template <int S, bool JAC>
+__device__ __forceinline__ void wl_fj(const double* __restrict__ rxc, uint64_t mask, const double* u, double* f,
+                                         double (*J)[2]) {
+  const double u0 = u[0], u1 = S > 1 ? u[1] : 0.0;
+  const double p0[4] = {1.0, u0, u0 * u0, u0 * u0 * u0};
+  const double p1[4] = {1.0, u1, u1 * u1, u1 * u1 * u1};
+  double fa[2] = {0.0, 0.0}, j0[2] = {0.0, 0.0}, j1[2] = {0.0, 0.0};
+  for (uint64_t m = mask; m; m &= m - 1) {
+    const int t = __builtin_ctzll(m);
+    const int sp = t >> 4, aa = (t >> 2) & 3, bb = t & 3;
+    const double c = rxc[t];
+    const double pa = aa == 0 ? p0[0] : (aa == 1 ? p0[1] : (aa == 2 ? p0[2] : p0[3]));
+    const double pb = bb == 0 ? p1[0] : (bb == 1 ? p1[1] : (bb == 2 ? p1[2] : p1[3]));
+    const double v = c * pa * pb;
+    if (sp == 0) fa[0] += v; else fa[1] += v;
+    if (JAC) {
+      if (aa > 0) {
+        const double pm = aa == 1 ? p0[0] : (aa == 2 ? p0[1] : p0[2]);
+        const double w = c * aa * pm * pb;
+        if (sp == 0) j0[0] += w; else j0[1] += w;
+      }
+      if (bb > 0) {
+        const double pm = bb == 1 ? p1[0] : (bb == 2 ? p1[1] : p1[2]);
+        const double w = c * bb * pa * pm;
+        if (sp == 0) j1[0] += w; else j1[1] += w;
+      }
+    }
+  }
+  f[0] = fa[0];
+  f[1] = fa[1];
+  if (JAC) {
+    J[0][0] = j0[0];
+    J[0][1] = j1[0];
+    J[1][0] = j0[1];
+    J[1][1] = j1[1];
+  }
+}
+
+// The pointwise map of a pass (as rx_map) with wl_fj.
+template <int S>
+__device__ __forceinline__ void wl_map(const double* __restrict__ rxc, uint64_t mask, int mode, double dt2,
+                                          const double* u, const double* g, double* out) {
+  if (mode == RX_CORR) {
+    double f[2], J[2][2];
+    wl_fj<S, true>(rxc, mask, u, f, J);
+    if (S == 1) {
+      out[0] = g[0] / (1.0 - dt2 * J[0][0]);
+      out[1] = 0.0;
+    } else {
+      const double A = 1.0 - dt2 * J[0][0], Bq = -dt2 * J[0][1];
+      const double C = -dt2 * J[1][0], D = 1.0 - dt2 * J[1][1];
+      const double det = A * D - Bq * C;
+      out[0] = (D * g[0] - Bq * g[1]) / det;
+      out[1] = (A * g[1] - C * g[0]) / det;
+    }
+  } else if (mode == RX_LOCAL) {
+    const double w0 = u[0], w1v = S > 1 ? u[1] : 0.0;
+    const double wmag = fmax(1.0, fmax(fabs(w0), fabs(w1v)));
+    double x[2] = {w0, w1v};
+    for (int it = 0; it <= RX_LOCAL_MAX_ITER; ++it) {
+      double f[2], J[2][2];
+      wl_fj<S, true>(rxc, mask, x, f, J);
+      const double g0 = x[0] - dt2 * f[0] - w0, g1 = S > 1 ? x[1] - dt2 * f[1] - w1v : 0.0;
+      if (fmax(fabs(g0), fabs(g1)) <= RX_LOCAL_TOL * wmag || it == RX_LOCAL_MAX_ITER) break;
+      if (S == 1) {
+        x[0] -= g0 / (1.0 - dt2 * J[0][0]);
+      } else {
+        const double A = 1.0 - dt2 * J[0][0], Bq = -dt2 * J[0][1];
+        const double C = -dt2 * J[1][0], D = 1.0 - dt2 * J[1][1];
+        const double det = A * D - Bq * C;
+        x[0] -= (D * g0 - Bq * g1) / det;
+        x[1] -= (A * g1 - C * g0) / det;
+      }
+    }
+    out[0] = x[0];
+    out[1] = x[1];
+  } else {
+    wl_fj<S, false>(rxc, mask, u, out, nullptr);
+  }
+}
+
+
+template <int K1, int S, int NIN>
+__global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTask* __restrict__ tasks, int ntask,
+                                                         int ninst, int mode, RxArgs a, int64_t rws, int64_t nwork) {
+  constexpr int NP = S * NIN;
+  constexpr int WL = 64 * K1 * 2;  // doubles of a wave's lines per pair (64 lanes, two cells each at most)
+  __shared__ double Ms[64];     // ML, MR, cL, cR (16 each, row length K1)
+  __shared__ double rxs[32];    // reaction coefficients
+  // each wave stages its lines: inputs [NP][WL], projections [S][WL]; global
+  // loads and stores are then whole contiguous runs of lines
+  __shared__ double stage[RX_THREADS / 64][(NP + S) * WL];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nwv = RX_THREADS / 64;
+  // per-instance state, reloaded when the workgroup's instance changes
+  int loaded = -1;
+  int d = 0, N = 0, n1 = 0, nl2 = 0, LPL = 1, cpl = 1, LPW = 1, Lc = 0;
+  int64_t xoff = 0, yoff = 0, npre = 0;
+  uint64_t mask = 0;
+  double mL[K1][K1], mR[K1][K1], cL[K1][K1], cR[K1][K1];  // two-scale matrices (each lane selects its side)
+  double ELn[K1][K1], wgq[K1];  // finest-level basis at the K1 points of a cell (the same in every cell), weights
+  for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const int rhs = (int)(w / ntask);
+    const LineTask t = tasks[w - (int64_t)rhs * ntask];
+    if (a.conv && a.conv[rhs * ninst + t.inst]) continue;
+    if (t.inst != loaded) {
+      const RInst& I = R.inst[t.inst];
+      __syncthreads();
+      if (threadIdx.x < 64) Ms[threadIdx.x] = R.mats[I.mats_off + threadIdx.x];
+      if (threadIdx.x < 32) rxs[threadIdx.x] = (&I.rx[0][0][0])[threadIdx.x];
+      __syncthreads();
+      loaded = t.inst;
+      d = I.d;
+      N = I.N;
+      n1 = I.n1;
+      xoff = I.X_off[d - 1];
+      yoff = I.Y_off[d - 1];
+      npre = I.npre[d - 1];
+      mask = __ballot(lane < 16 * S && rxs[min(lane, 31)] != 0.0);
+      nl2 = N < 6 ? N : 6;
+      LPL = 1 << nl2;
+      cpl = (1 << N) >> nl2;
+      LPW = 64 / LPL;
+      Lc = lane & (LPL - 1);
+#pragma unroll
+      for (int i = 0; i < K1; ++i)
+#pragma unroll
+        for (int j = 0; j < K1; ++j) {
+          mL[i][j] = Ms[i * K1 + j];
+          mR[i][j] = Ms[16 + i * K1 + j];
+          cL[i][j] = Ms[32 + i * K1 + j];
+          cR[i][j] = Ms[48 + i * K1 + j];
+        }
+      const double* __restrict__ ELg = R.EL + I.EL_off + (int64_t)N * I.np1 * K1;
+#pragma unroll
+      for (int gq = 0; gq < K1; ++gq) {
+        wgq[gq] = R.w1[I.w_off + gq];
+#pragma unroll
+        for (int p = 0; p < K1; ++p) ELn[gq][p] = ELg[gq * K1 + p];
+      }
+    }
+    double* xr = a.rws + (int64_t)rhs * rws;
+    const double dt2 = a.dt2;
+    double* lin = stage[wv];
+    double* lout = stage[wv] + NP * WL;
+    for (int l0 = wv * LPW; l0 < t.nl; l0 += nwv * LPW) {
+      const int li = lane / LPL;
+      const int nline = min(LPW, t.nl - l0);
+      const bool act = li < nline;
+      const int64_t pre0 = t.pre0 + l0;
+#pragma unroll
+      for (int pr = 0; pr < NP; ++pr) {
+        const int z = pr / S, sp = pr - z * S;
+        const double* __restrict__ src = xr + xoff + (((int64_t)z * S + sp) * npre + pre0) * n1;
+        for (int e = lane; e < nline * n1; e += 64) lin[pr * WL + e] = src[e];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int lq = act ? li : 0;
+      // inverse transform down the lane's path
+      double sf[NP][2][K1];
+#pragma unroll
+      for (int pr = 0; pr < NP; ++pr) {
+        const double* xl = lin + pr * WL + lq * n1;
+        double sc[K1];
+#pragma unroll
+        for (int p = 0; p < K1; ++p) sc[p] = xl[p];
+        for (int n = 1; n <= nl2; ++n) {
+          const int jp = Lc >> (nl2 - n + 1), side = (Lc >> (nl2 - n)) & 1;
+          double wc[K1], ch[K1];
+#pragma unroll
+          for (int p = 0; p < K1; ++p) wc[p] = xl[(K1 << (n - 1)) + jp * K1 + p];
+#pragma unroll
+          for (int q = 0; q < K1; ++q) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < K1; ++i) acc += (side ? mR[q][i] : mL[q][i]) * sc[i];
+#pragma unroll
+            for (int p = 0; p < K1; ++p) acc += (side ? cR[p][q] : cL[p][q]) * wc[p];
+            ch[q] = acc;
+          }
+#pragma unroll
+          for (int q = 0; q < K1; ++q) sc[q] = ch[q];
+        }
+        if (cpl == 2) {  // the lane's two finest cells, children of its level-6 cell Lc
+          double wc[K1];
+#pragma unroll
+          for (int p = 0; p < K1; ++p) wc[p] = xl[(K1 << (N - 1)) + Lc * K1 + p];
+#pragma unroll
+          for (int side = 0; side < 2; ++side)
+#pragma unroll
+            for (int q = 0; q < K1; ++q) {
+              double acc = 0.0;
+#pragma unroll
+              for (int i = 0; i < K1; ++i) acc += (side ? mR[q][i] : mL[q][i]) * sc[i];
+#pragma unroll
+              for (int p = 0; p < K1; ++p) acc += (side ? cR[p][q] : cL[p][q]) * wc[p];
+              sf[pr][side][q] = acc;
+            }
+        } else {
+#pragma unroll
+          for (int q = 0; q < K1; ++q) sf[pr][0][q] = sc[q];
+        }
+      }
+      // values at the Gauss points, the map, weights, projection onto the cell's functions
+      double pj[S][2][K1];
+#pragma unroll
+      for (int tc = 0; tc < 2; ++tc)
+        if (tc < cpl) {
+          double ow[2][K1];
+#pragma unroll
+          for (int gq = 0; gq < K1; ++gq) {
+            double u[NP];
+#pragma unroll
+            for (int pr = 0; pr < NP; ++pr) {
+              double v = 0.0;
+#pragma unroll
+              for (int p = 0; p < K1; ++p) v += sf[pr][tc][p] * ELn[gq][p];
+              u[pr] = v;
+            }
+            // pair z S + s: input z, species s
+            double uu[2] = {u[0], 0.0}, gg[2] = {0.0, 0.0};
+            if (S > 1) uu[1] = u[S > 1 ? 1 : 0];
+            if (NIN > 1) gg[0] = u[NIN > 1 ? S : 0];
+            if (NIN > 1 && S > 1) gg[1] = u[NP - 1];
+            double o[2];
+            wl_map<S>(rxs, mask, mode, dt2, uu, gg, o);
+            ow[0][gq] = wgq[gq] * o[0];
+            ow[1][gq] = wgq[gq] * o[1];
+          }
+#pragma unroll
+          for (int sp = 0; sp < S; ++sp)
+#pragma unroll
+            for (int p = 0; p < K1; ++p) {
+              double acc = 0.0;
+#pragma unroll
+              for (int gq = 0; gq < K1; ++gq) acc += ow[sp][gq] * ELn[gq][p];
+              pj[sp][tc][p] = acc;
+            }
+        }
+      // forward transform up the tree
+      auto down = [&](const double* sl, const double* sr, double* pc, double* wc) {
+#pragma unroll
+        for (int i = 0; i < K1; ++i) {
+          double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+          for (int q = 0; q < K1; ++q) {
+            a0 += mL[q][i] * sl[q] + mR[q][i] * sr[q];
+            a1 += cL[i][q] * sl[q] + cR[i][q] * sr[q];
+          }
+          pc[i] = a0;
+          wc[i] = a1;
+        }
+      };
+#pragma unroll
+      for (int sp = 0; sp < S; ++sp) {
+        double* yl = lout + sp * WL + lq * n1;
+        double sc[K1];
+        if (cpl == 2) {
+          double wc[K1];
+          down(pj[sp][0], pj[sp][1], sc, wc);
+          if (act)
+#pragma unroll
+            for (int p = 0; p < K1; ++p) yl[(K1 << (N - 1)) + Lc * K1 + p] = wc[p];
+        } else {
+#pragma unroll
+          for (int p = 0; p < K1; ++p) sc[p] = pj[sp][0][p];
+        }
+        for (int n = nl2; n >= 1; --n) {
+          const int off = 1 << (nl2 - n), j = Lc >> (nl2 - n);
+          double sib[K1], pc[K1], wc[K1];
+#pragma unroll
+          for (int p = 0; p < K1; ++p) sib[p] = __shfl_xor(sc[p], off, 64);
+          if (j & 1)
+            down(sib, sc, pc, wc);
+          else
+            down(sc, sib, pc, wc);
+          if (act && (Lc & (2 * off - 1)) == 0)
+#pragma unroll
+            for (int p = 0; p < K1; ++p) yl[(K1 << (n - 1)) + (j >> 1) * K1 + p] = wc[p];
+#pragma unroll
+          for (int p = 0; p < K1; ++p) sc[p] = pc[p];
+        }
+        if (act && Lc == 0)
+#pragma unroll
+          for (int p = 0; p < K1; ++p) yl[p] = sc[p];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int sp = 0; sp < S; ++sp) {
+        double* __restrict__ dst = xr + yoff + ((int64_t)sp * npre + pre0) * n1;
+        for (int e = lane; e < nline * n1; e += 64) dst[e] = lout[sp * WL + e];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+}
+
 void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s,
                    const std::function<void(int)>* mark) {
   const RHost* rh = (const RHost*)plan->rdata;
@@ -1055,6 +1390,29 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
     });
   for (const LineClass& lc : rh->lclass) {
     if (mark) (*mark)(1);
+    if (d >= 2 && lc.N <= RX_WLINE_MAXN) {
+      const int ntask = (int)lc.tasks[nin].size();
+      const int64_t nwork = (int64_t)ntask * nrhs;
+      const unsigned grid = (unsigned)std::min<int64_t>(nwork, (int64_t)std::max(rh->ncu, 1) * 16);
+      auto wl = [&](auto k1, auto sp, auto ni) {
+        constexpr int K1 = decltype(k1)::value, S = decltype(sp)::value, NIN = decltype(ni)::value;
+        hipLaunchKernelGGL((k_rx_wline<K1, S, NIN>), dim3(grid), dim3(RX_THREADS), 0, s, rh->dev, lc.dev[nin], ntask,
+                           ninst, (int)mode, a, rh->rws, nwork);
+      };
+      auto by_s = [&](auto k1) {
+        if (lc.S == 1) {
+          if (nin == 1) wl(k1, std::integral_constant<int, 1>(), std::integral_constant<int, 1>());
+          else wl(k1, std::integral_constant<int, 1>(), std::integral_constant<int, 2>());
+        } else {
+          if (nin == 1) wl(k1, std::integral_constant<int, 2>(), std::integral_constant<int, 1>());
+          else wl(k1, std::integral_constant<int, 2>(), std::integral_constant<int, 2>());
+        }
+      };
+      if (lc.K1 == 2) by_s(std::integral_constant<int, 2>());
+      else if (lc.K1 == 3) by_s(std::integral_constant<int, 3>());
+      else by_s(std::integral_constant<int, 4>());
+      continue;
+    }
     const dim3 grid((unsigned)lc.tasks[nin].size(), (unsigned)nrhs), blk((unsigned)lc.threads[nin]);
     switch (lc.K1) {
       case 2:

@@ -132,10 +132,13 @@ def test_reaction_F_d1_and_multi_instance():
     (3, 3, 3, "quadratic"),
     (5, 2, 1, "quadratic"),
     (6, 2, 1, "gray_scott"),
+    (3, 6, 3, "gray_scott"),
 ])
 def test_reaction_F_cubic_degree_and_high_dimension(d, N, k, rx):
     """k = 3 (four Gauss points per axis) and d = 5, 6 (the deepest chains of
-    per-axis expansion and contraction stages), one and two species."""
+    per-axis expansion and contraction stages), one and two species; d=3 N=6
+    k=3 with two species runs its last axis in the wave form of the line
+    kernel with 64 finest cells per line and four inputs per point."""
     sg = lib()
     import torch
 
