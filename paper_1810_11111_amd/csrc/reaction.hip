@@ -95,7 +95,7 @@ constexpr int RX_ITEMS = 2;            // transform items per thread of a line t
 constexpr int RX_TAIL = 64 + 32 + 8;   // two-scale matrices, reaction coefficients, per-wave partial sums
 constexpr int64_t RX_THREADS_WANTED = 1 << 17;
 constexpr int RX_WALK = 64;  // most points one thread of an expansion / contraction walks
-constexpr int RX_WLINE_MAXN = 7;   // last-axis wave form: at most two finest cells per lane
+constexpr int RX_WLINE_MAXN = 8;   // last-axis wave form: lines of at most 64 lanes (N <= 8 at k = 1)
 constexpr int RX_WLINE_ROUNDS = 16; // its tiles: at most 16 rounds of one line per wave (more lines for N < 6)
 
 // LDS of the last-axis kernel: per line 2.5 npair n1 doubles (inputs, and the
@@ -289,7 +289,9 @@ sgdg_status reaction_build(sgdg_plan* plan) {
           // wave form: a whole number of wave rounds (4 waves, LPW lines each),
           // up to 16 rounds, and about 2048 tiles per instance where it has
           // fewer lines (small problems keep many workgroups)
-          const int64_t round = (int64_t)(RX_THREADS / 64) << std::max(0, 6 - N);
+          const int cplh = std::min(K1 == 2 ? 8 : 4, 1 << N);  // finest cells per lane (wl_cpl)
+          const int hh = N - (cplh == 8 ? 3 : cplh == 4 ? 2 : cplh == 2 ? 1 : 0);
+          const int64_t round = (int64_t)(RX_THREADS / 64) * (64 >> std::min(hh, 6));
           const int64_t want = std::max<int64_t>(1, r.npre[d - 1] / 2048 / round);
           nl = round * std::min<int64_t>(want, RX_WLINE_ROUNDS);
         }
@@ -1043,20 +1045,27 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, const LineTas
 }
 
 // Last axis, wave form (d >= 2, N <= RX_WLINE_MAXN): a group of lanes takes a
-// whole line, one finest cell per lane (two when N = 7).  A wave copies its
-// lines (a contiguous run) into its own LDS buffer with coalesced loads,
-// works on them there, and writes the projections back as one run.  Each lane follows
-// the cells that contain its own down the tree (inverse fast multiwavelet
-// transform by the two-scale relations; every lane reads the wavelets on its
-// path, so no data moves between lanes), evaluates the K1 Gauss points of its
-// cells, applies the map and the weighted projection, and the forward
-// transform goes back up with the sibling cell fetched from the neighbouring
-// lane group by a shuffle; the first lane of a parent's group writes its
-// wavelets.  No LDS buffers and no barriers: the waves of a workgroup run
-// their lines independently, and a workgroup walks its tiles in a grid-stride
+// whole line; each lane owns a subtree of the line's cells (its level-h cell,
+// 2^h lanes per line, and the up to WL_CPL<K1> finest cells below it).  A
+// wave copies its lines (a contiguous run) into its own LDS buffer with
+// coalesced loads.  The inverse fast multiwavelet transform (two-scale
+// relations) runs down each lane's path to its level-h cell (the same
+// coarse cells in every lane of a line) and then through its subtree in
+// registers; the lane evaluates its Gauss points, applies the map and the
+// weighted projection, and the forward transform climbs its subtree in
+// registers, then the levels above h with the sibling cell fetched from the
+// neighbouring lane group by a shuffle (the first lane of a parent's group
+// writes its wavelets).  The projections overwrite the line's inputs in the
+// wave's buffer (every input is read before the first output is written) and
+// go back to HBM as one run.  No barriers; tiles are walked in a grid-stride
 // loop (a pass whose problems have converged costs one flag test per tile).
 // The arithmetic of every value is the line kernel's (the same two-scale,
 // point and projection sums in the same order).
+template <int K1>
+constexpr int wl_cpl() {
+  return K1 == 2 ? 8 : 4;  // finest cells per lane (at most)
+}
+
 // f and (for the correction and local modes) its Jacobian at one point,
 // summing only the nonzero coefficients of the reaction polynomial: mask has
 // bit s*16 + 4a + b set where c[s][a][b] != 0 (a wave-uniform value, so the
@@ -1149,19 +1158,18 @@ template <int K1, int S, int NIN>
 __global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTask* __restrict__ tasks, int ntask,
                                                          int ninst, int mode, RxArgs a, int64_t rws, int64_t nwork) {
   constexpr int NP = S * NIN;
-  constexpr int WL = 64 * K1 * 2;  // doubles of a wave's lines per pair (64 lanes, two cells each at most)
+  constexpr int CP = wl_cpl<K1>();
+  constexpr int WL = 64 * K1 * CP;  // doubles of a wave's lines per pair
   __shared__ double Ms[64];     // ML, MR, cL, cR (16 each, row length K1)
   __shared__ double rxs[32];    // reaction coefficients
-  // each wave stages its lines: inputs [NP][WL], projections [S][WL]; global
-  // loads and stores are then whole contiguous runs of lines
-  __shared__ double stage[RX_THREADS / 64][(NP + S) * WL];
+  __shared__ double stage[RX_THREADS / 64][NP * WL];  // each wave's lines, inputs then projections
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nwv = RX_THREADS / 64;
   // per-instance state, reloaded when the workgroup's instance changes
   int loaded = -1;
-  int d = 0, N = 0, n1 = 0, nl2 = 0, LPL = 1, cpl = 1, LPW = 1, Lc = 0;
+  int N = 0, n1 = 0, h = 0, LPL = 1, cpl = 1, LPW = 1, Lc = 0;
   int64_t xoff = 0, yoff = 0, npre = 0;
   uint64_t mask = 0;
-  double mL[K1][K1], mR[K1][K1], cL[K1][K1], cR[K1][K1];  // two-scale matrices (each lane selects its side)
+  double mL[K1][K1], mR[K1][K1], cL[K1][K1], cR[K1][K1];  // two-scale matrices
   double ELn[K1][K1], wgq[K1];  // finest-level basis at the K1 points of a cell (the same in every cell), weights
   for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int rhs = (int)(w / ntask);
@@ -1174,16 +1182,16 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTa
       if (threadIdx.x < 32) rxs[threadIdx.x] = (&I.rx[0][0][0])[threadIdx.x];
       __syncthreads();
       loaded = t.inst;
-      d = I.d;
+      const int d = I.d;
       N = I.N;
       n1 = I.n1;
       xoff = I.X_off[d - 1];
       yoff = I.Y_off[d - 1];
       npre = I.npre[d - 1];
       mask = __ballot(lane < 16 * S && rxs[min(lane, 31)] != 0.0);
-      nl2 = N < 6 ? N : 6;
-      LPL = 1 << nl2;
-      cpl = (1 << N) >> nl2;
+      cpl = min(CP, 1 << N);
+      h = N - (31 - __clz(cpl));  // level at which a lane owns one cell
+      LPL = 1 << h;
       LPW = 64 / LPL;
       Lc = lane & (LPL - 1);
 #pragma unroll
@@ -1203,10 +1211,42 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTa
         for (int p = 0; p < K1; ++p) ELn[gq][p] = ELg[gq * K1 + p];
       }
     }
+    // children (left, right) of a cell from its coefficients and wavelets
+    auto up2 = [&](const double* sc, const double* wc, double* cl, double* cr) {
+#pragma unroll
+      for (int q = 0; q < K1; ++q) {
+        double al = 0.0, ar = 0.0;
+#pragma unroll
+        for (int i = 0; i < K1; ++i) {
+          al += mL[q][i] * sc[i];
+          ar += mR[q][i] * sc[i];
+        }
+#pragma unroll
+        for (int p = 0; p < K1; ++p) {
+          al += cL[p][q] * wc[p];
+          ar += cR[p][q] * wc[p];
+        }
+        cl[q] = al;
+        cr[q] = ar;
+      }
+    };
+    // parent coefficients and wavelets from the two children
+    auto down = [&](const double* sl, const double* sr, double* pc, double* wc) {
+#pragma unroll
+      for (int i = 0; i < K1; ++i) {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < K1; ++q) {
+          a0 += mL[q][i] * sl[q] + mR[q][i] * sr[q];
+          a1 += cL[i][q] * sl[q] + cR[i][q] * sr[q];
+        }
+        pc[i] = a0;
+        wc[i] = a1;
+      }
+    };
     double* xr = a.rws + (int64_t)rhs * rws;
     const double dt2 = a.dt2;
-    double* lin = stage[wv];
-    double* lout = stage[wv] + NP * WL;
+    double* buf = stage[wv];
     for (int l0 = wv * LPW; l0 < t.nl; l0 += nwv * LPW) {
       const int li = lane / LPL;
       const int nline = min(LPW, t.nl - l0);
@@ -1216,61 +1256,56 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTa
       for (int pr = 0; pr < NP; ++pr) {
         const int z = pr / S, sp = pr - z * S;
         const double* __restrict__ src = xr + xoff + (((int64_t)z * S + sp) * npre + pre0) * n1;
-        for (int e = lane; e < nline * n1; e += 64) lin[pr * WL + e] = src[e];
+        for (int e = lane; e < nline * n1; e += 64) buf[pr * WL + e] = src[e];
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const int lq = act ? li : 0;
-      // inverse transform down the lane's path
-      double sf[NP][2][K1];
+      // inverse transform: down the path to the lane's level-h cell, then its subtree
+      double fin[NP][CP][K1];
 #pragma unroll
       for (int pr = 0; pr < NP; ++pr) {
-        const double* xl = lin + pr * WL + lq * n1;
+        const double* xl = buf + pr * WL + lq * n1;
         double sc[K1];
 #pragma unroll
         for (int p = 0; p < K1; ++p) sc[p] = xl[p];
-        for (int n = 1; n <= nl2; ++n) {
-          const int jp = Lc >> (nl2 - n + 1), side = (Lc >> (nl2 - n)) & 1;
-          double wc[K1], ch[K1];
+        for (int n = 1; n <= h; ++n) {
+          const int jp = Lc >> (h - n + 1), side = (Lc >> (h - n)) & 1;
+          double wc[K1], cl[K1], cr[K1];
 #pragma unroll
           for (int p = 0; p < K1; ++p) wc[p] = xl[(K1 << (n - 1)) + jp * K1 + p];
+          up2(sc, wc, cl, cr);
 #pragma unroll
-          for (int q = 0; q < K1; ++q) {
-            double acc = 0.0;
+          for (int q = 0; q < K1; ++q) sc[q] = side ? cr[q] : cl[q];
+        }
 #pragma unroll
-            for (int i = 0; i < K1; ++i) acc += (side ? mR[q][i] : mL[q][i]) * sc[i];
+        for (int q = 0; q < K1; ++q) fin[pr][0][q] = sc[q];
+        // subtree levels h+1..N: cells of level n below the lane's cell are
+        // Lc 2^(n-h) + c, c < 2^(n-h); expanded in place from the last parent down
 #pragma unroll
-            for (int p = 0; p < K1; ++p) acc += (side ? cR[p][q] : cL[p][q]) * wc[p];
-            ch[q] = acc;
+        for (int g = 1; g < CP; g *= 2)
+          if (g < cpl) {
+            const int n = h + 1 + (31 - __clz(g));  // level formed in this round (g parents)
+#pragma unroll
+            for (int c = CP / 2 - 1; c >= 0; --c)
+              if (c < g) {
+                double wc[K1], cl[K1], cr[K1];
+#pragma unroll
+                for (int p = 0; p < K1; ++p) wc[p] = xl[(K1 << (n - 1)) + (Lc * g + c) * K1 + p];
+                up2(fin[pr][c], wc, cl, cr);
+#pragma unroll
+                for (int q = 0; q < K1; ++q) {
+                  fin[pr][2 * c][q] = cl[q];
+                  fin[pr][2 * c + 1][q] = cr[q];
+                }
+              }
           }
-#pragma unroll
-          for (int q = 0; q < K1; ++q) sc[q] = ch[q];
-        }
-        if (cpl == 2) {  // the lane's two finest cells, children of its level-6 cell Lc
-          double wc[K1];
-#pragma unroll
-          for (int p = 0; p < K1; ++p) wc[p] = xl[(K1 << (N - 1)) + Lc * K1 + p];
-#pragma unroll
-          for (int side = 0; side < 2; ++side)
-#pragma unroll
-            for (int q = 0; q < K1; ++q) {
-              double acc = 0.0;
-#pragma unroll
-              for (int i = 0; i < K1; ++i) acc += (side ? mR[q][i] : mL[q][i]) * sc[i];
-#pragma unroll
-              for (int p = 0; p < K1; ++p) acc += (side ? cR[p][q] : cL[p][q]) * wc[p];
-              sf[pr][side][q] = acc;
-            }
-        } else {
-#pragma unroll
-          for (int q = 0; q < K1; ++q) sf[pr][0][q] = sc[q];
-        }
       }
       // values at the Gauss points, the map, weights, projection onto the cell's functions
-      double pj[S][2][K1];
+      double pj[S][CP][K1];
 #pragma unroll
-      for (int tc = 0; tc < 2; ++tc)
+      for (int tc = 0; tc < CP; ++tc)
         if (tc < cpl) {
           double ow[2][K1];
 #pragma unroll
@@ -1280,7 +1315,7 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTa
             for (int pr = 0; pr < NP; ++pr) {
               double v = 0.0;
 #pragma unroll
-              for (int p = 0; p < K1; ++p) v += sf[pr][tc][p] * ELn[gq][p];
+              for (int p = 0; p < K1; ++p) v += fin[pr][tc][p] * ELn[gq][p];
               u[pr] = v;
             }
             // pair z S + s: input z, species s
@@ -1303,36 +1338,36 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTa
               pj[sp][tc][p] = acc;
             }
         }
-      // forward transform up the tree
-      auto down = [&](const double* sl, const double* sr, double* pc, double* wc) {
-#pragma unroll
-        for (int i = 0; i < K1; ++i) {
-          double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-          for (int q = 0; q < K1; ++q) {
-            a0 += mL[q][i] * sl[q] + mR[q][i] * sr[q];
-            a1 += cL[i][q] * sl[q] + cR[i][q] * sr[q];
-          }
-          pc[i] = a0;
-          wc[i] = a1;
-        }
-      };
+      // every input of the wave's lines has been read: the projections go to
+      // the buffers of input 0 (pair sp)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // forward transform: the subtree in registers, then the levels above h
 #pragma unroll
       for (int sp = 0; sp < S; ++sp) {
-        double* yl = lout + sp * WL + lq * n1;
+        double* yl = buf + sp * WL + lq * n1;
+#pragma unroll
+        for (int g = CP / 2; g >= 1; g /= 2)
+          if (g < cpl) {
+            const int n = h + 1 + (31 - __clz(g));  // level of the children combined in this round
+#pragma unroll
+            for (int c = 0; c < CP / 2; ++c)
+              if (c < g) {
+                double pc[K1], wc[K1];
+                down(pj[sp][2 * c], pj[sp][2 * c + 1], pc, wc);
+                if (act)
+#pragma unroll
+                  for (int p = 0; p < K1; ++p) yl[(K1 << (n - 1)) + (Lc * g + c) * K1 + p] = wc[p];
+#pragma unroll
+                for (int p = 0; p < K1; ++p) pj[sp][c][p] = pc[p];
+              }
+          }
         double sc[K1];
-        if (cpl == 2) {
-          double wc[K1];
-          down(pj[sp][0], pj[sp][1], sc, wc);
-          if (act)
 #pragma unroll
-            for (int p = 0; p < K1; ++p) yl[(K1 << (N - 1)) + Lc * K1 + p] = wc[p];
-        } else {
-#pragma unroll
-          for (int p = 0; p < K1; ++p) sc[p] = pj[sp][0][p];
-        }
-        for (int n = nl2; n >= 1; --n) {
-          const int off = 1 << (nl2 - n), j = Lc >> (nl2 - n);
+        for (int p = 0; p < K1; ++p) sc[p] = pj[sp][0][p];
+        for (int n = h; n >= 1; --n) {
+          const int off = 1 << (h - n), j = Lc >> (h - n);
           double sib[K1], pc[K1], wc[K1];
 #pragma unroll
           for (int p = 0; p < K1; ++p) sib[p] = __shfl_xor(sc[p], off, 64);
@@ -1356,7 +1391,7 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTa
 #pragma unroll
       for (int sp = 0; sp < S; ++sp) {
         double* __restrict__ dst = xr + yoff + ((int64_t)sp * npre + pre0) * n1;
-        for (int e = lane; e < nline * n1; e += 64) dst[e] = lout[sp * WL + e];
+        for (int e = lane; e < nline * n1; e += 64) dst[e] = buf[sp * WL + e];
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
