@@ -71,14 +71,22 @@ def build_ic(plan, wl, inst_of=None, nrhs=1):
 
 # ----------------------------------------------------------------------------- timed steps
 
-def run_steps(sg, torch, insts, prec, wl, U0, steps, warmup, nrhs=1, local=False, iif3=False):
-    """`steps` graph-replayed steps after `warmup` untimed ones.  Returns
-    (seconds, final U, stats)."""
+TUNING = {}
+
+
+def run_steps(sg, torch, insts, prec, wl, U0, steps, warmup, nrhs=1, local=False, iif3=False, tag=None):
+    """`steps` graph-replayed steps after `warmup` untimed ones, on a plan whose
+    last-axis launch shapes were autotuned first (outside the timed region;
+    the report goes to TUNING[tag]).  Returns (seconds, final U, stats)."""
     plan = sg.Plan(insts, prec)
     Ud = torch.from_numpy(np.ascontiguousarray(U0.reshape(nrhs, -1))).cuda()
     F = torch.zeros_like(Ud)
     _, ib = plan.workspace_size(wl.M, nrhs)
     ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
+    t0 = time.perf_counter()
+    rep = plan.tune(ws, nrhs=nrhs)
+    if tag:
+        TUNING[tag] = {"seconds": time.perf_counter() - t0, "classes": rep}
     st = torch.zeros(nrhs * len(insts) * 2 * sg.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     plan.reaction(Ud, F, ws, nrhs=nrhs)
     Fp = None
@@ -162,6 +170,7 @@ def reaction_stage_times(sg, torch, insts, nrhs, U0, reps):
     F = torch.zeros_like(U)
     _, ib = plan.workspace_size(1, nrhs)
     ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
+    plan.tune(ws, nrhs=nrhs)  # (the shapes of the timed steps, from the process cache)
     plan.reaction(U, F, ws, nrhs=nrhs)  # warm
     torch.cuda.synchronize()
     runs = [plan.reaction_timed(U, F, ws, nrhs=nrhs) for _ in range(reps)]
@@ -313,18 +322,25 @@ def counters(name, reps):
         F = torch.zeros_like(U)
         _, ib = plan.workspace_size(1, nrhs)
         ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
+        plan.tune(ws, nrhs=nrhs)
         for _ in range(reps):
             plan.reaction(U, F, ws, nrhs=nrhs)
         what = f"{reps} reaction passes, nrhs={nrhs}"
     else:
         raise SystemExit(f"unknown counter workload {name}")
     torch.cuda.synchronize()
+    # calibration: a copy of 256 MiB whose source has been pushed out of every
+    # cache (2 GiB written after it), so FETCH_SIZE and WRITE_SIZE of the copy
+    # read 256 MiB each from and to HBM
     n = (256 << 20) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
+    flush = torch.ones((2 << 30) // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    print(f"[counters] {name}: {what}; copy of {n * 8} bytes", flush=True)
+    del flush
+    print(f"[counters] {name}: {what}; copy of {n * 8} bytes (the second elementwise kernel after the 2 GiB fill)",
+          flush=True)
 
 
 # ----------------------------------------------------------------------------- main
@@ -362,7 +378,8 @@ def main():
     plan0.close()
     dofs = ndof * NRHS
     log(f"[bench] d=4 N=6 k=1, {NRHS} right-hand sides, fp64: {args.steps} steps, warmup {args.warmup}")
-    secs, U64, st64 = run_steps(sg, torch, insts, "fp64", wl, U0, args.steps, args.warmup, nrhs=NRHS)
+    secs, U64, st64 = run_steps(sg, torch, insts, "fp64", wl, U0, args.steps, args.warmup, nrhs=NRHS,
+                                tag="quadratic_d4_batch16")
     ok64 = status_ok(st64, 2 * NRHS)
     if not ok64:
         log("[bench] error: a step did not converge or produced non-finite values", st64["status"][: 2 * NRHS])
@@ -396,8 +413,8 @@ def main():
     triad_gbs, triad_bytes = triad(torch)
     out["roofline"] = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-        "traffic": traffic_record("k_rx_line_quadratic_d4_rhs16", REACTION_SOURCES),
-        "kernel": "k_rx_line<2> (last-axis reaction kernel: inverse transform, f, forward transform)",
+        "traffic": traffic_record("k_rx_wline_quadratic_d4_rhs16", REACTION_SOURCES),
+        "kernel": "k_rx_wline<2,1,1> (last-axis reaction kernel, wave form: inverse transform, f, forward transform)",
         "avg_us": line_ms * 1e3, "bytes_per_launch": line_bytes, "frac_of_triad": achieved / triad_gbs,
         "reaction_pass": {"stage_kinds": kinds, "stage_ms": ms, "pass_ms": pass_ms,
                           "note": "kinds: 0 expansion (axes 0..2), 1 last axis, 2 contraction; F pass, 16 RHS"},
@@ -405,6 +422,9 @@ def main():
                 "268M points per RHS read once, its projection written once); duration from HIP events "
                 "around the launch on its stream",
     }
+    out["autotune"] = dict(TUNING, note="last-axis reaction kernel: rounds per tile and workgroups per CU chosen "
+                                         "from timed trials (sg_dg_tune) before the timed steps; index 0 / 1 = one / "
+                                         "two inputs per point")
     out["triad"] = {"achieved_gbs": triad_gbs, "bytes": triad_bytes, "frac_of_peak": triad_gbs / HBM_PEAK_GBS,
                     "note": "c = a + 0.5 b over three 1 GiB FP64 arrays"}
 
@@ -436,6 +456,11 @@ def main():
                 ref3 = u
             else:
                 ent[prec]["rel_l2_vs_fp64"] = float(np.linalg.norm(u - ref3) / np.linalg.norm(ref3))
+                ent[prec]["l2_vs_fp64_over_initial_norm"] = float(np.linalg.norm(u - ref3) / np.linalg.norm(u3))
+        ent["note"] = ("the state decays by about 4 orders of magnitude per step (all 8 modes have |freq|^2 >= 1 "
+                       "under k_ii >= 0.5), so after the timed steps the relative difference measures BF16 "
+                       "rounding against a vanishing state; the difference is also stated against the initial norm, "
+                       "and rel_l2_vs_oracle holds the two-step errors against the oracle")
         extras["allen_cahn_d3"] = ent
         # d=2 Schnakenberg (two species), IIF2 / IIF3 / local stage
         w2 = I.schnakenberg_d2()
@@ -504,8 +529,25 @@ def main():
                 errs[f"rhs{r}_{prec}"] = float(np.linalg.norm(d_) / np.linalg.norm(g["U2"][0]))
                 del ws
                 plan.close()
+        g = np.load(os.path.join(ROOT, "tests", "golden", "fullsize_c3.npz"), allow_pickle=False)
+        w3 = I.allen_cahn_d3()
+        for prec in ("fp64", "bf16"):
+            plan = sg.Plan(w3.instances, prec)
+            Ud = torch.from_numpy(g["U0"].copy()).cuda()
+            F = torch.zeros_like(Ud)
+            _, ib = plan.workspace_size(w3.M, 1)
+            ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
+            plan.reaction(Ud, F, ws)
+            for _ in range(2):
+                plan.iif2_step(w3.dt, w3.M, Ud, F, ws, newton_tol=NEWTON_TOL, newton_max=12)
+            torch.cuda.synchronize()
+            d_ = Ud.cpu().numpy()[0] - g["U2"][0]
+            errs[f"allen_cahn_d3_{prec}"] = float(np.linalg.norm(d_) / np.linalg.norm(g["U2"][0]))
+            del ws
+            plan.close()
         out["rel_l2_vs_oracle"] = dict(errs, note="two IIF2 steps from the oracle's projection of the initial data, "
-                                                  "against the oracle's full-size states")
+                                                  "against the oracle's full-size states (d=4 N=6 right-hand sides "
+                                                  "0 and 15; d=3 Allen-Cahn)")
     if not args.no_cpu:
         log("[bench] cpu oracle (all threads)")
         out["cpu_baseline"] = cpu_baseline_d4(iters)

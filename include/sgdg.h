@@ -270,6 +270,46 @@ sgdg_status iif2_step_local(const sgdg_plan* plan, int32_t nrhs, double dt, int3
 sgdg_status rk_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t order, double* U, void* workspace,
                     size_t workspace_bytes, void* stream);
 
+/* ---- Launch-shape autotuning ------------------------------------------------
+ * The last axis of the reaction transforms (Sec. 5: F(U) = P f(R U), applied
+ * axis by axis) runs, for every class of instances with the same degree,
+ * level and species count and N <= 8 (d >= 2), as tiles of whole lines walked
+ * by a grid-stride launch.  Its shape -- lines per tile (in rounds: one round
+ * gives every wave of a workgroup its lines once) and workgroups per compute
+ * unit -- changes only which workgroup computes which line: every value is
+ * computed the same way, so results are bit for bit the same for every
+ * shape.  These calls change a plan's launch shapes: no other call may use
+ * the plan while they run. */
+#define SGDG_TUNE_MAXCLASS 16
+typedef struct {
+  int32_t nclass;                                  /* classes reported (wave-form last axis only)      */
+  int32_t k[SGDG_TUNE_MAXCLASS], n[SGDG_TUNE_MAXCLASS], nspecies[SGDG_TUNE_MAXCLASS];
+  int32_t cls[SGDG_TUNE_MAXCLASS];                 /* class index for sg_dg_line_shape                  */
+  int32_t rounds[SGDG_TUNE_MAXCLASS][2];           /* chosen rounds per tile, one and two inputs/point */
+  int32_t wgcu[SGDG_TUNE_MAXCLASS][2];             /* chosen workgroups per compute unit               */
+  float ms_default[SGDG_TUNE_MAXCLASS][2];         /* one launch at the shape found on entry           */
+  float ms_best[SGDG_TUNE_MAXCLASS][2];            /* one launch at the chosen shape                   */
+  int32_t from_cache[SGDG_TUNE_MAXCLASS][2];       /* 1: taken from this process's earlier tuning      */
+} sgdg_tune_report;
+
+/* Times every candidate shape (rounds 1, 2, 4, 8, 16, 32 x workgroups per CU
+ * 4, 8, 16, 32) of each class's last-axis launch for nrhs right-hand sides,
+ * one and two inputs per point, with HIP events on `stream` (synchronising
+ * it), and keeps the fastest.  Choices are cached per process by device,
+ * (degree, level, species), inputs, nrhs and line count; a cached class is
+ * set without timing.  workspace: at least iif2_bytes for M = 1 and nrhs
+ * (sg_dg_workspace_size); its contents are overwritten.  report: host
+ * pointer, may be NULL.  Errors: SGDG_ERR_ARG, _UNSUPPORTED (no reaction
+ * tables for this plan), _HIP.                                              */
+sgdg_status sg_dg_tune(sgdg_plan* plan, int32_t nrhs, void* workspace, size_t workspace_bytes,
+                       sgdg_tune_report* report, void* stream);
+
+/* Sets the shape of class `cls`, `ninputs` (1: F and residual passes, 2: the
+ * stage correction) to `rounds` rounds per tile (1..64) and `wgcu` workgroups
+ * per compute unit (1..64).  Errors: SGDG_ERR_ARG, _UNSUPPORTED (the class
+ * does not run the wave form), _HIP.                                        */
+sgdg_status sg_dg_line_shape(sgdg_plan* plan, int32_t cls, int32_t ninputs, int32_t rounds, int32_t wgcu);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,8 +18,10 @@
 //   solve U - 5/12 dt F(U) = W the same way from U = W + 5/12 dt F^n.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -482,4 +484,136 @@ extern "C" sgdg_status iif2_step_local(const sgdg_plan* plan, int32_t nrhs, doub
   reaction_pass(plan, nrhs, RX_F, b, s);
   if (S_next) hipLaunchKernelGGL(k_axpy, vg, vb, 0, s, Fcache, Fcache, 1.0, S_next, n);
   return check_launch("iif2_step_local launch");
+}
+
+// ---------------------------------------------------------------- launch-shape autotuning
+namespace {
+std::mutex g_tune_mu;
+std::map<std::array<int64_t, 7>, std::pair<int, int>> g_tune_cache;  // -> (rounds, workgroups per CU)
+}  // namespace
+
+extern "C" sgdg_status sg_dg_line_shape(sgdg_plan* plan, int32_t cls, int32_t ninputs, int32_t rounds, int32_t wgcu) {
+  if (!plan) return fail(SGDG_ERR_ARG, "sg_dg_line_shape: null plan");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "sg_dg_line_shape: the plan has no reaction tables");
+  // (queued work of any stream may still read the tile list being replaced)
+  const hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "sg_dg_line_shape: synchronise");
+  return reaction_set_line_shape(plan, cls, ninputs, rounds, wgcu);
+}
+
+extern "C" sgdg_status sg_dg_tune(sgdg_plan* plan, int32_t nrhs, void* workspace, size_t workspace_bytes,
+                                  sgdg_tune_report* report, void* stream) {
+  if (!plan) return fail(SGDG_ERR_ARG, "sg_dg_tune: null plan");
+  if (nrhs < 1 || nrhs > 65535) return fail(SGDG_ERR_ARG, "sg_dg_tune: nrhs must be in 1..65535");
+  if (!workspace) return fail(SGDG_ERR_ARG, "sg_dg_tune: null workspace");
+  if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "sg_dg_tune: the plan has no reaction tables");
+  if (workspace_bytes < iif2_ws_bytes(plan, 1, nrhs)) return fail(SGDG_ERR_ARG, "sg_dg_tune: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  sgdg_tune_report rep{};
+  // (queued work of any stream may still read the tile lists being replaced)
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "sg_dg_tune: synchronise");
+  IifWs w = carve(plan, 1, nrhs, workspace);
+  // fixed inputs for the timed launches: the reaction workspace and both input vectors zero
+  const size_t tot = (size_t)plan->total * nrhs;
+  e = hipMemsetAsync(w.rws, 0, (size_t)reaction_ws_doubles(plan) * nrhs * 8, s);
+  if (e == hipSuccess) e = hipMemsetAsync(w.v, 0, tot * 8, s);
+  if (e == hipSuccess) e = hipMemsetAsync(w.W, 0, tot * 8, s);
+  if (e != hipSuccess) return hip_fail(e, "sg_dg_tune: workspace fill");
+  RxArgs a{};
+  a.rws = w.rws;
+  a.U = w.v;
+  a.G = w.W;
+  a.F = w.F;
+  a.Gout = w.G;
+  a.W = w.W2;
+  a.part = w.part;
+  a.dt2 = 1e-3;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(e, "sg_dg_tune: events");
+  }
+  static const int kRounds[] = {1, 2, 4, 8, 16, 32};
+  static const int kWgcu[] = {4, 8, 16, 32};
+  constexpr int kReps = 3;
+  sgdg_status st = SGDG_OK;
+  const int ncls = reaction_line_classes(plan);
+  for (int c = 0; c < ncls && st == SGDG_OK; ++c) {
+    const LineClass& lc = reaction_line_class(plan, c);
+    if (!lc.wave || rep.nclass >= SGDG_TUNE_MAXCLASS) continue;
+    const int slot = rep.nclass++;
+    rep.k[slot] = lc.K1 - 1;
+    rep.n[slot] = lc.N;
+    rep.nspecies[slot] = lc.S;
+    rep.cls[slot] = c;
+    int64_t lines = 0, most = 0;
+    for (const auto& il : lc.lines) {
+      lines += il.second;
+      most = std::max(most, il.second);
+    }
+    for (int nin = 1; nin <= 2 && st == SGDG_OK; ++nin) {
+      const RxMode mode = nin == 1 ? RX_F : RX_CORR;
+      // one launch of the class's last axis at a shape, averaged over kReps after a warm-up
+      auto time_shape = [&](int r, int g, float* ms) -> sgdg_status {
+        sgdg_status q = reaction_set_line_shape(plan, c, nin, r, g);
+        if (q != SGDG_OK) return q;
+        reaction_line_stage(plan, nrhs, mode, a, s, c);
+        hipError_t he = hipEventRecord(e0, s);
+        for (int i = 0; i < kReps && he == hipSuccess; ++i) {
+          reaction_line_stage(plan, nrhs, mode, a, s, c);
+          he = hipGetLastError();
+        }
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+        if (he != hipSuccess) return hip_fail(he, "sg_dg_tune: timed launch");
+        *ms = t / kReps;
+        return SGDG_OK;
+      };
+      const std::array<int64_t, 7> key{plan->device, lc.K1, lc.N, lc.S, nin, nrhs, lines};
+      {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+          st = reaction_set_line_shape(plan, c, nin, it->second.first, it->second.second);
+          rep.rounds[slot][nin - 1] = it->second.first;
+          rep.wgcu[slot][nin - 1] = it->second.second;
+          rep.from_cache[slot][nin - 1] = 1;
+          continue;
+        }
+      }
+      const int r0 = lc.rounds[nin], g0 = lc.wgcu[nin];
+      float t0 = 0.f;
+      if ((st = time_shape(r0, g0, &t0)) != SGDG_OK) break;
+      int rb = r0, gb = g0;
+      float tb = t0;
+      for (int r : kRounds) {
+        if (r > 1 && (int64_t)lc.lpr * (r / 2) >= most) break;  // (no more lines per tile than the largest instance has)
+        for (int g : kWgcu) {
+          float t = 0.f;
+          if ((st = time_shape(r, g, &t)) != SGDG_OK) break;
+          if (t < tb) {
+            tb = t;
+            rb = r;
+            gb = g;
+          }
+        }
+        if (st != SGDG_OK) break;
+      }
+      if (st != SGDG_OK) break;
+      if ((st = reaction_set_line_shape(plan, c, nin, rb, gb)) != SGDG_OK) break;
+      rep.rounds[slot][nin - 1] = rb;
+      rep.wgcu[slot][nin - 1] = gb;
+      rep.ms_default[slot][nin - 1] = t0;
+      rep.ms_best[slot][nin - 1] = tb;
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      g_tune_cache[key] = {rb, gb};
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (report) *report = rep;
+  return st;
 }

@@ -64,6 +64,16 @@ struct LineClass {
   LineTask* dev[3] = {};
   size_t lds[3] = {};  // dynamic LDS bytes
   int threads[3] = {}; // workgroup size
+  // wave form (d >= 2, N <= RX_WLINE_MAXN): a tile is `rounds` rounds of
+  // `lpr` lines (one round: every wave of the workgroup takes its lines once);
+  // its grid-stride launch has wgcu workgroups per compute unit.  Launch
+  // shapes only: every line is computed the same way whatever the shape.
+  bool wave = false;
+  int lpr = 0;
+  int rounds[3] = {};
+  int wgcu[3] = {};
+  size_t cap_tasks[3] = {};                     // room in dev[nin] (tiles of one round)
+  std::vector<std::pair<int, int64_t>> lines;   // (instance, lines of its last axis)
 };
 
 struct RHost {
@@ -111,5 +121,13 @@ struct RxArgs {
 void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s,
                    const std::function<void(int)>* mark = nullptr);
 int64_t reaction_ws_doubles(const sgdg_plan* plan);
+
+// Launch shapes of the last-axis kernels (autotuning).  Classes are the plan's
+// (degree, level, species) groups of instances.
+int reaction_line_classes(const sgdg_plan* plan);
+const LineClass& reaction_line_class(const sgdg_plan* plan, int c);
+sgdg_status reaction_set_line_shape(sgdg_plan* plan, int c, int nin, int rounds, int wgcu);
+// Only the last-axis launch of class c of a pass (inputs: the reaction workspace).
+void reaction_line_stage(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s, int c);
 
 }  // namespace sgdg

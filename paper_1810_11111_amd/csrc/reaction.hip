@@ -96,7 +96,8 @@ constexpr int RX_TAIL = 64 + 32 + 8;   // two-scale matrices, reaction coefficie
 constexpr int64_t RX_THREADS_WANTED = 1 << 17;
 constexpr int RX_WALK = 64;  // most points one thread of an expansion / contraction walks
 constexpr int RX_WLINE_MAXN = 8;   // last-axis wave form: lines of at most 64 lanes (N <= 8 at k = 1)
-constexpr int RX_WLINE_ROUNDS = 16; // its tiles: at most 16 rounds of one line per wave (more lines for N < 6)
+constexpr int RX_WLINE_ROUNDS = 16;    // its default tiles: at most 16 rounds of one line per wave (more for N < 6)
+constexpr int RX_WLINE_MAXROUNDS = 64; // the most rounds a tile may take (autotuning)
 
 // LDS of the last-axis kernel: per line 2.5 npair n1 doubles (inputs, and the
 // two scaling buffers of the transforms), plus the tail
@@ -105,6 +106,17 @@ static size_t line_tile_doubles(int npair, int nl, int n1, int K1) {
   return (size_t)line_doubles(npair, n1) * nl + RX_TAIL + (size_t)n1 * (K1 + 1);
 }
 static sgdg_status set_line_lds(const RHost* rh);
+
+// Tiles of the wave-form last-axis kernel: `rounds` rounds of lc.lpr lines,
+// instance by instance.
+static std::vector<LineTask> wave_tiles(const LineClass& lc, int rounds) {
+  std::vector<LineTask> t;
+  const int64_t nl = (int64_t)lc.lpr * rounds;
+  for (const auto& il : lc.lines)
+    for (int64_t p0 = 0; p0 < il.second; p0 += nl)
+      t.push_back(LineTask{il.first, (int32_t)std::min<int64_t>(nl, il.second - p0), p0});
+  return t;
+}
 
 sgdg_status reaction_build(sgdg_plan* plan) {
   RHost* rh = new RHost();
@@ -279,30 +291,34 @@ sgdg_status reaction_build(sgdg_plan* plan) {
         lc->N = N;
         lc->S = S;
       }
-      for (int nin = 1; nin <= 2; ++nin) {
-        // lines per tile: the LDS budget of one workgroup; threads: about
-        // RX_ITEMS transform items each at the finest level, 64..256 (the wave
-        // form: 16 lines per wave, a lane per finest cell or two)
-        const int npair = nin * S;
-        int64_t nl = ((int64_t)RX_LINE_LDS / 8 - RX_TAIL - (int64_t)r.n1 * (K1 + 1)) / line_doubles(npair, r.n1);
-        if (d >= 2 && N <= RX_WLINE_MAXN) {
-          // wave form: a whole number of wave rounds (4 waves, LPW lines each),
-          // up to 16 rounds, and about 2048 tiles per instance where it has
-          // fewer lines (small problems keep many workgroups)
-          const int cplh = std::min(K1 == 2 ? 8 : 4, 1 << N);  // finest cells per lane (wl_cpl)
-          const int hh = N - (cplh == 8 ? 3 : cplh == 4 ? 2 : cplh == 2 ? 1 : 0);
-          const int64_t round = (int64_t)(RX_THREADS / 64) * (64 >> std::min(hh, 6));
-          const int64_t want = std::max<int64_t>(1, r.npre[d - 1] / 2048 / round);
-          nl = round * std::min<int64_t>(want, RX_WLINE_ROUNDS);
+      if (d >= 2 && N <= RX_WLINE_MAXN) {
+        // wave form: tiles of whole rounds (4 waves, LPW lines each); the
+        // default shape takes about 2048 tiles per instance, up to 16 rounds
+        // (small problems keep many workgroups), and 16 workgroups per CU
+        const int cplh = std::min(K1 == 2 ? 8 : 4, 1 << N);  // finest cells per lane (wl_cpl)
+        const int hh = N - (cplh == 8 ? 3 : cplh == 4 ? 2 : cplh == 2 ? 1 : 0);
+        lc->wave = true;
+        lc->lpr = (RX_THREADS / 64) * (64 >> std::min(hh, 6));
+        lc->lines.push_back({i, r.npre[d - 1]});
+        const int64_t want = std::max<int64_t>(1, r.npre[d - 1] / 2048 / lc->lpr);
+        for (int nin = 1; nin <= 2; ++nin) {
+          lc->rounds[nin] = (int)std::min<int64_t>(want, RX_WLINE_ROUNDS);
+          lc->wgcu[nin] = 16;
         }
-        nl = std::max<int64_t>(1, std::min<int64_t>(nl, r.npre[d - 1]));
-        int th = 64;
-        while (th < RX_THREADS && (int64_t)npair * nl * r.n1 > (int64_t)th * RX_ITEMS) th *= 2;
-        for (int64_t p0 = 0; p0 < r.npre[d - 1]; p0 += nl)
-          lc->tasks[nin].push_back(LineTask{i, (int32_t)std::min<int64_t>(nl, r.npre[d - 1] - p0), p0});
-        if (d >= 2 && N <= RX_WLINE_MAXN) continue;  // (the wave form takes no dynamic LDS)
-        lc->lds[nin] = std::max(lc->lds[nin], line_tile_doubles(npair, (int)nl, r.n1, K1) * sizeof(double));
-        lc->threads[nin] = std::max(lc->threads[nin], th);
+      } else {
+        for (int nin = 1; nin <= 2; ++nin) {
+          // lines per tile: the LDS budget of one workgroup; threads: about
+          // RX_ITEMS transform items each at the finest level, 64..256
+          const int npair = nin * S;
+          int64_t nl = ((int64_t)RX_LINE_LDS / 8 - RX_TAIL - (int64_t)r.n1 * (K1 + 1)) / line_doubles(npair, r.n1);
+          nl = std::max<int64_t>(1, std::min<int64_t>(nl, r.npre[d - 1]));
+          int th = 64;
+          while (th < RX_THREADS && (int64_t)npair * nl * r.n1 > (int64_t)th * RX_ITEMS) th *= 2;
+          for (int64_t p0 = 0; p0 < r.npre[d - 1]; p0 += nl)
+            lc->tasks[nin].push_back(LineTask{i, (int32_t)std::min<int64_t>(nl, r.npre[d - 1] - p0), p0});
+          lc->lds[nin] = std::max(lc->lds[nin], line_tile_doubles(npair, (int)nl, r.n1, K1) * sizeof(double));
+          lc->threads[nin] = std::max(lc->threads[nin], th);
+        }
       }
     }
     rh->cum_fin.push_back(rh->cum_fin.back() + (d >= 2 ? (int64_t)S * r.ntile[0] : 1));
@@ -320,7 +336,18 @@ sgdg_status reaction_build(sgdg_plan* plan) {
     if ((st = up(plan, rh->cum_x[m], &rh->dev.cum_x[m])) != SGDG_OK) return st;
   for (LineClass& lc : rh->lclass)
     for (int nin = 1; nin <= 2; ++nin) {
-      if ((st = up(plan, lc.tasks[nin], &lc.dev[nin])) != SGDG_OK) return st;
+      if (lc.wave) {
+        // room for the most tiles (one round each); the current shape's tiles are written into it
+        lc.cap_tasks[nin] = wave_tiles(lc, 1).size();
+        lc.tasks[nin] = wave_tiles(lc, 1);
+        if ((st = up(plan, lc.tasks[nin], &lc.dev[nin])) != SGDG_OK) return st;
+        lc.tasks[nin] = wave_tiles(lc, lc.rounds[nin]);
+        const hipError_t e = hipMemcpy(lc.dev[nin], lc.tasks[nin].data(), lc.tasks[nin].size() * sizeof(LineTask),
+                                       hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(line tiles)");
+      } else if ((st = up(plan, lc.tasks[nin], &lc.dev[nin])) != SGDG_OK) {
+        return st;
+      }
     }
   if (hipDeviceGetAttribute(&rh->ncu, hipDeviceAttributeMultiprocessorCount, plan->device) != hipSuccess) {
     rh->ncu = 0;
@@ -1400,6 +1427,53 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTa
   }
 }
 
+// The last-axis launch of one class of instances in a pass.
+static void launch_line(const sgdg_plan* plan, const LineClass& lc, int nrhs, RxMode mode, const RxArgs& a,
+                        hipStream_t s) {
+  const RHost* rh = (const RHost*)plan->rdata;
+  const int ninst = plan->ninst;
+  const int nin = mode == RX_CORR ? 2 : 1;
+  const int64_t nfin = rh->cum_fin.back();
+  if (lc.wave) {
+    const int ntask = (int)lc.tasks[nin].size();
+    const int64_t nwork = (int64_t)ntask * nrhs;
+    const unsigned grid = (unsigned)std::min<int64_t>(nwork, (int64_t)std::max(rh->ncu, 1) * lc.wgcu[nin]);
+    auto wl = [&](auto k1, auto sp, auto ni) {
+      constexpr int K1 = decltype(k1)::value, S = decltype(sp)::value, NIN = decltype(ni)::value;
+      hipLaunchKernelGGL((k_rx_wline<K1, S, NIN>), dim3(grid), dim3(RX_THREADS), 0, s, rh->dev, lc.dev[nin], ntask,
+                         ninst, (int)mode, a, rh->rws, nwork);
+    };
+    auto by_s = [&](auto k1) {
+      if (lc.S == 1) {
+        if (nin == 1) wl(k1, std::integral_constant<int, 1>(), std::integral_constant<int, 1>());
+        else wl(k1, std::integral_constant<int, 1>(), std::integral_constant<int, 2>());
+      } else {
+        if (nin == 1) wl(k1, std::integral_constant<int, 2>(), std::integral_constant<int, 1>());
+        else wl(k1, std::integral_constant<int, 2>(), std::integral_constant<int, 2>());
+      }
+    };
+    if (lc.K1 == 2) by_s(std::integral_constant<int, 2>());
+    else if (lc.K1 == 3) by_s(std::integral_constant<int, 3>());
+    else by_s(std::integral_constant<int, 4>());
+    return;
+  }
+  const dim3 grid((unsigned)lc.tasks[nin].size(), (unsigned)nrhs), blk((unsigned)lc.threads[nin]);
+  switch (lc.K1) {
+    case 2:
+      hipLaunchKernelGGL(k_rx_line<2>, grid, blk, lc.lds[nin], s, rh->dev, lc.dev[nin], ninst, (int)mode, plan->total,
+                         a, rh->rws, nin, nfin);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_rx_line<3>, grid, blk, lc.lds[nin], s, rh->dev, lc.dev[nin], ninst, (int)mode, plan->total,
+                         a, rh->rws, nin, nfin);
+      break;
+    default:
+      hipLaunchKernelGGL(k_rx_line<4>, grid, blk, lc.lds[nin], s, rh->dev, lc.dev[nin], ninst, (int)mode, plan->total,
+                         a, rh->rws, nin, nfin);
+      break;
+  }
+}
+
 void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s,
                    const std::function<void(int)>* mark) {
   const RHost* rh = (const RHost*)plan->rdata;
@@ -1425,44 +1499,7 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
     });
   for (const LineClass& lc : rh->lclass) {
     if (mark) (*mark)(1);
-    if (d >= 2 && lc.N <= RX_WLINE_MAXN) {
-      const int ntask = (int)lc.tasks[nin].size();
-      const int64_t nwork = (int64_t)ntask * nrhs;
-      const unsigned grid = (unsigned)std::min<int64_t>(nwork, (int64_t)std::max(rh->ncu, 1) * 16);
-      auto wl = [&](auto k1, auto sp, auto ni) {
-        constexpr int K1 = decltype(k1)::value, S = decltype(sp)::value, NIN = decltype(ni)::value;
-        hipLaunchKernelGGL((k_rx_wline<K1, S, NIN>), dim3(grid), dim3(RX_THREADS), 0, s, rh->dev, lc.dev[nin], ntask,
-                           ninst, (int)mode, a, rh->rws, nwork);
-      };
-      auto by_s = [&](auto k1) {
-        if (lc.S == 1) {
-          if (nin == 1) wl(k1, std::integral_constant<int, 1>(), std::integral_constant<int, 1>());
-          else wl(k1, std::integral_constant<int, 1>(), std::integral_constant<int, 2>());
-        } else {
-          if (nin == 1) wl(k1, std::integral_constant<int, 2>(), std::integral_constant<int, 1>());
-          else wl(k1, std::integral_constant<int, 2>(), std::integral_constant<int, 2>());
-        }
-      };
-      if (lc.K1 == 2) by_s(std::integral_constant<int, 2>());
-      else if (lc.K1 == 3) by_s(std::integral_constant<int, 3>());
-      else by_s(std::integral_constant<int, 4>());
-      continue;
-    }
-    const dim3 grid((unsigned)lc.tasks[nin].size(), (unsigned)nrhs), blk((unsigned)lc.threads[nin]);
-    switch (lc.K1) {
-      case 2:
-        hipLaunchKernelGGL(k_rx_line<2>, grid, blk, lc.lds[nin], s, rh->dev, lc.dev[nin], ninst, (int)mode, plan->total,
-                           a, rh->rws, nin, nfin);
-        break;
-      case 3:
-        hipLaunchKernelGGL(k_rx_line<3>, grid, blk, lc.lds[nin], s, rh->dev, lc.dev[nin], ninst, (int)mode, plan->total,
-                           a, rh->rws, nin, nfin);
-        break;
-      default:
-        hipLaunchKernelGGL(k_rx_line<4>, grid, blk, lc.lds[nin], s, rh->dev, lc.dev[nin], ninst, (int)mode, plan->total,
-                           a, rh->rws, nin, nfin);
-        break;
-    }
+    launch_line(plan, lc, nrhs, mode, a, s);
   }
   for (int m = d - 2; m >= 0; --m)
     each([&](auto k1) {
@@ -1478,6 +1515,34 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
                            rh->rws, rh->lam[m], 0, nfin);
     });
   if (mark) (*mark)(-1);
+}
+
+int reaction_line_classes(const sgdg_plan* plan) {
+  const RHost* rh = (const RHost*)plan->rdata;
+  return rh->supported ? (int)rh->lclass.size() : 0;
+}
+const LineClass& reaction_line_class(const sgdg_plan* plan, int c) { return ((const RHost*)plan->rdata)->lclass[c]; }
+
+sgdg_status reaction_set_line_shape(sgdg_plan* plan, int c, int nin, int rounds, int wgcu) {
+  RHost* rh = (RHost*)plan->rdata;
+  if (!rh->supported || c < 0 || c >= (int)rh->lclass.size() || nin < 1 || nin > 2)
+    return fail(SGDG_ERR_ARG, "line shape: no such class");
+  LineClass& lc = rh->lclass[c];
+  if (!lc.wave) return fail(SGDG_ERR_UNSUPPORTED, "line shape: the class runs the LDS-tile form");
+  if (rounds < 1 || rounds > RX_WLINE_MAXROUNDS || wgcu < 1 || wgcu > 64)
+    return fail(SGDG_ERR_ARG, "line shape: rounds must be in 1..64 and workgroups per CU in 1..64");
+  std::vector<LineTask> t = wave_tiles(lc, rounds);
+  if (t.size() > lc.cap_tasks[nin]) return fail(SGDG_ERR_ARG, "line shape: too many tiles");
+  const hipError_t e = hipMemcpy(lc.dev[nin], t.data(), t.size() * sizeof(LineTask), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(line tiles)");
+  lc.tasks[nin].swap(t);
+  lc.rounds[nin] = rounds;
+  lc.wgcu[nin] = wgcu;
+  return SGDG_OK;
+}
+
+void reaction_line_stage(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s, int c) {
+  launch_line(plan, ((const RHost*)plan->rdata)->lclass[c], nrhs, mode, a, s);
 }
 
 static sgdg_status set_line_lds(const RHost* rh) {

@@ -43,6 +43,17 @@ class Factor1D(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("a", C.c_double), ("b", C.c_double)]
 
 
+TUNE_MAXCLASS = 16
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("nclass", C.c_int32), ("k", C.c_int32 * TUNE_MAXCLASS), ("n", C.c_int32 * TUNE_MAXCLASS),
+                ("nspecies", C.c_int32 * TUNE_MAXCLASS), ("cls", C.c_int32 * TUNE_MAXCLASS),
+                ("rounds", (C.c_int32 * 2) * TUNE_MAXCLASS), ("wgcu", (C.c_int32 * 2) * TUNE_MAXCLASS),
+                ("ms_default", (C.c_float * 2) * TUNE_MAXCLASS), ("ms_best", (C.c_float * 2) * TUNE_MAXCLASS),
+                ("from_cache", (C.c_int32 * 2) * TUNE_MAXCLASS)]
+
+
 class Stats(C.Structure):
     _fields_ = [("krylov_m", C.c_int32), ("newton_iters", C.c_int32), ("h_next", C.c_double),
                 ("residual", C.c_double), ("status", C.c_int32), ("pad", C.c_int32)]
@@ -72,6 +83,8 @@ _sigs = {
     "iif3_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _vp, _f64, _i32, _vp, _sz, _vp, _vp], C.c_int),
     "rk_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _sz, _vp], C.c_int),
     "iif2_step_local": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _vp, _sz, _vp, _vp], C.c_int),
+    "sg_dg_tune": ([_vp, _i32, _vp, _sz, C.POINTER(TuneReport), _vp], C.c_int),
+    "sg_dg_line_shape": ([_vp, _i32, _i32, _i32, _i32], C.c_int),
 }
 EXPORTED = sorted(_sigs)
 for _name, (_args, _res) in _sigs.items():
@@ -243,6 +256,27 @@ class Plan:
     def rk_step(self, dt, order, U, workspace, nrhs=1, stream=None):
         _check(_lib.rk_step(self._h, nrhs, float(dt), order, _ptr(U), _ptr(workspace),
                             workspace.numel() * workspace.element_size(), _stream(stream)), "rk_step")
+
+    def tune(self, workspace, nrhs=1, stream=None):
+        """Autotune the launch shapes of the last-axis reaction kernels (sg_dg_tune); returns the report."""
+        r = TuneReport()
+        _check(_lib.sg_dg_tune(self._h, nrhs, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                               C.byref(r), _stream(stream)), "sg_dg_tune")
+        return _tune_dict(r)
+
+    def line_shape(self, cls, ninputs, rounds, wg_per_cu):
+        _check(_lib.sg_dg_line_shape(self._h, cls, ninputs, rounds, wg_per_cu), "sg_dg_line_shape")
+
+
+def _tune_dict(r):
+    out = []
+    for i in range(r.nclass):
+        out.append({"class": r.cls[i], "k": r.k[i], "N": r.n[i], "species": r.nspecies[i],
+                    "rounds": [r.rounds[i][0], r.rounds[i][1]], "wg_per_cu": [r.wgcu[i][0], r.wgcu[i][1]],
+                    "ms_default": [r.ms_default[i][0], r.ms_default[i][1]],
+                    "ms_best": [r.ms_best[i][0], r.ms_best[i][1]],
+                    "from_cache": [r.from_cache[i][0], r.from_cache[i][1]]})
+    return out
 
 
 def stats_array(stats_tensor):

@@ -55,6 +55,8 @@ def test_argument_errors_return_before_device_work():
     assert L.iif3_step(None, 1, 0.1, 10, None, None, None, None, 1e-14, 5, None, 0, None, None) in (1, 4)
     assert L.rk_step(None, 1, 0.1, 2, None, None, 0, None) in (1, 4)
     assert L.iif2_step_local(None, 1, 0.1, 10, None, None, None, None, 0, None, None) in (1, 4)
+    assert L.sg_dg_tune(None, 1, None, 0, None, None) == 1
+    assert L.sg_dg_line_shape(None, 0, 1, 1, 1) == 1
     assert L.sg_dg_destroy(None) == 1
 
 
