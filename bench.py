@@ -329,18 +329,17 @@ def counters(name, reps):
     else:
         raise SystemExit(f"unknown counter workload {name}")
     torch.cuda.synchronize()
-    # calibration: a copy of 256 MiB whose source has been pushed out of every
-    # cache (2 GiB written after it), so FETCH_SIZE and WRITE_SIZE of the copy
-    # read 256 MiB each from and to HBM
+    # calibration: a 256 MiB elementwise copy whose source has been pushed out
+    # of every cache (2 GiB written after it): it reads 256 MiB from HBM and
+    # writes 256 MiB
     n = (256 << 20) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     flush = torch.ones((2 << 30) // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    torch.mul(a, 1.0, out=b)  # a shader kernel (a device-to-device hipMemcpy may run on a DMA engine)
     torch.cuda.synchronize()
     del flush
-    print(f"[counters] {name}: {what}; copy of {n * 8} bytes (the second elementwise kernel after the 2 GiB fill)",
-          flush=True)
+    print(f"[counters] {name}: {what}; copy of {n * 8} bytes (the multiply kernel after the 2 GiB fill)", flush=True)
 
 
 # ----------------------------------------------------------------------------- main

@@ -295,9 +295,12 @@ typedef struct {
 /* Times every candidate shape (rounds 1, 2, 4, 8, 16, 32 x workgroups per CU
  * 4, 8, 16, 32) of each class's last-axis launch for nrhs right-hand sides,
  * one and two inputs per point, with HIP events on `stream` (synchronising
- * it), and keeps the fastest.  Choices are cached per process by device,
- * (degree, level, species), inputs, nrhs and line count; a cached class is
- * set without timing.  workspace: at least iif2_bytes for M = 1 and nrhs
+ * it), and keeps the fastest.  Choices are cached per process by GPU
+ * architecture and compute-unit count, (degree, level, species), inputs,
+ * nrhs and line count; a cached class is set without timing.  If the
+ * environment variable SGDG_TUNE_CACHE names a file, the cache is also read
+ * from it (once per process) and every new choice is appended to it (one line
+ * "arch cus K1 N species inputs nrhs lines rounds wgcu").  workspace: at least iif2_bytes for M = 1 and nrhs
  * (sg_dg_workspace_size); its contents are overwritten.  report: host
  * pointer, may be NULL.  Errors: SGDG_ERR_ARG, _UNSUPPORTED (no reaction
  * tables for this plan), _HIP.                                              */

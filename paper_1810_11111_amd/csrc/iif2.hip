@@ -20,6 +20,9 @@
 
 #include <array>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <tuple>
 #include <functional>
 #include <map>
 #include <mutex>
@@ -488,8 +491,40 @@ extern "C" sgdg_status iif2_step_local(const sgdg_plan* plan, int32_t nrhs, doub
 
 // ---------------------------------------------------------------- launch-shape autotuning
 namespace {
+// key: architecture name, compute units, K1, N, species, inputs, nrhs, lines of the class
+using TuneKey = std::tuple<std::string, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t>;
 std::mutex g_tune_mu;
-std::map<std::array<int64_t, 7>, std::pair<int, int>> g_tune_cache;  // -> (rounds, workgroups per CU)
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;  // -> (rounds, workgroups per CU)
+bool g_tune_file_read = false;
+
+// The file named by SGDG_TUNE_CACHE (if set) extends the process cache: one
+// line per choice, "arch cus K1 N S inputs nrhs lines rounds wgcu"; read once,
+// appended to after every new choice.  (Called with g_tune_mu held.)
+void tune_file_read() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char* path = std::getenv("SGDG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char arch[64];
+  long long v[9];
+  while (std::fscanf(f, "%63s %lld %lld %lld %lld %lld %lld %lld %lld %lld", arch, &v[0], &v[1], &v[2], &v[3], &v[4],
+                     &v[5], &v[6], &v[7], &v[8]) == 10)
+    g_tune_cache[TuneKey{arch, v[0], v[1], v[2], v[3], v[4], v[5], v[6]}] = {(int)v[7], (int)v[8]};
+  std::fclose(f);
+}
+
+void tune_file_append(const TuneKey& k, int rounds, int wgcu) {
+  const char* path = std::getenv("SGDG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %lld %lld %lld %lld %lld %lld %lld %d %d\n", std::get<0>(k).c_str(), (long long)std::get<1>(k),
+               (long long)std::get<2>(k), (long long)std::get<3>(k), (long long)std::get<4>(k),
+               (long long)std::get<5>(k), (long long)std::get<6>(k), (long long)std::get<7>(k), rounds, wgcu);
+  std::fclose(f);
+}
 }  // namespace
 
 extern "C" sgdg_status sg_dg_line_shape(sgdg_plan* plan, int32_t cls, int32_t ninputs, int32_t rounds, int32_t wgcu) {
@@ -534,6 +569,14 @@ extern "C" sgdg_status sg_dg_tune(sgdg_plan* plan, int32_t nrhs, void* workspace
     if (e0) (void)hipEventDestroy(e0);
     return hip_fail(e, "sg_dg_tune: events");
   }
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, plan->device)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return hip_fail(e, "sg_dg_tune: device properties");
+  }
+  const std::string arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
+  const int64_t ncu = prop.multiProcessorCount;
   static const int kRounds[] = {1, 2, 4, 8, 16, 32};
   static const int kWgcu[] = {4, 8, 16, 32};
   constexpr int kReps = 3;
@@ -572,9 +615,10 @@ extern "C" sgdg_status sg_dg_tune(sgdg_plan* plan, int32_t nrhs, void* workspace
         *ms = t / kReps;
         return SGDG_OK;
       };
-      const std::array<int64_t, 7> key{plan->device, lc.K1, lc.N, lc.S, nin, nrhs, lines};
+      const TuneKey key{arch, ncu, lc.K1, lc.N, lc.S, nin, nrhs, lines};
       {
         std::lock_guard<std::mutex> g(g_tune_mu);
+        tune_file_read();
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
           st = reaction_set_line_shape(plan, c, nin, it->second.first, it->second.second);
@@ -610,6 +654,7 @@ extern "C" sgdg_status sg_dg_tune(sgdg_plan* plan, int32_t nrhs, void* workspace
       rep.ms_best[slot][nin - 1] = tb;
       std::lock_guard<std::mutex> g(g_tune_mu);
       g_tune_cache[key] = {rb, gb};
+      tune_file_append(key, rb, gb);
     }
   }
   (void)hipEventDestroy(e0);

@@ -7,6 +7,8 @@ decides which workgroup computes which line.  So a tuned plan, and plans
 forced to the extreme shapes, must give the default plan's F and IIF2 steps
 (Sec. 3, eq. 3.5) bit for bit.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -90,6 +92,35 @@ def test_tuned_and_forced_shapes_match_default(name):
         for a, b in zip(got, ref):
             assert np.array_equal(a, b), (rounds, wgcu)
         forced.close()
+
+
+def test_tune_cache_file(tmp_path):
+    """Choices written to the SGDG_TUNE_CACHE file by one process are read by
+    another (a fresh interpreter), which then sets them without timing."""
+    import subprocess
+    import sys
+
+    from _gpu_common import ROOT
+
+    path = tmp_path / "tune.txt"
+    prog = (
+        "import sys, torch; sys.path.insert(0, %r); sys.path.insert(0, %r)\n"
+        "from paper_1810_11111_amd import sgdg as sg, inputs as I\n"
+        "p = sg.Plan(I.quadratic_d4(N=3).instances, 'fp64'); _, ib = p.workspace_size(1, 2)\n"
+        "ws = torch.empty(ib, dtype=torch.uint8, device='cuda')\n"
+        "r = p.tune(ws, nrhs=2); print([c['from_cache'] for c in r], [c['rounds'] + c['wg_per_cu'] for c in r])\n"
+    ) % (ROOT, os.path.join(ROOT, "tests"))
+    env = dict(os.environ, SGDG_TUNE_CACHE=str(path))
+    say("tune cache file")
+    first = subprocess.run([sys.executable, "-c", prog], env=env, capture_output=True, text=True, timeout=240)
+    assert first.returncode == 0, first.stderr[-2000:]
+    assert path.exists() and len(path.read_text().splitlines()) >= 2
+    second = subprocess.run([sys.executable, "-c", prog], env=env, capture_output=True, text=True, timeout=240)
+    assert second.returncode == 0, second.stderr[-2000:]
+    f1 = first.stdout.strip().splitlines()[-1]
+    f2 = second.stdout.strip().splitlines()[-1]
+    assert f1.startswith("[[0, 0]") and f2.startswith("[[1, 1]")
+    assert f1.split("] [", 1)[1] == f2.split("] [", 1)[1]  # the same shapes
 
 
 def test_line_shape_argument_errors():
