@@ -95,6 +95,7 @@ constexpr int RX_ITEMS = 2;            // transform items per thread of a line t
 constexpr int RX_TAIL = 64 + 32 + 8;   // two-scale matrices, reaction coefficients, per-wave partial sums
 constexpr int64_t RX_THREADS_WANTED = 1 << 17;
 constexpr int RX_WALK = 64;  // most points one thread of an expansion / contraction walks
+constexpr int RX_XS_LDS = 32 * 1024;  // largest hierarchical block an expansion / contraction tile stages in LDS
 constexpr int RX_WLINE_MAXN = 8;   // last-axis wave form: lines of at most 64 lanes (N <= 8 at k = 1)
 constexpr int RX_WLINE_ROUNDS = 16;    // its default tiles: at most 16 rounds of one line per wave (more for N < 6)
 constexpr int RX_WLINE_MAXROUNDS = 64; // the most rounds a tile may take (autotuning)
@@ -323,6 +324,18 @@ sgdg_status reaction_build(sgdg_plan* plan) {
     }
     rh->cum_fin.push_back(rh->cum_fin.back() + (d >= 2 ? (int64_t)S * r.ntile[0] : 1));
     ri.push_back(r);
+  }
+  // stages whose tiles hold whole prefixes of a small hierarchical block
+  // stage that block in LDS (expansion: its input; contraction, m >= 1: its
+  // output)
+  for (int m = 0; m + 1 <= d - 1; ++m) {
+    int64_t mx = 0;
+    bool whole = true;
+    for (const RInst& r : ri) {
+      whole = whole && r.ntile[m] == 1;
+      mx = std::max(mx, r.gdof[d - m]);
+    }
+    rh->xs_lds[m] = whole && mx * (int64_t)sizeof(double) <= RX_XS_LDS ? (int)(mx * sizeof(double)) : 0;
   }
   rh->rws = ws;
   sgdg_status st;
@@ -590,38 +603,78 @@ __device__ __forceinline__ TileIdx tile_index(const RInst& I, int m, int64_t le,
   return t;
 }
 
-// expansion stage m: hierarchical along axis m -> point values, grid (tiles, rhs, input)
-template <int K1, bool LANES>
+// Largest level that any fibre of the calling wave holds (the level loops of
+// a walk stop there: the same bound for the whole wave, so the basis-table
+// loads stay wave-uniform).
+__device__ __forceinline__ int wave_max_level(int L) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) L = max(L, __shfl_xor(L, off, 64));
+  return __builtin_amdgcn_readfirstlane(L);
+}
+
+// Copy n doubles from global memory to LDS, four loads of every thread in
+// flight together.
+__device__ __forceinline__ void stage_block(double* __restrict__ dst, const double* __restrict__ src, int n) {
+  for (int i0 = threadIdx.x; i0 < n; i0 += 4 * RX_THREADS) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * RX_THREADS;
+      v[u] = src[i < n ? i : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u * RX_THREADS < n) dst[i0 + u * RX_THREADS] = v[u];
+  }
+}
+
+// expansion stage m: hierarchical along axis m -> point values, grid (tiles, rhs, input).
+// XS: the tile holds every fibre of its (species, prefix) and the prefix's
+// hierarchical block is first copied to LDS (xs), so that the walk reads only
+// LDS and issues nothing but stores to global memory.
+template <int K1, bool LANES, bool XS>
 __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg, int inst, int m, int64_t total,
-                               const RxArgs& a, int64_t rws, int lam, int ll) {
+                               const RxArgs& a, int64_t rws, int lam, int ll, double* xs) {
   const RInst& I = R.inst[inst];
   const int z = blockIdx.z, rhs = blockIdx.y;
   const int d = I.d, r = d - m, N = I.N, S = I.S, np1 = I.np1;
   const TileIdx t = tile_index<LANES>(I, m, (int64_t)blockIdx.x - pick(R.cum_x, m)[inst], lam, ll);
   const int64_t gd_in = I.gdof[r], gd_out = I.gdof[r - 1];
-  if (t.eo >= gd_out) return;
-  constexpr int LM = rx_levels<K1>();
-  const Fibre<LM> F = fibre_geometry<LM>(R, I, r, t.eo);
   double* xr = a.rws + (int64_t)rhs * rws;
   const double* __restrict__ in =
       m == 0 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)t.s * I.ndof
              : xr + I.X_off[m] + (((int64_t)z * S + t.s) * I.npre[m] + t.pre) * gd_in;
+  constexpr int LM = rx_levels<K1>();
+  const bool valid = t.eo < gd_out;
+  const Fibre<LM> F = fibre_geometry<LM>(R, I, r, valid ? t.eo : 0);
+  if constexpr (XS) {
+    stage_block(xs, in, (int)gd_in);
+    __syncthreads();
+  }
+  if (!valid) return;
+  const int Lw = wave_max_level(F.L);
+  auto ld = [&](int64_t i) -> double {
+    if constexpr (XS)
+      return xs[i];
+    else
+      return in[i];
+  };
   double* __restrict__ out =
       xr + I.X_off[m + 1] + (((int64_t)z * S + t.s) * I.npre[m + 1] + t.pre * np1) * gd_out + t.eo;
   const double* __restrict__ EH = EHg + I.EH_off;
   const int NL1 = N + 1;
   const int cw = (1 << N) >> lam, c0 = t.qc * cw;
   // coefficients of the current cell of every level (zero past the fibre's
-  // budget); the level loops run to N, the same bound for the whole wave
+  // budget); the level loops run to the wave's largest budget
   double cf[LM][K1];
 #pragma unroll
   for (int l = 0; l < LM; ++l)
-    if (l <= N) {
+    if (l <= Lw) {
       const int j = l == 0 ? 0 : c0 >> (N - l + 1);
       const bool on = l <= F.L;
 #pragma unroll
       for (int p = 0; p < K1; ++p) {
-        const double v = in[F.bl[l] + (int64_t)((on ? j : 0) * K1 + p) * F.Sb];
+        const double v = ld(F.bl[l] + (int64_t)((on ? j : 0) * K1 + p) * F.Sb);
         cf[l][p] = on ? v : 0.0;
       }
     }
@@ -629,12 +682,12 @@ __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg,
     if (c != c0) {
 #pragma unroll
       for (int l = 1; l < LM; ++l)
-        if (l <= N && (c & ((1 << (N - l + 1)) - 1)) == 0) {
+        if (l <= Lw && (c & ((1 << (N - l + 1)) - 1)) == 0) {
           const int j = c >> (N - l + 1);
           const bool on = l <= F.L;
 #pragma unroll
           for (int p = 0; p < K1; ++p) {
-            const double v = in[F.bl[l] + (int64_t)((on ? j : 0) * K1 + p) * F.Sb];
+            const double v = ld(F.bl[l] + (int64_t)((on ? j : 0) * K1 + p) * F.Sb);
             cf[l][p] = on ? v : 0.0;
           }
         }
@@ -646,7 +699,7 @@ __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg,
       double u = 0.0;
 #pragma unroll
       for (int l = 0; l < LM; ++l)
-        if (l <= N)
+        if (l <= Lw)
 #pragma unroll
           for (int p = 0; p < K1; ++p) u += eh[l * K1 + p] * cf[l][p];
       out[(int64_t)q * gd_out] = u;
@@ -658,20 +711,25 @@ __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg,
 // of another degree return at once
 // (the basis table is its own argument: its loads are wave-uniform and go
 // through the scalar cache)
-template <int K1, bool LANES>
+template <int K1, bool LANES, bool XS>
 __global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, const double* __restrict__ EHg, int ninst, int m,
                                                           int64_t total, RxArgs a, int64_t rws, int lam, int ll) {
+  extern __shared__ double xs_dyn[];
   const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
   if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
-  rx_expand_body<K1, LANES>(R, EHg, inst, m, total, a, rws, lam, ll);
+  rx_expand_body<K1, LANES, XS>(R, EHg, inst, m, total, a, rws, lam, ll, xs_dyn);
 }
 
 // contraction stage m: weighted point values along axis m -> hierarchical
-// (m >= 1 writes Y_m; m == 0 finishes plan vectors), grid (tiles, rhs)
-template <int K1, bool LANES>
+// (m >= 1 writes Y_m; m == 0 finishes plan vectors), grid (tiles, rhs).
+// XS (m >= 1): the tile holds every fibre of its (species, prefix); the
+// outputs are collected in an LDS image of the prefix's hierarchical block
+// (ys) and written out together at the end, so that the walk issues only
+// loads to global memory.
+template <int K1, bool LANES, bool XS>
 __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EHg, const double* __restrict__ w1g,
                                  int inst, int m, int mode, int64_t total, const RxArgs& a, int64_t rws, int lam,
-                                 int ll, int64_t nfin) {
+                                 int ll, int64_t nfin, double* ys) {
   // partial sums of the levels whose cells span several chunks: [wave][level <= 2][p][lane]
   __shared__ double red[4][3][K1][64];
   __shared__ double wsum[RX_THREADS / 64];
@@ -689,8 +747,11 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
   constexpr int LM = rx_levels<K1>();
   const Fibre<LM> F = fibre_geometry<LM>(R, I, r, valid ? t.eo : 0);
   const int L = valid ? F.L : -1;
+  const int Lw = wave_max_level(L);
   double* xr = a.rws + (int64_t)rhs * rws;
-  const double* __restrict__ in = xr + I.Y_off[m + 1] + ((int64_t)t.s * I.npre[m + 1] + t.pre * np1) * gd_in + t.eo;
+  // (threads past the fibre set read fibre 0's points and weight them by zero)
+  const double* __restrict__ in =
+      xr + I.Y_off[m + 1] + ((int64_t)t.s * I.npre[m + 1] + t.pre * np1) * gd_in + (valid ? t.eo : 0);
   const double* __restrict__ EH = EHg + I.EH_off;
   const double* __restrict__ w1 = w1g + I.w_off;
   double* outm = m > 0 ? xr + I.Y_off[m] + ((int64_t)t.s * I.npre[m] + t.pre) * gd_out : nullptr;
@@ -698,7 +759,9 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
   double g2 = 0.0;
   auto emit = [&](int l, int j, int p, double v) {
     const int64_t o = F.bl[l] + (int64_t)(j * K1 + p) * F.Sb;
-    if (m > 0)
+    if constexpr (XS)
+      ys[o] = v;
+    else if (m > 0)
       outm[o] = v;
     else
       g2 += finish(a, mode, base + o, v);
@@ -710,17 +773,24 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
   for (int l = 0; l < LM; ++l)
 #pragma unroll
     for (int p = 0; p < K1; ++p) acc[l][p] = 0.0;
-  // the point values of CB cells are loaded together ahead of their use
+  // the point values of CB cells are loaded together, one batch ahead of
+  // their use (the last batch loads itself again: every iteration issues the
+  // same loads, so the wait for a batch never includes the next one)
   constexpr int CB = LANES ? 1 : (K1 == 2 ? 4 : 2);
-  for (int cb = c0; cb < c0 + cw; cb += CB) {
-    double gv[CB][K1];
+  double gv[CB][K1];
+  auto fetch = [&](int cb, double (&g)[CB][K1]) {
 #pragma unroll
     for (int b = 0; b < CB; ++b)
 #pragma unroll
       for (int gq = 0; gq < K1; ++gq) {
-        const int q = (cb + b) * K1 + gq;
-        gv[b][gq] = valid && cb + b < c0 + cw ? in[(int64_t)q * gd_in] : 0.0;
+        const int q = min(cb + b, c0 + cw - 1) * K1 + gq;
+        g[b][gq] = in[(int64_t)q * gd_in];
       }
+  };
+  fetch(c0, gv);
+  for (int cb = c0; cb < c0 + cw; cb += CB) {
+    double gn[CB][K1];
+    fetch(cb + CB < c0 + cw ? cb + CB : cb, gn);
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
       const int c = cb + b;
@@ -729,10 +799,10 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
       for (int gq = 0; gq < K1; ++gq) {
         const int q = c * K1 + gq;
         const double* __restrict__ eh = EH + (int64_t)q * NL1 * K1;
-        const double g = w1[q] * gv[b][gq];
+        const double g = valid ? w1[q] * gv[b][gq] : 0.0;
 #pragma unroll
         for (int l = 0; l < LM; ++l)
-          if (l <= N)
+          if (l <= Lw)
 #pragma unroll
             for (int p = 0; p < K1; ++p) acc[l][p] += eh[l * K1 + p] * g;  // (unused past the fibre's budget)
       }
@@ -747,6 +817,10 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
           }
         }
     }
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+#pragma unroll
+      for (int gq = 0; gq < K1; ++gq) gv[b][gq] = gn[b][gq];
   }
   // coarser levels span 2^g chunks, g = lam - l + 1 (level 0: g = lam):
   // fixed-order butterfly over the lane bits of the chunk, then the wave of
@@ -792,20 +866,25 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
         }
       }
     }
+  if constexpr (XS) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < gd_out; i += RX_THREADS) outm[i] = ys[i];
+  }
   if (m == 0 && mode == RX_RESID) {
     g2 = block_sum(g2, wsum);
     if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + blockIdx.x] = g2;
   }
 }
 
-template <int K1, bool LANES>
+template <int K1, bool LANES, bool XS>
 __global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, const double* __restrict__ EHg,
                                                             const double* __restrict__ w1g, int ninst, int m, int mode,
                                                             int64_t total, RxArgs a, int64_t rws, int lam, int ll,
                                                             int64_t nfin) {
+  extern __shared__ double ys_dyn[];
   const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
   if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
-  rx_contract_body<K1, LANES>(R, EHg, w1g, inst, m, mode, total, a, rws, lam, ll, nfin);
+  rx_contract_body<K1, LANES, XS>(R, EHg, w1g, inst, m, mode, total, a, rws, lam, ll, nfin, ys_dyn);
 }
 
 // Last axis: a tile of nl whole lines (consecutive prefixes).  LDS: the
@@ -1486,16 +1565,25 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
     if (rh->k1mask & 8) launch(std::integral_constant<int, 3>());
     if (rh->k1mask & 16) launch(std::integral_constant<int, 4>());
   };
+  using std::integral_constant;
+  // a stage launch with its lane-chunk and LDS-staging forms picked at run time
+  auto forms = [&](int m, bool xs, auto go) {
+    const bool ln = rh->llane[m] > 0;
+    if (ln && xs) go(integral_constant<bool, true>(), integral_constant<bool, true>());
+    else if (ln) go(integral_constant<bool, true>(), integral_constant<bool, false>());
+    else if (xs) go(integral_constant<bool, false>(), integral_constant<bool, true>());
+    else go(integral_constant<bool, false>(), integral_constant<bool, false>());
+  };
   for (int m = 0; m + 1 <= d - 1; ++m)
     each([&](auto k1) {
       if (mark) (*mark)(0);
       const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin);
-      if (rh->llane[m] > 0)
-        hipLaunchKernelGGL((k_rx_expand<decltype(k1)::value, true>), grid, dim3(RX_THREADS), 0, s, rh->dev,
-                           (const double*)rh->dev.EH, ninst, m, plan->total, a, rh->rws, rh->lam[m], rh->llane[m]);
-      else
-        hipLaunchKernelGGL((k_rx_expand<decltype(k1)::value, false>), grid, dim3(RX_THREADS), 0, s, rh->dev,
-                           (const double*)rh->dev.EH, ninst, m, plan->total, a, rh->rws, rh->lam[m], 0);
+      const int xs = rh->xs_lds[m];
+      forms(m, xs > 0, [&](auto lanes, auto stg) {
+        hipLaunchKernelGGL((k_rx_expand<decltype(k1)::value, decltype(lanes)::value, decltype(stg)::value>), grid,
+                           dim3(RX_THREADS), stg ? xs : 0, s, rh->dev, (const double*)rh->dev.EH, ninst, m,
+                           plan->total, a, rh->rws, rh->lam[m], rh->llane[m]);
+      });
     });
   for (const LineClass& lc : rh->lclass) {
     if (mark) (*mark)(1);
@@ -1505,14 +1593,13 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
     each([&](auto k1) {
       if (mark) (*mark)(2);
       const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs);
-      if (rh->llane[m] > 0)
-        hipLaunchKernelGGL((k_rx_contract<decltype(k1)::value, true>), grid, dim3(RX_THREADS), 0, s, rh->dev,
-                           (const double*)rh->dev.EH, (const double*)rh->dev.w1, ninst, m, (int)mode, plan->total, a,
-                           rh->rws, rh->lam[m], rh->llane[m], nfin);
-      else
-        hipLaunchKernelGGL((k_rx_contract<decltype(k1)::value, false>), grid, dim3(RX_THREADS), 0, s, rh->dev,
-                           (const double*)rh->dev.EH, (const double*)rh->dev.w1, ninst, m, (int)mode, plan->total, a,
-                           rh->rws, rh->lam[m], 0, nfin);
+      const int xs = m > 0 ? rh->xs_lds[m] : 0;
+      forms(m, xs > 0, [&](auto lanes, auto stg) {
+        hipLaunchKernelGGL((k_rx_contract<decltype(k1)::value, decltype(lanes)::value, decltype(stg)::value>), grid,
+                           dim3(RX_THREADS), stg ? xs : 0, s, rh->dev, (const double*)rh->dev.EH,
+                           (const double*)rh->dev.w1, ninst, m, (int)mode, plan->total, a, rh->rws, rh->lam[m],
+                           rh->llane[m], nfin);
+      });
     });
   if (mark) (*mark)(-1);
 }
