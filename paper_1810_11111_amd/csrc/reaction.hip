@@ -85,11 +85,6 @@ static std::vector<std::vector<int>> grid_blocks(int r, int N) {
 constexpr int RX_THREADS = 256;        // every reaction kernel
 constexpr int RX_MAX_N1 = 2048;        // (k+1) 2^N per axis
 constexpr int RX_LMAX = 11;            // levels 0..10 (k >= 1, (k+1) 2^N <= 2048)
-// levels of a fibre for degree K1 - 1: N <= log2(2048 / K1)
-template <int K1>
-constexpr int rx_levels() {
-  return K1 == 2 ? 11 : 10;
-}
 constexpr int RX_LINE_LDS = 32 * 1024; // LDS budget of a line tile (several tiles per compute unit)
 constexpr int RX_ITEMS = 2;            // transform items per thread of a line tile at the finest level
 constexpr int RX_TAIL = 64 + 32 + 8;   // two-scale matrices, reaction coefficients, per-wave partial sums
@@ -335,8 +330,13 @@ sgdg_status reaction_build(sgdg_plan* plan) {
       whole = whole && r.ntile[m] == 1;
       mx = std::max(mx, r.gdof[d - m]);
     }
-    rh->xs_lds[m] = whole && mx * (int64_t)sizeof(double) <= RX_XS_LDS ? (int)(mx * sizeof(double)) : 0;
+    rh->xs_lds[m] =
+        whole && rh->llane[m] == 0 && mx * (int64_t)sizeof(double) <= RX_XS_LDS ? (int)(mx * sizeof(double)) : 0;
   }
+  // level bucket per degree: the smallest of 5, 7, 9, RX_LMAX levels that
+  // holds every instance of that degree
+  for (const RInst& r : ri) rh->lm[r.K1] = std::max(rh->lm[r.K1], r.N + 1);
+  for (int& v : rh->lm) v = v <= 5 ? 5 : v <= 7 ? 7 : v <= 9 ? 9 : RX_LMAX;
   rh->rws = ws;
   sgdg_status st;
   if ((st = up(plan, ri, &rh->dev.inst)) != SGDG_OK || (st = up(plan, rblk, &rh->dev.rblk)) != SGDG_OK ||
@@ -632,7 +632,7 @@ __device__ __forceinline__ void stage_block(double* __restrict__ dst, const doub
 // XS: the tile holds every fibre of its (species, prefix) and the prefix's
 // hierarchical block is first copied to LDS (xs), so that the walk reads only
 // LDS and issues nothing but stores to global memory.
-template <int K1, bool LANES, bool XS>
+template <int K1, int LM, bool LANES, bool XS>
 __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg, int inst, int m, int64_t total,
                                const RxArgs& a, int64_t rws, int lam, int ll, double* xs) {
   const RInst& I = R.inst[inst];
@@ -644,7 +644,6 @@ __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg,
   const double* __restrict__ in =
       m == 0 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)t.s * I.ndof
              : xr + I.X_off[m] + (((int64_t)z * S + t.s) * I.npre[m] + t.pre) * gd_in;
-  constexpr int LM = rx_levels<K1>();
   const bool valid = t.eo < gd_out;
   const Fibre<LM> F = fibre_geometry<LM>(R, I, r, valid ? t.eo : 0);
   if constexpr (XS) {
@@ -707,17 +706,17 @@ __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg,
   }
 }
 
-// one kernel per degree (register use follows K1); workgroups of instances
-// of another degree return at once
+// one kernel per degree and level bucket LM >= N + 1 (register use follows
+// K1 and LM); workgroups of instances of another degree return at once
 // (the basis table is its own argument: its loads are wave-uniform and go
 // through the scalar cache)
-template <int K1, bool LANES, bool XS>
+template <int K1, int LM, bool LANES, bool XS>
 __global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, const double* __restrict__ EHg, int ninst, int m,
                                                           int64_t total, RxArgs a, int64_t rws, int lam, int ll) {
   extern __shared__ double xs_dyn[];
   const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
   if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
-  rx_expand_body<K1, LANES, XS>(R, EHg, inst, m, total, a, rws, lam, ll, xs_dyn);
+  rx_expand_body<K1, LM, LANES, XS>(R, EHg, inst, m, total, a, rws, lam, ll, xs_dyn);
 }
 
 // contraction stage m: weighted point values along axis m -> hierarchical
@@ -726,7 +725,7 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, const doubl
 // outputs are collected in an LDS image of the prefix's hierarchical block
 // (ys) and written out together at the end, so that the walk issues only
 // loads to global memory.
-template <int K1, bool LANES, bool XS>
+template <int K1, int LM, bool LANES, bool XS>
 __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EHg, const double* __restrict__ w1g,
                                  int inst, int m, int mode, int64_t total, const RxArgs& a, int64_t rws, int lam,
                                  int ll, int64_t nfin, double* ys) {
@@ -741,15 +740,14 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
   const int lw = LANES ? lam - ll : lam;
   const int w = t.wc * (4 >> lw) + t.fb;
   const int64_t gd_in = I.gdof[r - 1], gd_out = I.gdof[r];
-  // every thread passes the barriers; threads past the fibre set carry zeros
-  // and emit nothing
+  // every thread passes the barriers; threads past the fibre set emit nothing
   const bool valid = t.eo < gd_in;
-  constexpr int LM = rx_levels<K1>();
   const Fibre<LM> F = fibre_geometry<LM>(R, I, r, valid ? t.eo : 0);
   const int L = valid ? F.L : -1;
   const int Lw = wave_max_level(L);
   double* xr = a.rws + (int64_t)rhs * rws;
-  // (threads past the fibre set read fibre 0's points and weight them by zero)
+  // (threads past the fibre set walk fibre 0's points; their sums, kept apart
+  // from every valid fibre's, are never emitted)
   const double* __restrict__ in =
       xr + I.Y_off[m + 1] + ((int64_t)t.s * I.npre[m + 1] + t.pre * np1) * gd_in + (valid ? t.eo : 0);
   const double* __restrict__ EH = EHg + I.EH_off;
@@ -799,7 +797,7 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
       for (int gq = 0; gq < K1; ++gq) {
         const int q = c * K1 + gq;
         const double* __restrict__ eh = EH + (int64_t)q * NL1 * K1;
-        const double g = valid ? w1[q] * gv[b][gq] : 0.0;
+        const double g = w1[q] * gv[b][gq];
 #pragma unroll
         for (int l = 0; l < LM; ++l)
           if (l <= Lw)
@@ -876,7 +874,7 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
   }
 }
 
-template <int K1, bool LANES, bool XS>
+template <int K1, int LM, bool LANES, bool XS>
 __global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, const double* __restrict__ EHg,
                                                             const double* __restrict__ w1g, int ninst, int m, int mode,
                                                             int64_t total, RxArgs a, int64_t rws, int lam, int ll,
@@ -884,7 +882,7 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, const dou
   extern __shared__ double ys_dyn[];
   const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
   if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
-  rx_contract_body<K1, LANES, XS>(R, EHg, w1g, inst, m, mode, total, a, rws, lam, ll, nfin, ys_dyn);
+  rx_contract_body<K1, LM, LANES, XS>(R, EHg, w1g, inst, m, mode, total, a, rws, lam, ll, nfin, ys_dyn);
 }
 
 // Last axis: a tile of nl whole lines (consecutive prefixes).  LDS: the
@@ -1566,21 +1564,30 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
     if (rh->k1mask & 16) launch(std::integral_constant<int, 4>());
   };
   using std::integral_constant;
-  // a stage launch with its lane-chunk and LDS-staging forms picked at run time
-  auto forms = [&](int m, bool xs, auto go) {
-    const bool ln = rh->llane[m] > 0;
-    if (ln && xs) go(integral_constant<bool, true>(), integral_constant<bool, true>());
-    else if (ln) go(integral_constant<bool, true>(), integral_constant<bool, false>());
-    else if (xs) go(integral_constant<bool, false>(), integral_constant<bool, true>());
-    else go(integral_constant<bool, false>(), integral_constant<bool, false>());
+  // a stage launch with its level bucket and its lane-chunk or LDS-staging
+  // form picked at run time (lane chunks and staging never meet: staging
+  // needs lam <= 2)
+  auto forms = [&](int K1, int m, bool xs, auto go) {
+    auto lm = [&](auto lanes, auto stg) {
+      switch (rh->lm[K1]) {
+        case 5: go(integral_constant<int, 5>(), lanes, stg); break;
+        case 7: go(integral_constant<int, 7>(), lanes, stg); break;
+        case 9: go(integral_constant<int, 9>(), lanes, stg); break;
+        default: go(integral_constant<int, RX_LMAX>(), lanes, stg); break;
+      }
+    };
+    if (rh->llane[m] > 0) lm(integral_constant<bool, true>(), integral_constant<bool, false>());
+    else if (xs) lm(integral_constant<bool, false>(), integral_constant<bool, true>());
+    else lm(integral_constant<bool, false>(), integral_constant<bool, false>());
   };
   for (int m = 0; m + 1 <= d - 1; ++m)
     each([&](auto k1) {
       if (mark) (*mark)(0);
       const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin);
       const int xs = rh->xs_lds[m];
-      forms(m, xs > 0, [&](auto lanes, auto stg) {
-        hipLaunchKernelGGL((k_rx_expand<decltype(k1)::value, decltype(lanes)::value, decltype(stg)::value>), grid,
+      forms(decltype(k1)::value, m, xs > 0, [&](auto lmv, auto lanes, auto stg) {
+        hipLaunchKernelGGL((k_rx_expand<decltype(k1)::value, decltype(lmv)::value, decltype(lanes)::value,
+                                        decltype(stg)::value>), grid,
                            dim3(RX_THREADS), stg ? xs : 0, s, rh->dev, (const double*)rh->dev.EH, ninst, m,
                            plan->total, a, rh->rws, rh->lam[m], rh->llane[m]);
       });
@@ -1594,8 +1601,9 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
       if (mark) (*mark)(2);
       const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs);
       const int xs = m > 0 ? rh->xs_lds[m] : 0;
-      forms(m, xs > 0, [&](auto lanes, auto stg) {
-        hipLaunchKernelGGL((k_rx_contract<decltype(k1)::value, decltype(lanes)::value, decltype(stg)::value>), grid,
+      forms(decltype(k1)::value, m, xs > 0, [&](auto lmv, auto lanes, auto stg) {
+        hipLaunchKernelGGL((k_rx_contract<decltype(k1)::value, decltype(lmv)::value, decltype(lanes)::value,
+                                          decltype(stg)::value>), grid,
                            dim3(RX_THREADS), stg ? xs : 0, s, rh->dev, (const double*)rh->dev.EH,
                            (const double*)rh->dev.w1, ninst, m, (int)mode, plan->total, a, rh->rws, rh->lam[m],
                            rh->llane[m], nfin);
