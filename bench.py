@@ -410,10 +410,13 @@ def main():
     achieved = line_bytes / (line_ms / 1e3) / 1e9
     log("[bench] triad")
     triad_gbs, triad_bytes = triad(torch)
+    # the build the autotuner chose for one input per point (register budget 0 or 3)
+    waves = TUNING.get("quadratic_d4_batch16", {}).get("classes", [{}])[0].get("waves", [0, 0])[0]
+    kname = ("k_rx_wline_w3" if waves == 3 else "k_rx_wline") + "<2,1,1>"
     out["roofline"] = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic_record("k_rx_wline_quadratic_d4_rhs16", REACTION_SOURCES),
-        "kernel": "k_rx_wline<2,1,1> (last-axis reaction kernel, wave form: inverse transform, f, forward transform)",
+        "kernel": kname + " (last-axis reaction kernel, wave form: inverse transform, f, forward transform)",
         "avg_us": line_ms * 1e3, "bytes_per_launch": line_bytes, "frac_of_triad": achieved / triad_gbs,
         "reaction_pass": {"stage_kinds": kinds, "stage_ms": ms, "pass_ms": pass_ms,
                           "note": "kinds: 0 expansion (axes 0..2), 1 last axis, 2 contraction; F pass, 16 RHS"},
@@ -421,9 +424,10 @@ def main():
                 "268M points per RHS read once, its projection written once); duration from HIP events "
                 "around the launch on its stream",
     }
-    out["autotune"] = dict(TUNING, note="last-axis reaction kernel: rounds per tile and workgroups per CU chosen "
-                                         "from timed trials (sg_dg_tune) before the timed steps; index 0 / 1 = one / "
-                                         "two inputs per point")
+    out["autotune"] = dict(TUNING, note="last-axis reaction kernel: rounds per tile, workgroups per CU and register "
+                                         "budget (waves 0: the compiler's, 3: at most 168 VGPRs) chosen from timed "
+                                         "trials (sg_dg_tune) before the timed steps; index 0 / 1 = one / two inputs "
+                                         "per point")
     out["triad"] = {"achieved_gbs": triad_gbs, "bytes": triad_bytes, "frac_of_peak": triad_gbs / HBM_PEAK_GBS,
                     "note": "c = a + 0.5 b over three 1 GiB FP64 arrays"}
 

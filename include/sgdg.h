@@ -278,8 +278,10 @@ sgdg_status rk_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t orde
  * gives every wave of a workgroup its lines once) and workgroups per compute
  * unit -- changes only which workgroup computes which line: every value is
  * computed the same way, so results are bit for bit the same for every
- * shape.  These calls change a plan's launch shapes: no other call may use
- * the plan while they run. */
+ * shape.  A shape also picks one of two builds of the kernel: the compiler's
+ * register allocation (waves 0) or at most 168 VGPRs, i.e. three waves per
+ * SIMD, spilling what does not fit (waves 3).  These calls change a plan's
+ * launch shapes: no other call may use the plan while they run. */
 #define SGDG_TUNE_MAXCLASS 16
 typedef struct {
   int32_t nclass;                                  /* classes reported (wave-form last axis only)      */
@@ -287,20 +289,23 @@ typedef struct {
   int32_t cls[SGDG_TUNE_MAXCLASS];                 /* class index for sg_dg_line_shape                  */
   int32_t rounds[SGDG_TUNE_MAXCLASS][2];           /* chosen rounds per tile, one and two inputs/point */
   int32_t wgcu[SGDG_TUNE_MAXCLASS][2];             /* chosen workgroups per compute unit               */
+  int32_t waves[SGDG_TUNE_MAXCLASS][2];            /* chosen register budget: 0 or 3 (see above)       */
   float ms_default[SGDG_TUNE_MAXCLASS][2];         /* one launch at the shape found on entry           */
   float ms_best[SGDG_TUNE_MAXCLASS][2];            /* one launch at the chosen shape                   */
   int32_t from_cache[SGDG_TUNE_MAXCLASS][2];       /* 1: taken from this process's earlier tuning      */
 } sgdg_tune_report;
 
 /* Times every candidate shape (rounds 1, 2, 4, 8, 16, 32 x workgroups per CU
- * 4, 8, 16, 32) of each class's last-axis launch for nrhs right-hand sides,
+ * 4, 8, 16, 32 with waves 0, then waves 3 with each workgroup count at the
+ * best rounds) of each class's last-axis launch for nrhs right-hand sides,
  * one and two inputs per point, with HIP events on `stream` (synchronising
  * it), and keeps the fastest.  Choices are cached per process by GPU
  * architecture and compute-unit count, (degree, level, species), inputs,
  * nrhs and line count; a cached class is set without timing.  If the
  * environment variable SGDG_TUNE_CACHE names a file, the cache is also read
  * from it (once per process) and every new choice is appended to it (one line
- * "arch cus K1 N species inputs nrhs lines rounds wgcu").  workspace: at least iif2_bytes for M = 1 and nrhs
+ * "arch cus K1 N species inputs nrhs lines rounds wgcu waves"; a line without
+ * the last field reads as waves 0).  workspace: at least iif2_bytes for M = 1 and nrhs
  * (sg_dg_workspace_size); its contents are overwritten.  report: host
  * pointer, may be NULL.  Errors: SGDG_ERR_ARG, _UNSUPPORTED (no reaction
  * tables for this plan), _HIP.                                              */
@@ -308,10 +313,11 @@ sgdg_status sg_dg_tune(sgdg_plan* plan, int32_t nrhs, void* workspace, size_t wo
                        sgdg_tune_report* report, void* stream);
 
 /* Sets the shape of class `cls`, `ninputs` (1: F and residual passes, 2: the
- * stage correction) to `rounds` rounds per tile (1..64) and `wgcu` workgroups
- * per compute unit (1..64).  Errors: SGDG_ERR_ARG, _UNSUPPORTED (the class
- * does not run the wave form), _HIP.                                        */
-sgdg_status sg_dg_line_shape(sgdg_plan* plan, int32_t cls, int32_t ninputs, int32_t rounds, int32_t wgcu);
+ * stage correction) to `rounds` rounds per tile (1..64), `wgcu` workgroups
+ * per compute unit (1..64) and register budget `waves` (0 or 3).  Errors:
+ * SGDG_ERR_ARG, _UNSUPPORTED (the class does not run the wave form), _HIP.   */
+sgdg_status sg_dg_line_shape(sgdg_plan* plan, int32_t cls, int32_t ninputs, int32_t rounds, int32_t wgcu,
+                             int32_t waves);
 
 #ifdef __cplusplus
 }

@@ -494,12 +494,16 @@ namespace {
 // key: architecture name, compute units, K1, N, species, inputs, nrhs, lines of the class
 using TuneKey = std::tuple<std::string, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t>;
 std::mutex g_tune_mu;
-std::map<TuneKey, std::pair<int, int>> g_tune_cache;  // -> (rounds, workgroups per CU)
+struct TuneShape {
+  int rounds, wgcu, waves;
+};
+std::map<TuneKey, TuneShape> g_tune_cache;
 bool g_tune_file_read = false;
 
 // The file named by SGDG_TUNE_CACHE (if set) extends the process cache: one
-// line per choice, "arch cus K1 N S inputs nrhs lines rounds wgcu"; read once,
-// appended to after every new choice.  (Called with g_tune_mu held.)
+// line per choice, "arch cus K1 N S inputs nrhs lines rounds wgcu waves"
+// (a line without the last field means waves 0); read once, appended to
+// after every new choice.  (Called with g_tune_mu held.)
 void tune_file_read() {
   if (g_tune_file_read) return;
   g_tune_file_read = true;
@@ -507,33 +511,39 @@ void tune_file_read() {
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  char arch[64];
-  long long v[9];
-  while (std::fscanf(f, "%63s %lld %lld %lld %lld %lld %lld %lld %lld %lld", arch, &v[0], &v[1], &v[2], &v[3], &v[4],
-                     &v[5], &v[6], &v[7], &v[8]) == 10)
-    g_tune_cache[TuneKey{arch, v[0], v[1], v[2], v[3], v[4], v[5], v[6]}] = {(int)v[7], (int)v[8]};
+  char line[512], arch[64];
+  long long v[10];
+  while (std::fgets(line, sizeof line, f)) {
+    v[9] = 0;
+    const int n = std::sscanf(line, "%63s %lld %lld %lld %lld %lld %lld %lld %lld %lld %lld", arch, &v[0], &v[1], &v[2],
+                              &v[3], &v[4], &v[5], &v[6], &v[7], &v[8], &v[9]);
+    if (n == 10 || n == 11)
+      g_tune_cache[TuneKey{arch, v[0], v[1], v[2], v[3], v[4], v[5], v[6]}] = {(int)v[7], (int)v[8], (int)v[9]};
+  }
   std::fclose(f);
 }
 
-void tune_file_append(const TuneKey& k, int rounds, int wgcu) {
+void tune_file_append(const TuneKey& k, const TuneShape& t) {
   const char* path = std::getenv("SGDG_TUNE_CACHE");
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %lld %lld %lld %lld %lld %lld %lld %d %d\n", std::get<0>(k).c_str(), (long long)std::get<1>(k),
-               (long long)std::get<2>(k), (long long)std::get<3>(k), (long long)std::get<4>(k),
-               (long long)std::get<5>(k), (long long)std::get<6>(k), (long long)std::get<7>(k), rounds, wgcu);
+  std::fprintf(f, "%s %lld %lld %lld %lld %lld %lld %lld %d %d %d\n", std::get<0>(k).c_str(),
+               (long long)std::get<1>(k), (long long)std::get<2>(k), (long long)std::get<3>(k),
+               (long long)std::get<4>(k), (long long)std::get<5>(k), (long long)std::get<6>(k),
+               (long long)std::get<7>(k), t.rounds, t.wgcu, t.waves);
   std::fclose(f);
 }
 }  // namespace
 
-extern "C" sgdg_status sg_dg_line_shape(sgdg_plan* plan, int32_t cls, int32_t ninputs, int32_t rounds, int32_t wgcu) {
+extern "C" sgdg_status sg_dg_line_shape(sgdg_plan* plan, int32_t cls, int32_t ninputs, int32_t rounds, int32_t wgcu,
+                                        int32_t waves) {
   if (!plan) return fail(SGDG_ERR_ARG, "sg_dg_line_shape: null plan");
   if (!reaction_supported(plan)) return fail(SGDG_ERR_UNSUPPORTED, "sg_dg_line_shape: the plan has no reaction tables");
   // (queued work of any stream may still read the tile list being replaced)
   const hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "sg_dg_line_shape: synchronise");
-  return reaction_set_line_shape(plan, cls, ninputs, rounds, wgcu);
+  return reaction_set_line_shape(plan, cls, ninputs, rounds, wgcu, waves);
 }
 
 extern "C" sgdg_status sg_dg_tune(sgdg_plan* plan, int32_t nrhs, void* workspace, size_t workspace_bytes,
@@ -598,8 +608,8 @@ extern "C" sgdg_status sg_dg_tune(sgdg_plan* plan, int32_t nrhs, void* workspace
     for (int nin = 1; nin <= 2 && st == SGDG_OK; ++nin) {
       const RxMode mode = nin == 1 ? RX_F : RX_CORR;
       // one launch of the class's last axis at a shape, averaged over kReps after a warm-up
-      auto time_shape = [&](int r, int g, float* ms) -> sgdg_status {
-        sgdg_status q = reaction_set_line_shape(plan, c, nin, r, g);
+      auto time_shape = [&](int r, int g, int wv, float* ms) -> sgdg_status {
+        sgdg_status q = reaction_set_line_shape(plan, c, nin, r, g, wv);
         if (q != SGDG_OK) return q;
         reaction_line_stage(plan, nrhs, mode, a, s, c);
         hipError_t he = hipEventRecord(e0, s);
@@ -621,40 +631,50 @@ extern "C" sgdg_status sg_dg_tune(sgdg_plan* plan, int32_t nrhs, void* workspace
         tune_file_read();
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-          st = reaction_set_line_shape(plan, c, nin, it->second.first, it->second.second);
-          rep.rounds[slot][nin - 1] = it->second.first;
-          rep.wgcu[slot][nin - 1] = it->second.second;
+          const TuneShape& t = it->second;
+          st = reaction_set_line_shape(plan, c, nin, t.rounds, t.wgcu, t.waves);
+          rep.rounds[slot][nin - 1] = t.rounds;
+          rep.wgcu[slot][nin - 1] = t.wgcu;
+          rep.waves[slot][nin - 1] = t.waves;
           rep.from_cache[slot][nin - 1] = 1;
           continue;
         }
       }
-      const int r0 = lc.rounds[nin], g0 = lc.wgcu[nin];
+      const int r0 = lc.rounds[nin], g0 = lc.wgcu[nin], v0 = lc.waves[nin];
       float t0 = 0.f;
-      if ((st = time_shape(r0, g0, &t0)) != SGDG_OK) break;
-      int rb = r0, gb = g0;
+      if ((st = time_shape(r0, g0, v0, &t0)) != SGDG_OK) break;
+      TuneShape b{r0, g0, v0};
       float tb = t0;
+      auto trial = [&](int r, int g, int wv) -> sgdg_status {
+        float t = 0.f;
+        const sgdg_status q = time_shape(r, g, wv, &t);
+        if (q == SGDG_OK && t < tb) {
+          tb = t;
+          b = {r, g, wv};
+        }
+        return q;
+      };
+      // the grid of shapes with the compiler's registers, then the capped
+      // register budget at the best rounds with every workgroup count
       for (int r : kRounds) {
         if (r > 1 && (int64_t)lc.lpr * (r / 2) >= most) break;  // (no more lines per tile than the largest instance has)
-        for (int g : kWgcu) {
-          float t = 0.f;
-          if ((st = time_shape(r, g, &t)) != SGDG_OK) break;
-          if (t < tb) {
-            tb = t;
-            rb = r;
-            gb = g;
-          }
-        }
+        for (int g : kWgcu)
+          if ((st = trial(r, g, 0)) != SGDG_OK) break;
         if (st != SGDG_OK) break;
       }
+      const int rbest = b.rounds;
+      for (int g : kWgcu)
+        if (st == SGDG_OK) st = trial(rbest, g, 3);
       if (st != SGDG_OK) break;
-      if ((st = reaction_set_line_shape(plan, c, nin, rb, gb)) != SGDG_OK) break;
-      rep.rounds[slot][nin - 1] = rb;
-      rep.wgcu[slot][nin - 1] = gb;
+      if ((st = reaction_set_line_shape(plan, c, nin, b.rounds, b.wgcu, b.waves)) != SGDG_OK) break;
+      rep.rounds[slot][nin - 1] = b.rounds;
+      rep.wgcu[slot][nin - 1] = b.wgcu;
+      rep.waves[slot][nin - 1] = b.waves;
       rep.ms_default[slot][nin - 1] = t0;
       rep.ms_best[slot][nin - 1] = tb;
       std::lock_guard<std::mutex> g(g_tune_mu);
-      g_tune_cache[key] = {rb, gb};
-      tune_file_append(key, rb, gb);
+      g_tune_cache[key] = b;
+      tune_file_append(key, b);
     }
   }
   (void)hipEventDestroy(e0);

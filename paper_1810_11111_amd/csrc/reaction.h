@@ -66,12 +66,14 @@ struct LineClass {
   int threads[3] = {}; // workgroup size
   // wave form (d >= 2, N <= RX_WLINE_MAXN): a tile is `rounds` rounds of
   // `lpr` lines (one round: every wave of the workgroup takes its lines once);
-  // its grid-stride launch has wgcu workgroups per compute unit.  Launch
-  // shapes only: every line is computed the same way whatever the shape.
+  // its grid-stride launch has wgcu workgroups per compute unit and one of
+  // two register budgets.  Launch shapes only: every line is computed the
+  // same way whatever the shape.
   bool wave = false;
   int lpr = 0;
   int rounds[3] = {};
   int wgcu[3] = {};
+  int waves[3] = {};  // 0: the compiler's register allocation; 3: at most 168 VGPRs (three waves per SIMD)
   size_t cap_tasks[3] = {};                     // room in dev[nin] (tiles of one round)
   std::vector<std::pair<int, int64_t>> lines;   // (instance, lines of its last axis)
 };
@@ -128,7 +130,7 @@ int64_t reaction_ws_doubles(const sgdg_plan* plan);
 // (degree, level, species) groups of instances.
 int reaction_line_classes(const sgdg_plan* plan);
 const LineClass& reaction_line_class(const sgdg_plan* plan, int c);
-sgdg_status reaction_set_line_shape(sgdg_plan* plan, int c, int nin, int rounds, int wgcu);
+sgdg_status reaction_set_line_shape(sgdg_plan* plan, int c, int nin, int rounds, int wgcu, int waves);
 // Only the last-axis launch of class c of a pass (inputs: the reaction workspace).
 void reaction_line_stage(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a, hipStream_t s, int c);
 

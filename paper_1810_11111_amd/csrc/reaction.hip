@@ -1165,6 +1165,8 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, const LineTas
 // loop (a pass whose problems have converged costs one flag test per tile).
 // The arithmetic of every value is the line kernel's (the same two-scale,
 // point and projection sums in the same order).
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
 template <int K1>
 constexpr int wl_cpl() {
   return K1 == 2 ? 8 : 4;  // finest cells per lane (at most)
@@ -1259,8 +1261,8 @@ __device__ __forceinline__ void wl_map(const double* __restrict__ rxc, uint64_t 
 
 
 template <int K1, int S, int NIN>
-__global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTask* __restrict__ tasks, int ntask,
-                                                         int ninst, int mode, RxArgs a, int64_t rws, int64_t nwork) {
+__device__ __forceinline__ void rx_wline_body(const RTables& R, const LineTask* __restrict__ tasks, int ntask,
+                                              int ninst, int mode, const RxArgs& a, int64_t rws, int64_t nwork) {
   constexpr int NP = S * NIN;
   constexpr int CP = wl_cpl<K1>();
   constexpr int WL = 64 * K1 * CP;  // doubles of a wave's lines per pair
@@ -1356,12 +1358,29 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTa
       const int nline = min(LPW, t.nl - l0);
       const bool act = li < nline;
       const int64_t pre0 = t.pre0 + l0;
+      // the wave's lines go straight from HBM to its LDS buffer (direct
+      // global -> LDS loads, all issued before the one wait; 16 bytes per lane
+      // and instruction when the run is 16-byte aligned, else 4)
+      const int ne = nline * n1;
 #pragma unroll
       for (int pr = 0; pr < NP; ++pr) {
         const int z = pr / S, sp = pr - z * S;
         const double* __restrict__ src = xr + xoff + (((int64_t)z * S + sp) * npre + pre0) * n1;
-        for (int e = lane; e < nline * n1; e += 64) buf[pr * WL + e] = src[e];
+        double* dst = buf + pr * WL;
+        if (((uintptr_t)src & 15) == 0 && (ne & 1) == 0) {
+#pragma unroll
+          for (int u = 0; u < WL / 128; ++u)
+            if (2 * (64 * u + lane) < ne)
+              __builtin_amdgcn_global_load_lds((const void*)(src + 2 * (64 * u + lane)), (lds_ptr)(dst + 128 * u), 16,
+                                               0, 0);
+        } else {
+          const uint32_t* s4 = (const uint32_t*)src;
+          for (int u = 0; u < WL / 32; ++u)
+            if (64 * u + lane < 2 * ne)
+              __builtin_amdgcn_global_load_lds((const void*)(s4 + 64 * u + lane), (lds_ptr)(dst + 32 * u), 4, 0, 0);
+        }
       }
+      __builtin_amdgcn_s_waitcnt(0);  // the direct loads have landed
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1495,13 +1514,36 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTa
 #pragma unroll
       for (int sp = 0; sp < S; ++sp) {
         double* __restrict__ dst = xr + yoff + ((int64_t)sp * npre + pre0) * n1;
-        for (int e = lane; e < nline * n1; e += 64) dst[e] = buf[sp * WL + e];
+#pragma unroll
+        for (int u0 = 0; u0 < WL / 64; u0 += 4) {
+          double v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = buf[sp * WL + lane + 64 * (u0 + u)];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (lane + 64 * (u0 + u) < ne) dst[lane + 64 * (u0 + u)] = v[u];
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
+}
+
+// The wave-form kernel with the compiler's register allocation, and with at
+// most 168 VGPRs (three waves per SIMD, spilling what does not fit): which
+// is faster depends on the instantiation and is measured by the autotuner.
+template <int K1, int S, int NIN>
+__global__ __launch_bounds__(RX_THREADS) void k_rx_wline(RTables R, const LineTask* __restrict__ tasks, int ntask,
+                                                         int ninst, int mode, RxArgs a, int64_t rws, int64_t nwork) {
+  rx_wline_body<K1, S, NIN>(R, tasks, ntask, ninst, mode, a, rws, nwork);
+}
+template <int K1, int S, int NIN>
+__global__ __launch_bounds__(RX_THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_rx_wline_w3(
+    RTables R, const LineTask* __restrict__ tasks, int ntask, int ninst, int mode, RxArgs a, int64_t rws,
+    int64_t nwork) {
+  rx_wline_body<K1, S, NIN>(R, tasks, ntask, ninst, mode, a, rws, nwork);
 }
 
 // The last-axis launch of one class of instances in a pass.
@@ -1517,8 +1559,12 @@ static void launch_line(const sgdg_plan* plan, const LineClass& lc, int nrhs, Rx
     const unsigned grid = (unsigned)std::min<int64_t>(nwork, (int64_t)std::max(rh->ncu, 1) * lc.wgcu[nin]);
     auto wl = [&](auto k1, auto sp, auto ni) {
       constexpr int K1 = decltype(k1)::value, S = decltype(sp)::value, NIN = decltype(ni)::value;
-      hipLaunchKernelGGL((k_rx_wline<K1, S, NIN>), dim3(grid), dim3(RX_THREADS), 0, s, rh->dev, lc.dev[nin], ntask,
-                         ninst, (int)mode, a, rh->rws, nwork);
+      if (lc.waves[nin] == 3)
+        hipLaunchKernelGGL((k_rx_wline_w3<K1, S, NIN>), dim3(grid), dim3(RX_THREADS), 0, s, rh->dev, lc.dev[nin],
+                           ntask, ninst, (int)mode, a, rh->rws, nwork);
+      else
+        hipLaunchKernelGGL((k_rx_wline<K1, S, NIN>), dim3(grid), dim3(RX_THREADS), 0, s, rh->dev, lc.dev[nin], ntask,
+                           ninst, (int)mode, a, rh->rws, nwork);
     };
     auto by_s = [&](auto k1) {
       if (lc.S == 1) {
@@ -1618,7 +1664,7 @@ int reaction_line_classes(const sgdg_plan* plan) {
 }
 const LineClass& reaction_line_class(const sgdg_plan* plan, int c) { return ((const RHost*)plan->rdata)->lclass[c]; }
 
-sgdg_status reaction_set_line_shape(sgdg_plan* plan, int c, int nin, int rounds, int wgcu) {
+sgdg_status reaction_set_line_shape(sgdg_plan* plan, int c, int nin, int rounds, int wgcu, int waves) {
   RHost* rh = (RHost*)plan->rdata;
   if (!rh->supported || c < 0 || c >= (int)rh->lclass.size() || nin < 1 || nin > 2)
     return fail(SGDG_ERR_ARG, "line shape: no such class");
@@ -1626,6 +1672,7 @@ sgdg_status reaction_set_line_shape(sgdg_plan* plan, int c, int nin, int rounds,
   if (!lc.wave) return fail(SGDG_ERR_UNSUPPORTED, "line shape: the class runs the LDS-tile form");
   if (rounds < 1 || rounds > RX_WLINE_MAXROUNDS || wgcu < 1 || wgcu > 64)
     return fail(SGDG_ERR_ARG, "line shape: rounds must be in 1..64 and workgroups per CU in 1..64");
+  if (waves != 0 && waves != 3) return fail(SGDG_ERR_ARG, "line shape: waves per SIMD must be 0 (compiler's) or 3");
   std::vector<LineTask> t = wave_tiles(lc, rounds);
   if (t.size() > lc.cap_tasks[nin]) return fail(SGDG_ERR_ARG, "line shape: too many tiles");
   const hipError_t e = hipMemcpy(lc.dev[nin], t.data(), t.size() * sizeof(LineTask), hipMemcpyHostToDevice);
@@ -1633,6 +1680,7 @@ sgdg_status reaction_set_line_shape(sgdg_plan* plan, int c, int nin, int rounds,
   lc.tasks[nin].swap(t);
   lc.rounds[nin] = rounds;
   lc.wgcu[nin] = wgcu;
+  lc.waves[nin] = waves;
   return SGDG_OK;
 }
 

@@ -50,6 +50,7 @@ class TuneReport(C.Structure):
     _fields_ = [("nclass", C.c_int32), ("k", C.c_int32 * TUNE_MAXCLASS), ("n", C.c_int32 * TUNE_MAXCLASS),
                 ("nspecies", C.c_int32 * TUNE_MAXCLASS), ("cls", C.c_int32 * TUNE_MAXCLASS),
                 ("rounds", (C.c_int32 * 2) * TUNE_MAXCLASS), ("wgcu", (C.c_int32 * 2) * TUNE_MAXCLASS),
+                ("waves", (C.c_int32 * 2) * TUNE_MAXCLASS),
                 ("ms_default", (C.c_float * 2) * TUNE_MAXCLASS), ("ms_best", (C.c_float * 2) * TUNE_MAXCLASS),
                 ("from_cache", (C.c_int32 * 2) * TUNE_MAXCLASS)]
 
@@ -84,7 +85,7 @@ _sigs = {
     "rk_step": ([_vp, _i32, _f64, _i32, _vp, _vp, _sz, _vp], C.c_int),
     "iif2_step_local": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _vp, _sz, _vp, _vp], C.c_int),
     "sg_dg_tune": ([_vp, _i32, _vp, _sz, C.POINTER(TuneReport), _vp], C.c_int),
-    "sg_dg_line_shape": ([_vp, _i32, _i32, _i32, _i32], C.c_int),
+    "sg_dg_line_shape": ([_vp, _i32, _i32, _i32, _i32, _i32], C.c_int),
 }
 EXPORTED = sorted(_sigs)
 for _name, (_args, _res) in _sigs.items():
@@ -264,8 +265,8 @@ class Plan:
                                C.byref(r), _stream(stream)), "sg_dg_tune")
         return _tune_dict(r)
 
-    def line_shape(self, cls, ninputs, rounds, wg_per_cu):
-        _check(_lib.sg_dg_line_shape(self._h, cls, ninputs, rounds, wg_per_cu), "sg_dg_line_shape")
+    def line_shape(self, cls, ninputs, rounds, wg_per_cu, waves=0):
+        _check(_lib.sg_dg_line_shape(self._h, cls, ninputs, rounds, wg_per_cu, waves), "sg_dg_line_shape")
 
 
 def _tune_dict(r):
@@ -273,6 +274,7 @@ def _tune_dict(r):
     for i in range(r.nclass):
         out.append({"class": r.cls[i], "k": r.k[i], "N": r.n[i], "species": r.nspecies[i],
                     "rounds": [r.rounds[i][0], r.rounds[i][1]], "wg_per_cu": [r.wgcu[i][0], r.wgcu[i][1]],
+                    "waves": [r.waves[i][0], r.waves[i][1]],
                     "ms_default": [r.ms_default[i][0], r.ms_default[i][1]],
                     "ms_best": [r.ms_best[i][0], r.ms_best[i][1]],
                     "from_cache": [r.from_cache[i][0], r.from_cache[i][1]]})

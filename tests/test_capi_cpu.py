@@ -56,7 +56,7 @@ def test_argument_errors_return_before_device_work():
     assert L.rk_step(None, 1, 0.1, 2, None, None, 0, None) in (1, 4)
     assert L.iif2_step_local(None, 1, 0.1, 10, None, None, None, None, 0, None, None) in (1, 4)
     assert L.sg_dg_tune(None, 1, None, 0, None, None) == 1
-    assert L.sg_dg_line_shape(None, 0, 1, 1, 1) == 1
+    assert L.sg_dg_line_shape(None, 0, 1, 1, 1, 0) == 1
     assert L.sg_dg_destroy(None) == 1
 
 

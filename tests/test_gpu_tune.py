@@ -2,10 +2,11 @@
 sg_dg_line_shape).
 
 The last axis of F(U) = P f(R U) (Sec. 5, applied axis by axis) runs as tiles
-of whole lines; a shape (lines per tile, workgroups per compute unit) only
-decides which workgroup computes which line.  So a tuned plan, and plans
-forced to the extreme shapes, must give the default plan's F and IIF2 steps
-(Sec. 3, eq. 3.5) bit for bit.
+of whole lines; a shape (lines per tile, workgroups per compute unit, and
+which of two register budgets the kernel is built with) only decides which
+workgroup computes which line and how the compiler keeps its values.  So a
+tuned plan, and plans forced to the extreme shapes, must give the default
+plan's F and IIF2 steps (Sec. 3, eq. 3.5) bit for bit.
 """
 import os
 
@@ -69,7 +70,7 @@ def test_tuned_and_forced_shapes_match_default(name):
     assert len(rep) >= 1
     for r in rep:
         for i in range(2):
-            assert 1 <= r["rounds"][i] <= 64 and 1 <= r["wg_per_cu"][i] <= 64
+            assert 1 <= r["rounds"][i] <= 64 and 1 <= r["wg_per_cu"][i] <= 64 and r["waves"][i] in (0, 3)
             assert r["ms_best"][i] <= r["ms_default"][i]
     got = _run(tuned, U0, nrhs, dt, M)
     for a, b in zip(got, ref):
@@ -79,24 +80,26 @@ def test_tuned_and_forced_shapes_match_default(name):
     again = sg.Plan(insts, "fp64")
     rep2 = again.tune(_ws(again, 1, nrhs), nrhs=nrhs)
     assert all(r["from_cache"] == [1, 1] for r in rep2)
-    assert [(r["rounds"], r["wg_per_cu"]) for r in rep2] == [(r["rounds"], r["wg_per_cu"]) for r in rep]
+    assert [(r["rounds"], r["wg_per_cu"], r["waves"]) for r in rep2] == [
+        (r["rounds"], r["wg_per_cu"], r["waves"]) for r in rep]
     again.close()
     tuned.close()
 
-    for rounds, wgcu in ((1, 1), (64, 64), (3, 5)):
+    for rounds, wgcu, waves in ((1, 1, 0), (64, 64, 3), (3, 5, 0), (2, 16, 3)):
         forced = sg.Plan(insts, "fp64")
         for r in rep:
             for nin in (1, 2):
-                forced.line_shape(r["class"], nin, rounds, wgcu)
+                forced.line_shape(r["class"], nin, rounds, wgcu, waves)
         got = _run(forced, U0, nrhs, dt, M)
         for a, b in zip(got, ref):
-            assert np.array_equal(a, b), (rounds, wgcu)
+            assert np.array_equal(a, b), (rounds, wgcu, waves)
         forced.close()
 
 
 def test_tune_cache_file(tmp_path):
     """Choices written to the SGDG_TUNE_CACHE file by one process are read by
     another (a fresh interpreter), which then sets them without timing."""
+    import json
     import subprocess
     import sys
 
@@ -108,7 +111,9 @@ def test_tune_cache_file(tmp_path):
         "from paper_1810_11111_amd import sgdg as sg, inputs as I\n"
         "p = sg.Plan(I.quadratic_d4(N=3).instances, 'fp64'); _, ib = p.workspace_size(1, 2)\n"
         "ws = torch.empty(ib, dtype=torch.uint8, device='cuda')\n"
-        "r = p.tune(ws, nrhs=2); print([c['from_cache'] for c in r], [c['rounds'] + c['wg_per_cu'] for c in r])\n"
+        "r = p.tune(ws, nrhs=2); import json\n"
+        "print(json.dumps({'cache': [c['from_cache'] for c in r],"
+        " 'shapes': [c['rounds'] + c['wg_per_cu'] + c['waves'] for c in r]}))\n"
     ) % (ROOT, os.path.join(ROOT, "tests"))
     env = dict(os.environ, SGDG_TUNE_CACHE=str(path))
     say("tune cache file")
@@ -117,10 +122,18 @@ def test_tune_cache_file(tmp_path):
     assert path.exists() and len(path.read_text().splitlines()) >= 2
     second = subprocess.run([sys.executable, "-c", prog], env=env, capture_output=True, text=True, timeout=240)
     assert second.returncode == 0, second.stderr[-2000:]
-    f1 = first.stdout.strip().splitlines()[-1]
-    f2 = second.stdout.strip().splitlines()[-1]
-    assert f1.startswith("[[0, 0]") and f2.startswith("[[1, 1]")
-    assert f1.split("] [", 1)[1] == f2.split("] [", 1)[1]  # the same shapes
+    f1 = json.loads(first.stdout.strip().splitlines()[-1])
+    f2 = json.loads(second.stdout.strip().splitlines()[-1])
+    assert all(c == [0, 0] for c in f1["cache"]) and all(c == [1, 1] for c in f2["cache"])
+    assert f1["shapes"] == f2["shapes"]
+    # lines of the older ten-field form (no register budget) read as waves 0
+    lines = path.read_text().splitlines()
+    path.write_text("".join(" ".join(ln.split()[:10]) + "\n" for ln in lines))
+    third = subprocess.run([sys.executable, "-c", prog], env=env, capture_output=True, text=True, timeout=240)
+    assert third.returncode == 0, third.stderr[-2000:]
+    f3 = json.loads(third.stdout.strip().splitlines()[-1])
+    assert all(c == [1, 1] for c in f3["cache"])
+    assert all(s[:4] == t[:4] and s[4:] == [0, 0] for s, t in zip(f3["shapes"], f1["shapes"]))
 
 
 def test_line_shape_argument_errors():
@@ -134,4 +147,6 @@ def test_line_shape_argument_errors():
         plan.line_shape(0, 1, 1, 65)
     with pytest.raises(sg.SgdgError):
         plan.line_shape(99, 1, 1, 1)
+    with pytest.raises(sg.SgdgError):
+        plan.line_shape(0, 1, 1, 1, waves=2)
     plan.close()
