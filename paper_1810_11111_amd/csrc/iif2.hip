@@ -54,7 +54,7 @@ size_t iif2_ws_bytes(const sgdg_plan* plan, int M, int nrhs) {
   b += al256((size_t)nrhs * reaction_final_fibres(plan) * 8);
   b += al256((size_t)nrhs * plan->nchunks * 8);
   b += al256((size_t)nrhs * plan->ninst * 8);
-  b += al256((size_t)nrhs * plan->ninst * 4);
+  b += al256(((size_t)nrhs * plan->ninst + 1) * 4);
   return b;
 }
 
@@ -78,7 +78,7 @@ static IifWs carve(const sgdg_plan* plan, int M, int nrhs, void* base) {
   w.part = (double*)take((size_t)nrhs * reaction_final_fibres(plan) * 8);
   w.partw = (double*)take((size_t)nrhs * plan->nchunks * 8);
   w.wnorm = (double*)take((size_t)nrhs * plan->ninst * 8);
-  w.conv = (int32_t*)take((size_t)nrhs * plan->ninst * 4);
+  w.conv = (int32_t*)take(((size_t)nrhs * plan->ninst + 1) * 4);  // flags, then their count
   return w;
 }
 
@@ -126,6 +126,7 @@ __global__ __launch_bounds__(CHUNK) void k_stage_init(DevTables T, int ninst, in
     for (int w = 0; w < CHUNK / 64; ++w) t += red[w];
     partw[(int64_t)rhs * nchunks + c] = t;
     if (c == T.pchunk0[ch.inst * 2] ) conv[rhs * ninst + ch.inst] = 0;
+    if (c == 0 && rhs == 0) conv[(int64_t)ninst * gridDim.y] = 0;  // the count of flags set
   }
 }
 
@@ -161,7 +162,10 @@ __global__ __launch_bounds__(64) void k_check(DevTables T, const int64_t* __rest
   const bool fin = isfinite(res);
   const bool ok = fin && res <= tol * fmax(1.0, wnorm[ci]);
   const bool last = it >= newton_max;
-  if (ok || !fin || last) conv[ci] = 1;
+  if (ok || !fin || last) {
+    conv[ci] = 1;
+    atomicAdd(&conv[gridDim.x * gridDim.y], 1);  // (grid: one workgroup per problem)
+  }
   if (stats)
     for (int s = 0; s < S; ++s) {
       sgdg_stats& st = stats[ci * 2 + s];
@@ -196,6 +200,7 @@ static void implicit_stage(const sgdg_plan* plan, int nrhs, double c, double* U,
   a.G = w.G;
   a.part = w.part;
   a.conv = w.conv;
+  a.nprob = plan->ninst * nrhs;
   const int64_t nfin = reaction_final_fibres(plan);
   for (int it = 0; it <= newton_max; ++it) {
     reaction_pass(plan, nrhs, RX_RESID, a, s);

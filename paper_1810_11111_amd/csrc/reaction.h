@@ -108,7 +108,9 @@ constexpr int RX_LOCAL_MAX_ITER = 30;
 //   RX_RESID: F = P f(R U), G = U - dt2 F - W, per-final-workgroup |G|^2 into part
 //   RX_CORR : U <- U - P[(I - dt2 J_f(R U))^{-1} R G]
 //   RX_LOCAL: Gout = P u, u solving u - dt2 f(u) = R U at every point (U holds W)
-// Instances with conv[rhs * ninst + inst] != 0 are skipped (conv may be null).
+// Instances with conv[rhs * ninst + inst] != 0 are skipped (conv may be null);
+// conv[nprob] counts the flags set (nprob = ninst * nrhs), and a launch
+// returns at once when all are.
 struct RxArgs {
   double* U;
   const double* G;
@@ -117,6 +119,7 @@ struct RxArgs {
   const double* W;
   double* part;  // [rhs][final workgroup]
   const int32_t* conv;
+  int32_t nprob;
   double dt2;
   double* rws;  // reaction workspace base
 };

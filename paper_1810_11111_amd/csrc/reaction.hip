@@ -385,6 +385,13 @@ int64_t reaction_final_fibres(const sgdg_plan* plan) {
 
 // the instance of work item e from the ascending first items cum[0..ninst)
 // (one round of loads per 64 instances)
+// Every problem of the pass has converged (the count after the flags, kept
+// by the convergence check): a launch of a finished stage iteration returns
+// at once.
+__device__ __forceinline__ bool all_converged(const RxArgs& a) {
+  return a.conv && __builtin_amdgcn_readfirstlane(a.conv[a.nprob]) >= a.nprob;
+}
+
 __device__ __forceinline__ int find_inst(const int64_t* __restrict__ cum, int ninst, int64_t e) {
   if (ninst == 1) return 0;  // no table load for single-instance plans
   const int lane = threadIdx.x & 63;
@@ -628,17 +635,18 @@ __device__ __forceinline__ void stage_block(double* __restrict__ dst, const doub
   }
 }
 
-// expansion stage m: hierarchical along axis m -> point values, grid (tiles, rhs, input).
+// expansion stage m: hierarchical along axis m -> point values, one tile bx
+// (of the stage's tiles over all instances) of right-hand side rhs and input z.
 // XS: the tile holds every fibre of its (species, prefix) and the prefix's
 // hierarchical block is first copied to LDS (xs), so that the walk reads only
 // LDS and issues nothing but stores to global memory.
 template <int K1, int LM, bool LANES, bool XS>
 __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg, int inst, int m, int64_t total,
-                               const RxArgs& a, int64_t rws, int lam, int ll, double* xs) {
+                               const RxArgs& a, int64_t rws, int lam, int ll, double* xs, int64_t bx, int rhs,
+                               int z) {
   const RInst& I = R.inst[inst];
-  const int z = blockIdx.z, rhs = blockIdx.y;
   const int d = I.d, r = d - m, N = I.N, S = I.S, np1 = I.np1;
-  const TileIdx t = tile_index<LANES>(I, m, (int64_t)blockIdx.x - pick(R.cum_x, m)[inst], lam, ll);
+  const TileIdx t = tile_index<LANES>(I, m, bx - pick(R.cum_x, m)[inst], lam, ll);
   const int64_t gd_in = I.gdof[r], gd_out = I.gdof[r - 1];
   double* xr = a.rws + (int64_t)rhs * rws;
   const double* __restrict__ in =
@@ -714,9 +722,11 @@ template <int K1, int LM, bool LANES, bool XS>
 __global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, const double* __restrict__ EHg, int ninst, int m,
                                                           int64_t total, RxArgs a, int64_t rws, int lam, int ll) {
   extern __shared__ double xs_dyn[];
+  if (all_converged(a)) return;
   const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
   if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
-  rx_expand_body<K1, LM, LANES, XS>(R, EHg, inst, m, total, a, rws, lam, ll, xs_dyn);
+  rx_expand_body<K1, LM, LANES, XS>(R, EHg, inst, m, total, a, rws, lam, ll, xs_dyn, blockIdx.x, blockIdx.y,
+                                    blockIdx.z);
 }
 
 // contraction stage m: weighted point values along axis m -> hierarchical
@@ -728,14 +738,14 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, const doubl
 template <int K1, int LM, bool LANES, bool XS>
 __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EHg, const double* __restrict__ w1g,
                                  int inst, int m, int mode, int64_t total, const RxArgs& a, int64_t rws, int lam,
-                                 int ll, int64_t nfin, double* ys) {
+                                 int ll, int64_t nfin, double* ys, int64_t bx, int rhs) {
   // partial sums of the levels whose cells span several chunks: [wave][level <= 2][p][lane]
   __shared__ double red[4][3][K1][64];
   __shared__ double wsum[RX_THREADS / 64];
   const RInst& I = R.inst[inst];
-  const int rhs = blockIdx.y, ln = threadIdx.x & 63;
+  const int ln = threadIdx.x & 63;
   const int d = I.d, r = d - m, N = I.N, np1 = I.np1;
-  const int64_t le = (int64_t)blockIdx.x - pick(R.cum_x, m)[inst];
+  const int64_t le = bx - pick(R.cum_x, m)[inst];
   const TileIdx t = tile_index<LANES>(I, m, le, lam, ll);
   const int lw = LANES ? lam - ll : lam;
   const int w = t.wc * (4 >> lw) + t.fb;
@@ -870,7 +880,7 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
   }
   if (m == 0 && mode == RX_RESID) {
     g2 = block_sum(g2, wsum);
-    if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + blockIdx.x] = g2;
+    if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + bx] = g2;
   }
 }
 
@@ -880,9 +890,11 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, const dou
                                                             int64_t total, RxArgs a, int64_t rws, int lam, int ll,
                                                             int64_t nfin) {
   extern __shared__ double ys_dyn[];
+  if (all_converged(a)) return;
   const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
   if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
-  rx_contract_body<K1, LM, LANES, XS>(R, EHg, w1g, inst, m, mode, total, a, rws, lam, ll, nfin, ys_dyn);
+  rx_contract_body<K1, LM, LANES, XS>(R, EHg, w1g, inst, m, mode, total, a, rws, lam, ll, nfin, ys_dyn, blockIdx.x,
+                                      blockIdx.y);
 }
 
 // Last axis: a tile of nl whole lines (consecutive prefixes).  LDS: the
@@ -1119,7 +1131,7 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, const LineTas
   const int tid = threadIdx.x, nt = blockDim.x;
   const LineTask t = tasks[blockIdx.x];
   const int rhs = blockIdx.y;
-  if (a.conv && a.conv[rhs * ninst + t.inst]) return;
+  if (all_converged(a) || (a.conv && a.conv[rhs * ninst + t.inst])) return;
   const RInst& I = R.inst[t.inst];
   const int d = I.d, N = I.N, S = I.S, np1 = I.np1, n1 = I.n1;
   const int npair = nin * S;
@@ -1277,6 +1289,7 @@ __device__ __forceinline__ void rx_wline_body(const RTables& R, const LineTask* 
   uint64_t mask = 0;
   double mL[K1][K1], mR[K1][K1], cL[K1][K1], cR[K1][K1];  // two-scale matrices
   double ELn[K1][K1], wgq[K1];  // finest-level basis at the K1 points of a cell (the same in every cell), weights
+  if (all_converged(a)) return;
   for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int rhs = (int)(w / ntask);
     const LineTask t = tasks[w - (int64_t)rhs * ntask];
@@ -1629,12 +1642,11 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
   for (int m = 0; m + 1 <= d - 1; ++m)
     each([&](auto k1) {
       if (mark) (*mark)(0);
-      const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin);
       const int xs = rh->xs_lds[m];
       forms(decltype(k1)::value, m, xs > 0, [&](auto lmv, auto lanes, auto stg) {
-        hipLaunchKernelGGL((k_rx_expand<decltype(k1)::value, decltype(lmv)::value, decltype(lanes)::value,
-                                        decltype(stg)::value>), grid,
-                           dim3(RX_THREADS), stg ? xs : 0, s, rh->dev, (const double*)rh->dev.EH, ninst, m,
+        auto k = k_rx_expand<decltype(k1)::value, decltype(lmv)::value, decltype(lanes)::value, decltype(stg)::value>;
+        const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin);
+        hipLaunchKernelGGL(k, grid, dim3(RX_THREADS), stg ? xs : 0, s, rh->dev, (const double*)rh->dev.EH, ninst, m,
                            plan->total, a, rh->rws, rh->lam[m], rh->llane[m]);
       });
     });
@@ -1645,12 +1657,12 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
   for (int m = d - 2; m >= 0; --m)
     each([&](auto k1) {
       if (mark) (*mark)(2);
-      const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs);
       const int xs = m > 0 ? rh->xs_lds[m] : 0;
       forms(decltype(k1)::value, m, xs > 0, [&](auto lmv, auto lanes, auto stg) {
-        hipLaunchKernelGGL((k_rx_contract<decltype(k1)::value, decltype(lmv)::value, decltype(lanes)::value,
-                                          decltype(stg)::value>), grid,
-                           dim3(RX_THREADS), stg ? xs : 0, s, rh->dev, (const double*)rh->dev.EH,
+        auto k =
+            k_rx_contract<decltype(k1)::value, decltype(lmv)::value, decltype(lanes)::value, decltype(stg)::value>;
+        const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs);
+        hipLaunchKernelGGL(k, grid, dim3(RX_THREADS), stg ? xs : 0, s, rh->dev, (const double*)rh->dev.EH,
                            (const double*)rh->dev.w1, ninst, m, (int)mode, plan->total, a, rh->rws, rh->lam[m],
                            rh->llane[m], nfin);
       });
