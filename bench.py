@@ -314,6 +314,18 @@ def counters(name, reps):
         for _ in range(reps):
             plan.apply(x, y)
         what = f"{reps} sweeps of {plan.total} DOF ({16 * plan.total} algorithmic bytes each)"
+    elif name == "krylov_quadratic_d4_rhs16":
+        # Krylov exponentials of the headline plan (M = 40, 16 right-hand
+        # sides): the sweeps, updates and the matrix-core exponential
+        wl = I.quadratic_d4(nrhs=NRHS)
+        plan = sg.Plan(wl.instances[:1], "fp64")
+        v = torch.from_numpy(build_ic(plan, wl, inst_of=lambda r, i: r, nrhs=NRHS)).cuda()
+        w = torch.empty_like(v)
+        _, ib = plan.workspace_size(wl.M, NRHS)
+        ws = torch.empty(ib, dtype=torch.uint8, device="cuda")
+        for _ in range(reps):
+            plan.krylov_expv(wl.dt, wl.M, v, w, ws, nrhs=NRHS)
+        what = f"{reps} Krylov exponentials, M={wl.M}, nrhs={NRHS}"
     elif name in ("reaction_quadratic_d4", "reaction_quadratic_d4_rhs16"):
         wl = I.quadratic_d4(nrhs=NRHS if name.endswith("rhs16") else 1)
         nrhs = NRHS if name.endswith("rhs16") else 1
