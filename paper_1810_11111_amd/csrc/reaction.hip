@@ -337,6 +337,7 @@ sgdg_status reaction_build(sgdg_plan* plan) {
   // holds every instance of that degree
   for (const RInst& r : ri) rh->lm[r.K1] = std::max(rh->lm[r.K1], r.N + 1);
   for (int& v : rh->lm) v = v <= 5 ? 5 : v <= 7 ? 7 : v <= 9 ? 9 : RX_LMAX;
+  EH.resize(EH.size() + RX_LMAX * 4, 0.0);  // (whole-row reads of the last point of the last instance)
   rh->rws = ws;
   sgdg_status st;
   if ((st = up(plan, ri, &rh->dev.inst)) != SGDG_OK || (st = up(plan, rblk, &rh->dev.rblk)) != SGDG_OK ||
@@ -638,12 +639,13 @@ __device__ __forceinline__ void stage_block(double* __restrict__ dst, const doub
 // expansion stage m: hierarchical along axis m -> point values, one tile bx
 // (of the stage's tiles over all instances) of right-hand side rhs and input z.
 // XS: the tile holds every fibre of its (species, prefix) and the prefix's
-// hierarchical block is first copied to LDS (xs), so that the walk reads only
-// LDS and issues nothing but stores to global memory.
+// hierarchical block is first copied to LDS (xs; the call with stage = true
+// does only that, the caller synchronises), so that the walk reads only LDS
+// and issues nothing but stores to global memory.
 template <int K1, int LM, bool LANES, bool XS>
 __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg, int inst, int m, int64_t total,
                                const RxArgs& a, int64_t rws, int lam, int ll, double* xs, int64_t bx, int rhs,
-                               int z) {
+                               int z, bool stage) {
   const RInst& I = R.inst[inst];
   const int d = I.d, r = d - m, N = I.N, S = I.S, np1 = I.np1;
   const TileIdx t = tile_index<LANES>(I, m, bx - pick(R.cum_x, m)[inst], lam, ll);
@@ -652,12 +654,14 @@ __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg,
   const double* __restrict__ in =
       m == 0 ? plan_in(a, z, (int64_t)rhs * total) + I.seg + (int64_t)t.s * I.ndof
              : xr + I.X_off[m] + (((int64_t)z * S + t.s) * I.npre[m] + t.pre) * gd_in;
+  if constexpr (XS) {
+    if (stage) {
+      stage_block(xs, in, (int)gd_in);
+      return;
+    }
+  }
   const bool valid = t.eo < gd_out;
   const Fibre<LM> F = fibre_geometry<LM>(R, I, r, valid ? t.eo : 0);
-  if constexpr (XS) {
-    stage_block(xs, in, (int)gd_in);
-    __syncthreads();
-  }
   if (!valid) return;
   const int Lw = wave_max_level(F.L);
   auto ld = [&](int64_t i) -> double {
@@ -718,23 +722,59 @@ __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg,
 // K1 and LM); workgroups of instances of another degree return at once
 // (the basis table is its own argument: its loads are wave-uniform and go
 // through the scalar cache)
+// The tiles of a staged (XS) launch go two to a workgroup, both blocks
+// staged before either walk: half the workgroups to dispatch (a converged
+// pass returns from every one of them), and no load after a store inside a
+// workgroup.  xsd: LDS doubles per tile.
+constexpr int RX_XS_TILES = 2;
+
+// tile bx of stage m runs for right-hand side rhs: in range, of degree K1,
+// problem not converged (inst: its instance)
+template <int K1>
+__device__ __forceinline__ bool tile_live(const RTables& R, const RxArgs& a, int ninst, int m, int64_t bx, int rhs,
+                                          int& inst) {
+  if (bx >= pick(R.cum_x, m)[ninst]) return false;
+  inst = find_inst(pick(R.cum_x, m), ninst, bx);
+  return R.inst[inst].K1 == K1 && !(a.conv && a.conv[rhs * ninst + inst]);
+}
+
 template <int K1, int LM, bool LANES, bool XS>
 __global__ __launch_bounds__(RX_THREADS) void k_rx_expand(RTables R, const double* __restrict__ EHg, int ninst, int m,
-                                                          int64_t total, RxArgs a, int64_t rws, int lam, int ll) {
+                                                          int64_t total, RxArgs a, int64_t rws, int lam, int ll,
+                                                          int xsd) {
   extern __shared__ double xs_dyn[];
   if (all_converged(a)) return;
-  const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
-  if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
-  rx_expand_body<K1, LM, LANES, XS>(R, EHg, inst, m, total, a, rws, lam, ll, xs_dyn, blockIdx.x, blockIdx.y,
-                                    blockIdx.z);
+  const int rhs = blockIdx.y, z = blockIdx.z;
+  if constexpr (XS) {
+    int inst[RX_XS_TILES];
+    bool live[RX_XS_TILES];
+#pragma unroll
+    for (int j = 0; j < RX_XS_TILES; ++j) {
+      const int64_t bx = (int64_t)blockIdx.x * RX_XS_TILES + j;
+      live[j] = tile_live<K1>(R, a, ninst, m, bx, rhs, inst[j]);
+      if (live[j])
+        rx_expand_body<K1, LM, LANES, XS>(R, EHg, inst[j], m, total, a, rws, lam, ll, xs_dyn + j * xsd, bx, rhs, z,
+                                          true);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RX_XS_TILES; ++j)
+      if (live[j])
+        rx_expand_body<K1, LM, LANES, XS>(R, EHg, inst[j], m, total, a, rws, lam, ll, xs_dyn + j * xsd,
+                                          (int64_t)blockIdx.x * RX_XS_TILES + j, rhs, z, false);
+  } else {
+    int inst = 0;
+    if (!tile_live<K1>(R, a, ninst, m, blockIdx.x, rhs, inst)) return;
+    rx_expand_body<K1, LM, LANES, XS>(R, EHg, inst, m, total, a, rws, lam, ll, xs_dyn, blockIdx.x, rhs, z, false);
+  }
 }
 
 // contraction stage m: weighted point values along axis m -> hierarchical
 // (m >= 1 writes Y_m; m == 0 finishes plan vectors), grid (tiles, rhs).
 // XS (m >= 1): the tile holds every fibre of its (species, prefix); the
 // outputs are collected in an LDS image of the prefix's hierarchical block
-// (ys) and written out together at the end, so that the walk issues only
-// loads to global memory.
+// (ys) that the caller writes out after the workgroup's last walk, so that
+// the walks issue only loads to global memory.
 template <int K1, int LM, bool LANES, bool XS>
 __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EHg, const double* __restrict__ w1g,
                                  int inst, int m, int mode, int64_t total, const RxArgs& a, int64_t rws, int lam,
@@ -742,6 +782,7 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
   // partial sums of the levels whose cells span several chunks: [wave][level <= 2][p][lane]
   __shared__ double red[4][3][K1][64];
   __shared__ double wsum[RX_THREADS / 64];
+  if constexpr (XS) __syncthreads();  // (the workgroup's previous tile has finished with red)
   const RInst& I = R.inst[inst];
   const int ln = threadIdx.x & 63;
   const int d = I.d, r = d - m, N = I.N, np1 = I.np1;
@@ -808,11 +849,26 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
         const int q = c * K1 + gq;
         const double* __restrict__ eh = EH + (int64_t)q * NL1 * K1;
         const double g = w1[q] * gv[b][gq];
+        if constexpr (XS) {
+          // the whole row at once (one round of scalar loads; rows past the
+          // instance's levels read the next row or the table's zero padding)
+          double e[LM][K1];
 #pragma unroll
-        for (int l = 0; l < LM; ++l)
-          if (l <= Lw)
+          for (int l = 0; l < LM; ++l)
 #pragma unroll
-            for (int p = 0; p < K1; ++p) acc[l][p] += eh[l * K1 + p] * g;  // (unused past the fibre's budget)
+            for (int p = 0; p < K1; ++p) e[l][p] = eh[l * K1 + p];
+#pragma unroll
+          for (int l = 0; l < LM; ++l)
+            if (l <= Lw)
+#pragma unroll
+              for (int p = 0; p < K1; ++p) acc[l][p] += e[l][p] * g;
+        } else {
+#pragma unroll
+          for (int l = 0; l < LM; ++l)
+            if (l <= Lw)
+#pragma unroll
+              for (int p = 0; p < K1; ++p) acc[l][p] += eh[l * K1 + p] * g;  // (unused past the fibre's budget)
+        }
       }
       // levels whose cells lie inside one chunk: a cell is complete when the walk leaves it
 #pragma unroll
@@ -874,10 +930,6 @@ __device__ void rx_contract_body(const RTables& R, const double* __restrict__ EH
         }
       }
     }
-  if constexpr (XS) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < gd_out; i += RX_THREADS) outm[i] = ys[i];
-  }
   if (m == 0 && mode == RX_RESID) {
     g2 = block_sum(g2, wsum);
     if (threadIdx.x == 0) a.part[(int64_t)rhs * nfin + bx] = g2;
@@ -888,13 +940,42 @@ template <int K1, int LM, bool LANES, bool XS>
 __global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, const double* __restrict__ EHg,
                                                             const double* __restrict__ w1g, int ninst, int m, int mode,
                                                             int64_t total, RxArgs a, int64_t rws, int lam, int ll,
-                                                            int64_t nfin) {
+                                                            int64_t nfin, int xsd) {
   extern __shared__ double ys_dyn[];
   if (all_converged(a)) return;
-  const int inst = find_inst(pick(R.cum_x, m), ninst, blockIdx.x);
-  if (R.inst[inst].K1 != K1 || (a.conv && a.conv[blockIdx.y * ninst + inst])) return;
-  rx_contract_body<K1, LM, LANES, XS>(R, EHg, w1g, inst, m, mode, total, a, rws, lam, ll, nfin, ys_dyn, blockIdx.x,
-                                      blockIdx.y);
+  const int rhs = blockIdx.y;
+  if constexpr (XS) {
+    int inst[RX_XS_TILES];
+    bool live[RX_XS_TILES];
+#pragma unroll
+    for (int j = 0; j < RX_XS_TILES; ++j) {
+      const int64_t bx = (int64_t)blockIdx.x * RX_XS_TILES + j;
+      live[j] = tile_live<K1>(R, a, ninst, m, bx, rhs, inst[j]);
+      if (live[j])
+        rx_contract_body<K1, LM, LANES, XS>(R, EHg, w1g, inst[j], m, mode, total, a, rws, lam, ll, nfin,
+                                            ys_dyn + j * xsd, bx, rhs);
+    }
+    __syncthreads();
+    // every tile's hierarchical block to Y_m
+#pragma unroll
+    for (int j = 0; j < RX_XS_TILES; ++j)
+      if (live[j]) {
+        const RInst& I = R.inst[inst[j]];
+        const int64_t le = (int64_t)blockIdx.x * RX_XS_TILES + j - pick(R.cum_x, m)[inst[j]];
+        const int64_t per_s = I.npre[m] * I.ntile[m];  // (one tile per prefix)
+        const int s = (int)(le / per_s);
+        const int64_t pre = (le - (int64_t)s * per_s) / I.ntile[m];
+        const int64_t gd_out = I.gdof[I.d - m];
+        double* outm = a.rws + (int64_t)rhs * rws + I.Y_off[m] + ((int64_t)s * I.npre[m] + pre) * gd_out;
+        const double* y = ys_dyn + j * xsd;
+        for (int i = threadIdx.x; i < gd_out; i += RX_THREADS) outm[i] = y[i];
+      }
+  } else {
+    int inst = 0;
+    if (!tile_live<K1>(R, a, ninst, m, blockIdx.x, rhs, inst)) return;
+    rx_contract_body<K1, LM, LANES, XS>(R, EHg, w1g, inst, m, mode, total, a, rws, lam, ll, nfin, ys_dyn, blockIdx.x,
+                                        rhs);
+  }
 }
 
 // Last axis: a tile of nl whole lines (consecutive prefixes).  LDS: the
@@ -1645,9 +1726,11 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
       const int xs = rh->xs_lds[m];
       forms(decltype(k1)::value, m, xs > 0, [&](auto lmv, auto lanes, auto stg) {
         auto k = k_rx_expand<decltype(k1)::value, decltype(lmv)::value, decltype(lanes)::value, decltype(stg)::value>;
-        const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs, (unsigned)nin);
-        hipLaunchKernelGGL(k, grid, dim3(RX_THREADS), stg ? xs : 0, s, rh->dev, (const double*)rh->dev.EH, ninst, m,
-                           plan->total, a, rh->rws, rh->lam[m], rh->llane[m]);
+        const int64_t nt = rh->cum_x[m].back();
+        const dim3 grid((unsigned)(stg ? (nt + RX_XS_TILES - 1) / RX_XS_TILES : nt), (unsigned)nrhs, (unsigned)nin);
+        hipLaunchKernelGGL(k, grid, dim3(RX_THREADS), stg ? RX_XS_TILES * xs : 0, s, rh->dev,
+                           (const double*)rh->dev.EH, ninst, m, plan->total, a, rh->rws, rh->lam[m], rh->llane[m],
+                           xs / (int)sizeof(double));
       });
     });
   for (const LineClass& lc : rh->lclass) {
@@ -1661,10 +1744,11 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
       forms(decltype(k1)::value, m, xs > 0, [&](auto lmv, auto lanes, auto stg) {
         auto k =
             k_rx_contract<decltype(k1)::value, decltype(lmv)::value, decltype(lanes)::value, decltype(stg)::value>;
-        const dim3 grid((unsigned)rh->cum_x[m].back(), (unsigned)nrhs);
-        hipLaunchKernelGGL(k, grid, dim3(RX_THREADS), stg ? xs : 0, s, rh->dev, (const double*)rh->dev.EH,
-                           (const double*)rh->dev.w1, ninst, m, (int)mode, plan->total, a, rh->rws, rh->lam[m],
-                           rh->llane[m], nfin);
+        const int64_t nt = rh->cum_x[m].back();
+        const dim3 grid((unsigned)(stg ? (nt + RX_XS_TILES - 1) / RX_XS_TILES : nt), (unsigned)nrhs);
+        hipLaunchKernelGGL(k, grid, dim3(RX_THREADS), stg ? RX_XS_TILES * xs : 0, s, rh->dev,
+                           (const double*)rh->dev.EH, (const double*)rh->dev.w1, ninst, m, (int)mode, plan->total, a,
+                           rh->rws, rh->lam[m], rh->llane[m], nfin, xs / (int)sizeof(double));
       });
     });
   if (mark) (*mark)(-1);
