@@ -86,7 +86,7 @@ struct RHost {
   int lam[SGDG_MAX_D] = {};    // stage m splits each fibre's points into 2^lam chunks (lam <= 8)
   int llane[SGDG_MAX_D] = {};  // of which the low llane chunk bits are lane bits (lam - llane <= 2)
   int xs_lds[SGDG_MAX_D] = {};  // stage m stages each tile's hierarchical block in LDS (bytes; 0: it does not)
-  int lm[5] = {};               // [K1]: levels held per fibre by the expansion / contraction kernels (5, 7, 9, 11)
+  int lm[5] = {};               // [K1]: levels held per fibre by the expansion / contraction kernels (7, 9, 11)
   int64_t rws = 0;           // doubles of reaction workspace per right-hand side
   int max_n1 = 0, max_np1 = 0;
   int k1mask = 0;  // bit K1 set when an instance has degree K1 - 1

@@ -333,10 +333,10 @@ sgdg_status reaction_build(sgdg_plan* plan) {
     rh->xs_lds[m] =
         whole && rh->llane[m] == 0 && mx * (int64_t)sizeof(double) <= RX_XS_LDS ? (int)(mx * sizeof(double)) : 0;
   }
-  // level bucket per degree: the smallest of 5, 7, 9, RX_LMAX levels that
+  // level bucket per degree: the smallest of 7, 9, RX_LMAX levels that
   // holds every instance of that degree
   for (const RInst& r : ri) rh->lm[r.K1] = std::max(rh->lm[r.K1], r.N + 1);
-  for (int& v : rh->lm) v = v <= 5 ? 5 : v <= 7 ? 7 : v <= 9 ? 9 : RX_LMAX;
+  for (int& v : rh->lm) v = v <= 7 ? 7 : v <= 9 ? 9 : RX_LMAX;
   EH.resize(EH.size() + RX_LMAX * 4, 0.0);  // (whole-row reads of the last point of the last instance)
   rh->rws = ws;
   sgdg_status st;
@@ -726,7 +726,8 @@ __device__ void rx_expand_body(const RTables& R, const double* __restrict__ EHg,
 // staged before either walk: half the workgroups to dispatch (a converged
 // pass returns from every one of them), and no load after a store inside a
 // workgroup.  xsd: LDS doubles per tile.
-constexpr int RX_XS_TILES = 2;
+constexpr int RX_XS_TILES = 2;      // expansion
+constexpr int RX_XS_TILES_CON = 2;  // contraction
 
 // tile bx of stage m runs for right-hand side rhs: in range, of degree K1,
 // problem not converged (inst: its instance)
@@ -945,11 +946,11 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, const dou
   if (all_converged(a)) return;
   const int rhs = blockIdx.y;
   if constexpr (XS) {
-    int inst[RX_XS_TILES];
-    bool live[RX_XS_TILES];
+    int inst[RX_XS_TILES_CON];
+    bool live[RX_XS_TILES_CON];
 #pragma unroll
-    for (int j = 0; j < RX_XS_TILES; ++j) {
-      const int64_t bx = (int64_t)blockIdx.x * RX_XS_TILES + j;
+    for (int j = 0; j < RX_XS_TILES_CON; ++j) {
+      const int64_t bx = (int64_t)blockIdx.x * RX_XS_TILES_CON + j;
       live[j] = tile_live<K1>(R, a, ninst, m, bx, rhs, inst[j]);
       if (live[j])
         rx_contract_body<K1, LM, LANES, XS>(R, EHg, w1g, inst[j], m, mode, total, a, rws, lam, ll, nfin,
@@ -958,10 +959,10 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_contract(RTables R, const dou
     __syncthreads();
     // every tile's hierarchical block to Y_m
 #pragma unroll
-    for (int j = 0; j < RX_XS_TILES; ++j)
+    for (int j = 0; j < RX_XS_TILES_CON; ++j)
       if (live[j]) {
         const RInst& I = R.inst[inst[j]];
-        const int64_t le = (int64_t)blockIdx.x * RX_XS_TILES + j - pick(R.cum_x, m)[inst[j]];
+        const int64_t le = (int64_t)blockIdx.x * RX_XS_TILES_CON + j - pick(R.cum_x, m)[inst[j]];
         const int64_t per_s = I.npre[m] * I.ntile[m];  // (one tile per prefix)
         const int s = (int)(le / per_s);
         const int64_t pre = (le - (int64_t)s * per_s) / I.ntile[m];
@@ -1710,7 +1711,6 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
   auto forms = [&](int K1, int m, bool xs, auto go) {
     auto lm = [&](auto lanes, auto stg) {
       switch (rh->lm[K1]) {
-        case 5: go(integral_constant<int, 5>(), lanes, stg); break;
         case 7: go(integral_constant<int, 7>(), lanes, stg); break;
         case 9: go(integral_constant<int, 9>(), lanes, stg); break;
         default: go(integral_constant<int, RX_LMAX>(), lanes, stg); break;
@@ -1745,8 +1745,8 @@ void reaction_pass(const sgdg_plan* plan, int nrhs, RxMode mode, const RxArgs& a
         auto k =
             k_rx_contract<decltype(k1)::value, decltype(lmv)::value, decltype(lanes)::value, decltype(stg)::value>;
         const int64_t nt = rh->cum_x[m].back();
-        const dim3 grid((unsigned)(stg ? (nt + RX_XS_TILES - 1) / RX_XS_TILES : nt), (unsigned)nrhs);
-        hipLaunchKernelGGL(k, grid, dim3(RX_THREADS), stg ? RX_XS_TILES * xs : 0, s, rh->dev,
+        const dim3 grid((unsigned)(stg ? (nt + RX_XS_TILES_CON - 1) / RX_XS_TILES_CON : nt), (unsigned)nrhs);
+        hipLaunchKernelGGL(k, grid, dim3(RX_THREADS), stg ? RX_XS_TILES_CON * xs : 0, s, rh->dev,
                            (const double*)rh->dev.EH, (const double*)rh->dev.w1, ninst, m, (int)mode, plan->total, a,
                            rh->rws, rh->lam[m], rh->llane[m], nfin, xs / (int)sizeof(double));
       });
