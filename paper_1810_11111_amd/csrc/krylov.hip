@@ -218,14 +218,20 @@ __global__ __launch_bounds__(CHUNK) void k_upd(DevTables T, int nchunks, int nin
   __builtin_amdgcn_sched_barrier(0);  // keep the sums below every load
   if (dn && j >= dn - 1) return;  // (the loads above are in range either way)
   {
-    // the same summation order on both paths (the padded terms are zeros)
+    // terms q = ps, ps + S, ... in order (the padded terms are zeros): the
+    // first QMAX from the loads above, then batches of QMAX whose loads are
+    // all issued before the first is added
     double acc = 0.0;
-    if (few) {
 #pragma unroll
-      for (int q = 0; q < QMAX; ++q) acc += ps + q * S < nc ? pq[q] : 0.0;
-    } else if (pact) {
-      for (int q = ps; q < nc; q += S) acc += psrc[(row0 + q) * (M + 2)];
-    }
+    for (int q = 0; q < QMAX; ++q) acc += ps + q * S < nc ? pq[q] : 0.0;
+    if (!few && pact)
+      for (int q0 = ps + QMAX * S; q0 < nc; q0 += QMAX * S) {
+        double t[QMAX];
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) t[q] = psrc[(row0 + min(q0 + q * S, nc - 1)) * (M + 2)];
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) acc += q0 + q * S < nc ? t[q] : 0.0;
+      }
     if (pact) red[tid] = acc;
   }
   __syncthreads();
