@@ -158,6 +158,51 @@ def test_reaction_F_cubic_degree_and_high_dimension(d, N, k, rx):
     assert err <= 1e-12 * max(1.0, np.abs(Fref).max()), err
 
 
+@pytest.mark.parametrize("case", ["lane_chunks", "staged_blocks"])
+def test_reaction_F_mixed_d3_plan_two_rhs(case):
+    """d=3 plans of instances of different degree, level and species count,
+    two right-hand sides; every degree runs its own register bucket.
+    lane_chunks: small instances, so the axis-1 stages split each fibre's
+    points over lanes.  staged_blocks: 65,536 fibres of at most 128 DOF
+    (N=6 k=1, N=5 k=3), so the axis-1 stages take whole prefixes and stage
+    their hierarchical blocks in LDS, two tiles per workgroup, on instances
+    of degree 1 and 3.  F (Sec. 5) of every instance and right-hand side
+    against the oracle."""
+    sg = lib()
+    import torch
+
+    insts = {
+        "lane_chunks": [
+            I.Instance(3, 4, 1, [1.0], I.rx_quadratic(-1.0)),
+            I.Instance(3, 3, 2, [1.0, 0.5], I.rx_gray_scott(0.04, 0.06)),
+            I.Instance(3, 2, 3, [1.0], I.rx_quadratic(-1.0)),
+            I.Instance(3, 5, 1, [1.0, 0.5], I.rx_schnakenberg(0.1, 0.9)),
+            I.Instance(3, 3, 1, [1.0], I.rx_allen_cahn()),
+        ],
+        "staged_blocks": [
+            I.Instance(3, 6, 1, [1.0, 0.5], I.rx_gray_scott(0.04, 0.06)),
+            I.Instance(3, 5, 3, [1.0], I.rx_quadratic(-1.0)),
+            I.Instance(3, 6, 1, [1.0], I.rx_allen_cahn()),
+        ],
+    }[case]
+    nrhs = 2
+    say("reaction F mixed d=3 plan, 2 rhs", case)
+    plan = sg.Plan(insts, "fp64")
+    U0 = 0.5 + 0.2 * I.smooth_random(plan.total * nrhs, 29, 1)[0].reshape(nrhs, plan.total)
+    Fd = torch.zeros(nrhs, plan.total, dtype=torch.float64, device="cuda")
+    plan.reaction(to_dev(U0), Fd, _ws(plan, 1, nrhs), nrhs=nrhs)
+    torch.cuda.synchronize()
+    F = Fd.cpu().numpy()
+    for r in range(nrhs):
+        for i, inst in enumerate(insts):
+            nd, off, _ = plan.info(i)
+            S = inst.species
+            Fref = reaction.F(reaction.Quadrature(3, inst.N, inst.k), inst.rx,
+                              U0[r, off : off + S * nd].reshape(S, nd)).ravel()
+            err = np.abs(F[r, off : off + S * nd] - Fref).max()
+            assert err <= 1e-12 * max(1.0, np.abs(Fref).max()), (r, i, err)
+
+
 # ----------------------------------------------------------------------------- projection
 
 def test_projection_matches_oracle():
