@@ -272,9 +272,9 @@ sgdg_status rk_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t orde
 
 /* ---- Launch-shape autotuning ------------------------------------------------
  * The last axis of the reaction transforms (Sec. 5: F(U) = P f(R U), applied
- * axis by axis) runs, for every class of instances with the same degree,
- * level and species count and N <= 8 (d >= 2), as tiles of whole lines walked
- * by a grid-stride launch.  Its shape -- lines per tile (in rounds: one round
+ * axis by axis) runs, for every class of instances with the same degree and
+ * species count and N <= 8 (d >= 2), as tiles of whole lines walked by one
+ * grid-stride launch.  Its shape -- lines per tile (in rounds: one round
  * gives every wave of a workgroup its lines once) and workgroups per compute
  * unit -- changes only which workgroup computes which line: every value is
  * computed the same way, so results are bit for bit the same for every
@@ -285,7 +285,7 @@ sgdg_status rk_step(const sgdg_plan* plan, int32_t nrhs, double dt, int32_t orde
 #define SGDG_TUNE_MAXCLASS 16
 typedef struct {
   int32_t nclass;                                  /* classes reported (wave-form last axis only)      */
-  int32_t k[SGDG_TUNE_MAXCLASS], n[SGDG_TUNE_MAXCLASS], nspecies[SGDG_TUNE_MAXCLASS];
+  int32_t k[SGDG_TUNE_MAXCLASS], n[SGDG_TUNE_MAXCLASS], nspecies[SGDG_TUNE_MAXCLASS];  /* n: largest level */
   int32_t cls[SGDG_TUNE_MAXCLASS];                 /* class index for sg_dg_line_shape                  */
   int32_t rounds[SGDG_TUNE_MAXCLASS][2];           /* chosen rounds per tile, one and two inputs/point */
   int32_t wgcu[SGDG_TUNE_MAXCLASS][2];             /* chosen workgroups per compute unit               */

@@ -606,9 +606,9 @@ extern "C" sgdg_status sg_dg_tune(sgdg_plan* plan, int32_t nrhs, void* workspace
     rep.nspecies[slot] = lc.S;
     rep.cls[slot] = c;
     int64_t lines = 0, most = 0;
-    for (const auto& il : lc.lines) {
-      lines += il.second;
-      most = std::max(most, il.second);
+    for (const WaveLines& il : lc.lines) {
+      lines += il.lines;
+      most = std::max(most, il.lines);
     }
     for (int nin = 1; nin <= 2 && st == SGDG_OK; ++nin) {
       const RxMode mode = nin == 1 ? RX_F : RX_CORR;

@@ -56,16 +56,25 @@ struct LineTask {
   int64_t pre0;
 };
 
-// Instances of the same degree, level and species count share one LDS layout
-// of the last-axis kernel and one launch (by number of inputs 1, 2).
+// Lines of one instance in a wave-form class: lpr lines per round (one
+// round: every wave of a workgroup takes its lines once).
+struct WaveLines {
+  int inst, lpr;
+  int64_t lines;
+};
+
+// One launch of the last-axis kernel per class and number of inputs (1, 2):
+// wave form, instances of the same degree and species count (N: the largest
+// level); LDS-tile form, instances of the same degree, level and species
+// count (one LDS layout).
 struct LineClass {
   int K1 = 0, N = 0, S = 0;
   std::vector<LineTask> tasks[3];
   LineTask* dev[3] = {};
   size_t lds[3] = {};  // dynamic LDS bytes
   int threads[3] = {}; // workgroup size
-  // wave form (d >= 2, N <= RX_WLINE_MAXN): a tile is `rounds` rounds of
-  // `lpr` lines (one round: every wave of the workgroup takes its lines once);
+  // wave form (d >= 2, N <= RX_WLINE_MAXN): a tile is `rounds` rounds of an
+  // instance's lines (lpr: lines per round of the class's largest instance);
   // its grid-stride launch has wgcu workgroups per compute unit and one of
   // two register budgets.  Launch shapes only: every line is computed the
   // same way whatever the shape.
@@ -75,7 +84,7 @@ struct LineClass {
   int wgcu[3] = {};
   int waves[3] = {};  // 0: the compiler's register allocation; 3: at most 168 VGPRs (three waves per SIMD)
   size_t cap_tasks[3] = {};                     // room in dev[nin] (tiles of one round)
-  std::vector<std::pair<int, int64_t>> lines;   // (instance, lines of its last axis)
+  std::vector<WaveLines> lines;                 // every instance's lines of its last axis
 };
 
 struct RHost {

@@ -103,14 +103,15 @@ static size_t line_tile_doubles(int npair, int nl, int n1, int K1) {
 }
 static sgdg_status set_line_lds(const RHost* rh);
 
-// Tiles of the wave-form last-axis kernel: `rounds` rounds of lc.lpr lines,
-// instance by instance.
+// Tiles of the wave-form last-axis kernel: `rounds` rounds of each
+// instance's lines per round, instance by instance.
 static std::vector<LineTask> wave_tiles(const LineClass& lc, int rounds) {
   std::vector<LineTask> t;
-  const int64_t nl = (int64_t)lc.lpr * rounds;
-  for (const auto& il : lc.lines)
-    for (int64_t p0 = 0; p0 < il.second; p0 += nl)
-      t.push_back(LineTask{il.first, (int32_t)std::min<int64_t>(nl, il.second - p0), p0});
+  for (const WaveLines& il : lc.lines) {
+    const int64_t nl = (int64_t)il.lpr * rounds;
+    for (int64_t p0 = 0; p0 < il.lines; p0 += nl)
+      t.push_back(LineTask{il.inst, (int32_t)std::min<int64_t>(nl, il.lines - p0), p0});
+  }
   return t;
 }
 
@@ -274,31 +275,40 @@ sgdg_status reaction_build(sgdg_plan* plan) {
       r.ntile[m] = (int32_t)((r.gdof[d - m - 1] + tw - 1) / tw);
       rh->cum_x[m].push_back(rh->cum_x[m].back() + (int64_t)S * r.npre[m] * r.ntile[m]);
     }
-    // line tiles: instances of the same (degree, level, species) form one
-    // class, one LDS layout and one launch
+    // line tiles: instances of the same degree and species count whose
+    // lines run in the wave form form one class and one launch (a wave loads
+    // a tile's instance state when the instance changes); the LDS-tile form
+    // groups by (degree, level, species), one LDS layout each
     {
+      const bool wave = d >= 2 && N <= RX_WLINE_MAXN;
       LineClass* lc = nullptr;
       for (LineClass& c : rh->lclass)
-        if (c.K1 == K1 && c.N == N && c.S == S) lc = &c;
+        if (c.wave == wave && c.K1 == K1 && c.S == S && (wave || c.N == N)) lc = &c;
+      const bool first = !lc;
       if (!lc) {
         rh->lclass.emplace_back();
         lc = &rh->lclass.back();
         lc->K1 = K1;
         lc->N = N;
         lc->S = S;
+        lc->wave = wave;
       }
-      if (d >= 2 && N <= RX_WLINE_MAXN) {
-        // wave form: tiles of whole rounds (4 waves, LPW lines each); the
-        // default shape takes about 2048 tiles per instance, up to 16 rounds
-        // (small problems keep many workgroups), and 16 workgroups per CU
+      if (wave) {
+        // tiles of whole rounds (4 waves, LPW lines each); the default shape
+        // takes about 2048 tiles per instance, up to 16 rounds (the class's
+        // smallest instance decides: small problems keep many workgroups),
+        // and 16 workgroups per CU
         const int cplh = std::min(K1 == 2 ? 8 : 4, 1 << N);  // finest cells per lane (wl_cpl)
         const int hh = N - (cplh == 8 ? 3 : cplh == 4 ? 2 : cplh == 2 ? 1 : 0);
-        lc->wave = true;
-        lc->lpr = (RX_THREADS / 64) * (64 >> std::min(hh, 6));
-        lc->lines.push_back({i, r.npre[d - 1]});
-        const int64_t want = std::max<int64_t>(1, r.npre[d - 1] / 2048 / lc->lpr);
+        const int lpr = (RX_THREADS / 64) * (64 >> std::min(hh, 6));
+        int64_t most = 0;
+        for (const WaveLines& wl : lc->lines) most = std::max(most, wl.lines);
+        if (r.npre[d - 1] > most) lc->lpr = lpr;  // (the lines per round of the class's largest instance)
+        lc->N = std::max(lc->N, N);
+        lc->lines.push_back({i, lpr, r.npre[d - 1]});
+        const int want = (int)std::min<int64_t>(std::max<int64_t>(1, r.npre[d - 1] / 2048 / lpr), RX_WLINE_ROUNDS);
         for (int nin = 1; nin <= 2; ++nin) {
-          lc->rounds[nin] = (int)std::min<int64_t>(want, RX_WLINE_ROUNDS);
+          lc->rounds[nin] = first ? want : std::min(lc->rounds[nin], want);
           lc->wgcu[nin] = 16;
         }
       } else {
