@@ -32,17 +32,34 @@ namespace sgdg {
 
 // Chunk-level inner products of the Arnoldi form (DotArgs): wl holds the
 // chunk's sweep output (zero past its end); wave w takes basis vectors
-// i = w, w + nwaves, ...; the order of every sum is fixed.
+// i = w, w + nwaves, ..., DB of them at a time with all their loads in
+// flight together; the order of every sum is fixed.
 template <class TV>
 __device__ __forceinline__ void chunk_dots_out(const DotArgs& da, int c, int rhs, const Chunk& ch, const double* wl) {
+  constexpr int DB = 4, QN = CHUNK / 64;
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
-  for (int i = wv; i <= da.j; i += nw) {
-    const TV* v = (const TV*)da.V + ((int64_t)i * da.nrhs + rhs) * da.total + ch.start;
-    double s = 0.0;
-    for (int q = ln; q < ch.count; q += 64) s += (double)v[q] * wl[q];
+  double w[QN];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (ln == 0) da.part[((int64_t)rhs * da.nchunks + c) * da.ld + i] = s;
+  for (int u = 0; u < QN; ++u) w[u] = wl[ln + 64 * u];
+  for (int i0 = wv; i0 <= da.j; i0 += DB * nw) {
+    double x[DB][QN];
+#pragma unroll
+    for (int b = 0; b < DB; ++b) {
+      const int i = min(i0 + b * nw, da.j);
+      const TV* v = (const TV*)da.V + ((int64_t)i * da.nrhs + rhs) * da.total + ch.start;
+#pragma unroll
+      for (int u = 0; u < QN; ++u) x[b][u] = (double)v[min(ln + 64 * u, ch.count - 1)];
+    }
+#pragma unroll
+    for (int b = 0; b < DB; ++b) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < QN; ++u)
+        if (ln + 64 * u < ch.count) s += x[b][u] * w[u];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (ln == 0 && i0 + b * nw <= da.j) da.part[((int64_t)rhs * da.nchunks + c) * da.ld + i0 + b * nw] = s;
+    }
   }
 }
 
