@@ -1267,8 +1267,9 @@ __global__ __launch_bounds__(RX_THREADS) void k_rx_line(RTables R, const LineTas
 // wave's buffer (every input is read before the first output is written) and
 // go back to HBM as one run.  No barriers; tiles are walked in a grid-stride
 // loop (a pass whose problems have converged costs one flag test per tile).
-// The arithmetic of every value is the line kernel's (the same two-scale,
-// point and projection sums in the same order).
+// The formulas are the line kernel's (the same two-scale, point and
+// projection sums); some sums are taken in another order, so the two forms
+// agree to rounding, not bit for bit.
 typedef __attribute__((address_space(3))) void* lds_ptr;
 
 template <int K1>
