@@ -173,6 +173,32 @@ sgdg_status sg_dg_norm_inf(const sgdg_plan* plan, int32_t inst, int32_t species,
  * bfloat16 (uint16 bits)/float.  Errors: SGDG_ERR_ARG, SGDG_ERR_HIP.        */
 sgdg_status sg_dg_apply(const sgdg_plan* plan, int32_t nrhs, const void* x, void* y, void* stream);
 
+/* How sg_dg_apply (and rk_step's operator products) evaluate y = A x; the
+ * Krylov products keep the chunked form (they fuse the Arnoldi inner
+ * products into it).
+ *   1: chunked gather -- every output walks its rows of the 1D operators.
+ *   2: fibre form, FP64 plans only -- direction by direction, each fibre of
+ *      the sparse grid along that direction (the DOFs sharing every other
+ *      axis' level and position; it spans levels 0..b of the axis, b = N -
+ *      the other levels' sum) is taken from hierarchical coefficients to the
+ *      level-b cell-Legendre basis by the two-scale relation, multiplied by
+ *      the block-tridiagonal level-b form of B_i (Sec. 2.1, eq. 2.10
+ *      restricted to that space) and transformed back: x read once per
+ *      direction, O(1) work per value.  Same operator, different rounding
+ *      (agrees with form 1 to a few units of 1e-13 |A||x|).  The first
+ *      selection builds its tables on the device (allocates).
+ *   3: form 2 with every fibre of budget b >= 2 split at level b/2 (the
+ *      two-level path that form 2 takes for fibres longer than one LDS
+ *      tile: coarse levels synthesised first, subtrees as tiles, coarse
+ *      levels analysed last); selectable for testing.
+ *   0: automatic -- form 2 for FP64 plans of at least 2^22 DOFs whose
+ *      species segments all exceed the staged sweeps' LDS, else form 1
+ *      (what sg_dg_build selects).
+ * Synchronises the device.  Errors: SGDG_ERR_ARG (null plan, unknown form),
+ * SGDG_ERR_UNSUPPORTED (forms 2, 3 on an FP32/BF16 plan), SGDG_ERR_ALLOC /
+ * SGDG_ERR_HIP (the plan then keeps form 1).                                */
+sgdg_status sg_dg_sweep_form(sgdg_plan* plan, int32_t form);
+
 /* w ~ exp(h A) v (Sec. 3, eq. 3.8): Arnoldi (eq. 3.7) with M products per
  * species, instance and right-hand side, classical Gram-Schmidt with one
  * re-orthogonalisation pass, happy breakdown when h_{j+1,j} <= 1e-12 ||A_s||_inf,

@@ -524,6 +524,11 @@ static void launch_any(const sgdg_plan* plan, int nrhs, const void* x, void* y, 
 
 template <class P>
 void launch_apply(const sgdg_plan* plan, int nrhs, const void* x, void* y, int64_t xs, int64_t ys, hipStream_t s) {
+  if constexpr (std::is_same_v<P, PrecF64>)
+    if (plan->fibre_on) {
+      launch_fibre(plan, nrhs, (const double*)x, (double*)y, xs, ys, s);
+      return;
+    }
   launch_any<P, void>(plan, nrhs, x, y, xs, ys, DotArgs{}, s);
 }
 

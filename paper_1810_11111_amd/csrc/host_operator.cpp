@@ -45,24 +45,30 @@ inline double kval(const sgdg_kdiag& kd, double x) { return kd.a0 + kd.a1 * std:
 
 }  // namespace
 
-Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd, int bc) {
-  const Basis1D& bs = basis1d(k);
+// Full-grid SIPG matrices on the level-N cells: volume (per cell, or one when
+// k(x) is constant), interior faces (2K1 x 2K1, rows/cols [left cell q |
+// right cell q]; per face, or one) and the two zero-Dirichlet boundary faces
+// (K1 x K1 on the end cells).  Every matrix is [target q][source r].
+CellMats cell_mats(int N, int k, double sigma, const sgdg_kdiag& kd) {
   const int K1 = k + 1, K2 = K1 * K1;
   const long nc = 1L << N;
   const double h = std::ldexp(1.0, -N);
-  const bool constk = (kd.a1 == 0.0);
+  CellMats cm;
+  cm.constk = (kd.a1 == 0.0);
+  const bool constk = cm.constk;
 
   // volume matrices per finest cell: (1/h^2) sum_g w_g k(x_g) phi'_q phi'_r
   std::vector<double> xg, wg;
   gauss01(12, xg, wg);
   std::vector<double> dphi(xg.size() * K1);
   for (size_t g = 0; g < xg.size(); ++g) legendre01_all(k, xg[g], nullptr, &dphi[g * K1]);
-  std::vector<double> kvol((constk ? 1 : nc) * K2, 0.0);
+  cm.kvol.assign((constk ? 1 : nc) * K2, 0.0);
   for (long c = 0; c < (constk ? 1 : nc); ++c)
     for (size_t g = 0; g < xg.size(); ++g) {
       double kv = kval(kd, (c + xg[g]) * h);
       for (int q = 0; q < K1; ++q)
-        for (int r = 0; r < K1; ++r) kvol[c * K2 + q * K1 + r] += wg[g] * kv * dphi[g * K1 + q] * dphi[g * K1 + r] / (h * h);
+        for (int r = 0; r < K1; ++r)
+          cm.kvol[c * K2 + q * K1 + r] += wg[g] * kv * dphi[g * K1 + q] * dphi[g * K1 + r] / (h * h);
     }
   // face matrices (2K1 x 2K1): rows/cols [left cell q | right cell q]
   double v0[16], v1[16], d0[16], d1[16];
@@ -75,38 +81,42 @@ Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd, int bc) {
     mder[q] = 0.5 * d1[q] / (h * std::sqrt(h));
     mder[K1 + q] = 0.5 * d0[q] / (h * std::sqrt(h));
   }
-  std::vector<double> F0;
-  auto face = [&](long e, std::vector<double>& F) {
-    double ke = kval(kd, e * h);
-    F.assign(4 * K2, 0.0);
+  const long nf = constk ? 1 : nc;
+  cm.face.assign(nf * 4 * K2, 0.0);
+  for (long e = 0; e < nf; ++e) {
+    const double ke = kval(kd, e * h);
+    double* F = &cm.face[e * 4 * K2];
     for (int a = 0; a < 2 * K1; ++a)
       for (int b = 0; b < 2 * K1; ++b)
         F[a * 2 * K1 + b] = -ke * jump[a] * mder[b] - ke * mder[a] * jump[b] + sigma / h * jump[a] * jump[b];
-  };
-  std::vector<double> Fconst, Fall;
-  if (constk) {
-    face(0, Fconst);
-  } else {
-    Fall.resize(nc * 4 * K2);
-    for (long e = 0; e < nc; ++e) {
-      face(e, F0);
-      std::copy(F0.begin(), F0.end(), Fall.begin() + e * 4 * K2);
-    }
   }
 
   // zero-Dirichlet boundary face matrices (K1 x K1, on one cell): x = 0 acts on
   // cell 0 (jump -v0/sqrt(h), flux d0/h^1.5), x = 1 on cell nc-1 (v1, d1)
-  std::vector<double> FB0(K2), FB1(K2);
+  cm.FB0.assign(K2, 0.0);
+  cm.FB1.assign(K2, 0.0);
   {
     const double k0 = kval(kd, 0.0), k1 = kval(kd, 1.0), sh = std::sqrt(h), h15 = h * sh;
     for (int a = 0; a < K1; ++a)
       for (int b = 0; b < K1; ++b) {
         const double ja0 = -v0[a] / sh, jb0 = -v0[b] / sh, da0 = d0[a] / h15, db0 = d0[b] / h15;
         const double ja1 = v1[a] / sh, jb1 = v1[b] / sh, da1 = d1[a] / h15, db1 = d1[b] / h15;
-        FB0[a * K1 + b] = -k0 * ja0 * db0 - k0 * da0 * jb0 + sigma / h * ja0 * jb0;
-        FB1[a * K1 + b] = -k1 * ja1 * db1 - k1 * da1 * jb1 + sigma / h * ja1 * jb1;
+        cm.FB0[a * K1 + b] = -k0 * ja0 * db0 - k0 * da0 * jb0 + sigma / h * ja0 * jb0;
+        cm.FB1[a * K1 + b] = -k1 * ja1 * db1 - k1 * da1 * jb1 + sigma / h * ja1 * jb1;
       }
   }
+  return cm;
+}
+
+Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd, int bc) {
+  const Basis1D& bs = basis1d(k);
+  const int K1 = k + 1, K2 = K1 * K1;
+  const long nc = 1L << N;
+  const CellMats cm = cell_mats(N, k, sigma, kd);
+  const bool constk = cm.constk;
+  const std::vector<double>& kvol = cm.kvol;
+  const std::vector<double>& FB0 = cm.FB0;
+  const std::vector<double>& FB1 = cm.FB1;
   const double scale_est = sigma * std::ldexp(1.0, 2 * N);
   std::map<std::pair<int32_t, int32_t>, std::vector<double>> blocks;  // (target cell, source cell) -> [pt][ps]
 
@@ -211,7 +221,7 @@ Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd, int bc) {
           }
         continue;
       }
-      const double* Fp = constk ? Fconst.data() : &Fall[em * 4 * K2];
+      const double* Fp = &cm.face[(constk ? 0 : em) * 4 * K2];
       long L = em - 1, R = em;
       for (int p = 0; p < K1; ++p) {
         double u[32];
@@ -312,6 +322,87 @@ Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd, int bc) {
   }
   for (long c = 0; c < nc; ++c) op.cptr[c + 1] += op.cptr[c];
   return op;
+}
+
+// The same operator restricted to the piecewise polynomials on the level-b
+// cells, b = 0..N, in the cell-Legendre (single-scale) basis of level b.  On
+// level N it is the full-grid SIPG form itself: block tridiagonal, cell c
+// coupling to c-1 (block L), itself (D) and c+1 (R), indices taken mod 2^N
+// (periodic) or with the end blocks absent (zero Dirichlet, whose boundary
+// faces sit on the diagonal).  Each coarser level is the Galerkin restriction
+// of the finer one through the two-scale relation (a level-b cell function
+// is ML / MR times its coefficients on the left / right child), which keeps
+// the block-tridiagonal shape: for parent P,
+//   D'_P = ML^T D_2P ML + ML^T R_2P MR + MR^T L_2P+1 ML + MR^T D_2P+1 MR,
+//   L'_P = ML^T L_2P MR,   R'_P = MR^T R_2P+1 ML.
+// Since the hierarchical basis of levels 0..b is an orthonormal basis of the
+// same space, the hierarchical operator restricted to levels 0..b equals
+// this level-b matrix conjugated by the multiwavelet transform (Sec. 2.1,
+// eq. 2.10 on the space of a fibre of the sparse grid).
+// Layout: level b at off[b], cells c = 0..2^b - 1 (one cell when uniform),
+// blocks L, D, R of K1 x K1 each, [target q][source r].
+std::vector<double> build_ss_levels(const Op1D& op, std::vector<int64_t>& off, bool& uniform) {
+  const int N = op.N, k = op.k, K1 = k + 1, K2 = K1 * K1, B3 = 3 * K2;
+  const sgdg_kdiag kd{op.kd[0], op.kd[1], op.kd[2], op.kd[3]};
+  const CellMats cm = cell_mats(N, k, op.sigma, kd);
+  const Basis1D& bs = basis1d(k);
+  uniform = cm.constk && op.bc == 0;
+  auto ncell = [&](int b) -> long { return uniform ? 1L : (1L << b); };
+  off.assign(N + 2, 0);
+  for (int b = 0; b <= N; ++b) off[b + 1] = off[b] + ncell(b) * B3;
+  std::vector<double> T(off[N + 1], 0.0);
+  // level N
+  {
+    const long nc = 1L << N;
+    double* lv = &T[off[N]];
+    for (long c = 0; c < ncell(N); ++c)
+      for (int i = 0; i < K2; ++i) lv[c * B3 + K2 + i] = cm.kvol[(cm.constk ? 0 : c) * K2 + i];
+    for (long e = 0; e < (uniform ? 1 : nc); ++e) {
+      if (op.bc == 1 && e == 0) {
+        for (int i = 0; i < K2; ++i) {
+          lv[0 * B3 + K2 + i] += cm.FB0[i];
+          lv[(nc - 1) * B3 + K2 + i] += cm.FB1[i];
+        }
+        continue;
+      }
+      const double* F = &cm.face[(cm.constk ? 0 : e) * 4 * K2];
+      const long cl = uniform ? 0 : (e - 1 + nc) % nc, cr = uniform ? 0 : e;
+      for (int a = 0; a < K1; ++a)
+        for (int b = 0; b < K1; ++b) {
+          lv[cl * B3 + K2 + a * K1 + b] += F[a * 2 * K1 + b];                // D of the left cell
+          lv[cl * B3 + 2 * K2 + a * K1 + b] += F[a * 2 * K1 + K1 + b];       // R of the left cell
+          lv[cr * B3 + a * K1 + b] += F[(K1 + a) * 2 * K1 + b];              // L of the right cell
+          lv[cr * B3 + K2 + a * K1 + b] += F[(K1 + a) * 2 * K1 + K1 + b];    // D of the right cell
+        }
+    }
+  }
+  // Galerkin restriction level by level: out += Mt^T B Ms
+  auto rap = [&](double* out, const double* Bm, const double* Mt, const double* Ms) {
+    for (int i = 0; i < K1; ++i)
+      for (int j = 0; j < K1; ++j) {
+        double acc = 0;
+        for (int q = 0; q < K1; ++q)
+          for (int r = 0; r < K1; ++r) acc += Mt[q * K1 + i] * Bm[q * K1 + r] * Ms[r * K1 + j];
+        out[i * K1 + j] += acc;
+      }
+  };
+  const double* ML = bs.ML.data();
+  const double* MR = bs.MR.data();
+  for (int b = N; b >= 1; --b) {
+    const double* fine = &T[off[b]];
+    double* crs = &T[off[b - 1]];
+    for (long P = 0; P < ncell(b - 1); ++P) {
+      const long c0 = uniform ? 0 : 2 * P, c1 = uniform ? 0 : 2 * P + 1;
+      double* o = &crs[P * B3];
+      rap(o + K2, fine + c0 * B3 + K2, ML, ML);
+      rap(o + K2, fine + c0 * B3 + 2 * K2, ML, MR);
+      rap(o + K2, fine + c1 * B3, MR, ML);
+      rap(o + K2, fine + c1 * B3 + K2, MR, MR);
+      rap(o, fine + c0 * B3, ML, MR);
+      rap(o + 2 * K2, fine + c1 * B3 + 2 * K2, MR, ML);
+    }
+  }
+  return T;
 }
 
 }  // namespace sgdg

@@ -137,6 +137,7 @@ extern "C" sgdg_status sg_dg_destroy(sgdg_plan* plan) {
   if (!plan) return fail(SGDG_ERR_ARG, "sg_dg_destroy: null plan");
   hipDeviceSynchronize();
   reaction_destroy(plan);
+  fibre_destroy(plan);
   for (void* p : plan->allocations) hipFree(p);
   delete plan;
   return SGDG_OK;
@@ -583,6 +584,13 @@ extern "C" sgdg_status sg_dg_build(const sgdg_desc* descs, int32_t ninst, int32_
   if ((st = reaction_build(p)) != SGDG_OK) {
     sg_dg_destroy(p);
     return st;
+  }
+  if (fibre_auto(p)) {
+    if ((st = fibre_build(p, false)) != SGDG_OK) {
+      sg_dg_destroy(p);
+      return st;
+    }
+    p->fibre_on = true;
   }
   *out = p;
   return SGDG_OK;

@@ -15,6 +15,8 @@
 
 namespace sgdg {
 
+struct FibreData;  // fibre form of the operator sweep (fibre.hip)
+
 // One level block of one species of one instance.
 struct GBlock {
   int64_t start;  // first element in a plan vector
@@ -149,6 +151,10 @@ struct sgdg_plan {
   std::vector<void*> allocations;
   // reaction tables (filled by the reaction module)
   void* rdata = nullptr;
+  // fibre form of the operator sweep: tables (built on first selection) and
+  // whether sg_dg_apply takes it
+  sgdg::FibreData* fdata = nullptr;
+  bool fibre_on = false;
 };
 
 namespace sgdg {
@@ -158,6 +164,12 @@ constexpr int APPLY_LDS_BYTES_HOST = 160 * 1024;  // same budget as the staged s
 constexpr int SWEEP_TIERS = 3;
 constexpr int APPLY_G = 4;  // lanes per output element in the staged sweeps (the least; rows with more work get more)
 constexpr int APPLY_GMAX = 64;
+
+// fibre form of the operator sweep (fibre.hip)
+bool fibre_auto(const sgdg_plan* p);
+sgdg_status fibre_build(sgdg_plan* p, bool test_split);
+void fibre_destroy(sgdg_plan* p);
+void launch_fibre(const sgdg_plan* p, int nrhs, const double* x, double* y, int64_t xs, int64_t ys, hipStream_t s);
 
 // error reporting
 sgdg_status fail(sgdg_status st, const std::string& msg);
@@ -175,7 +187,15 @@ const Basis1D& basis1d(int k);
 double hier_value(const Basis1D& b, int level, int j, int p, double x, bool deriv);
 
 // 1D operator (host_operator.cpp)
+struct CellMats {  // full-grid SIPG matrices on the finest cells
+  bool constk = true;
+  std::vector<double> kvol;      // per cell (one when k is constant): K1 x K1
+  std::vector<double> face;      // per face e between cells e-1 and e (one when k is constant): 2K1 x 2K1
+  std::vector<double> FB0, FB1;  // zero-Dirichlet faces at x = 0 (on cell 0) and x = 1 (on the last cell)
+};
+CellMats cell_mats(int N, int k, double sigma, const sgdg_kdiag& kd);
 Op1D build_op1d(int N, int k, double sigma, const sgdg_kdiag& kd, int bc);
+std::vector<double> build_ss_levels(const Op1D& op, std::vector<int64_t>& off, bool& uniform);
 
 // enumeration helpers
 __host__ __device__ inline int level_count(int l) { return l == 0 ? 1 : (1 << (l - 1)); }

@@ -76,6 +76,7 @@ _sigs = {
     "sg_dg_project": ([_vp, _i32, _f64, C.POINTER(Factor1D), _vp], C.c_int),
     "sg_dg_norm_inf": ([_vp, _i32, _i32, C.POINTER(_f64)], C.c_int),
     "sg_dg_apply": ([_vp, _i32, _vp, _vp, _vp], C.c_int),
+    "sg_dg_sweep_form": ([_vp, _i32], C.c_int),
     "krylov_expv": ([_vp, _i32, _f64, _i32, _vp, _vp, _vp, _sz, _vp, _vp], C.c_int),
     "sgdg_reaction": ([_vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
     "sgdg_reaction_timed": ([_vp, _i32, _vp, _vp, _vp, _sz, _vp, _vp, C.POINTER(_i32), _vp], C.c_int),
@@ -212,6 +213,10 @@ class Plan:
     # ---- device calls ---------------------------------------------------
     def apply(self, x, y, nrhs=1, stream=None):
         _check(_lib.sg_dg_apply(self._h, nrhs, _ptr(x), _ptr(y), _stream(stream)), "sg_dg_apply")
+
+    def sweep_form(self, form):
+        """0 automatic, 1 chunked gather, 2 fibre form (FP64 only), 3 fibre form with every fibre split (testing)."""
+        _check(_lib.sg_dg_sweep_form(self._h, form), "sg_dg_sweep_form")
 
     def krylov_expv(self, h, M, v, w, workspace, stats=None, nrhs=1, stream=None):
         _check(_lib.krylov_expv(self._h, nrhs, float(h), M, _ptr(v), _ptr(w), _ptr(workspace),

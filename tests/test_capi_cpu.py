@@ -50,6 +50,7 @@ def test_argument_errors_return_before_device_work():
     assert L.sg_dg_info(None, 0, C.byref(n), None, None) == 1
     assert L.sg_dg_total(None, C.byref(n)) == 1
     assert L.sg_dg_apply(None, 1, None, None, None) == 1
+    assert L.sg_dg_sweep_form(None, 2) == 1
     assert L.krylov_expv(None, 1, 0.1, 10, None, None, None, 0, None, None) in (1, 4)
     assert L.iif2_step(None, 1, 0.1, 10, None, None, None, 1e-14, 5, None, 0, None, None) in (1, 4)
     assert L.iif3_step(None, 1, 0.1, 10, None, None, None, None, 1e-14, 5, None, 0, None, None) in (1, 4)

@@ -1,0 +1,177 @@
+"""GPU parity of the fibre form of y = A x (sg_dg_sweep_form 2 and 3) against
+the oracle's explicit A (Sec. 2.1, eq. 2.10).
+
+The fibre form takes each fibre of the sparse grid along direction i to the
+cell-Legendre basis of its finest level, applies the block-tridiagonal SIPG
+form there and transforms back.  Same operator, different arithmetic: the
+bounds are those of the chunked sweep (1e-13 of max(|A||x|); 1e-12 / 2e-12
+where the library's and the oracle's 1D tables already differ by that much).
+Form 3 splits every fibre of budget b >= 2 at level b/2 (coarse levels
+synthesised into scratch, the subtrees below them as tiles with their edge
+cells synthesised along the neighbouring subtrees, coarse levels analysed
+back), the path form 2 takes only for fibres longer than one LDS tile, so
+both paths meet the oracle at sizes it can assemble.
+"""
+import numpy as np
+import pytest
+
+from oracle import operator
+from paper_1810_11111_amd import inputs as I
+
+from _gpu_common import lib, say, to_dev
+from test_gpu_apply import CASES
+
+pytestmark = pytest.mark.gpu
+
+DIRICHLET = [
+    # (d, N, k, D, kdiag, bc, tol): zero Dirichlet on every face, with and without
+    # k_ii(x).  Degree 3 carries the rounding of the 1D tables that the chunked
+    # sweep's cases at k = 3 already show against the oracle (6.2e-13 of
+    # max(|A||x|) at d=3 N=6, bound 2e-12); measured 2.6e-13 here.
+    (2, 5, 2, [1.0], (1.0, 0.5, 1.0), 1, 1e-13),
+    (3, 4, 1, [0.5, 2.0], None, 1, 1e-13),
+    (1, 7, 3, [1.0], (1.0, 0.25, 2.0), 1, 2e-12),
+]
+
+
+def _oracle_A(d, N, k, kdiag, bc=0):
+    kap = None
+    if kdiag is not None:
+        a0, a1, f = kdiag
+        fn = lambda x: a0 + a1 * np.sin(2 * np.pi * f * x)  # noqa: E731
+        kap = [fn] * d
+    return operator.assemble_A(d, N, k, 20.0, kap, 1.0, bc="dirichlet" if bc else "periodic")
+
+
+def _check(y, yref, A, x, tol, what):
+    scale = np.abs(A) @ np.abs(x)
+    err = np.abs(y - yref).max()
+    assert err <= tol * max(scale.max(), 1e-300), f"{what}: err {err:.3e} scale {scale.max():.3e}"
+    return err / max(scale.max(), 1e-300)
+
+
+def _run(case, form, bc=0, nrhs=3, tol=None):
+    sg = lib()
+    import torch
+
+    d, N, k, D, kdiag = case[:5]
+    if tol is None:
+        tol = case[5] if len(case) > 5 else 1e-13
+    inst = I.Instance(d, N, k, D, I.rx_zeros(len(D)), kdiag=kdiag, bc=bc)
+    say("fibre form", form, case, "bc", bc)
+    plan = sg.Plan([inst], "fp64")
+    plan.sweep_form(form)
+    nd, off, _ = plan.info(0)
+    A1 = _oracle_A(d, N, k, kdiag, bc)
+    X = I.smooth_random(plan.total, 17 + d * 10 + N, nrhs)
+    xd = to_dev(X)
+    yd = torch.full_like(xd, np.nan)  # every element must be written
+    plan.apply(xd, yd, nrhs=nrhs)
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy()
+    worst = 0.0
+    for r in range(nrhs):
+        for s, Ds in enumerate(D):
+            seg = slice(off + s * nd, off + (s + 1) * nd)
+            worst = max(worst, _check(Y[r, seg], Ds * (A1 @ X[r, seg]), Ds * A1, X[r, seg], tol,
+                                      f"form {form} rhs {r} species {s}"))
+    say("  err / max(|A||x|)", f"{worst:.2e}", "bound", tol)
+    plan.close()
+
+
+@pytest.mark.parametrize("form", [2, 3])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"d{c[0]}N{c[1]}k{c[2]}s{len(c[3])}")
+def test_fibre_form_matches_explicit_operator(case, form):
+    _run(case, form)
+
+
+@pytest.mark.parametrize("form", [2, 3])
+@pytest.mark.parametrize("case", DIRICHLET, ids=lambda c: f"d{c[0]}N{c[1]}k{c[2]}dirichlet")
+def test_fibre_form_dirichlet_and_variable_coefficients(case, form):
+    _run(case[:5], form, bc=case[5], nrhs=2, tol=case[6])
+
+
+@pytest.mark.parametrize("form", [2, 3])
+def test_fibre_form_multi_instance_mixed_degree(form):
+    """Instances of degree 1, 2 and 3 (one launch per direction and degree),
+    uneven levels, two species, two right-hand sides."""
+    sg = lib()
+    import torch
+
+    insts = [I.Instance(3, 2 + (i % 3), 1 + (i % 3), [0.5 + i, 0.25], I.rx_zeros(2)) for i in range(6)]
+    say("fibre form multi-instance", form)
+    plan = sg.Plan(insts, "fp64")
+    plan.sweep_form(form)
+    X = I.smooth_random(plan.total, 123, 2)
+    yd = torch.full_like(to_dev(X), np.nan)
+    plan.apply(to_dev(X), yd, nrhs=2)
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy()
+    for i, inst in enumerate(insts):
+        nd, off, _ = plan.info(i)
+        A1 = _oracle_A(3, inst.N, inst.k, None)
+        for r in range(2):
+            for s, Ds in enumerate(inst.D):
+                seg = slice(off + s * nd, off + (s + 1) * nd)
+                _check(Y[r, seg], Ds * (A1 @ X[r, seg]), Ds * A1, X[r, seg], 1e-13, f"inst {i} rhs {r} species {s}")
+    plan.close()
+
+
+def test_fibre_form_long_fibres_and_out_of_cache():
+    """Fibres longer than an LDS tile (d=2 N=14 k=1: up to 32768 values, split
+    into subtrees) and
+    the out-of-cache sweep (d=3 N=16 k=1, 24.6M DOF, the automatic choice):
+    the fibre form against the chunked form (itself checked against the
+    oracle above), elementwise within 1e-12 ||A||_inf max|x| (rounding of
+    both is ~1e-14 of that), plus the properties that hold at any size:
+    x.Ay = y.Ax, x.Ax < 0, and A annihilates the constant."""
+    sg = lib()
+    import torch
+
+    for d, N in ((2, 14), (3, 16)):
+        inst = I.Instance(d, N, 1, [1.0], I.rx_zeros(1))
+        say("fibre vs chunked", d, N)
+        plan = sg.Plan([inst], "fp64")
+        n = plan.total
+        X = to_dev(I.smooth_random(n, 9, 2))
+        Yf = torch.full_like(X, np.nan)
+        plan.sweep_form(2)
+        plan.apply(X, Yf, nrhs=2)
+        plan.sweep_form(1)
+        Yc = torch.empty_like(X)
+        plan.apply(X, Yc, nrhs=2)
+        torch.cuda.synchronize()
+        scale = plan.norm_inf(0, 0) * float(X.abs().max())
+        err = float((Yf - Yc).abs().max())
+        say("  max |fibre - chunked| / (||A|| max|x|)", f"{err / scale:.2e}")
+        assert err <= 1e-12 * scale
+        x, y, Ax, Ay = (t.cpu().numpy() for t in (X[0], X[1], Yf[0], Yf[1]))
+        nx, nAy = np.linalg.norm(x), np.linalg.norm(Ay)
+        assert abs(x @ Ay - y @ Ax) <= 1e-12 * nx * nAy
+        assert x @ Ax < 0 and y @ Ay < 0
+        e = torch.zeros(n, dtype=torch.float64, device="cuda")
+        e[0] = 1.0
+        Ae = torch.empty_like(e)
+        plan.sweep_form(2)
+        plan.apply(e, Ae)
+        torch.cuda.synchronize()
+        assert float(Ae.abs().max()) <= 1e-13 * plan.norm_inf(0, 0)
+        plan.close()
+
+
+def test_fibre_form_selection():
+    """Automatic choice: the fibre form for large FP64 plans whose segments
+    all exceed the staged sweeps; FP32 / BF16 plans refuse it."""
+    sg = lib()
+
+    p32 = sg.Plan([I.Instance(2, 4, 1, [1.0], I.rx_zeros(1))], "fp32")
+    with pytest.raises(sg.SgdgError) as ei:
+        p32.sweep_form(2)
+    assert ei.value.status == 4
+    p32.sweep_form(1)
+    p32.sweep_form(0)
+    p32.close()
+    p64 = sg.Plan([I.Instance(2, 4, 1, [1.0], I.rx_zeros(1))], "fp64")
+    with pytest.raises(sg.SgdgError):
+        p64.sweep_form(4)
+    p64.close()
