@@ -146,7 +146,7 @@ def kernel_source_hash(files):
 
 
 REACTION_SOURCES = ("reaction.hip", "reaction.h", "iif2.hip", "internal.h")
-SWEEP_SOURCES = ("apply.hip", "kernels.h", "internal.h", "host_plan.cpp")
+SWEEP_SOURCES = ("apply.hip", "kernels.h", "internal.h", "host_plan.cpp", "fibre.hip", "host_operator.cpp")
 
 
 def traffic_record(name, sources):
@@ -182,12 +182,15 @@ def reaction_stage_times(sg, torch, insts, nrhs, U0, reps):
     return kinds, avg
 
 
-def time_sweep(sg, torch, insts, prec, reps, seed=7):
-    """Average duration of one sweep launch (sg_dg_apply, nrhs=1), HIP events
-    around a captured graph of `reps` back-to-back launches on one stream."""
+def time_sweep(sg, torch, insts, prec, reps, seed=7, form=0):
+    """Average duration of one sweep (sg_dg_apply, nrhs=1; form as
+    sg_dg_sweep_form, 0 = the plan's automatic choice), HIP events around a
+    captured graph of `reps` back-to-back sweeps on one stream."""
     from paper_1810_11111_amd import inputs as I
 
     plan = sg.Plan(insts, prec)
+    if form:
+        plan.sweep_form(form)
     dt = torch.float64 if prec == "fp64" else torch.float32
     x = torch.from_numpy(I.smooth_random(plan.total, seed, 1)[0]).to(dt).cuda()
     y = torch.empty_like(x)
@@ -520,12 +523,17 @@ def main():
         log("[bench] out-of-cache sweep d=3 N=16 k=1")
         big = [I.Instance(3, 16, 1, [1.0], I.rx_zeros(1))]
         avg_b, nbytes_b, tot_b = time_sweep(sg, torch, big, "fp64", reps=10)
+        avg_c, _, _ = time_sweep(sg, torch, big, "fp64", reps=10, form=1)
         gbs = nbytes_b / avg_b / 1e9
         out["apply_out_of_cache"] = {"workload": "sweep d=3 N=16 k=1 (24.6M DOF, 197 MB per FP64 vector)",
+                                     "form": "fibre (the automatic choice: 3 directions x coarse synthesis, "
+                                             "tiles, coarse analysis)",
+                                     "chunked_form_avg_ms": avg_c * 1e3,
                                      "dof": tot_b, "avg_ms": avg_b * 1e3, "achieved_gbs": gbs,
                                      "frac_of_peak": gbs / HBM_PEAK_GBS, "frac_of_triad": gbs / triad_gbs,
-                                     "bytes_per_launch": nbytes_b,
-                                     "traffic": traffic_record("sweep_d3_n16_k1", SWEEP_SOURCES)}
+                                     "algorithmic_bytes_per_sweep": nbytes_b,
+                                     "traffic_bytes_per_sweep": traffic_record("k_fibre_sweep_d3_n16_k1",
+                                                                               SWEEP_SOURCES)}
         # FP64 / FP32 against the oracle's full-size states (two steps, two of the 16 RHS)
         errs = {}
         for r in (0, 15):

@@ -191,7 +191,7 @@ sgdg_status sg_dg_apply(const sgdg_plan* plan, int32_t nrhs, const void* x, void
  *      two-level path that form 2 takes for fibres longer than one LDS
  *      tile: coarse levels synthesised first, subtrees as tiles, coarse
  *      levels analysed last); selectable for testing.
- *   0: automatic -- form 2 for FP64 plans of at least 2^22 DOFs whose
+ *   0: automatic -- form 2 for FP64 plans of at least 2^19 DOFs whose
  *      species segments all exceed the staged sweeps' LDS, else form 1
  *      (what sg_dg_build selects).
  * Synchronises the device.  Errors: SGDG_ERR_ARG (null plan, unknown form),

@@ -41,10 +41,10 @@ namespace sgdg {
 namespace {
 
 constexpr int FB_NT = 256;     // threads per workgroup
-constexpr int FB_CAP = 4096;   // values of one LDS tile (and as many old y values)
+constexpr int FB_CAP = 2048;   // values of one LDS tile (and as many old y values): 4 workgroups per CU
 constexpr int FB_FMAX = 512;   // fibres per tile
 constexpr int FB_LDS = 2 * FB_CAP * 8 + FB_FMAX * 8 + 32 * 8 + 8 * 8;
-constexpr int64_t FIBRE_AUTO_MIN = int64_t(1) << 22;  // DOFs
+constexpr int64_t FIBRE_AUTO_MIN = int64_t(1) << 19;  // DOFs
 
 enum TileMode : int32_t { WHOLE = 0, SUBTREE = 1, COARSE_SYN = 2, COARSE_ANA = 3 };
 
@@ -416,7 +416,7 @@ __device__ void tile_body(const FibreTask& tk, const TwoScale& __restrict__ ts, 
 }
 
 template <int K1>
-__global__ __launch_bounds__(FB_NT) void k_fibre(
+__global__ __launch_bounds__(FB_NT) __attribute__((amdgpu_waves_per_eu(4))) void k_fibre(
     const FibreTask* __restrict__ tasks, const int64_t* __restrict__ bases, const double* __restrict__ ops,
     double* __restrict__ scratch, const double* __restrict__ x, double* __restrict__ y, int64_t xs, int64_t ys,
     int nrhs, int acc, const TwoScale* __restrict__ tsp) {
