@@ -44,6 +44,7 @@ constexpr int FB_NT = 256;     // threads per workgroup
 constexpr int FB_CAP = 2048;   // values of one LDS tile (and as many old y values): 4 workgroups per CU
 constexpr int FB_FMAX = 512;   // fibres per tile
 constexpr int FB_LDS = 2 * FB_CAP * 8 + FB_FMAX * 8 + 32 * 8 + 8 * 8;
+constexpr int XRUN = 32;       // consecutive tasks per XCD
 constexpr int64_t FIBRE_AUTO_MIN = int64_t(1) << 19;  // DOFs
 
 enum TileMode : int32_t { WHOLE = 0, SUBTREE = 1, COARSE_SYN = 2, COARSE_ANA = 3 };
@@ -428,7 +429,12 @@ __global__ __launch_bounds__(FB_NT) __attribute__((amdgpu_waves_per_eu(4))) void
   int* fsuf = fpre + FB_FMAX;
   int64_t* lb = (int64_t*)(fsuf + FB_FMAX);
   double* halo = (double*)(lb + 32);
-  const FibreTask tk = tasks[blockIdx.x];
+  // workgroups go to the 8 XCDs round robin; the k-th workgroup of XCD x
+  // takes task ((k / XRUN) 8 + x) XRUN + k % XRUN, so that runs of XRUN
+  // consecutive tasks (tiles of neighbouring fibres, whose values share cache
+  // lines) meet in one XCD's L2 (the list is padded to a multiple of 8 XRUN)
+  const int k8 = blockIdx.x >> 3;
+  const FibreTask tk = tasks[((k8 / XRUN) * 8 + (blockIdx.x & 7)) * XRUN + k8 % XRUN];
   const int tid = threadIdx.x;
   if (tid <= tk.bfull) lb[tid] = bases[tk.base + tid];
   for (int f = tid; f < tk.F; f += FB_NT) {
@@ -627,13 +633,19 @@ sgdg_status fibre_build(sgdg_plan* p, bool test_split) {
         }
       }
       if (whole.empty() && sub.empty()) continue;
-      // larger tiles first (the split fibres' subtrees are the largest)
-      auto byb = [](const FibreTask& a, const FibreTask& c) { return a.b > c.b; };
-      std::stable_sort(whole.begin(), whole.end(), byb);
       g.ph[0].tasks = syn;
       g.ph[1].tasks = sub;
       g.ph[1].tasks.insert(g.ph[1].tasks.end(), whole.begin(), whole.end());
       g.ph[2].tasks = ana;
+      for (Launch& l : g.ph)
+        if (!l.tasks.empty()) {
+          FibreTask pad{};  // no valid fibre: loads and stores nothing
+          pad.mode = WHOLE;
+          pad.F = 1;
+          pad.S = 1;
+          pad.sS = pad.sT = -1;
+          while (l.tasks.size() % (8 * XRUN)) l.tasks.push_back(pad);
+        }
       scratch_max = std::max(scratch_max, scr);
       fd->groups.push_back(std::move(g));
     }
