@@ -74,6 +74,7 @@ struct TwoScale {
 struct Launch {  // one kernel launch: the tasks of one phase of one (direction, degree) group
   std::vector<FibreTask> tasks;
   FibreTask* dtasks = nullptr;
+  int uc = 0;  // operator blocks: 0 one triple per level for every task, 1 per cell for every task, 2 mixed
 };
 
 struct Group {  // direction dir, degree K1 - 1: coarse synthesis, tiles, coarse analysis
@@ -157,7 +158,7 @@ __device__ void edge_cell(const FibreTask& tk, const TwoScale& __restrict__ ts, 
 // One tile.  LDS layout [f][cell][p] for subtrees and for fibres along the
 // last axis (S = 1: a fibre's values are contiguous in each block), else
 // [cell][p][f] (consecutive fibres are consecutive in memory).
-template <int K1>
+template <int K1, int UC>
 __device__ void tile_body(const FibreTask& tk, const TwoScale& __restrict__ ts, const double* __restrict__ ops,
                           const double* __restrict__ x, double* __restrict__ y, double* __restrict__ scratch, int acc,
                           double* buf, double* ybuf, const int* fpre, const int* fsuf, const int64_t* lb,
@@ -322,7 +323,7 @@ __device__ void tile_body(const FibreTask& tk, const TwoScale& __restrict__ ts, 
         st[r][q] = a * tk.negD;
       }
     };
-    if (!tk.ucell) {
+    if (UC == 0 || (UC == 2 && !tk.ucell)) {
       // one block triple for every cell (a uniform address)
       const double* Bu = ops + tk.opoff;
 #pragma unroll
@@ -416,7 +417,7 @@ __device__ void tile_body(const FibreTask& tk, const TwoScale& __restrict__ ts, 
   }
 }
 
-template <int K1>
+template <int K1, int UC>
 __global__ __launch_bounds__(FB_NT) __attribute__((amdgpu_waves_per_eu(4))) void k_fibre(
     const FibreTask* __restrict__ tasks, const int64_t* __restrict__ bases, const double* __restrict__ ops,
     double* __restrict__ scratch, const double* __restrict__ x, double* __restrict__ y, int64_t xs, int64_t ys,
@@ -444,7 +445,7 @@ __global__ __launch_bounds__(FB_NT) __attribute__((amdgpu_waves_per_eu(4))) void
   }
   __syncthreads();
   for (int r = 0; r < nrhs; ++r) {
-    tile_body<K1>(tk, ts, ops, x + r * xs, y + r * ys, scratch, acc, buf, ybuf, fpre, fsuf, lb, halo);
+    tile_body<K1, UC>(tk, ts, ops, x + r * xs, y + r * ys, scratch, acc, buf, ybuf, fpre, fsuf, lb, halo);
     __syncthreads();
   }
 }
@@ -639,6 +640,9 @@ sgdg_status fibre_build(sgdg_plan* p, bool test_split) {
       g.ph[2].tasks = ana;
       for (Launch& l : g.ph)
         if (!l.tasks.empty()) {
+          bool any0 = false, any1 = false;
+          for (const FibreTask& t : l.tasks) (t.ucell ? any1 : any0) = true;
+          l.uc = any0 && any1 ? 2 : (any1 ? 1 : 0);
           FibreTask pad{};  // no valid fibre: loads and stores nothing
           pad.mode = WHOLE;
           pad.F = 1;
@@ -669,17 +673,31 @@ sgdg_status fibre_build(sgdg_plan* p, bool test_split) {
   return SGDG_OK;
 }
 
+template <int K1, int UC>
+static void launch_uc(const FibreData& fd, const Launch& l, int nrhs, const double* x, double* y, int64_t xs,
+                      int64_t ys, int acc, hipStream_t s) {
+  static std::atomic<bool> attr{false};
+  if (!attr.load()) {
+    (void)hipFuncSetAttribute((const void*)k_fibre<K1, UC>, hipFuncAttributeMaxDynamicSharedMemorySize, FB_LDS);
+    attr.store(true);
+  }
+  hipLaunchKernelGGL((k_fibre<K1, UC>), dim3((unsigned)l.tasks.size()), dim3(FB_NT), FB_LDS, s, l.dtasks, fd.bases,
+                     fd.ops, fd.scratch, x, y, xs, ys, nrhs, acc, fd.dts + K1);
+}
+
+// The kernel is built for launches whose operators all keep one block triple
+// per level (translation invariant: constant k, periodic), all keep one per
+// cell, or a mix: the first two leave the other branch out of the register
+// budget.
 template <int K1>
 static void launch_phase(const FibreData& fd, const Launch& l, int nrhs, const double* x, double* y, int64_t xs,
                          int64_t ys, int acc, hipStream_t s) {
-  static std::atomic<bool> attr{false};
-  if (!attr.load()) {
-    (void)hipFuncSetAttribute((const void*)k_fibre<K1>, hipFuncAttributeMaxDynamicSharedMemorySize, FB_LDS);
-    attr.store(true);
-  }
   if (l.tasks.empty()) return;
-  hipLaunchKernelGGL(k_fibre<K1>, dim3((unsigned)l.tasks.size()), dim3(FB_NT), FB_LDS, s, l.dtasks, fd.bases, fd.ops,
-                     fd.scratch, x, y, xs, ys, nrhs, acc, fd.dts + K1);
+  switch (l.uc) {
+    case 0: launch_uc<K1, 0>(fd, l, nrhs, x, y, xs, ys, acc, s); break;
+    case 1: launch_uc<K1, 1>(fd, l, nrhs, x, y, xs, ys, acc, s); break;
+    default: launch_uc<K1, 2>(fd, l, nrhs, x, y, xs, ys, acc, s); break;
+  }
 }
 
 template <int K1>
