@@ -164,7 +164,8 @@ __device__ void tile_body(const FibreTask& tk, const TwoScale& __restrict__ ts, 
                           double* buf, double* ybuf, const int* fpre, const int* fsuf, const int64_t* lb,
                           double* halo) {
   constexpr int K2 = K1 * K1;
-  constexpr int RS = (FB_CAP / (2 * K1) + FB_NT - 1) / FB_NT;  // parents per thread (transforms)
+  constexpr int RS = (FB_CAP / (2 * K1) + FB_NT - 1) / FB_NT;  // parents per thread (one-level step)
+  constexpr int RS2 = (FB_CAP / (4 * K1) + FB_NT - 1) / FB_NT; // grandparents per thread (two-level step)
   constexpr int RT = (FB_CAP / K1 + FB_NT - 1) / FB_NT;        // cells per thread (tridiagonal)
   const int tid = threadIdx.x;
   const int mode = tk.mode, b = tk.b, F = tk.F, S = tk.S;
@@ -233,44 +234,70 @@ __device__ void tile_body(const FibreTask& tk, const TwoScale& __restrict__ ts, 
   __builtin_amdgcn_s_waitcnt(0);  // this thread's direct loads have landed
   __syncthreads();
 
-  // synthesis: level l single-scale cells 2j, 2j+1 from level l-1 cell j and wavelet j of level l
-  if (mode != COARSE_ANA)
-    for (int l = 1; l <= b; ++l) {
-      const int ln = l - 1, n = 1 << ln, items = F << ln;
+  // two-scale relation: children (left, right) of a cell from its
+  // coefficients and its wavelet's; parent and wavelet from the children
+  auto children = [&](const double* sv, const double* w, double* lo, double* hi) {
+#pragma unroll
+    for (int q = 0; q < K1; ++q) {
+      double a = 0, c = 0;
+#pragma unroll
+      for (int i = 0; i < K1; ++i) {
+        a += ts.ML[q * K1 + i] * sv[i] + ts.cL[i * K1 + q] * w[i];
+        c += ts.MR[q * K1 + i] * sv[i] + ts.cR[i * K1 + q] * w[i];
+      }
+      lo[q] = a;
+      hi[q] = c;
+    }
+  };
+  auto parent = [&](const double* vl, const double* vr, double* pa, double* wa) {
+#pragma unroll
+    for (int i = 0; i < K1; ++i) {
+      double a = 0, c = 0;
+#pragma unroll
+      for (int q = 0; q < K1; ++q) {
+        a += ts.ML[q * K1 + i] * vl[q] + ts.MR[q * K1 + i] * vr[q];
+        c += ts.cL[i * K1 + q] * vl[q] + ts.cR[i * K1 + q] * vr[q];
+      }
+      pa[i] = a;
+      wa[i] = c;
+    }
+  };
+  // item it of a step with 2^ln cells per fibre on its coarse level
+  auto item = [&](int it, int ln, int& f, int& j) {
+    f = last ? (it >> ln) : (it & (F - 1));
+    j = last ? (it & ((1 << ln) - 1)) : (it >> lF);
+  };
+
+  // synthesis, coarse to fine: one level (cells 2j, 2j+1 of level lo+1 from
+  // cell j of level lo and wavelet n + j, n = 2^lo) when b is odd, then two
+  // levels per pair of barriers (cells 4j..4j+3 of level lo+2 from cell j,
+  // wavelet n + j of level lo+1 and wavelets 2n + 2j, 2n + 2j + 1 of level lo+2)
+  if (mode != COARSE_ANA && b > 0) {
+    int lo = 0;
+    if (b & 1) {
       double st[RS][2 * K1];
 #pragma unroll
       for (int r = 0; r < RS; ++r) {
         const int it = tid + r * FB_NT;
-        if (it < items) {
-          const int f = last ? (it >> ln) : (it & (F - 1));
-          const int j = last ? (it & (n - 1)) : (it >> lF);
+        if (it < F) {
+          int f, j;
+          item(it, 0, f, j);
           double sv[K1], w[K1];
 #pragma unroll
           for (int i = 0; i < K1; ++i) {
             sv[i] = buf[idx(f, j, i)];
-            w[i] = buf[idx(f, n + j, i)];
+            w[i] = buf[idx(f, 1 + j, i)];
           }
-#pragma unroll
-          for (int q = 0; q < K1; ++q) {
-            double lo = 0, hi = 0;
-#pragma unroll
-            for (int i = 0; i < K1; ++i) {
-              lo += ts.ML[q * K1 + i] * sv[i] + ts.cL[i * K1 + q] * w[i];
-              hi += ts.MR[q * K1 + i] * sv[i] + ts.cR[i * K1 + q] * w[i];
-            }
-            st[r][q] = lo;
-            st[r][K1 + q] = hi;
-          }
+          children(sv, w, st[r], st[r] + K1);
         }
-        asm volatile("" ::: "memory");  // bounds the LDS reads kept in flight
       }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < RS; ++r) {
         const int it = tid + r * FB_NT;
-        if (it < items) {
-          const int f = last ? (it >> ln) : (it & (F - 1));
-          const int j = last ? (it & (n - 1)) : (it >> lF);
+        if (it < F) {
+          int f, j;
+          item(it, 0, f, j);
 #pragma unroll
           for (int q = 0; q < K1; ++q) {
             buf[idx(f, 2 * j, q)] = st[r][q];
@@ -279,7 +306,47 @@ __device__ void tile_body(const FibreTask& tk, const TwoScale& __restrict__ ts, 
         }
       }
       __syncthreads();
+      lo = 1;
     }
+    for (; lo + 2 <= b; lo += 2) {
+      const int n = 1 << lo, items = F << lo;
+      double st[RS2][4 * K1];
+#pragma unroll
+      for (int r = 0; r < RS2; ++r) {
+        const int it = tid + r * FB_NT;
+        if (it < items) {
+          int f, j;
+          item(it, lo, f, j);
+          double sv[K1], w1[K1], wa[K1], wb[K1], m0[K1], m1[K1];
+#pragma unroll
+          for (int i = 0; i < K1; ++i) {
+            sv[i] = buf[idx(f, j, i)];
+            w1[i] = buf[idx(f, n + j, i)];
+            wa[i] = buf[idx(f, 2 * n + 2 * j, i)];
+            wb[i] = buf[idx(f, 2 * n + 2 * j + 1, i)];
+          }
+          children(sv, w1, m0, m1);
+          children(m0, wa, st[r], st[r] + K1);
+          children(m1, wb, st[r] + 2 * K1, st[r] + 3 * K1);
+        }
+        asm volatile("" ::: "memory");  // bounds the LDS reads kept in flight
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RS2; ++r) {
+        const int it = tid + r * FB_NT;
+        if (it < items) {
+          int f, j;
+          item(it, lo, f, j);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < K1; ++q) buf[idx(f, 4 * j + u, q)] = st[r][u * K1 + q];
+        }
+      }
+      __syncthreads();
+    }
+  }
 
   // block-tridiagonal product on level bfull, scaled by -D_s: within each
   // whole fibre (cell indices mod 2^b), or across the tile's consecutive
@@ -352,53 +419,83 @@ __device__ void tile_body(const FibreTask& tk, const TwoScale& __restrict__ ts, 
     __syncthreads();
   }
 
-  // analysis: level l-1 cell j and wavelet j of level l from level-l cells 2j, 2j+1
-  if (mode != COARSE_SYN)
-    for (int l = b; l >= 1; --l) {
-      const int ln = l - 1, n = 1 << ln, items = F << ln;
+  // analysis, fine to coarse: two levels per pair of barriers (cell j of
+  // level lo, wavelet n + j of level lo+1 and wavelets 2n + 2j, 2n + 2j + 1 of
+  // level lo+2 from cells 4j..4j+3 of level lo+2), then one level when b is odd
+  if (mode != COARSE_SYN && b > 0) {
+    int hi = b;
+    for (; hi >= 2; hi -= 2) {
+      const int lo = hi - 2, n = 1 << lo, items = F << lo;
+      double st[RS2][4 * K1];
+#pragma unroll
+      for (int r = 0; r < RS2; ++r) {
+        const int it = tid + r * FB_NT;
+        if (it < items) {
+          int f, j;
+          item(it, lo, f, j);
+          double v[4][K1], m0[K1], m1[K1];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < K1; ++q) v[u][q] = buf[idx(f, 4 * j + u, q)];
+          parent(v[0], v[1], m0, st[r] + 2 * K1);
+          parent(v[2], v[3], m1, st[r] + 3 * K1);
+          parent(m0, m1, st[r], st[r] + K1);
+        }
+        asm volatile("" ::: "memory");
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RS2; ++r) {
+        const int it = tid + r * FB_NT;
+        if (it < items) {
+          int f, j;
+          item(it, lo, f, j);
+#pragma unroll
+          for (int i = 0; i < K1; ++i) {
+            buf[idx(f, j, i)] = st[r][i];
+            buf[idx(f, n + j, i)] = st[r][K1 + i];
+            buf[idx(f, 2 * n + 2 * j, i)] = st[r][2 * K1 + i];
+            buf[idx(f, 2 * n + 2 * j + 1, i)] = st[r][3 * K1 + i];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (hi == 1) {
       double st[RS][2 * K1];
 #pragma unroll
       for (int r = 0; r < RS; ++r) {
         const int it = tid + r * FB_NT;
-        if (it < items) {
-          const int f = last ? (it >> ln) : (it & (F - 1));
-          const int j = last ? (it & (n - 1)) : (it >> lF);
+        if (it < F) {
+          int f, j;
+          item(it, 0, f, j);
           double vl[K1], vr[K1];
 #pragma unroll
           for (int q = 0; q < K1; ++q) {
             vl[q] = buf[idx(f, 2 * j, q)];
             vr[q] = buf[idx(f, 2 * j + 1, q)];
           }
-#pragma unroll
-          for (int i = 0; i < K1; ++i) {
-            double pa = 0, wa = 0;
-#pragma unroll
-            for (int q = 0; q < K1; ++q) {
-              pa += ts.ML[q * K1 + i] * vl[q] + ts.MR[q * K1 + i] * vr[q];
-              wa += ts.cL[i * K1 + q] * vl[q] + ts.cR[i * K1 + q] * vr[q];
-            }
-            st[r][i] = pa;
-            st[r][K1 + i] = wa;
-          }
+          parent(vl, vr, st[r], st[r] + K1);
         }
-        asm volatile("" ::: "memory");
       }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < RS; ++r) {
         const int it = tid + r * FB_NT;
-        if (it < items) {
-          const int f = last ? (it >> ln) : (it & (F - 1));
-          const int j = last ? (it & (n - 1)) : (it >> lF);
+        if (it < F) {
+          int f, j;
+          item(it, 0, f, j);
 #pragma unroll
           for (int i = 0; i < K1; ++i) {
             buf[idx(f, j, i)] = st[r][i];
-            buf[idx(f, n + j, i)] = st[r][K1 + i];
+            buf[idx(f, 1 + j, i)] = st[r][K1 + i];
           }
         }
       }
       __syncthreads();
     }
+  }
 
   // store: y (plus its old value after the first direction), or the coarse
   // values / a subtree root's image to scratch
