@@ -175,3 +175,33 @@ def test_fibre_form_selection():
     with pytest.raises(sg.SgdgError):
         p64.sweep_form(4)
     p64.close()
+
+
+def test_fibre_form_graph_replay_matches_eager():
+    """The fibre form captured in a HIP graph (the benchmark times it that
+    way): d=2 N=14 k=1 has split fibres (coarse synthesis, subtree tiles,
+    coarse analysis per direction).  Three replays, with eager work on the
+    same stream in between, each bit for bit equal to the eager sweep."""
+    sg = lib()
+    import torch
+
+    plan = sg.Plan([I.Instance(2, 14, 1, [1.0], I.rx_zeros(1))], "fp64")
+    plan.sweep_form(2)
+    say("fibre form graph replay d=2 N=14")
+    x = to_dev(I.smooth_random(plan.total, 21, 1)[0])
+    ye = torch.empty_like(x)
+    plan.apply(x, ye)
+    torch.cuda.synchronize()
+    yg = torch.full_like(x, np.nan)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.apply(x, yg)
+    other = torch.empty_like(x)
+    for rep in range(3):
+        yg.fill_(np.nan)
+        g.replay()
+        plan.apply(ye, other)  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(yg, ye), f"replay {rep}"
+    del g
+    plan.close()
